@@ -1,0 +1,343 @@
+"""Plain FP64 CPU oracle for matrix-free stochastic reconfiguration (SR) and the
+linear method (LM), after Neuscamman, Umrigar and Chan, "Optimizing large parameter
+sets in variational quantum Monte Carlo" (arXiv:1108.0900).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports this module; only
+the test suite, the smoke check and the CPU-baseline leg of the benchmark may call
+it.  It shares no code with the GPU path: it is written directly from the paper's
+equations in numpy/scipy, float64 throughout, with no blocking, fusion or
+reordering beyond what each definition states.
+
+Notation (all arrays float64 unless stated):
+  O[k, i]   derivative ratio Psi^i_n / Psi_n of parameter i on sample k
+            (Sec. II.A, the ratios inside Eq. sr_overlap); N_s rows, N_p columns.
+  E[k]      local energy (H Psi)_n / Psi_n of sample k.
+  w[k]      weight of sample k.  Eq. sr_overlap sums over all configurations with
+            weight |Psi_n|^2/<Psi|Psi>; Monte Carlo sampling from that distribution
+            replaces it by the uniform weight 1/N_s, which is the default here.
+  S         overlap matrix, centred form (see the reading below).
+  g         energy gradient, the right-hand side of the centred SR system.
+
+Reading of the SR system (Sec. II.A, Eq. sr_lin_eq).  The paper's system is posed in
+the (N_p+1)-dimensional basis {Psi, d_i Psi}.  Eliminating x_0 (the coefficient of
+Psi) by a Schur complement leaves the centred N_p-dimensional system
+    S_c x = -(tau/2) g,  S_c = <(O_i - <O_i>)(O_j - <O_j>)>,  g_i = 2<(E - <E>)(O_i - <O_i>)>,
+and x_0 = 1 - tau<E> - <O>.x.  The hot path solves (S_c + eps I) x = g; the caller
+applies the -(tau/2) factor.  `paper_linear_system` builds the uncentred system so
+the test suite can check this equivalence.
+
+Functions and the passage each follows:
+  sample_weights, sample_mean ............ Sec. II.A, Eq. sr_overlap (weights)
+  overlap_matrix ......................... Sec. II.A, Eq. sr_overlap (formed explicitly)
+  overlap_matrix_uncentred ............... Sec. II.A, Eq. sr_overlap with Psi^0 = Psi
+  energy_gradient, diag_overlap .......... Sec. II.A, Eq. sr_lin_eq (centred right-hand side)
+  sv_product_dense ....................... Sec. II.A, Eq. sr_multiply_1 (explicit S times z)
+  sv_product_swapped ..................... Sec. II.A, Eq. sr_multiply_2 (sums interchanged)
+  paper_linear_system, sr_update ......... Sec. II.A, Eq. sr_lin_eq and alpha' = alpha + x_i/x_0
+  solve_dense ............................ Sec. II.A, Eq. sr_lin_eq solved by Cholesky
+  cg_solve ............................... Sec. II.A, conjugate gradient (Hestenes-Stiefel)
+  lm_matrices, lm_hv_dense ............... Sec. II.B, Eq. linear_eigen (H and S in Omega)
+  lm_lowest_eigenpair .................... Sec. II.B, Eq. linear_eigen (dense generalized solve)
+  quantize_bf16, dequantize_bf16 ......... precision form of the stored ratios (not in the paper)
+  solve_adjoint_gradients ................ implicit-adjoint derivative of the solve (not in the paper)
+
+Every function is pinned by the CPU tests against something other than itself
+(library routines, closed forms, invariants, exact enumeration of a tiny Hilbert
+space, finite differences).  Parity pins are listed in the test files.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "sample_weights", "sample_mean", "centred", "overlap_matrix", "overlap_matrix_uncentred",
+    "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
+    "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense",
+    "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "solve_adjoint_gradients",
+]
+
+
+# ----------------------------------------------------------------------------------------------
+# Sampled averages (Sec. II.A, Eq. sr_overlap)
+# ----------------------------------------------------------------------------------------------
+def sample_weights(n_s: int, w=None) -> np.ndarray:
+    """Weights of the sampled configurations.
+
+    Eq. sr_overlap weights each configuration by |Psi_n|^2/<Psi|Psi>; sampling from that
+    distribution turns the sum into a plain average, i.e. weight 1/N_s per sample.
+    An explicit `w` (summing to one) is used for exact enumeration of small spaces.
+    """
+    if w is None:
+        return np.full(n_s, 1.0 / n_s)
+    w = np.asarray(w, dtype=np.float64)
+    assert w.shape == (n_s,)
+    return w
+
+
+def sample_mean(O, w=None) -> np.ndarray:
+    """<O_i> = sum_n w_n O_ni, the overlap of Psi with Psi^i over <Psi|Psi>."""
+    O = np.asarray(O, dtype=np.float64)
+    w = sample_weights(O.shape[0], w)
+    return w @ O
+
+
+def energy_mean(E, w=None) -> float:
+    """<E> = sum_n w_n E_n, the sampled energy."""
+    E = np.asarray(E, dtype=np.float64)
+    w = sample_weights(E.shape[0], w)
+    return float(w @ E)
+
+
+def centred(O, w=None) -> np.ndarray:
+    """Ratios of the centred derivatives Psi^i - <O_i> Psi (R1 reading of Eq. sr_lin_eq)."""
+    O = np.asarray(O, dtype=np.float64)
+    return O - sample_mean(O, w)[None, :]
+
+
+def overlap_matrix(O, w=None) -> np.ndarray:
+    """Centred overlap S_ij = <(O_i - <O_i>)(O_j - <O_j>)>, formed explicitly.
+
+    This is Eq. sr_overlap (the sampled <Psi^i|Psi^j>/<Psi|Psi>) taken in the centred basis;
+    building it costs O(N_s N_p^2), which the matrix-free method avoids.
+    """
+    Oc = centred(O, w)
+    w = sample_weights(Oc.shape[0], w)
+    return Oc.T @ (w[:, None] * Oc)
+
+
+def overlap_matrix_uncentred(O, w=None) -> np.ndarray:
+    """The paper's (N_p+1)-dimensional overlap of Eq. sr_overlap, with Psi^0 = Psi (ratio 1)."""
+    O = np.asarray(O, dtype=np.float64)
+    A = np.concatenate([np.ones((O.shape[0], 1)), O], axis=1)
+    w = sample_weights(O.shape[0], w)
+    return A.T @ (w[:, None] * A)
+
+
+def energy_gradient(O, E, w=None) -> np.ndarray:
+    """g_i = 2 <(E - <E>)(O_i - <O_i>)>, the energy gradient dE/dalpha_i of a real Psi.
+
+    It is the right-hand side of the centred SR system (R1 reading of Eq. sr_lin_eq).
+    """
+    Oc = centred(O, w)
+    E = np.asarray(E, dtype=np.float64)
+    w = sample_weights(Oc.shape[0], w)
+    ec = E - energy_mean(E, w)
+    return 2.0 * (Oc.T @ (w * ec))
+
+
+def diag_overlap(O, w=None) -> np.ndarray:
+    """Diagonal of the centred overlap, S_ii = <(O_i - <O_i>)^2>."""
+    Oc = centred(O, w)
+    w = sample_weights(Oc.shape[0], w)
+    return (w[:, None] * Oc * Oc).sum(axis=0)
+
+
+# ----------------------------------------------------------------------------------------------
+# Products with S (Sec. II.A, Eqs. sr_multiply_1 and sr_multiply_2)
+# ----------------------------------------------------------------------------------------------
+def sv_product_dense(O, v, eps: float = 0.0, w=None) -> np.ndarray:
+    """(S + eps I) v with S formed explicitly first (Eq. sr_multiply_1 summed as written)."""
+    S = overlap_matrix(O, w)
+    v = np.asarray(v, dtype=np.float64)
+    return S @ v + eps * v
+
+
+def sv_product_swapped(O, v, eps: float = 0.0, w=None) -> np.ndarray:
+    """(S + eps I) v with the sums interchanged (Eq. sr_multiply_2): per sample, the scalar
+    sum_j O_nj v_j first, then sum_n w_n O_ni times that scalar.  Never forms S.
+    Used as the CPU timing baseline of the matrix-free method."""
+    Oc = centred(O, w)
+    w = sample_weights(Oc.shape[0], w)
+    v = np.asarray(v, dtype=np.float64)
+    t = Oc @ v
+    return Oc.T @ (w * t) + eps * v
+
+
+# ----------------------------------------------------------------------------------------------
+# The SR linear system (Sec. II.A, Eq. sr_lin_eq)
+# ----------------------------------------------------------------------------------------------
+def paper_linear_system(O, E, tau: float, w=None):
+    """Uncentred system of Eq. sr_lin_eq: <Psi^i|(1 - tau H)|Psi> = sum_j <Psi^i|Psi^j> x_j.
+
+    With Psi^0 = Psi, the left side sampled is <O_i (1 - tau E)> (O_0 = 1).
+    Returns (A, b) with A the (N_p+1)^2 overlap and b the (N_p+1) right-hand side.
+    """
+    O = np.asarray(O, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    w = sample_weights(O.shape[0], w)
+    A = overlap_matrix_uncentred(O, w)
+    Ofull = np.concatenate([np.ones((O.shape[0], 1)), O], axis=1)
+    b = Ofull.T @ (w * (1.0 - tau * E))
+    return A, b
+
+
+def sr_update(alpha, x_full) -> np.ndarray:
+    """Parameter update alpha'_i = alpha_i + x_i / x_0 (Sec. II.A)."""
+    x_full = np.asarray(x_full, dtype=np.float64)
+    return np.asarray(alpha, dtype=np.float64) + x_full[1:] / x_full[0]
+
+
+def solve_dense(O, g, eps: float, w=None) -> np.ndarray:
+    """x = (S + eps I)^{-1} g with S built explicitly and factored by Cholesky.
+
+    For eps = 0 and singular S the system is consistent (g lies in the range of S) and the
+    result is defined as the minimum-norm solution pinv(S) g.
+    """
+    S = overlap_matrix(O, w)
+    g = np.asarray(g, dtype=np.float64)
+    n = S.shape[0]
+    if eps > 0.0:
+        c = sla.cho_factor(S + eps * np.eye(n), lower=True)
+        return sla.cho_solve(c, g)
+    return np.linalg.pinv(S, rcond=1e-12, hermitian=True) @ g
+
+
+def cg_solve(apply_A, b, rtol: float = 1e-10, max_iter: int | None = None,
+             refresh_every: int = 0, x0=None):
+    """Conjugate gradient (Hestenes-Stiefel) for a symmetric positive (semi)definite A.
+
+    Sec. II.A: iterate with matrix-vector products only, until the requested accuracy.
+    Stops when ||r|| <= rtol ||b|| on the recurrence residual.  With refresh_every = m > 0,
+    every m-th iteration replaces r by the true residual b - A x (keeping p).
+    Returns (x, iterations, relative recurrence residual).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    if max_iter is None:
+        max_iter = n + 100
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply_A(x) if x0 is not None else b.copy()
+    p = r.copy()
+    rho = float(r @ r)
+    bnorm = float(np.sqrt(b @ b))
+    if bnorm == 0.0:
+        return np.zeros(n), 0, 0.0
+    it = 0
+    while it < max_iter and np.sqrt(rho) > rtol * bnorm:
+        q = apply_A(p)
+        alpha = rho / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        if refresh_every and it % refresh_every == 0:
+            r = b - apply_A(x)
+        rho_new = float(r @ r)
+        beta = rho_new / rho
+        p = r + beta * p
+        rho = rho_new
+    return x, it, float(np.sqrt(rho) / bnorm)
+
+
+# ----------------------------------------------------------------------------------------------
+# Linear method (Sec. II.B, Eq. linear_eigen)
+# ----------------------------------------------------------------------------------------------
+def lm_matrices(O, E, D, w=None):
+    """Sampled H and S of the linear method in the basis {Psi, Psi^i - <O_i> Psi}.
+
+    Reading: the paper's H.x (Eq. linear_multiply) needs the Hamiltonian itself; the
+    sampled estimator used here needs only local energies E and their parameter
+    derivatives D[k, j] = d E_L / d alpha_j, through (H Psi^j)_n / Psi_n = D_nj + E_n O_nj.
+    In the centred basis that gives
+        H_00 = <E>,  H_i0 = <Oc_i E>,  H_0j = <E Oc_j> + <D_j>,  H_ij = <Oc_i E Oc_j> + <Oc_i D_j>,
+    and S = 1 (+) S_c (block diagonal).
+    """
+    O = np.asarray(O, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    w = sample_weights(O.shape[0], w)
+    Oc = centred(O, w)
+    n = O.shape[1]
+    H = np.empty((n + 1, n + 1))
+    H[0, 0] = w @ E
+    H[1:, 0] = Oc.T @ (w * E)
+    H[0, 1:] = (w * E) @ Oc + w @ D
+    H[1:, 1:] = Oc.T @ (w[:, None] * (E[:, None] * Oc + D))
+    S = np.zeros((n + 1, n + 1))
+    S[0, 0] = 1.0
+    S[1:, 1:] = Oc.T @ (w[:, None] * Oc)
+    return H, S
+
+
+def lm_hv_dense(O, E, D, v, w=None) -> np.ndarray:
+    """H v with H from `lm_matrices`, formed explicitly."""
+    H, _ = lm_matrices(O, E, D, w)
+    return H @ np.asarray(v, dtype=np.float64)
+
+
+def lm_lowest_eigenpair(H, S):
+    """Lowest real eigenpair of H x = E S x (Eq. linear_eigen) by a dense generalized solve."""
+    vals, vecs = sla.eig(H, S)
+    vals = np.real_if_close(vals)
+    finite = np.isfinite(vals)
+    idx = np.where(finite)[0][np.argmin(np.real(vals[finite]))]
+    return float(np.real(vals[idx])), np.real(vecs[:, idx])
+
+
+# ----------------------------------------------------------------------------------------------
+# Precision form: bf16 storage with a per-column float32 scale (not in the paper)
+# ----------------------------------------------------------------------------------------------
+def _f64_to_f32_round_to_odd(t: np.ndarray) -> np.ndarray:
+    """float64 -> float32 bit patterns with round-to-odd (truncate, then set the last bit
+    if anything was discarded).  Rounding to odd first and to nearest-even second gives the
+    same bf16 value as one nearest-even rounding of the float64 value."""
+    t = np.asarray(t, dtype=np.float64)
+    f = t.astype(np.float32)                     # nearest-even
+    fb = f.view(np.uint32).copy()
+    back = f.astype(np.float64)
+    # step toward zero where nearest rounded away from zero
+    away = np.abs(back) > np.abs(t)
+    fb[away] -= np.uint32(1)
+    inexact = back != t
+    fb[inexact] |= np.uint32(1)
+    return fb
+
+
+def quantize_bf16(O):
+    """Per-column float32 scale s_j = max_k |O_kj| (1 for an all-zero column) and
+    q_kj = round-to-nearest-even bf16 of O_kj / s_j (the quotient taken in float64).
+
+    Returns (q as uint16 bit patterns, s as float32)."""
+    O = np.asarray(O, dtype=np.float64)
+    amax = np.abs(O).max(axis=0) if O.shape[0] else np.zeros(O.shape[1])
+    s = amax.astype(np.float32)
+    s[s == 0] = np.float32(1.0)
+    t = O / s.astype(np.float64)[None, :]
+    fb = _f64_to_f32_round_to_odd(t)
+    rounded = (fb.astype(np.uint64) + np.uint64(0x7FFF) + ((fb.astype(np.uint64) >> np.uint64(16)) & np.uint64(1)))
+    q = (rounded >> np.uint64(16)).astype(np.uint16)
+    return q, s
+
+
+def dequantize_bf16(q, s) -> np.ndarray:
+    """Stored value s_j * q_kj lifted to float64."""
+    q = np.asarray(q, dtype=np.uint16)
+    f = (q.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+    return f * np.asarray(s, dtype=np.float32).astype(np.float64)[None, :]
+
+
+# ----------------------------------------------------------------------------------------------
+# Implicit-adjoint derivatives of the solve (not in the paper)
+# ----------------------------------------------------------------------------------------------
+def solve_adjoint_gradients(O, E, eps: float, dL_dx):
+    """Derivatives of a scalar L(x) with x = (S + eps I)^{-1} g, g = energy_gradient(O, E).
+
+    With lambda = (S + eps I)^{-1} dL/dx, p1 = Oc x, p2 = Oc lambda, e_c = E - <E> and
+    uniform weights 1/N:
+        dL/dO = (1/N) [ (2 e_c - p1) lambda^T - p2 x^T ],  dL/dE = (2/N) p2,
+        dL/dg = lambda,  dL/deps = -lambda . x.
+    Returns a dict with x, lam, dO, dE, dg, deps.
+    """
+    O = np.asarray(O, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    n_s = O.shape[0]
+    g = energy_gradient(O, E)
+    x = solve_dense(O, g, eps)
+    lam = solve_dense(O, np.asarray(dL_dx, dtype=np.float64), eps)
+    Oc = centred(O)
+    ec = E - E.mean()
+    p1 = Oc @ x
+    p2 = Oc @ lam
+    dO = (np.outer(2.0 * ec - p1, lam) - np.outer(p2, x)) / n_s
+    dE = 2.0 * p2 / n_s
+    return {"x": x, "lam": lam, "dO": dO, "dE": dE, "dg": lam, "deps": -float(lam @ x)}
