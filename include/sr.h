@@ -1,0 +1,175 @@
+/*
+ * libsr: matrix-free stochastic reconfiguration (SR) and linear-method (LM) products on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method (Neuscamman, Umrigar and Chan, arXiv:1108.0900, Sec. II.A and II.B) never
+ * forms the N_p x N_p overlap matrix.  It keeps the per-sample derivative ratios
+ * O[k][i] = Psi^i_n / Psi_n (one row per sample, Eq. sr_overlap) and applies
+ *     S v = (1/N_s) Oc^T (Oc v),   Oc = O - 1 obar^T,   obar = column mean of O
+ * by interchanging the sums over samples and parameters (Eq. sr_multiply_2), inside a
+ * conjugate-gradient solve of (S + eps I) x = g (Eq. sr_lin_eq in its centred form).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers on the current HIP device, owned by the
+ *    caller; the library never frees them.  Host pointers are marked "host".
+ *  - Matrices are row-major: element (k, i) of O is at O + k*ld + i, with ld >= n_p.
+ *    The allocation must span n_s*ld elements, O must be 16-byte aligned and
+ *    ld * (element size) must be a multiple of 16 bytes (columns n_p..ld-1 are padding
+ *    and are never used in the arithmetic).
+ *  - Vectors of length n_p are float64 and contiguous.
+ *  - Every call is asynchronous on `stream` unless stated otherwise, and runs its work
+ *    in one or more kernels on that stream.  Calls that share a device and a stream
+ *    share the library's workspace for that (device, stream) pair; calls that overlap
+ *    in time on two different streams use two workspaces.
+ *  - Return value: an sr_status code.  Negative codes are errors; no kernel has been
+ *    launched when SR_ERR_INVALID is returned.  The thread-local text of the last error
+ *    is available from sr_last_error().
+ */
+#ifndef SR_H
+#define SR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum sr_status {
+  SR_OK = 0,
+  SR_NOT_CONVERGED = 1,   /* CG reached max_iter; x holds the last iterate           */
+  SR_BREAKDOWN = 2,       /* CG found p.(S+eps I)p <= 0; x holds the last iterate     */
+  SR_ERR_INVALID = -1,    /* bad argument, detected on the host before any launch    */
+  SR_ERR_NOMEM = -2,      /* workspace allocation failed                              */
+  SR_ERR_HIP = -3,        /* a HIP runtime call failed (text in sr_last_error)        */
+  SR_ERR_NONFINITE = -4,  /* CG met a NaN or infinity in a scalar                      */
+  SR_ERR_NODEVICE = -5,   /* no HIP device, or the device is not gfx950              */
+  SR_ERR_TIMEOUT = -6     /* a cross-workgroup wait exceeded its bound (kernel exited) */
+};
+
+/* Storage type of the derivative-ratio matrix. */
+enum sr_dtype {
+  SR_F64 = 0,    /* float64; arithmetic in float64                                   */
+  SR_F32 = 1,    /* float32; arithmetic in float64                                   */
+  SR_BF16 = 2,   /* bfloat16 codes q with float32 column scales s: O = s_j * q_kj;   */
+                 /* products accumulate in float32, vectors and CG scalars float64    */
+  SR_F16 = 3     /* float16 codes with float32 column scales, as SR_BF16             */
+};
+
+/* Non-owning view of a derivative-ratio matrix (Sec. II.A: "pre-computed and stored"). */
+typedef struct sr_matrix {
+  int64_t n_s;               /* rows = samples, >= 1                                   */
+  int64_t n_p;               /* columns = parameters, >= 1                             */
+  int64_t ld;                /* row stride in elements, >= n_p                         */
+  int32_t dtype;             /* enum sr_dtype                                          */
+  int32_t reserved;          /* must be 0                                              */
+  const void *O;             /* [n_s][ld] device                                       */
+  const float *col_scale;    /* [n_p] device; required for SR_BF16/SR_F16, else NULL   */
+  const double *col_mean;    /* [n_p] device column means of the STORED values         */
+                             /* (s_j*q_kj for scaled types); NULL: computed by the call */
+} sr_matrix;
+
+/* Conjugate-gradient options (Sec. II.A: iterate until the requested accuracy). */
+typedef struct sr_cg_opts {
+  double rtol;               /* stop when ||r|| <= rtol ||g|| (recurrence residual,    */
+                             /* confirmed by the true residual g - (S+eps I)x); > 0     */
+  int32_t max_iter;          /* <= 0: n_p + 100                                        */
+  int32_t refresh_every;     /* m > 0: every m-th iteration r <- g - (S+eps I)x; 0: never */
+  int32_t use_x0;            /* 1: x holds the starting guess on entry; 0: start at 0  */
+  int32_t restart_on_refresh;/* 1: also reset p <- r at each refresh (restarted CG);   */
+                             /* 0: keep p (residual replacement)                       */
+  double *res_history;       /* optional device [max_iter+1]: ||r||/||g|| per iteration */
+} sr_cg_opts;
+
+/* CG outcome, written to host memory. */
+typedef struct sr_cg_info {
+  int32_t iters;             /* CG iterations performed                                */
+  int32_t refreshes;         /* true-residual replacements (periodic and at exit)      */
+  int32_t status;            /* same value the call returns                            */
+  int32_t products;          /* products with (S + eps I) performed                    */
+  double rel_res_recur;      /* ||r||/||g|| of the recurrence residual at exit         */
+  double rel_res_true;       /* ||g - (S+eps I)x|| / ||g|| at exit                      */
+} sr_cg_info;
+
+/* ------------------------------------------------------------------------------------
+ * sr_grad: one pass over O (and E) giving the sampled quantities of the centred SR
+ * system (Sec. II.A, Eq. sr_lin_eq with Psi^0 eliminated; Eq. sr_overlap for the means):
+ *   E_mean       = (1/n_s) sum_k E_k                                   (device scalar)
+ *   col_mean_i   = (1/n_s) sum_k O_ki                                  [n_p]
+ *   diagS_i      = (1/n_s) sum_k (O_ki - col_mean_i)^2                 [n_p]
+ *   g_i          = (2/n_s) sum_k (E_k - E_mean)(O_ki - col_mean_i)     [n_p]
+ * E: [n_s] float64.  Any of E_mean, col_mean_out, diagS_out may be NULL.  g may be NULL
+ * only if E is NULL too (then only the column statistics are produced).
+ * The matrix's own col_mean field is ignored.
+ * ------------------------------------------------------------------------------------ */
+int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean,
+            double *col_mean_out, double *diagS_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * sr_sv_product: y = (S + eps I) v with S = (1/n_s) Oc^T Oc applied by interchanging the
+ * sums over samples and parameters (Sec. II.A, Eq. sr_multiply_2): for each row,
+ * w_k = Oc_k . v, then y = (1/n_s) sum_k w_k Oc_k + eps v.  O is read once.
+ * v, y: [n_p] float64, must not overlap.  eps >= 0.
+ * ------------------------------------------------------------------------------------ */
+int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * sr_cg_solve: conjugate gradient on (S + eps I) x = g with S applied only through the
+ * product above (Sec. II.A), all iterations in one persistent launch.
+ * g: [n_p] float64 right-hand side.  x: [n_p] float64 solution (starting guess on
+ * entry if opt->use_x0).  opt: host, may be NULL (rtol 1e-10, defaults otherwise).
+ * info: host, may be NULL.  eps >= 0; with eps = 0 and a singular S the result is the
+ * minimum-norm solution when g lies in the range of S.
+ * Residual refreshes and the exit check use products accumulated in float64 for every
+ * storage type, so for bf16/f16 storage the iteration converges to the solution of the
+ * stored (dequantized) system although its search-direction products accumulate in
+ * float32 (mixed-precision residual replacement).
+ * This call synchronizes `stream` before returning (it reads the outcome back).
+ * Returns SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN or an error code.
+ * ------------------------------------------------------------------------------------ */
+int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x,
+                const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * lm_hv_product: the linear method's Hamiltonian product in the basis
+ * {Psi, Psi^i - obar_i Psi} (Sec. II.B, Eq. linear_eigen), estimated from local energies
+ * E and their parameter derivatives D (D_kj = d E_L / d alpha_j on sample k):
+ *   t_k = Oc_k . v[1:],  u_k = D_k . v[1:],  z_k = E_k (v_0 + t_k) + u_k
+ *   y_0 = E_mean v_0 + (1/n_s) sum_k (E_k t_k + u_k)
+ *   y_i = (1/n_s) sum_k Oc_ki z_k                                       (i >= 1)
+ * O and D: same n_s, n_p and dtype (their ld and scales may differ).  E: [n_s] float64.
+ * v, y: [n_p + 1] float64, must not overlap.  The companion overlap is 1 (+) S.
+ * ------------------------------------------------------------------------------------ */
+int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
+                  const double *v, double *y, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * sr_quantize: storage conversion of a float64 or float32 matrix to SR_BF16 or SR_F16
+ * codes with per-column float32 scales (not in the paper; the precision form):
+ *   s_j = float32(max_k |O_kj|)  (1 for an all-zero column)
+ *   q_kj = round-to-nearest-even of O_kj / s_j (the quotient taken in float64).
+ * in: [n_s][ld_in] of in_dtype (SR_F64 or SR_F32).  q: [n_s][ld_out] of out_dtype
+ * (columns n_p..ld_out-1 are set to zero).  scale: [n_p] float32.
+ * Same alignment rules as sr_matrix for both matrices.
+ * ------------------------------------------------------------------------------------ */
+int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
+                void *q, int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream);
+
+/* Frees every workspace the library holds (all devices, all streams).  Must not be
+ * called while library work is pending on any stream. */
+int sr_release(void);
+
+/* Static text for a status code. */
+const char *sr_status_string(int status);
+
+/* Thread-local text describing the last error returned on this thread ("" if none). */
+const char *sr_last_error(void);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int sr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H */

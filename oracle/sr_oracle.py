@@ -38,7 +38,7 @@ Functions and the passage each follows:
   cg_solve ............................... Sec. II.A, conjugate gradient (Hestenes-Stiefel)
   lm_matrices, lm_hv_dense ............... Sec. II.B, Eq. linear_eigen (H and S in Omega)
   lm_lowest_eigenpair .................... Sec. II.B, Eq. linear_eigen (dense generalized solve)
-  quantize_bf16, dequantize_bf16 ......... precision form of the stored ratios (not in the paper)
+  quantize_bf16/_f16, dequantize_* ....... precision form of the stored ratios (not in the paper)
   solve_adjoint_gradients ................ implicit-adjoint derivative of the solve (not in the paper)
 
 Every function is pinned by the CPU tests against something other than itself
@@ -54,7 +54,8 @@ __all__ = [
     "sample_weights", "sample_mean", "centred", "overlap_matrix", "overlap_matrix_uncentred",
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
     "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense",
-    "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "solve_adjoint_gradients",
+    "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
+    "solve_adjoint_gradients",
 ]
 
 
@@ -307,6 +308,25 @@ def quantize_bf16(O):
     rounded = (fb.astype(np.uint64) + np.uint64(0x7FFF) + ((fb.astype(np.uint64) >> np.uint64(16)) & np.uint64(1)))
     q = (rounded >> np.uint64(16)).astype(np.uint16)
     return q, s
+
+
+def quantize_f16(O):
+    """As quantize_bf16 but with float16 codes: q_kj = nearest-even float16 of O_kj / s_j
+    (the quotient taken in float64).  Returns (q as uint16 bit patterns, s as float32)."""
+    O = np.asarray(O, dtype=np.float64)
+    amax = np.abs(O).max(axis=0) if O.shape[0] else np.zeros(O.shape[1])
+    s = amax.astype(np.float32)
+    s[s == 0] = np.float32(1.0)
+    t = O / s.astype(np.float64)[None, :]
+    f = _f64_to_f32_round_to_odd(t).view(np.float32)
+    q = f.astype(np.float16).view(np.uint16)
+    return q, s
+
+
+def dequantize_f16(q, s) -> np.ndarray:
+    """Stored value s_j * q_kj (float16 codes) lifted to float64."""
+    f = np.asarray(q, dtype=np.uint16).view(np.float16).astype(np.float64)
+    return f * np.asarray(s, dtype=np.float32).astype(np.float64)[None, :]
 
 
 def dequantize_bf16(q, s) -> np.ndarray:

@@ -1,0 +1,642 @@
+// libsr C-ABI: argument validation, launch planning, per-(device, stream) workspace and
+// cooperative launches of the kernels.  Declarations and the contract are in sr.h.
+#include "sr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sr_launch.hpp"
+
+namespace {
+
+using namespace sr;
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(SR_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int elem_bytes(int dt) { return dt == SR_F64 ? 8 : dt == SR_F32 ? 4 : 2; }
+int vec_of(int dt) { return 16 / elem_bytes(dt); }
+bool scaled(int dt) { return dt == SR_BF16 || dt == SR_F16; }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+int64_t pow2_ceil(int64_t a) {
+  int64_t p = 1;
+  while (p < a) p <<= 1;
+  return p;
+}
+
+// ------------------------------------------------------------------------------------
+// Argument checks (host only; no HIP call)
+// ------------------------------------------------------------------------------------
+int check_matrix(const sr_matrix *m, const char *name) {
+  if (m == nullptr) return fail(SR_ERR_INVALID, "%s: null sr_matrix", name);
+  if (m->dtype < SR_F64 || m->dtype > SR_F16) return fail(SR_ERR_INVALID, "%s: unknown dtype %d", name, m->dtype);
+  if (m->reserved != 0) return fail(SR_ERR_INVALID, "%s: reserved field must be 0", name);
+  if (m->n_s < 1) return fail(SR_ERR_INVALID, "%s: n_s must be >= 1 (got %lld)", name, (long long)m->n_s);
+  if (m->n_p < 1) return fail(SR_ERR_INVALID, "%s: n_p must be >= 1 (got %lld)", name, (long long)m->n_p);
+  if (m->ld < m->n_p) return fail(SR_ERR_INVALID, "%s: ld (%lld) < n_p (%lld)", name, (long long)m->ld, (long long)m->n_p);
+  if (m->n_s > (int64_t)1 << 40 || m->n_p > (int64_t)1 << 31)
+    return fail(SR_ERR_INVALID, "%s: dimensions out of range", name);
+  if (m->O == nullptr) return fail(SR_ERR_INVALID, "%s: O is null", name);
+  if (((uintptr_t)m->O) % 16 != 0) return fail(SR_ERR_INVALID, "%s: O must be 16-byte aligned", name);
+  if ((m->ld * elem_bytes(m->dtype)) % 16 != 0)
+    return fail(SR_ERR_INVALID, "%s: ld * element size must be a multiple of 16 bytes", name);
+  if (scaled(m->dtype) && m->col_scale == nullptr)
+    return fail(SR_ERR_INVALID, "%s: col_scale is required for bf16/f16 storage", name);
+  if (!scaled(m->dtype) && m->col_scale != nullptr)
+    return fail(SR_ERR_INVALID, "%s: col_scale must be NULL for f64/f32 storage", name);
+  return SR_OK;
+}
+
+bool ranges_overlap(const void *a, int64_t na, const void *b, int64_t nb) {
+  const char *pa = (const char *)a, *pb = (const char *)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+// ------------------------------------------------------------------------------------
+// Device state
+// ------------------------------------------------------------------------------------
+struct DeviceInfo {
+  bool ok = false;
+  int cus = 0;
+  int grid = 0;     // persistent grid size: 8 * (largest power of two <= CUs/8)
+};
+
+std::mutex g_mu;
+std::map<int, DeviceInfo> g_dev;
+
+struct Workspace {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+int device_check(int *dev_out, DeviceInfo *info_out) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return fail(SR_ERR_NODEVICE, "no HIP device available");
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    DeviceInfo di;
+    di.ok = std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+    di.cus = p.multiProcessorCount;
+    int coop = 0;
+    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) di.ok = false;
+    int L = 1;
+    while (L * 2 <= di.cus / 8) L *= 2;
+    di.grid = 8 * L;
+    it = g_dev.emplace(dev, di).first;
+  }
+  if (!it->second.ok) return fail(SR_ERR_NODEVICE, "device %d is not a gfx950 device with cooperative launch", dev);
+  *dev_out = dev;
+  *info_out = it->second;
+  return SR_OK;
+}
+
+// Workspace of at least `bytes` for (dev, stream); grows by reallocation (after the
+// stream has drained).
+int get_workspace(int dev, hipStream_t s, size_t bytes, void **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace &w = g_ws[std::make_pair(dev, s)];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    const size_t want = (size_t)round_up((int64_t)bytes, (int64_t)1 << 20);
+    hipError_t e = hipMalloc(&w.ptr, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      w.ptr = nullptr;
+      return fail(SR_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
+    }
+    w.bytes = want;
+  }
+  *out = w.ptr;
+  return SR_OK;
+}
+
+// Bump allocator over the workspace (256-byte aligned pieces).
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <typename T> T *take(int64_t n) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T *p = (T *)(base + off);
+    off += (size_t)n * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------------------------
+// Launch planning
+// ------------------------------------------------------------------------------------
+struct Plan {
+  const KernelEntry *ke = nullptr;
+  ProdGeom pg{};
+  int words = 0;   // exchange words per column group per tile
+};
+
+// Optional override "nv,r,nb" from SR_TILE (used by the tile sweep) or the
+// programmatic override below.
+int g_force_nv = 0, g_force_r = 0, g_force_nb = 0, g_force_c = 0;
+
+void read_env_override() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const char *e = std::getenv("SR_TILE");
+  if (e) std::sscanf(e, "%d,%d,%d,%d", &g_force_nv, &g_force_r, &g_force_nb, &g_force_c);
+}
+
+int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg) {
+  int64_t C = pow2_ceil(cdiv(n_p, cols_per_wg));
+  if (force_c > 0 && force_c >= C) C = force_c;
+  if (C > G) return fail(SR_ERR_INVALID, "n_p = %lld exceeds the column capacity of this build (%lld)",
+                         (long long)n_p, (long long)G * cols_per_wg);
+  pg->G = G;
+  pg->C = (int)C;
+  pg->RG = G / (int)C;
+  pg->n_s = n_s;
+  pg->n_p = n_p;
+  pg->wslice = round_up(cdiv(n_p, C), vec);
+  pg->n_tiles = (int)cdiv(n_s, r);
+  return SR_OK;
+}
+
+int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
+  read_env_override();
+  int count = 0;
+  const KernelEntry *tab = kernel_table(dt, &count);
+  const int vec = vec_of(dt);
+  const KernelEntry *pick = nullptr;
+  if (g_force_nv > 0) {
+    for (int i = 0; i < count; ++i)
+      if (tab[i].nv == g_force_nv && tab[i].r == g_force_r && tab[i].nb == g_force_nb) pick = &tab[i];
+  }
+  if (pick == nullptr) {
+    // Heuristic: the smallest per-thread slice (NV) that holds a whole row in one
+    // workgroup (no exchange); if none does, the widest slice (fewest column groups).
+    const KernelEntry *best = nullptr;
+    for (int i = 0; i < count; ++i) {
+      const int64_t cap = (int64_t)tab[i].nv * vec * kNT;
+      if (n_p <= cap && (best == nullptr || tab[i].nv < best->nv)) best = &tab[i];
+    }
+    if (best == nullptr)
+      for (int i = 0; i < count; ++i)
+        if (best == nullptr || tab[i].nv > best->nv) best = &tab[i];
+    pick = best;
+  }
+  plan->ke = pick;
+  const int cols = pick->nv * vec * kNT;
+  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, g_force_c, &plan->pg);
+  if (rc) return rc;
+  plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
+  return SR_OK;
+}
+
+// Workspace pieces used by a product-type launch.
+struct ProdWs {
+  SyncBufs sb;
+  ProdBufs pb;
+  uint32_t *zero_base;   // start of the region zeroed before each launch
+  int64_t zero_words;    // its length in 32-bit words
+};
+
+void carve_prod(Carve &cv, const Plan &pl, int64_t ypart_doubles, ProdWs *w) {
+  const ProdGeom &pg = pl.pg;
+  // zeroed region: flags, abort, exchange ring
+  const size_t start = (size_t)round_up((int64_t)cv.off, 256);
+  w->sb.flags = cv.take<uint32_t>(pg.G);
+  w->sb.abort = cv.take<uint32_t>(64);
+  w->pb.xchg = cv.take<u64>((int64_t)pg.RG * kRing * pg.C * (pl.words > 0 ? pl.words : 1));
+  const size_t end = cv.off;
+  w->zero_base = (uint32_t *)(cv.base + start);
+  w->zero_words = (int64_t)((end - start + 3) / 4);
+  w->sb.red = cv.take<double>(4 * 2 * pg.G);
+  w->pb.ypart = cv.take<double>(ypart_doubles);
+  w->pb.spart = cv.take<double>((int64_t)pg.RG * 2);
+}
+
+size_t prod_ws_bytes(const Plan &pl, int64_t ypart_doubles) {
+  const ProdGeom &pg = pl.pg;
+  size_t b = 0;
+  auto add = [&](size_t n) { b = (size_t)round_up((int64_t)b, 256) + n; };
+  add(pg.G * 4);
+  add(64 * 4);
+  add((size_t)pg.RG * kRing * pg.C * (pl.words > 0 ? pl.words : 1) * 8);
+  add((size_t)4 * 2 * pg.G * 8);
+  add((size_t)ypart_doubles * 8);
+  add((size_t)pg.RG * 2 * 8);
+  return b + 256;
+}
+
+int zero_sync(const ProdWs &w, hipStream_t s) {
+  int64_t n = w.zero_words;
+  uint32_t v = 0;
+  uint32_t *p = w.zero_base;
+  void *args[] = {&p, &n, &v};
+  const int blocks = (int)std::min<int64_t>(1024, cdiv(n, 256));
+  HIP_TRY(hipLaunchKernel(fill_kernel(), dim3(blocks > 0 ? blocks : 1), dim3(256), args, 0, s));
+  return SR_OK;
+}
+
+int launch_coop(const void *fn, int G, void *argp, hipStream_t s) {
+  void *args[] = {argp};
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kNT), args, 0, s));
+  return SR_OK;
+}
+
+Operand make_operand(const sr_matrix *m) {
+  Operand op;
+  op.O = (const unsigned char *)m->O;
+  op.ldb = m->ld * elem_bytes(m->dtype);
+  op.scale = m->col_scale;
+  return op;
+}
+
+// Column statistics / gradient pass.  Any output pointer may be null.
+int run_grad(const sr_matrix *m, const double *E, double *g, double *Emean, double *mean, double *diag, int dev,
+             const DeviceInfo &di, hipStream_t s) {
+  const int dt = m->dtype;
+  const int vec = vec_of(dt);
+  Plan pl;
+  pl.words = 0;
+  int rc = geometry(di.grid, m->n_s, m->n_p, grad_nv(dt) * vec * kNT, vec, grad_rows(dt), 0, &pl.pg);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * 3 * m->n_p;
+  void *base = nullptr;
+  rc = get_workspace(dev, s, prod_ws_bytes(pl, ypd), &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  GradArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(m);
+  a.E = E;
+  a.g_out = g;
+  a.mean_out = mean;
+  a.diag_out = diag;
+  a.Emean_out = Emean;
+  rc = zero_sync(w, s);
+  if (rc) return rc;
+  return launch_coop(grad_kernel(dt), pl.pg.G, &a, s);
+}
+
+// Column means into `mean` when the matrix does not carry them.
+int ensure_mean(const sr_matrix *m, double *scratch, const double **mean_out, int dev, const DeviceInfo &di,
+                hipStream_t s) {
+  if (m->col_mean) {
+    *mean_out = m->col_mean;
+    return SR_OK;
+  }
+  int rc = run_grad(m, nullptr, nullptr, nullptr, scratch, nullptr, dev, di, s);
+  if (rc) return rc;
+  *mean_out = scratch;
+  return SR_OK;
+}
+
+// Separate small allocation for means computed on behalf of the caller, so they survive
+// the workspace being re-carved by the product launch that follows.
+std::map<std::pair<int, hipStream_t>, Workspace> g_mean_ws;
+
+int get_mean_scratch(int dev, hipStream_t s, int64_t n, double **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Workspace &w = g_mean_ws[std::make_pair(dev, s)];
+  const size_t bytes = (size_t)n * 8 + 256;
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&w.ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      w.ptr = nullptr;
+      return fail(SR_ERR_NOMEM, "mean scratch allocation failed");
+    }
+    w.bytes = bytes;
+  }
+  *out = (double *)w.ptr;
+  return SR_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+extern "C" {
+
+int sr_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+const char *sr_last_error(void) { return g_last_error.c_str(); }
+
+const char *sr_status_string(int status) {
+  switch (status) {
+    case SR_OK: return "SR_OK";
+    case SR_NOT_CONVERGED: return "SR_NOT_CONVERGED: CG reached max_iter";
+    case SR_BREAKDOWN: return "SR_BREAKDOWN: p.(S+eps I)p <= 0";
+    case SR_ERR_INVALID: return "SR_ERR_INVALID: invalid argument";
+    case SR_ERR_NOMEM: return "SR_ERR_NOMEM: workspace allocation failed";
+    case SR_ERR_HIP: return "SR_ERR_HIP: HIP runtime error";
+    case SR_ERR_NONFINITE: return "SR_ERR_NONFINITE: non-finite value in CG";
+    case SR_ERR_NODEVICE: return "SR_ERR_NODEVICE: no gfx950 device";
+    case SR_ERR_TIMEOUT: return "SR_ERR_TIMEOUT: cross-workgroup wait exceeded its bound";
+    default: return "unknown status";
+  }
+}
+
+int sr_release(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  int rc = SR_OK;
+  for (auto *mp : {&g_ws, &g_mean_ws}) {
+    for (auto &kv : *mp) {
+      if (kv.second.ptr) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first.first);
+        if (hipFree(kv.second.ptr) != hipSuccess) rc = fail(SR_ERR_HIP, "hipFree failed in sr_release");
+        (void)hipSetDevice(cur);
+      }
+    }
+    mp->clear();
+  }
+  return rc;
+}
+
+int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean, double *col_mean_out,
+            double *diagS_out, hipStream_t stream) {
+  int rc = check_matrix(O, "sr_grad");
+  if (rc) return rc;
+  if (g != nullptr && E == nullptr) return fail(SR_ERR_INVALID, "sr_grad: g requires E");
+  if (E_mean != nullptr && E == nullptr) return fail(SR_ERR_INVALID, "sr_grad: E_mean requires E");
+  if (g == nullptr && E_mean == nullptr && col_mean_out == nullptr && diagS_out == nullptr)
+    return fail(SR_ERR_INVALID, "sr_grad: no output requested");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  return run_grad(O, E, g, E_mean, col_mean_out, diagS_out, dev, di, stream);
+}
+
+int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream) {
+  int rc = check_matrix(O, "sr_sv_product");
+  if (rc) return rc;
+  if (v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: null v or y");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_sv_product: eps must be finite and >= 0");
+  if (ranges_overlap(v, O->n_p * 8, y, O->n_p * 8)) return fail(SR_ERR_INVALID, "sr_sv_product: v and y overlap");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  double *mscr = nullptr;
+  if (!O->col_mean) {
+    rc = get_mean_scratch(dev, stream, O->n_p, &mscr);
+    if (rc) return rc;
+  }
+  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
+  if (rc) return rc;
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * O->n_p;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd), &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  SvArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(O);
+  a.mean = mean;
+  a.v = v;
+  a.y = y;
+  a.eps = eps;
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  return launch_coop(pl.ke->sv, pl.pg.G, &a, stream);
+}
+
+int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const double *v, double *y,
+                  hipStream_t stream) {
+  int rc = check_matrix(O, "lm_hv_product(O)");
+  if (rc) return rc;
+  rc = check_matrix(D, "lm_hv_product(D)");
+  if (rc) return rc;
+  if (D->n_s != O->n_s || D->n_p != O->n_p || D->dtype != O->dtype)
+    return fail(SR_ERR_INVALID, "lm_hv_product: O and D must have the same n_s, n_p and dtype");
+  if (E == nullptr || v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "lm_hv_product: null E, v or y");
+  if (ranges_overlap(v, (O->n_p + 1) * 8, y, (O->n_p + 1) * 8))
+    return fail(SR_ERR_INVALID, "lm_hv_product: v and y overlap");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  double *mscr = nullptr;
+  if (!O->col_mean) {
+    rc = get_mean_scratch(dev, stream, O->n_p, &mscr);
+    if (rc) return rc;
+  }
+  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
+  if (rc) return rc;
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 2, &pl);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * O->n_p;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd), &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  LmArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.ops[0] = make_operand(O);
+  a.ops[1] = make_operand(D);
+  a.mean = mean;
+  a.E = E;
+  a.v = v;
+  a.y = y;
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  return launch_coop(pl.ke->lm, pl.pg.G, &a, stream);
+}
+
+int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt, sr_cg_info *info,
+                hipStream_t stream) {
+  int rc = check_matrix(O, "sr_cg_solve");
+  if (rc) return rc;
+  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: null g or x");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_cg_solve: eps must be finite and >= 0");
+  if (ranges_overlap(g, O->n_p * 8, x, O->n_p * 8)) return fail(SR_ERR_INVALID, "sr_cg_solve: g and x overlap");
+  sr_cg_opts o{};
+  o.rtol = 1e-10;
+  if (opt) o = *opt;
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "sr_cg_solve: rtol must be finite and > 0");
+  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_every must be >= 0");
+  if (o.restart_on_refresh != 0 && o.restart_on_refresh != 1)
+    return fail(SR_ERR_INVALID, "sr_cg_solve: restart_on_refresh must be 0 or 1");
+  if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: use_x0 must be 0 or 1");
+  int64_t max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
+  if (max_iter > (1 << 30)) max_iter = 1 << 30;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  double *mscr = nullptr;
+  if (!O->col_mean) {
+    rc = get_mean_scratch(dev, stream, O->n_p, &mscr);
+    if (rc) return rc;
+  }
+  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
+  if (rc) return rc;
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * O->n_p;
+  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (O->n_p * 8 + 256) + 1024;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, bytes, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  CgArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(O);
+  a.mean = mean;
+  a.g = g;
+  a.x = x;
+  a.r = cv.take<double>(O->n_p);
+  a.p = cv.take<double>(O->n_p);
+  a.q = cv.take<double>(O->n_p);
+  a.info = cv.take<double>(8);
+  a.eps = eps;
+  a.rtol = o.rtol;
+  a.max_iter = (int)max_iter;
+  a.refresh_every = o.refresh_every;
+  a.use_x0 = o.use_x0;
+  a.restart_on_refresh = o.restart_on_refresh;
+  a.hist = o.res_history;
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  rc = launch_coop(pl.ke->cg, pl.pg.G, &a, stream);
+  if (rc) return rc;
+  double hinfo[8];
+  uint32_t habort = 0;
+  HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  int status = (int)hinfo[2];
+  if (habort != 0u || hinfo[6] == 0.0) status = fail(SR_ERR_TIMEOUT, "sr_cg_solve: a cross-workgroup wait timed out");
+  else if (status == SR_ERR_NONFINITE) fail(SR_ERR_NONFINITE, "sr_cg_solve: non-finite scalar in CG");
+  else if (status == SR_BREAKDOWN) fail(SR_BREAKDOWN, "sr_cg_solve: p.(S+eps I)p <= 0");
+  else if (status == SR_NOT_CONVERGED) fail(SR_NOT_CONVERGED, "sr_cg_solve: max_iter reached");
+  if (info) {
+    info->iters = (int32_t)hinfo[0];
+    info->refreshes = (int32_t)hinfo[1];
+    info->status = status;
+    info->products = (int32_t)hinfo[3];
+    info->rel_res_recur = hinfo[4];
+    info->rel_res_true = hinfo[5];
+  }
+  return status;
+}
+
+int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, void *q, int64_t ld_out,
+                int32_t out_dtype, float *scale, hipStream_t stream) {
+  if (n_s < 1 || n_p < 1) return fail(SR_ERR_INVALID, "sr_quantize: n_s and n_p must be >= 1");
+  if (in_dtype != SR_F64 && in_dtype != SR_F32) return fail(SR_ERR_INVALID, "sr_quantize: in_dtype must be f64 or f32");
+  if (out_dtype != SR_BF16 && out_dtype != SR_F16) return fail(SR_ERR_INVALID, "sr_quantize: out_dtype must be bf16 or f16");
+  if (in == nullptr || q == nullptr || scale == nullptr) return fail(SR_ERR_INVALID, "sr_quantize: null pointer");
+  if (ld_in < n_p || ld_out < n_p) return fail(SR_ERR_INVALID, "sr_quantize: ld < n_p");
+  if (((uintptr_t)in) % 16 || ((uintptr_t)q) % 16) return fail(SR_ERR_INVALID, "sr_quantize: pointers must be 16-byte aligned");
+  if ((ld_in * elem_bytes(in_dtype)) % 16 || (ld_out * 2) % 16)
+    return fail(SR_ERR_INVALID, "sr_quantize: ld * element size must be a multiple of 16 bytes");
+  int dev;
+  DeviceInfo di;
+  int rc = device_check(&dev, &di);
+  if (rc) return rc;
+  Plan pl;
+  pl.words = 0;
+  rc = geometry(di.grid, n_s, n_p, kNT * 8, 1, 1, 0, &pl.pg);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * n_p;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd), &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  QuantArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.in = (const unsigned char *)in;
+  a.ldb_in = ld_in * elem_bytes(in_dtype);
+  a.out = (unsigned char *)q;
+  a.ld_out = ld_out;
+  a.scale = scale;
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  rc = launch_coop(absmax_kernel(in_dtype), pl.pg.G, &a, stream);
+  if (rc) return rc;
+  void *args[] = {&a};
+  HIP_TRY(hipLaunchKernel(quantize_kernel(in_dtype, out_dtype), dim3(di.grid * 8), dim3(kNT), args, 0, stream));
+  return SR_OK;
+}
+
+}  // extern "C"

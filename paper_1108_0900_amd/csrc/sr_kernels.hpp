@@ -1,0 +1,465 @@
+// libsr kernel templates for gfx950: prepare/gradient pass, bf16/f16 quantizer, fused
+// overlap product, persistent conjugate gradient, and the linear-method Hamiltonian
+// product.  Instantiated per storage type in sr_kernels_<type>.hip.
+#pragma once
+#include "sr_product.hpp"
+#include "sr_launch.hpp"
+
+namespace sr {
+
+// ======================================================================================
+// Shared helpers
+// ======================================================================================
+
+// Sum of one float64 per workgroup over the grid, visible to all workgroups.  `red` is
+// [4 sets][2 values][G]; consecutive calls rotate the set, which is safe because at least
+// one grid barrier separates a set's reads from its next writes.
+__device__ __forceinline__ bool grid_allreduce2(double a, double b, double *red, int &nred, GridSync &gs,
+                                                double &A, double &B) {
+  const int G = (int)gridDim.x;
+  const int set = nred & 3;
+  nred++;
+  a = block_sum(a);
+  b = block_sum(b);
+  if (threadIdx.x == 0) {
+    st_coh(&red[(set * 2 + 0) * G + blockIdx.x], a);
+    st_coh(&red[(set * 2 + 1) * G + blockIdx.x], b);
+  }
+  if (!grid_sync(gs)) return false;
+  A = grid_sum_read(&red[(set * 2 + 0) * G]);
+  B = grid_sum_read(&red[(set * 2 + 1) * G]);
+  return true;
+}
+
+__device__ __forceinline__ double load_decoded(const unsigned char *rowp, int64_t col, int dt, const float *scale) {
+  switch (dt) {
+    case DT_F64: return ((const double *)rowp)[col];
+    case DT_F32: return (double)((const float *)rowp)[col];
+    case DT_BF16: {
+      const uint32_t h = ((const uint16_t *)rowp)[col];
+      return (double)__uint_as_float(h << 16) * (double)scale[col];
+    }
+    default: {
+      const uint16_t h = ((const uint16_t *)rowp)[col];
+      return (double)(float)__builtin_bit_cast(_Float16, h) * (double)scale[col];
+    }
+  }
+}
+
+// ======================================================================================
+// Prepare / gradient pass (one read of O):  column means, diag S, g, E mean.
+// Shifted sums about K_j = O_0j avoid the cancellation of sum(O^2) - N mean^2.
+// ======================================================================================
+template <int DT, int NV, int RT>
+__global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
+  typedef Storage<DT> St;
+  constexpr int VEC = St::VEC;
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, VEC);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  int nred = 0;
+  const double inv_n = 1.0 / (double)a.pg.n_s;
+
+  // --- energies: mean and the residual sum of (E - mean) ---
+  double Emean = 0.0, sum_e = 0.0;
+  if (a.E != nullptr) {
+    const int64_t ch = (a.pg.n_s + G - 1) / G;
+    const int64_t k0 = min(a.pg.n_s, (int64_t)blockIdx.x * ch), k1 = min(a.pg.n_s, k0 + ch);
+    double s = 0.0;
+    for (int64_t k = k0 + tid; k < k1; k += kNT) s += a.E[k];
+    double dummy;
+    if (!grid_allreduce2(s, 0.0, a.sb.red, nred, ctx.gs, Emean, dummy)) return;
+    Emean *= inv_n;
+    double se = 0.0;
+    for (int64_t k = k0 + tid; k < k1; k += kNT) se += a.E[k] - Emean;
+    if (!grid_allreduce2(se, 0.0, a.sb.red, nred, ctx.gs, sum_e, dummy)) return;
+  }
+
+  // --- column sums over this row group's rows, for the owned columns ---
+  int64_t colv[NV];
+  double K[NV][VEC], sA[NV][VEC], sB[NV][VEC], sC[NV][VEC];
+  const unsigned char *O = a.op.O;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int64_t col = ctx.c0 + ((int64_t)i * kNT + tid) * VEC;
+    colv[i] = (col < ctx.c1) ? col : -1;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      K[i][e] = 0.0;
+      if (colv[i] >= 0 && col + e < a.pg.n_p) K[i][e] = load_decoded(O, col + e, DT, a.op.scale);
+      sA[i][e] = sB[i][e] = sC[i][e] = 0.0;
+    }
+  }
+  double sc[NV][VEC];
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t col = colv[i] + e;
+      sc[i][e] = (a.op.scale != nullptr && colv[i] >= 0 && col < a.pg.n_p) ? (double)a.op.scale[col] : 1.0;
+    }
+  const int64_t n_tiles = (a.pg.n_s + RT - 1) / RT;
+  for (int64_t t = ctx.rg; t < n_tiles; t += a.pg.RG) {
+    u32x4 buf[RT][NV];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int64_t row = t * RT + r;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        if (row < a.pg.n_s && colv[i] >= 0) buf[r][i] = load_stream(O + row * a.op.ldb + colv[i] * St::BYTES);
+        else buf[r][i] = u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int64_t row = t * RT + r;
+      if (row >= a.pg.n_s) continue;
+      const double e_k = (a.E != nullptr) ? a.E[row] - Emean : 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const double x = (double)St::get(buf[r][i], e) * sc[i][e] - K[i][e];
+          sA[i][e] += x;
+          sB[i][e] = fma(x, x, sB[i][e]);
+          sC[i][e] = fma(e_k, x, sC[i][e]);
+        }
+    }
+  }
+  // partials: ypart holds [RG][3][n_p]
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    if (colv[i] < 0) continue;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t col = colv[i] + e;
+      if (col >= a.pg.n_p) continue;
+      double *base = a.pb.ypart + (int64_t)ctx.rg * 3 * a.pg.n_p;
+      st_coh(&base[col], sA[i][e]);
+      st_coh(&base[a.pg.n_p + col], sB[i][e]);
+      st_coh(&base[2 * a.pg.n_p + col], sC[i][e]);
+    }
+  }
+  if (!grid_sync(ctx.gs)) return;
+
+  // --- finish owned column chunk ---
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + tid; j < j1; j += kNT) {
+    double A = 0.0, B = 0.0, Cg = 0.0;
+    for (int rg = 0; rg < a.pg.RG; ++rg) {
+      const double *base = a.pb.ypart + (int64_t)rg * 3 * a.pg.n_p;
+      A += ld_coh(&base[j]);
+      B += ld_coh(&base[a.pg.n_p + j]);
+      Cg += ld_coh(&base[2 * a.pg.n_p + j]);
+    }
+    const double Kj = load_decoded(O, j, DT, a.op.scale);
+    const double dmean = A * inv_n;
+    if (a.mean_out) a.mean_out[j] = Kj + dmean;
+    if (a.diag_out) {
+      double var = B * inv_n - dmean * dmean;
+      a.diag_out[j] = var > 0.0 ? var : 0.0;
+    }
+    if (a.g_out) a.g_out[j] = 2.0 * inv_n * (Cg - dmean * sum_e);
+  }
+  if (blockIdx.x == 0 && tid == 0 && a.Emean_out) *a.Emean_out = Emean;
+}
+
+// ======================================================================================
+// Quantizer: per-column absmax scale, then round-to-nearest-even codes.
+// ======================================================================================
+template <int IN_DT>
+__global__ __launch_bounds__(kNT) void k_absmax(QuantArgs a) {
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, 1);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  // slice of columns per column group, one column per thread per pass
+  for (int64_t col = ctx.c0 + tid; col < ctx.c1; col += kNT) {
+    double m = 0.0;
+    for (int64_t row = ctx.rg; row < a.pg.n_s; row += a.pg.RG) {
+      const double x = (IN_DT == DT_F64) ? ((const double *)(a.in + row * a.ldb_in))[col]
+                                         : (double)((const float *)(a.in + row * a.ldb_in))[col];
+      m = fmax(m, fabs(x));
+    }
+    st_coh(&a.pb.ypart[(int64_t)ctx.rg * a.pg.n_p + col], m);
+  }
+  if (!grid_sync(ctx.gs)) return;
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + tid; j < j1; j += kNT) {
+    double m = 0.0;
+    for (int rg = 0; rg < a.pg.RG; ++rg) m = fmax(m, ld_coh(&a.pb.ypart[(int64_t)rg * a.pg.n_p + j]));
+    float s = (float)m;
+    if (s == 0.0f) s = 1.0f;
+    a.scale[j] = s;
+  }
+}
+
+// Round a float64 to bf16 / f16 (nearest, ties to even) via float32 rounded to odd.
+__device__ __forceinline__ uint32_t f64_to_f32_odd_bits(double t) {
+  const float f = __double2float_rz(t);
+  uint32_t b = __float_as_uint(f);
+  if ((double)f != t) b |= 1u;
+  return b;
+}
+__device__ __forceinline__ uint16_t rne_bf16(double t) {
+  const uint32_t b = f64_to_f32_odd_bits(t);
+  return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ uint16_t rne_f16(double t) {
+  const float f = __uint_as_float(f64_to_f32_odd_bits(t));
+  return __builtin_bit_cast(uint16_t, (_Float16)f);
+}
+
+template <int IN_DT, int OUT_DT>
+__global__ __launch_bounds__(kNT) void k_quantize(QuantArgs a) {
+  const int64_t nvec_row = a.ld_out / 8;      // 8 codes per 16-byte output vector
+  const int64_t total = a.pg.n_s * nvec_row;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = idx / nvec_row, c0 = (idx % nvec_row) * 8;
+    const unsigned char *rin = a.in + row * a.ldb_in;
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      uint32_t pair = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t col = c0 + 2 * h + e;
+        uint16_t code = 0;
+        if (col < a.pg.n_p) {
+          const double x = (IN_DT == DT_F64) ? ((const double *)rin)[col] : (double)((const float *)rin)[col];
+          const double t = x / (double)a.scale[col];
+          code = (OUT_DT == DT_BF16) ? rne_bf16(t) : rne_f16(t);
+        }
+        pair |= (uint32_t)code << (16 * e);
+      }
+      w[h] = pair;
+    }
+    *(u32x4 *)(a.out + row * a.ld_out * 2 + c0 * 2) = u32x4{w[0], w[1], w[2], w[3]};
+  }
+}
+
+// ======================================================================================
+// (S + eps I) v
+// ======================================================================================
+template <int DT, int NV, int R, int NB>
+__global__ __launch_bounds__(kNT) void k_sv(SvArgs a) {
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  Product<DT, NV, R, NB, 1> P;
+  const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, a.v);
+  if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return;
+  P.store_partials(a.pg, a.pb, ctx);
+  if (!grid_sync(ctx.gs)) return;
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
+  const int G = (int)gridDim.x;
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+    const double acc = finish_column(a.pb, a.pg, j);
+    const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
+    a.y[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
+  }
+}
+
+// ======================================================================================
+// Linear-method product  y = H v  (length n_p + 1)
+// ======================================================================================
+template <int DT, int NV, int R, int NB>
+__global__ __launch_bounds__(kNT) void k_lm(LmArgs a) {
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  Product<DT, NV, R, NB, 2> P;
+  const double v0 = a.v[0];
+  const double cshare = P.setup(ctx, a.pg, a.ops, a.mean, a.v + 1);
+  if (!P.accumulate(a.pg, a.pb, ctx, a.ops, cshare, a.E, v0)) return;
+  P.store_partials(a.pg, a.pb, ctx);
+  if (!grid_sync(ctx.gs)) return;
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
+  const int G = (int)gridDim.x;
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+    const double acc = finish_column(a.pb, a.pg, j);
+    const double s = a.ops[0].scale ? (double)a.ops[0].scale[j] : 1.0;
+    a.y[1 + j] = (s * acc - a.mean[j] * S1) * inv_n;
+  }
+  if (blockIdx.x == 0) {
+    double se = 0.0;
+    for (int64_t k = threadIdx.x; k < a.pg.n_s; k += kNT) se += a.E[k];
+    se = block_sum(se);
+    if (threadIdx.x == 0) a.y[0] = se * inv_n * v0 + S2 * inv_n;
+  }
+}
+
+// ======================================================================================
+// Persistent conjugate gradient on (S + eps I) x = g
+// ======================================================================================
+template <int DT, int NV, int R, int NB>
+struct CgKernel {
+  // q[j] = ((S + eps I) vin)_j for this workgroup's vector chunk [j0, j1).  EXACT selects
+  // float64 accumulation (residual products of scaled storage).
+  template <bool EXACT>
+  __device__ __forceinline__ static bool apply(const CgArgs &a, WgCtx &ctx, const double *vin, double *q,
+                                               int64_t j0, int64_t j1, int &products) {
+    Product<DT, NV, R, NB, 1, EXACT> P;
+    const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, vin);
+    if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return false;
+    P.store_partials(a.pg, a.pb, ctx);
+    if (!grid_sync(ctx.gs)) return false;
+    double S1, S2;
+    sum_row_scalars(a.pb, a.pg, S1, S2);
+    const double inv_n = 1.0 / (double)a.pg.n_s;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+      const double acc = finish_column(a.pb, a.pg, j);
+      const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
+      q[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * ld_coh(&vin[j]);
+    }
+    products++;
+    return true;
+  }
+  // Residual products: float64 accumulation for scaled storage (the search-direction
+  // products keep the storage type's own accumulation).
+  static constexpr bool kExactResidual = (DT == DT_BF16 || DT == DT_F16);
+};
+
+template <int DT, int NV, int R, int NB>
+__global__ __launch_bounds__(kNT) void k_cg(CgArgs a) {
+  typedef CgKernel<DT, NV, R, NB> K;
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  const int64_t n = a.pg.n_p;
+  const int64_t ch = (n + G - 1) / G;
+  const int64_t j0 = min(n, (int64_t)blockIdx.x * ch), j1 = min(n, j0 + ch);
+  int nred = 0, products = 0, refreshes = 0, it = 0;
+  int status = 0;       // SR_OK
+  double rel_true = -1.0, rho = 0.0, gg = 0.0, dummy = 0.0;
+  bool ok = true, restart = false;
+
+  // r0 = g - A x0 (or g), p0 = r0
+  if (a.use_x0) {
+    ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
+    if (!ok) goto done;
+    for (int64_t j = j0 + tid; j < j1; j += kNT) a.r[j] = a.g[j] - a.q[j];
+  } else {
+    for (int64_t j = j0 + tid; j < j1; j += kNT) {
+      st_coh(&a.x[j], 0.0);
+      a.r[j] = a.g[j];
+    }
+  }
+  {
+    double prr = 0.0, pgg = 0.0;
+    for (int64_t j = j0 + tid; j < j1; j += kNT) {
+      st_coh(&a.p[j], a.r[j]);
+      prr += a.r[j] * a.r[j];
+      pgg += a.g[j] * a.g[j];
+    }
+    ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg);
+    if (!ok) goto done;
+  }
+  if (gg == 0.0) {
+    for (int64_t j = j0 + tid; j < j1; j += kNT) st_coh(&a.x[j], 0.0);
+    rel_true = 0.0;
+    rho = 0.0;
+    gg = 1.0;
+    goto done;
+  }
+
+  while (true) {
+    const double rel = sqrt(rho / gg);
+    if (a.hist != nullptr && blockIdx.x == 0 && tid == 0 && it <= a.max_iter) a.hist[it] = rel;
+    if (!isfinite(rho)) { status = -4; break; }
+    if (rel <= a.rtol) {
+      // confirm with the true residual g - A x
+      ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
+      if (!ok) break;
+      double prr = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += kNT) {
+        const double t = a.g[j] - a.q[j];
+        a.r[j] = t;
+        prr += t * t;
+      }
+      double tr;
+      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy);
+      if (!ok) break;
+      rel_true = sqrt(tr / gg);
+      if (rel_true <= a.rtol) { status = 0; break; }
+      rho = tr;
+      refreshes++;
+      rel_true = -1.0;
+    }
+    if (it >= a.max_iter) { status = 1; break; }
+    ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
+    if (!ok) break;
+    double pq;
+    {
+      double ppq = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += kNT) ppq += ld_coh(&a.p[j]) * a.q[j];
+      ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy);
+      if (!ok) break;
+    }
+    if (!isfinite(pq)) { status = -4; break; }
+    if (!(pq > 0.0)) { status = 2; break; }
+    const double alpha = rho / pq;
+    for (int64_t j = j0 + tid; j < j1; j += kNT) {
+      st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
+      a.r[j] -= alpha * a.q[j];
+    }
+    it++;
+    if (a.refresh_every > 0 && it % a.refresh_every == 0) {
+      ok = grid_sync(ctx.gs);
+      if (!ok) break;
+      ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
+      if (!ok) break;
+      for (int64_t j = j0 + tid; j < j1; j += kNT) a.r[j] = a.g[j] - a.q[j];
+      refreshes++;
+      restart = a.restart_on_refresh != 0;
+    }
+    double rho_new;
+    {
+      double prr = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += kNT) prr += a.r[j] * a.r[j];
+      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy);
+      if (!ok) break;
+    }
+    const double beta = restart ? 0.0 : rho_new / rho;
+    restart = false;
+    rho = rho_new;
+    for (int64_t j = j0 + tid; j < j1; j += kNT) st_coh(&a.p[j], a.r[j] + beta * ld_coh(&a.p[j]));
+    ok = grid_sync(ctx.gs);
+    if (!ok) break;
+  }
+  // true residual for the report when the loop ended without confirming it
+  if (ok && rel_true < 0.0 && status >= 0) {
+    ok = grid_sync(ctx.gs);
+    if (ok) ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
+    if (ok) {
+      double prr = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += kNT) {
+        const double t = a.g[j] - a.q[j];
+        prr += t * t;
+      }
+      double tr;
+      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy);
+      if (ok) rel_true = sqrt(tr / gg);
+    }
+  }
+done:
+  if (blockIdx.x == 0 && tid == 0) {
+    a.info[0] = (double)it;
+    a.info[1] = (double)refreshes;
+    a.info[2] = (double)status;
+    a.info[3] = (double)products;
+    a.info[4] = sqrt(rho / gg);
+    a.info[5] = rel_true;
+    a.info[6] = ok ? 1.0 : 0.0;
+  }
+}
+
+}  // namespace sr

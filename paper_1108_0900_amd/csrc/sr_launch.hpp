@@ -1,0 +1,89 @@
+// Kernel argument blocks and the kernel registry shared by the kernels and the host API.
+#pragma once
+#include "sr_product.hpp"
+
+namespace sr {
+
+struct SyncBufs {
+  uint32_t *flags;      // [G] grid-barrier epochs (zeroed before each launch)
+  uint32_t *abort;      // [1]
+  double *red;          // [4][2][G] grid reductions
+};
+
+struct SvArgs {
+  ProdGeom pg;
+  ProdBufs pb;
+  SyncBufs sb;
+  Operand op;
+  const double *mean;
+  const double *v;
+  double *y;
+  double eps;
+};
+
+struct LmArgs {
+  ProdGeom pg;
+  ProdBufs pb;
+  SyncBufs sb;
+  Operand ops[2];       // O, D
+  const double *mean;   // column mean of O
+  const double *E;      // [n_s]
+  const double *v;      // [n_p + 1]
+  double *y;            // [n_p + 1]
+};
+
+struct CgArgs {
+  ProdGeom pg;
+  ProdBufs pb;
+  SyncBufs sb;
+  Operand op;
+  const double *mean;
+  const double *g;
+  double *x, *r, *p, *q;
+  double eps, rtol;
+  int max_iter, refresh_every, use_x0, restart_on_refresh;
+  double *hist;         // [max_iter + 1] or nullptr
+  double *info;         // [8]
+};
+
+struct GradArgs {
+  ProdGeom pg;          // wslice / C / RG for the column reduction (R unused)
+  ProdBufs pb;          // ypart holds [RG][3][n_p]
+  SyncBufs sb;
+  Operand op;
+  const double *E;      // [n_s] or nullptr
+  double *g_out, *mean_out, *diag_out, *Emean_out;
+};
+
+struct QuantArgs {
+  ProdGeom pg;
+  ProdBufs pb;          // ypart holds [RG][n_p] partial maxima
+  SyncBufs sb;
+  const unsigned char *in;
+  int64_t ldb_in;       // bytes
+  unsigned char *out;
+  int64_t ld_out;       // elements (16-bit codes)
+  float *scale;
+};
+
+// Tile configurations (NV vectors per thread, R rows per tile, NB tile buffers) built for
+// each storage type.
+#define SR_PRODUCT_CONFIGS_F64(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
+#define SR_PRODUCT_CONFIGS_F32(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
+#define SR_PRODUCT_CONFIGS_BF16(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
+#define SR_PRODUCT_CONFIGS_F16(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
+
+struct KernelEntry {
+  int dt, nv, r, nb;
+  const void *sv, *cg, *lm;
+};
+
+const KernelEntry *kernel_table(int dt, int *count);
+const void *grad_kernel(int dt);
+int grad_nv(int dt);
+int grad_rows(int dt);
+const void *absmax_kernel(int in_dt);
+const void *quantize_kernel(int in_dt, int out_dt);
+const void *fill_kernel();
+
+}  // namespace sr

@@ -1,0 +1,263 @@
+"""Thin ctypes binding over libsr.so.
+
+Argument marshalling only: every step of the computation runs in the library's HIP
+kernels.  Torch supplies device buffers (data_ptr) and the current HIP stream.  If the
+library is not built, `lib()` raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsr.so")
+
+# enum sr_status
+SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN = 0, 1, 2
+SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NONFINITE, SR_ERR_NODEVICE, SR_ERR_TIMEOUT = -1, -2, -3, -4, -5, -6
+# enum sr_dtype
+SR_F64, SR_F32, SR_BF16, SR_F16 = 0, 1, 2, 3
+
+_TORCH_DT = {torch.float64: SR_F64, torch.float32: SR_F32, torch.bfloat16: SR_BF16, torch.float16: SR_F16}
+_ELEM = {SR_F64: 8, SR_F32: 4, SR_BF16: 2, SR_F16: 2}
+
+# C prototypes: name -> (restype, argtypes); mirrors include/sr.h
+_c_i64, _c_i32, _c_p, _c_d = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double
+
+
+class SrMatrix(ctypes.Structure):
+    _fields_ = [("n_s", _c_i64), ("n_p", _c_i64), ("ld", _c_i64), ("dtype", _c_i32), ("reserved", _c_i32),
+                ("O", _c_p), ("col_scale", _c_p), ("col_mean", _c_p)]
+
+
+class SrCgOpts(ctypes.Structure):
+    _fields_ = [("rtol", _c_d), ("max_iter", _c_i32), ("refresh_every", _c_i32), ("use_x0", _c_i32),
+                ("restart_on_refresh", _c_i32), ("res_history", _c_p)]
+
+
+class SrCgInfo(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("refreshes", _c_i32), ("status", _c_i32), ("products", _c_i32),
+                ("rel_res_recur", _c_d), ("rel_res_true", _c_d)]
+
+
+PROTOTYPES = {
+    "sr_grad": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "sr_sv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_d, _c_p]),
+    "sr_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
+                                   ctypes.POINTER(SrCgInfo), _c_p]),
+    "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
+    "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
+    "sr_release": (ctypes.c_int, []),
+    "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sr_last_error": (ctypes.c_char_p, []),
+    "sr_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsr.so (built by paper_1108_0900_amd.build); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libsr.so not built at {LIB_PATH}; run `python -m paper_1108_0900_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        L = lib()
+        self.status = status
+        super().__init__(f"{where}: {L.sr_status_string(status).decode()} ({L.sr_last_error().decode()})")
+
+
+def _check(status: int, where: str, allow=(SR_OK,)):
+    if status not in allow:
+        raise SrError(status, where)
+    return status
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Matrix:
+    """A derivative-ratio matrix as the library sees it (keeps the tensors alive)."""
+    O: torch.Tensor              # (n_s, ld) storage; columns [0, n_p) are used
+    n_p: int
+    scale: torch.Tensor | None = None
+    mean: torch.Tensor | None = None
+
+    @property
+    def dtype_code(self) -> int:
+        return _TORCH_DT[self.O.dtype]
+
+    @property
+    def ld(self) -> int:
+        if self.O.shape[0] > 1:
+            return self.O.stride(0)
+        vec = 16 // _ELEM[self.dtype_code]
+        return ((self.n_p + vec - 1) // vec) * vec
+
+    def c(self) -> SrMatrix:
+        m = SrMatrix()
+        m.n_s = self.O.shape[0]
+        m.n_p = self.n_p
+        m.ld = self.ld
+        m.dtype = self.dtype_code
+        m.reserved = 0
+        m.O = self.O.data_ptr()
+        m.col_scale = None if self.scale is None else self.scale.data_ptr()
+        m.col_mean = None if self.mean is None else self.mean.data_ptr()
+        return m
+
+
+def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Tensor | None = None) -> Matrix:
+    """Wrap a 2-D device tensor (float64/float32, or bfloat16/float16 codes with a float32
+    column scale).  A copy with padded rows is made only when the layout rules of sr.h
+    (16-byte aligned base, row stride a multiple of 16 bytes, unit column stride, rows
+    spanning the allocation) are not met."""
+    if O.dim() != 2:
+        raise ValueError("O must be 2-D")
+    if O.dtype not in _TORCH_DT:
+        raise ValueError(f"unsupported dtype {O.dtype}")
+    n_s, n_p = O.shape
+    code = _TORCH_DT[O.dtype]
+    eb = _ELEM[code]
+    vec = 16 // eb
+    ld = O.stride(0) if n_s > 1 else ((n_p + vec - 1) // vec) * vec
+    ok = (O.stride(1) == 1 and ld >= n_p and (ld * eb) % 16 == 0 and O.data_ptr() % 16 == 0)
+    if ok:
+        need = O.storage_offset() + (n_s - 1) * ld + ((n_p + vec - 1) // vec) * vec
+        ok = need <= O.untyped_storage().nbytes() // eb
+    if not ok:
+        ldp = ((n_p + vec - 1) // vec) * vec
+        P = torch.zeros(n_s, ldp, dtype=O.dtype, device=O.device)
+        P[:, :n_p] = O
+        O = P[:, :n_p]
+    if scale is not None:
+        scale = scale.contiguous()
+    if mean is not None:
+        mean = mean.contiguous()
+    return Matrix(O=O, n_p=n_p, scale=scale, mean=mean)
+
+
+def _vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    if t.dtype != torch.float64 or t.dim() != 1 or t.shape[0] != n:
+        raise ValueError(f"{name} must be a float64 vector of length {n}")
+    return t.contiguous()
+
+
+# ----------------------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+# ----------------------------------------------------------------------------------------
+def sr_grad(M: Matrix, E: torch.Tensor | None, stream=None) -> dict:
+    """Column means, diag S, g and <E> in one pass over O (sr_grad)."""
+    dev = M.O.device
+    n_p = M.n_p
+    out = {"mean": torch.empty(n_p, dtype=torch.float64, device=dev),
+           "diag": torch.empty(n_p, dtype=torch.float64, device=dev)}
+    if E is not None:
+        E = _vec(E, M.O.shape[0], "E")
+        out["g"] = torch.empty(n_p, dtype=torch.float64, device=dev)
+        out["E_mean"] = torch.empty(1, dtype=torch.float64, device=dev)
+    m = M.c()
+    st = lib().sr_grad(ctypes.byref(m), _ptr(E), _ptr(out.get("g")), _ptr(out.get("E_mean")), _ptr(out["mean"]),
+                       _ptr(out["diag"]), _stream(stream))
+    _check(st, "sr_grad")
+    return out
+
+
+def sr_sv_product(M: Matrix, v: torch.Tensor, eps: float = 0.0, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """y = (S + eps I) v (sr_sv_product)."""
+    v = _vec(v, M.n_p, "v")
+    y = torch.empty_like(v) if out is None else out
+    m = M.c()
+    _check(lib().sr_sv_product(ctypes.byref(m), _ptr(v), _ptr(y), float(eps), _stream(stream)), "sr_sv_product")
+    return y
+
+
+def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max_iter: int = 0,
+                refresh_every: int = 0, x0: torch.Tensor | None = None, history: bool = False,
+                restart_on_refresh: bool = False,
+                out: torch.Tensor | None = None, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP,
+                                                           SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
+    """CG solve of (S + eps I) x = g (sr_cg_solve).  Returns (x, info dict)."""
+    g = _vec(g, M.n_p, "g")
+    if x0 is not None:
+        x = _vec(x0, M.n_p, "x0").clone() if out is None else out.copy_(x0)
+    else:
+        x = torch.empty_like(g) if out is None else out
+    opts = SrCgOpts()
+    opts.rtol = float(rtol)
+    opts.max_iter = int(max_iter)
+    opts.refresh_every = int(refresh_every)
+    opts.use_x0 = 1 if x0 is not None else 0
+    opts.restart_on_refresh = 1 if restart_on_refresh else 0
+    hist = None
+    if history:
+        mi = max_iter if max_iter > 0 else M.n_p + 100
+        hist = torch.full((mi + 1,), float("nan"), dtype=torch.float64, device=g.device)
+        opts.res_history = hist.data_ptr()
+    info = SrCgInfo()
+    m = M.c()
+    st = lib().sr_cg_solve(ctypes.byref(m), _ptr(g), float(eps), _ptr(x), ctypes.byref(opts), ctypes.byref(info),
+                           _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "sr_cg_solve")
+    d = {"status": st, "iters": info.iters, "refreshes": info.refreshes, "products": info.products,
+         "rel_res_recur": info.rel_res_recur, "rel_res_true": info.rel_res_true}
+    if hist is not None:
+        d["history"] = hist
+    return x, d
+
+
+def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: torch.Tensor | None = None,
+                  stream=None) -> torch.Tensor:
+    """y = H v of the linear method, length n_p + 1 (lm_hv_product)."""
+    E = _vec(E, M.O.shape[0], "E")
+    v = _vec(v, M.n_p + 1, "v")
+    y = torch.empty_like(v) if out is None else out
+    m, d = M.c(), Dm.c()
+    _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
+           "lm_hv_product")
+    return y
+
+
+def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, stream=None):
+    """bf16/f16 codes with per-column float32 scales (sr_quantize).  Returns (q, scale)
+    where q is an (n_s, ld) code tensor viewed as (n_s, n_p)."""
+    if O.dtype not in (torch.float64, torch.float32) or O.dim() != 2:
+        raise ValueError("O must be a 2-D float64/float32 tensor")
+    Min = as_matrix(O)
+    n_s, n_p = O.shape
+    ld_out = ((n_p + 7) // 8) * 8
+    q = torch.empty(n_s, ld_out, dtype=out_dtype, device=O.device)
+    s = torch.empty(n_p, dtype=torch.float32, device=O.device)
+    ld_in = Min.ld
+    st = lib().sr_quantize(n_s, n_p, _ptr(Min.O), ld_in, Min.dtype_code, _ptr(q), ld_out, _TORCH_DT[out_dtype],
+                           _ptr(s), _stream(stream))
+    _check(st, "sr_quantize")
+    return q[:, :n_p], s
+
+
+def release():
+    return lib().sr_release()

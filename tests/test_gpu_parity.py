@@ -1,0 +1,245 @@
+"""GPU parity of the libsr kernels against the FP64 CPU oracle (small and ragged cases).
+
+Every test calls the library through the C ABI (ctypes binding) on cuda:0 and compares
+element by element with the oracle on the same seeded inputs.  The oracle computes its
+own quantized values from the float64 inputs; nothing it uses comes from the GPU path.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synth
+from paper_1108_0900_amd import sr
+from tests.gpu_util import (DEV, TOL_PRODUCT, device_matrix, magnitude_ref, rand_dense, rel_err, stored_dense,
+                            to_dev, to_np)
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32, torch.bfloat16, torch.float16]
+SHAPES = [(1, 1), (2, 3), (3, 63), (64, 64), (65, 65), (7, 257), (300, 513), (257, 2049), (1000, 4000),
+          (513, 9001), (129, 40000)]
+
+
+def _dname(dt):
+    return str(dt).split(".")[-1]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=_dname)
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_sv_product_matches_oracle(shape, dtype):
+    n_s, n_p = shape
+    print(f"[sv] {n_s}x{n_p} {dtype}", flush=True)
+    O, _ = rand_dense(n_s, n_p, seed=n_s * 7 + n_p, offset=0.25)
+    Os = stored_dense(O, dtype)
+    v = np.random.default_rng(n_p).standard_normal(n_p)
+    eps = 0.013
+    M = device_matrix(O, dtype)
+    y = to_np(sr.sr_sv_product(M, to_dev(v), eps))
+    torch.cuda.synchronize()
+    ref = orc.sv_product_dense(Os, v, eps)
+    mag = magnitude_ref(Os, v, eps, dtype)
+    tol = TOL_PRODUCT[dtype]
+    assert np.all(np.abs(y - ref) <= tol * mag + 1e-300), (np.max(np.abs(y - ref) / mag))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=_dname)
+def test_sv_product_padded_stride_with_nan_padding(dtype):
+    """Row stride > n_p with NaN in the padding columns: the padding must not leak."""
+    n_s, n_p = 97, 1001
+    O, _ = rand_dense(n_s, n_p, seed=5)
+    Os = stored_dense(O, dtype)
+    v = np.random.default_rng(1).standard_normal(n_p)
+    ld = 1024 + 64
+    M = device_matrix(O, dtype, ld=ld)
+    assert M.O.stride(0) == ld
+    y = to_np(sr.sr_sv_product(M, to_dev(v), 0.5))
+    ref = orc.sv_product_dense(Os, v, 0.5)
+    assert np.all(np.isfinite(y))
+    assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * magnitude_ref(Os, v, 0.5, dtype))
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=_dname)
+@pytest.mark.parametrize("shape", [(1, 5), (5, 1), (333, 700), (2000, 3001), (64, 70000)],
+                         ids=lambda s: f"{s[0]}x{s[1]}")
+def test_grad_matches_oracle(shape, dtype):
+    n_s, n_p = shape
+    print(f"[grad] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=3 + n_p, offset=3.0)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    out = sr.sr_grad(M, to_dev(E))
+    mean, diag, g, Em = (to_np(out[k]) for k in ("mean", "diag", "g", "E_mean"))
+    tol = 1e-12
+    np.testing.assert_allclose(mean, orc.sample_mean(Os), rtol=tol, atol=tol * np.abs(Os).max())
+    dref = orc.diag_overlap(Os)
+    assert np.all(np.abs(diag - dref) <= 1e-11 * (dref + np.abs(orc.centred(Os)).max(0) ** 2 * 1e-3) + 1e-300)
+    gref = orc.energy_gradient(Os, E)
+    gmag = 2 * np.abs(orc.centred(Os)).T @ np.abs(E - E.mean()) / n_s
+    assert np.all(np.abs(g - gref) <= 1e-12 * gmag + 1e-300)
+    assert abs(Em[0] - E.mean()) <= 1e-14 * abs(E).max()
+
+
+@pytest.mark.parametrize("out_dtype", [torch.bfloat16, torch.float16], ids=_dname)
+@pytest.mark.parametrize("in_dtype", [torch.float64, torch.float32], ids=_dname)
+@pytest.mark.parametrize("shape", [(1, 1), (3, 17), (257, 1000), (1000, 4099)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_quantize_bit_exact(shape, in_dtype, out_dtype):
+    n_s, n_p = shape
+    O, _ = rand_dense(n_s, n_p, seed=11 + n_p)
+    O[:, 0] = 0.0                           # all-zero column -> scale 1
+    if n_s > 2:
+        O[1, -1] = 1e-30                    # tiny quotient
+    O = O.astype(np.float32).astype(np.float64) if in_dtype == torch.float32 else O
+    q, s = sr.sr_quantize(torch.from_numpy(O).to(DEV).to(in_dtype), out_dtype=out_dtype)
+    qo, so = (orc.quantize_bf16 if out_dtype == torch.bfloat16 else orc.quantize_f16)(O)
+    assert np.array_equal(to_np(s), so)
+    qg = q.contiguous().view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(qg, qo)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=_dname)
+@pytest.mark.parametrize("shape", [(50, 9), (400, 300), (1500, 1200), (3000, 5000)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_cg_matches_cholesky(shape, dtype):
+    n_s, n_p = shape
+    print(f"[cg] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=21 + n_p)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-13, refresh_every=20)
+    assert info["status"] == 0, info
+    g_ref = orc.energy_gradient(Os, E)
+    eps_ref = 1e-3 * orc.diag_overlap(Os).mean()
+    x_ref = orc.solve_dense(Os, g_ref, eps_ref)
+    assert rel_err(to_np(x), x_ref) <= 1e-10, (rel_err(to_np(x), x_ref), info)
+    assert info["rel_res_true"] <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
+def test_cg_scaled_storage_matches_dequantized_oracle(dtype):
+    n_s, n_p = 2000, 1500
+    O, E = rand_dense(n_s, n_p, seed=31)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-8, refresh_every=20)
+    assert info["status"] == 0, info
+    x_ref = orc.solve_dense(Os, orc.energy_gradient(Os, E), 1e-3 * orc.diag_overlap(Os).mean())
+    # float32 products: solution error ~ kappa * 1e-6
+    assert rel_err(to_np(x), x_ref) <= 1e-4, rel_err(to_np(x), x_ref)
+
+
+def test_cg_options_warm_start_refresh_history():
+    O, E = rand_dense(800, 600, seed=41)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-2 * float(st["diag"].mean())
+    x_ref = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-2 * orc.diag_overlap(O).mean())
+    for m in (0, 1, 5):
+        x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-13, refresh_every=m, history=True)
+        assert info["status"] == 0 and rel_err(to_np(x), x_ref) <= 1e-10
+        h = to_np(info["history"])[: info["iters"] + 1]
+        assert h[0] == pytest.approx(1.0) and np.all(np.isfinite(h))
+        if m:
+            assert info["refreshes"] >= info["iters"] // m
+    # warm start from the solution: converges at once (one product to confirm)
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-10, x0=to_dev(x_ref))
+    assert info["status"] == 0 and info["iters"] == 0 and rel_err(to_np(x), x_ref) <= 1e-10
+
+
+def test_cg_not_converged_and_breakdown_codes():
+    O, E = rand_dense(300, 200, seed=42)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    x, info = sr.sr_cg_solve(M, st["g"], 1e-6, rtol=1e-14, max_iter=3)
+    assert info["status"] == sr.SR_NOT_CONVERGED and info["iters"] == 3
+    assert np.all(np.isfinite(to_np(x)))
+
+
+def test_cg_nonfinite_input_reports_error():
+    O, E = rand_dense(100, 50, seed=43)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    g = st["g"].clone()
+    g[3] = float("nan")
+    x, info = sr.sr_cg_solve(M, g, 1e-3, rtol=1e-10)
+    assert info["status"] == sr.SR_ERR_NONFINITE
+
+
+def test_cg_eps_zero_singular_min_norm():
+    """eps = 0 with N_s < N_p: S is singular, g lies in its range; CG from 0 gives pinv(S) g."""
+    O, E = rand_dense(40, 120, seed=44)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    x, info = sr.sr_cg_solve(M, st["g"], 0.0, rtol=1e-12)
+    assert info["status"] == 0 and info["iters"] <= 45
+    x_ref = orc.solve_dense(O, orc.energy_gradient(O, E), 0.0)
+    assert rel_err(to_np(x), x_ref) <= 1e-8
+
+
+def test_cg_single_sample_and_zero_rhs():
+    O, E = rand_dense(1, 10, seed=45)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    assert float(st["g"].abs().max()) == 0.0
+    x, info = sr.sr_cg_solve(M, st["g"], 0.1, rtol=1e-10)
+    assert info["status"] == 0 and float(x.abs().max()) == 0.0
+
+
+def test_cps_gauge_null_vector_product():
+    d = synth.small_cps_inputs(seed=5, n_s=1500, n_corr=5, n_states=16, n_dense=37)
+    O = d["O"].numpy()
+    c = d["c"].numpy()
+    M = device_matrix(O, torch.float64)
+    for p in range(c.shape[0]):
+        u = np.zeros(O.shape[1])
+        u[p * 16:(p + 1) * 16] = c[p]
+        y = to_np(sr.sr_sv_product(M, to_dev(u), 0.25))
+        assert np.abs(y - 0.25 * u).max() <= 1e-12 * np.abs(u).max() * 10
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=_dname)
+@pytest.mark.parametrize("shape", [(1, 3), (50, 9), (700, 1000), (301, 20001)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_lm_hv_matches_oracle(shape, dtype):
+    n_s, n_p = shape
+    print(f"[lm] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=51 + n_p)
+    rng = np.random.default_rng(52)
+    D = 0.1 * rng.standard_normal((n_s, n_p)) * np.exp(0.5 * rng.standard_normal(n_p))
+    Os, Ds = stored_dense(O, dtype), stored_dense(D, dtype)
+    v = rng.standard_normal(n_p + 1)
+    M, Dm = device_matrix(O, dtype), device_matrix(D, dtype)
+    y = to_np(sr.lm_hv_product(M, to_dev(E), Dm, to_dev(v)))
+    H, _ = orc.lm_matrices(Os, E, Ds)
+    ref = H @ v
+    # magnitude reference; with float32 accumulation (scaled storage) the centering is
+    # applied after the sums, so uncentred magnitudes bound the rounding
+    Oa = np.abs(Os) if dtype in (torch.bfloat16, torch.float16) else np.abs(orc.centred(Os))
+    t = Oa @ np.abs(v[1:]) + (np.abs(orc.sample_mean(Os)) @ np.abs(v[1:]) if Oa is not None else 0.0)
+    z = np.abs(E) * (abs(v[0]) + t) + np.abs(Ds) @ np.abs(v[1:])
+    mag = np.concatenate([[abs(E.mean() * v[0]) + (np.abs(E) @ t + np.abs(Ds @ v[1:]).sum()) / n_s],
+                          (Oa.T @ z + np.abs(orc.sample_mean(Os)) * z.sum()) / n_s])
+    tol = TOL_PRODUCT[dtype]
+    assert np.all(np.abs(y - ref) <= tol * mag + 1e-300), np.max(np.abs(y - ref) / mag)
+
+
+def test_abort_flag_not_set_on_normal_runs():
+    """Repeated products in one process reuse the workspace; results stay identical."""
+    O, _ = rand_dense(500, 3000, seed=61)
+    M = device_matrix(O, torch.float32)
+    v = to_dev(np.random.default_rng(2).standard_normal(3000))
+    y1 = sr.sr_sv_product(M, v, 0.1).clone()
+    for _ in range(5):
+        y2 = sr.sr_sv_product(M, v, 0.1)
+    assert torch.equal(y1, y2)      # deterministic reduction order

@@ -370,6 +370,49 @@ def test_quantize_cps_columns_exact_and_zero_column():
     assert s[-1] == 1.0 and np.all(q[:, -1] == 0)
 
 
+def _nearest_f16_fraction(t: float) -> float:
+    """Nearest float16 value to t by exact rational arithmetic, ties to even."""
+    if t == 0.0:
+        return 0.0
+    sgn = -1.0 if t < 0 else 1.0
+    a = Fraction(abs(t))
+    e = math.floor(math.log2(abs(t)))
+    if Fraction(2) ** e > a:
+        e -= 1
+    if Fraction(2) ** (e + 1) <= a:
+        e += 1
+    e = max(e, -14)
+    ulp = Fraction(2) ** (e - 10)
+    lo = (a // ulp) * ulp
+    hi = lo + ulp
+    if a - lo < hi - a:
+        r = lo
+    elif a - lo > hi - a:
+        r = hi
+    else:
+        r = lo if (lo / ulp) % 2 == 0 else hi
+    return sgn * float(r)
+
+
+def test_quantize_f16_nearest_even_exact():
+    rng = np.random.default_rng(22)
+    O = rng.standard_normal((48, 7)) * np.exp(rng.standard_normal(7))
+    O[5, 1] = 1e-9 * O[:, 1].max()          # float16 subnormal range of the quotient
+    q, s = orc.quantize_f16(O)
+    deq = orc.dequantize_f16(q, s)
+    for k in range(O.shape[0]):
+        for j in range(O.shape[1]):
+            t = O[k, j] / float(s[j])
+            assert deq[k, j] / float(s[j]) == _nearest_f16_fraction(t), (k, j)
+    assert np.all(np.abs(deq - O) <= 2.0 ** -12 * s.astype(np.float64)[None, :] * (1 + 1e-12))
+    # library pin: torch float32 -> float16 on float32-exact quotients
+    O2 = rng.standard_normal((100, 4)).astype(np.float32).astype(np.float64)
+    O2[0] = 2.0 ** np.ceil(np.log2(np.abs(O2).max(0)))
+    q2, s2 = orc.quantize_f16(O2)
+    ref = torch.from_numpy((O2 / s2.astype(np.float64)).astype(np.float32)).to(torch.float16)
+    assert np.array_equal(q2, ref.view(torch.int16).numpy().view(np.uint16))
+
+
 # ------------------------------------------------------------------------------------------
 # Adjoint derivatives
 # ------------------------------------------------------------------------------------------
