@@ -1,0 +1,256 @@
+"""Benchmark of the matrix-free SR hot path on one MI355X.
+
+A step is one pass of the hot path over one synthetic batch: the prepare/gradient pass
+(column means, diag S, g and <E> in one read of O) followed by the persistent CG solve of
+(S + eps I) x = g, whose products read O once each.  The default workload is the
+CPS-shaped 32768 x 500000 matrix stored as bf16 codes with float32 column scales; the
+float64 solve of the same matrix is timed beside it for the bf16-vs-f64 comparison.
+
+Prints ONE JSON line on stdout (progress goes to stderr).
+  value       algorithmic GB/s of the step: (one O read for the prepare pass + one O read
+              per product) / step time, inputs resident in HBM
+  roofline    the CG kernel (the step's dominant kernel): algorithmic bytes per launch /
+              its duration measured with HIP events on its stream, against 8 TB/s
+  cpu_baseline  the CPU oracle's matrix-free product on a bounded row sample, same unit
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "SR CG solve time & S·v GB/s (frac of HBM peak), N_p=5e5 N_s=32k, BF16 vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def elem_bytes(dt):
+    import torch
+    return {torch.float64: 8, torch.float32: 4, torch.bfloat16: 2, torch.float16: 2}[dt]
+
+
+def product_bytes(n_s, n_p, dt, scaled):
+    """Algorithmic bytes of one product: one read of O plus the O(N_p) vectors (scale,
+    column mean, v, y)."""
+    return n_s * n_p * elem_bytes(dt) + n_p * ((4 if scaled else 0) + 3 * 8)
+
+
+def grad_bytes(n_s, n_p, dt, scaled):
+    return n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
+
+
+def make_workload(name, device):
+    import synth
+    from synth.configs import CONFIGS
+    cfg = CONFIGS[name]
+    t0 = time.time()
+    if cfg.kind == "cps":
+        d = synth.cps_inputs(cfg.n_s, cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.seed, device=device)
+    else:
+        d = synth.dense_inputs(cfg.n_s, cfg.n_p, cfg.seed, device=device)
+    log(f"[bench] generated {name}: O {tuple(d['O'].shape)} in {time.time() - t0:.1f}s")
+    return cfg, d
+
+
+def timed_events(fn):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    out = fn()
+    e1.record()
+    e1.synchronize()
+    return out, e0.elapsed_time(e1)
+
+
+def cpu_baseline(O_dev, n_rows, eps, budget_s=15.0):
+    """The oracle's matrix-free product (sv_product_swapped) on the first n_rows rows."""
+    import numpy as np
+    import oracle as orc
+    sample = O_dev[:n_rows].double().cpu().numpy()
+    n_p = sample.shape[1]
+    v = np.random.default_rng(0).standard_normal(n_p)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    orc.sv_product_swapped(sample, v, eps)            # warm
+    reps, t_tot = 0, 0.0
+    while t_tot < budget_s and reps < 50:
+        t0 = time.perf_counter()
+        orc.sv_product_swapped(sample, v, eps)
+        t_tot += time.perf_counter() - t0
+        reps += 1
+    t = t_tot / reps
+    gbps = product_bytes(n_rows, n_p, __import__("torch").float64, False) / t / 1e9
+    return {"value": round(gbps, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle sv_product_swapped (float64, numpy/OpenBLAS) on the first {n_rows} rows x {n_p} "
+                      f"columns of the same matrix, {reps} repetitions, {t * 1e3:.1f} ms each"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--rtol", type=float, default=None, help="CG tolerance of the timed bf16 solve")
+    ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison solve")
+    ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
+              f"in DESIGN.md and is not built in this repository.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1108_0900_amd import sr
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+
+    cfg, d = make_workload(args.config, dev)
+    O64, E = d["O"], d["E"]
+    n_s, n_p = O64.shape
+    refresh = cfg.refresh_every or 20
+
+    # ---- storage forms ----
+    scaled = args.config == "c3"
+    if scaled:
+        q, s = sr.sr_quantize(O64, out_dtype=torch.bfloat16)
+        torch.cuda.synchronize()
+        Mt = sr.as_matrix(q, scale=s)
+        dt_t, dtype_name = torch.bfloat16, "bf16"
+        rtol = args.rtol if args.rtol is not None else 1e-6
+    else:
+        Mt = sr.as_matrix(O64)
+        dt_t, dtype_name = O64.dtype, {torch.float64: "f64", torch.float32: "f32"}[O64.dtype]
+        rtol = args.rtol if args.rtol is not None else cfg.rtol
+    M64 = sr.as_matrix(O64)
+
+    def step(M, tol):
+        st = sr.sr_grad(M, E)
+        M.mean = st["mean"]
+        eps = 1e-3 * float(st["diag"].mean()) if cfg.eps_abs is None else cfg.eps_abs
+        (x, info), ms_cg = timed_events(lambda: sr.sr_cg_solve(M, st["g"], eps, rtol=tol, refresh_every=refresh))
+        if info["status"] != 0:
+            raise RuntimeError(f"CG did not converge: {info}")
+        return x, info, ms_cg, eps
+
+    # ---- float64 comparison solve (not timed as a step) ----
+    f64 = None
+    x64 = None
+    if scaled and not args.no_f64:
+        log("[bench] float64 comparison solve")
+        step(M64, 1e-10)      # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x64, info64, ms64, eps64 = step(M64, 1e-10)
+        torch.cuda.synchronize()
+        f64_step_ms = (time.perf_counter() - t0) * 1e3
+        f64 = {"solve_ms": round(ms64, 3), "step_ms": round(f64_step_ms, 3), "iters": info64["iters"],
+               "products": info64["products"], "rel_res_true": info64["rel_res_true"], "rtol": 1e-10,
+               "GBps": round(info64["products"] * product_bytes(n_s, n_p, torch.float64, False) / ms64 / 1e6, 1)}
+        log(f"[bench] f64: {f64}")
+
+    # ---- timed steps ----
+    log(f"[bench] warmup {args.warmup} step(s)")
+    for _ in range(args.warmup):
+        step(Mt, rtol)
+    torch.cuda.synchronize()
+    cg_ms, infos = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, info, ms_cg, eps = step(Mt, rtol)
+        cg_ms.append(ms_cg)
+        infos.append(info)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms_per_step = wall_ms / args.steps
+    products = sum(i["products"] for i in infos) / len(infos)
+    pb = product_bytes(n_s, n_p, dt_t, scaled)
+    step_bytes = grad_bytes(n_s, n_p, dt_t, scaled) + products * pb
+    value = step_bytes / (ms_per_step * 1e6)
+    cg_avg = sum(cg_ms) / len(cg_ms)
+    achieved = products * pb / (cg_avg * 1e6)
+    log(f"[bench] {dtype_name}: {ms_per_step:.2f} ms/step, CG {cg_avg:.2f} ms, products {products}, "
+        f"{value:.0f} GB/s step, {achieved:.0f} GB/s CG")
+
+    # ---- standalone product timing ----
+    def sv_time(M, reps=5):
+        v = torch.randn(n_p, dtype=torch.float64, device=dev)
+        y = torch.empty_like(v)
+        sr.sr_sv_product(M, v, 0.1, out=y)
+        ts = []
+        for _ in range(reps):
+            _, ms = timed_events(lambda: sr.sr_sv_product(M, v, 0.1, out=y))
+            ts.append(ms)
+        ts.sort()
+        return ts[len(ts) // 2]
+    sv = {}
+    ms_t = sv_time(Mt)
+    sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb / ms_t / 1e6, 1),
+                      "frac": round(pb / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
+    if scaled:
+        ms_d = sv_time(M64)
+        b64 = product_bytes(n_s, n_p, torch.float64, False)
+        sv["f64"] = {"ms": round(ms_d, 3), "GBps": round(b64 / ms_d / 1e6, 1),
+                     "frac": round(b64 / ms_d / 1e6 / HBM_PEAK_GBPS, 4)}
+
+    err = None
+    if x64 is not None:
+        err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+
+    # ---- CPU baseline (oracle, bounded sample) ----
+    log("[bench] cpu baseline")
+    cpu = cpu_baseline(O64, min(args.cpu_rows, n_s), eps, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {
+            "workload": {"c3": "CPS-shaped O, 32768 samples x 500000 parameters (2048 correlators x 240 states + "
+                               "8480 dense pairing columns), bf16 codes + float32 column scales; prepare pass + "
+                               "CG to rel. residual %g, float64 residual refresh every %d" % (rtol, refresh),
+                         "c1": "dense O 8192 x 4000 float64; prepare pass + CG to %g" % rtol,
+                         "c2": "CPS-shaped O 65536 x 24512 float64; prepare pass + CG to %g" % rtol,
+                         "c5": "dense O 16384 x 16384 float32; prepare pass + CG to %g" % rtol}[args.config],
+            "n_s": n_s, "n_p": n_p, "seed": cfg.seed, "parallelism": "single GPU",
+        },
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "kernel": "k_cg (persistent CG; products read O once each)",
+                     "bytes_per_launch": round(products * pb), "launch_ms": round(cg_avg, 3)},
+        "cpu_baseline": cpu,
+        "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
+                  "rel_res_true": infos[-1]["rel_res_true"], "rtol": rtol, "eps": eps},
+        "sv_product": sv,
+        "f64_solve": f64,
+        "err_vs_f64": err,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+"""CPU-only checks of the C ABI: the library loads, exports every symbol include/sr.h
+declares, rejects invalid arguments on the host before any HIP call, and reports
+SR_ERR_NODEVICE (not a crash) when no GPU is present.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1108_0900_amd import sr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|int64_t|char\s*\*|const char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for n in ("sr_grad", "sr_sv_product", "sr_cg_solve", "lm_hv_product", "sr_quantize", "sr_release",
+              "sr_status_string", "sr_last_error", "sr_version"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol():
+    L = sr.lib()
+    for n in _declared_functions():
+        assert hasattr(L, n), f"libsr.so does not export {n}"
+    assert set(sr.PROTOTYPES) == set(_declared_functions())
+
+
+def test_struct_layouts_match_header():
+    # sr_matrix: 3 int64 + 2 int32 + 3 pointers; sr_cg_opts: double + 4 int32 + pointer;
+    # sr_cg_info: 4 int32 + 2 double
+    assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 3
+    assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8
+    assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
+
+
+def test_status_strings_and_version():
+    L = sr.lib()
+    assert L.sr_version() >= 10000
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        assert L.sr_status_string(code)
+    assert L.sr_status_string(12345) == b"unknown status"
+
+
+def _mat(n_s=4, n_p=3, ld=4, dtype=sr.SR_F64, O=256, scale=None, mean=None, reserved=0):
+    m = sr.SrMatrix()
+    m.n_s, m.n_p, m.ld, m.dtype, m.reserved = n_s, n_p, ld, dtype, reserved
+    m.O, m.col_scale, m.col_mean = O, scale, mean
+    return m
+
+
+BAD = [
+    ("null O", dict(O=None)),
+    ("n_s < 1", dict(n_s=0)),
+    ("n_p < 1", dict(n_p=0)),
+    ("ld < n_p", dict(n_p=8, ld=4)),
+    ("misaligned O", dict(O=264)),
+    ("ld bytes not multiple of 16", dict(ld=3)),
+    ("bf16 without scale", dict(dtype=sr.SR_BF16, ld=8)),
+    ("f64 with scale", dict(scale=512)),
+    ("bad dtype", dict(dtype=7)),
+    ("reserved", dict(reserved=1)),
+]
+
+
+@pytest.mark.parametrize("name,kw", BAD, ids=[b[0] for b in BAD])
+def test_invalid_matrix_rejected_before_any_launch(name, kw):
+    L = sr.lib()
+    m = _mat(**kw)
+    v, y = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert L.sr_sv_product(ctypes.byref(m), v, y, 0.0, None) == sr.SR_ERR_INVALID
+    assert L.sr_last_error()
+    assert L.sr_grad(ctypes.byref(m), None, None, None, v, None, None) == sr.SR_ERR_INVALID
+    opts = sr.SrCgOpts()
+    opts.rtol = 1e-8
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+
+
+def test_invalid_scalars_rejected():
+    L = sr.lib()
+    m = _mat()
+    v, y = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert L.sr_sv_product(None, v, y, 0.0, None) == sr.SR_ERR_INVALID
+    assert L.sr_sv_product(ctypes.byref(m), v, y, -1.0, None) == sr.SR_ERR_INVALID
+    assert L.sr_sv_product(ctypes.byref(m), v, y, float("nan"), None) == sr.SR_ERR_INVALID
+    assert L.sr_sv_product(ctypes.byref(m), v, ctypes.c_void_p(4096 + 8), 0.0, None) == sr.SR_ERR_INVALID  # overlap
+    assert L.sr_sv_product(ctypes.byref(m), None, y, 0.0, None) == sr.SR_ERR_INVALID
+    opts = sr.SrCgOpts()
+    for rtol in (0.0, -1.0, float("inf")):
+        opts.rtol = rtol
+        assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.rtol = 1e-8
+    opts.refresh_every = -1
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.refresh_every = 0
+    opts.use_x0 = 2
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    # grad: g without E
+    assert L.sr_grad(ctypes.byref(m), None, v, None, None, None, None) == sr.SR_ERR_INVALID
+    # lm: mismatched D
+    d = _mat(n_p=2)
+    E = ctypes.c_void_p(1 << 20)
+    assert L.lm_hv_product(ctypes.byref(m), E, ctypes.byref(d), v, y, None) == sr.SR_ERR_INVALID
+    # quantize
+    assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, 8, sr.SR_F32, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    assert L.sr_quantize(4, 3, v, 2, sr.SR_F64, y, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+
+
+def test_no_device_reported_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = sr.lib()
+    m = _mat()
+    v, y = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert L.sr_sv_product(ctypes.byref(m), v, y, 0.0, None) == sr.SR_ERR_NODEVICE
+    assert b"device" in L.sr_last_error()
+
+
+def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(sr, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(sr, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        sr.lib()
