@@ -156,6 +156,25 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
 int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
                 void *q, int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream);
 
+/* ------------------------------------------------------------------------------------
+ * Tuning hooks (not in the paper).  The fused product is built for a few tile
+ * configurations: nv 16-byte vectors per thread and row, `rows` rows per tile, `lookahead`
+ * tiles of loads in flight, a `poll_delay` of steps between publishing a tile's partial
+ * dots and reading the other column groups' ones, and `threads` per workgroup.
+ * sr_tile_configs: writes up to `max` configurations built for `dtype` (kind 0: SR
+ * products and CG, kind 1: linear-method products) as int32 quintuples
+ * (nv, rows, lookahead, poll_delay, threads) to the host array `out`; returns how many
+ * exist.  The first one listed is the default.
+ * sr_set_tile_config: process-wide override of the automatic choice for every later call
+ * (nv = 0 restores it); col_groups = 0 keeps the automatic number of column groups,
+ * otherwise it must be a power of two (used when larger than the minimum).  Not
+ * synchronized with calls running on other threads.  SR_ERR_INVALID if no kernel has
+ * that configuration.
+ * ------------------------------------------------------------------------------------ */
+int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max);
+int sr_set_tile_config(int32_t nv, int32_t rows, int32_t lookahead, int32_t poll_delay, int32_t threads,
+                       int32_t col_groups);
+
 /* Frees every workspace the library holds (all devices, all streams).  Must not be
  * called while library work is pending on any stream. */
 int sr_release(void);

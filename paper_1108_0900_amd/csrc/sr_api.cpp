@@ -174,16 +174,20 @@ struct Plan {
   int words = 0;   // exchange words per column group per tile
 };
 
-// Optional override "nv,r,nb" from SR_TILE (used by the tile sweep) or the
-// programmatic override below.
-int g_force_nv = 0, g_force_r = 0, g_force_nb = 0, g_force_c = 0;
+// Optional override "nv,r,look,poll,threads[,c]" from the SR_TILE environment variable
+// (tile sweeps): tile shape, pipeline depths, workgroup size and, optionally, a larger
+// power-of-two number of column groups.
+int g_force_nv = 0, g_force_r = 0, g_force_look = 0, g_force_poll = 0, g_force_nt = 0, g_force_c = 0;
 
 void read_env_override() {
   static bool done = false;
   if (done) return;
   done = true;
+  if (g_force_nv > 0) return;   // set through sr_set_tile_config
   const char *e = std::getenv("SR_TILE");
-  if (e) std::sscanf(e, "%d,%d,%d,%d", &g_force_nv, &g_force_r, &g_force_nb, &g_force_c);
+  if (e) std::sscanf(e, "%d,%d,%d,%d,%d,%d", &g_force_nv, &g_force_r, &g_force_look, &g_force_poll, &g_force_nt,
+                     &g_force_c);
+  if (g_force_c & (g_force_c - 1)) g_force_c = 0;   // column groups must be a power of two
 }
 
 int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg) {
@@ -206,26 +210,22 @@ int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
   int count = 0;
   const KernelEntry *tab = kernel_table(dt, &count);
   const int vec = vec_of(dt);
+  const int kind = ndot == 1 ? 0 : 1;
   const KernelEntry *pick = nullptr;
   if (g_force_nv > 0) {
     for (int i = 0; i < count; ++i)
-      if (tab[i].nv == g_force_nv && tab[i].r == g_force_r && tab[i].nb == g_force_nb) pick = &tab[i];
+      if (tab[i].kind == kind && tab[i].nv == g_force_nv && tab[i].r == g_force_r &&
+          tab[i].look == g_force_look && tab[i].poll == g_force_poll && tab[i].nt == g_force_nt)
+        pick = &tab[i];
   }
   if (pick == nullptr) {
-    // Heuristic: the smallest per-thread slice (NV) that holds a whole row in one
-    // workgroup (no exchange); if none does, the widest slice (fewest column groups).
-    const KernelEntry *best = nullptr;
-    for (int i = 0; i < count; ++i) {
-      const int64_t cap = (int64_t)tab[i].nv * vec * kNT;
-      if (n_p <= cap && (best == nullptr || tab[i].nv < best->nv)) best = &tab[i];
-    }
-    if (best == nullptr)
-      for (int i = 0; i < count; ++i)
-        if (best == nullptr || tab[i].nv > best->nv) best = &tab[i];
-    pick = best;
+    // Default: the first configuration listed for the kind (the tuned one); the
+    // tuning hooks select others.
+    for (int i = 0; i < count && pick == nullptr; ++i)
+      if (tab[i].kind == kind) pick = &tab[i];
   }
   plan->ke = pick;
-  const int cols = pick->nv * vec * kNT;
+  const int cols = pick->nv * vec * pick->nt;
   int rc = geometry(G, n_s, n_p, cols, vec, pick->r, g_force_c, &plan->pg);
   if (rc) return rc;
   plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
@@ -278,9 +278,10 @@ int zero_sync(const ProdWs &w, hipStream_t s) {
   return SR_OK;
 }
 
-int launch_coop(const void *fn, int G, void *argp, hipStream_t s) {
+int launch_coop(const void *fn, int G, void *argp, hipStream_t s, int block = kNT, int shmem = 0) {
   void *args[] = {argp};
-  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(G), dim3(kNT), args, 0, s));
+  if (shmem > 0) HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, shmem));
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(G), dim3(block), args, (unsigned)shmem, s));
   return SR_OK;
 }
 
@@ -407,6 +408,55 @@ int sr_release(void) {
   return rc;
 }
 
+int sr_set_tile_config(int32_t nv, int32_t rows, int32_t lookahead, int32_t poll_delay, int32_t threads,
+                       int32_t col_groups) {
+  if (nv == 0) {
+    g_force_nv = g_force_r = g_force_look = g_force_poll = g_force_nt = g_force_c = 0;
+    return SR_OK;
+  }
+  if (col_groups < 0 || (col_groups & (col_groups - 1)))
+    return fail(SR_ERR_INVALID, "sr_set_tile_config: col_groups must be 0 or a power of two");
+  bool found = false;
+  for (int dt = SR_F64; dt <= SR_F16 && !found; ++dt) {
+    int count = 0;
+    const KernelEntry *tab = kernel_table(dt, &count);
+    for (int i = 0; i < count; ++i)
+      if (tab[i].nv == nv && tab[i].r == rows && tab[i].look == lookahead && tab[i].poll == poll_delay &&
+          tab[i].nt == threads)
+        found = true;
+  }
+  if (!found)
+    return fail(SR_ERR_INVALID, "sr_set_tile_config: no kernel built for (%d, %d, %d, %d, %d)", nv, rows, lookahead,
+                poll_delay, threads);
+  read_env_override();
+  g_force_nv = nv;
+  g_force_r = rows;
+  g_force_look = lookahead;
+  g_force_poll = poll_delay;
+  g_force_nt = threads;
+  g_force_c = col_groups;
+  return SR_OK;
+}
+
+int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max) {
+  if (dtype < SR_F64 || dtype > SR_F16 || (kind != 0 && kind != 1) || max < 0 || (max > 0 && out == nullptr))
+    return fail(SR_ERR_INVALID, "sr_tile_configs: bad argument");
+  int count = 0, n = 0;
+  const KernelEntry *tab = kernel_table(dtype, &count);
+  for (int i = 0; i < count; ++i) {
+    if (tab[i].kind != kind) continue;
+    if (n < max) {
+      out[5 * n + 0] = tab[i].nv;
+      out[5 * n + 1] = tab[i].r;
+      out[5 * n + 2] = tab[i].look;
+      out[5 * n + 3] = tab[i].poll;
+      out[5 * n + 4] = tab[i].nt;
+    }
+    n++;
+  }
+  return n;
+}
+
 int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean, double *col_mean_out,
             double *diagS_out, hipStream_t stream) {
   int rc = check_matrix(O, "sr_grad");
@@ -461,7 +511,7 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   a.eps = eps;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  return launch_coop(pl.ke->sv, pl.pg.G, &a, stream);
+  return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
 int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const double *v, double *y,
@@ -509,7 +559,7 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const
   a.y = y;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  return launch_coop(pl.ke->lm, pl.pg.G, &a, stream);
+  return launch_coop(pl.ke->lm, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
 int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt, sr_cg_info *info,
@@ -573,7 +623,7 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.hist = o.res_history;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  rc = launch_coop(pl.ke->cg, pl.pg.G, &a, stream);
+  rc = launch_coop(pl.ke->cg, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
   if (rc) return rc;
   double hinfo[8];
   uint32_t habort = 0;

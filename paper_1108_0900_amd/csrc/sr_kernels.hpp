@@ -243,11 +243,11 @@ __global__ __launch_bounds__(kNT) void k_quantize(QuantArgs a) {
 // ======================================================================================
 // (S + eps I) v
 // ======================================================================================
-template <int DT, int NV, int R, int NB>
-__global__ __launch_bounds__(kNT) void k_sv(SvArgs a) {
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_sv(SvArgs a) {
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
-  Product<DT, NV, R, NB, 1> P;
+  Product<DT, NV, R, 1, false, L, P_, NT> P;
   const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, a.v);
   if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return;
   P.store_partials(a.pg, a.pb, ctx);
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kNT) void k_sv(SvArgs a) {
   const int G = (int)gridDim.x;
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
     const double acc = finish_column(a.pb, a.pg, j);
     const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
     a.y[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
@@ -268,11 +268,11 @@ __global__ __launch_bounds__(kNT) void k_sv(SvArgs a) {
 // ======================================================================================
 // Linear-method product  y = H v  (length n_p + 1)
 // ======================================================================================
-template <int DT, int NV, int R, int NB>
-__global__ __launch_bounds__(kNT) void k_lm(LmArgs a) {
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_lm(LmArgs a) {
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
-  Product<DT, NV, R, NB, 2> P;
+  Product<DT, NV, R, 2, false, L, P_, NT> P;
   const double v0 = a.v[0];
   const double cshare = P.setup(ctx, a.pg, a.ops, a.mean, a.v + 1);
   if (!P.accumulate(a.pg, a.pb, ctx, a.ops, cshare, a.E, v0)) return;
@@ -284,14 +284,14 @@ __global__ __launch_bounds__(kNT) void k_lm(LmArgs a) {
   const int G = (int)gridDim.x;
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
     const double acc = finish_column(a.pb, a.pg, j);
     const double s = a.ops[0].scale ? (double)a.ops[0].scale[j] : 1.0;
     a.y[1 + j] = (s * acc - a.mean[j] * S1) * inv_n;
   }
   if (blockIdx.x == 0) {
     double se = 0.0;
-    for (int64_t k = threadIdx.x; k < a.pg.n_s; k += kNT) se += a.E[k];
+    for (int64_t k = threadIdx.x; k < a.pg.n_s; k += NT) se += a.E[k];
     se = block_sum(se);
     if (threadIdx.x == 0) a.y[0] = se * inv_n * v0 + S2 * inv_n;
   }
@@ -300,14 +300,16 @@ __global__ __launch_bounds__(kNT) void k_lm(LmArgs a) {
 // ======================================================================================
 // Persistent conjugate gradient on (S + eps I) x = g
 // ======================================================================================
-template <int DT, int NV, int R, int NB>
+template <int DT, int NV, int R, int L, int P_, int NT>
 struct CgKernel {
   // q[j] = ((S + eps I) vin)_j for this workgroup's vector chunk [j0, j1).  EXACT selects
   // float64 accumulation (residual products of scaled storage).
   template <bool EXACT>
   __device__ __forceinline__ static bool apply(const CgArgs &a, WgCtx &ctx, const double *vin, double *q,
                                                int64_t j0, int64_t j1, int &products) {
-    Product<DT, NV, R, NB, 1, EXACT> P;
+    // the float64-accumulated residual product uses one-row tiles, one tile of lookahead
+    // and the shortest poll advance (same column geometry, fewer registers)
+    Product<DT, NV, (EXACT ? 1 : R), 1, EXACT, (EXACT ? 1 : L), 2, NT> P;
     const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, vin);
     if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return false;
     P.store_partials(a.pg, a.pb, ctx);
@@ -315,7 +317,7 @@ struct CgKernel {
     double S1, S2;
     sum_row_scalars(a.pb, a.pg, S1, S2);
     const double inv_n = 1.0 / (double)a.pg.n_s;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += kNT) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
       const double acc = finish_column(a.pb, a.pg, j);
       const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
       q[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * ld_coh(&vin[j]);
@@ -328,9 +330,17 @@ struct CgKernel {
   static constexpr bool kExactResidual = (DT == DT_BF16 || DT == DT_F16);
 };
 
-template <int DT, int NV, int R, int NB>
-__global__ __launch_bounds__(kNT) void k_cg(CgArgs a) {
-  typedef CgKernel<DT, NV, R, NB> K;
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
+  // Conjugate gradient (Hestenes-Stiefel) as a state machine with one product per pass
+  // through the loop, so the product code is instantiated once per accumulation type.
+  //   MODE_P        q = A p, then alpha, x += alpha p, r -= alpha q
+  //   MODE_REFRESH  q = A x, r = g - q (every refresh_every iterations)
+  //   MODE_CONFIRM  q = A x when the recurrence residual meets rtol; accept or replace r
+  //   MODE_FINAL    q = A x to report the true residual of an unconverged exit
+  //   MODE_X0       q = A x0 for a warm start
+  typedef CgKernel<DT, NV, R, L, P_, NT> K;
+  enum { MODE_P, MODE_REFRESH, MODE_CONFIRM, MODE_FINAL, MODE_X0, MODE_DONE };
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
   const int G = (int)gridDim.x, tid = (int)threadIdx.x;
@@ -339,118 +349,137 @@ __global__ __launch_bounds__(kNT) void k_cg(CgArgs a) {
   const int64_t j0 = min(n, (int64_t)blockIdx.x * ch), j1 = min(n, j0 + ch);
   int nred = 0, products = 0, refreshes = 0, it = 0;
   int status = 0;       // SR_OK
-  double rel_true = -1.0, rho = 0.0, gg = 0.0, dummy = 0.0;
+  double rel_true = -1.0, rho = 0.0, gg = 1.0, dummy = 0.0;
   bool ok = true, restart = false;
+  int mode;
 
-  // r0 = g - A x0 (or g), p0 = r0
-  if (a.use_x0) {
-    ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
-    if (!ok) goto done;
-    for (int64_t j = j0 + tid; j < j1; j += kNT) a.r[j] = a.g[j] - a.q[j];
-  } else {
-    for (int64_t j = j0 + tid; j < j1; j += kNT) {
-      st_coh(&a.x[j], 0.0);
-      a.r[j] = a.g[j];
-    }
-  }
-  {
-    double prr = 0.0, pgg = 0.0;
-    for (int64_t j = j0 + tid; j < j1; j += kNT) {
-      st_coh(&a.p[j], a.r[j]);
-      prr += a.r[j] * a.r[j];
-      pgg += a.g[j] * a.g[j];
-    }
-    ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg);
-    if (!ok) goto done;
-  }
-  if (gg == 0.0) {
-    for (int64_t j = j0 + tid; j < j1; j += kNT) st_coh(&a.x[j], 0.0);
-    rel_true = 0.0;
-    rho = 0.0;
-    gg = 1.0;
-    goto done;
-  }
-
-  while (true) {
+  // choose the next product from the recurrence residual
+  auto decide = [&]() -> int {
     const double rel = sqrt(rho / gg);
     if (a.hist != nullptr && blockIdx.x == 0 && tid == 0 && it <= a.max_iter) a.hist[it] = rel;
-    if (!isfinite(rho)) { status = -4; break; }
-    if (rel <= a.rtol) {
-      // confirm with the true residual g - A x
-      ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
-      if (!ok) break;
+    if (!isfinite(rho)) { status = -4; return MODE_DONE; }
+    if (rel <= a.rtol) return MODE_CONFIRM;
+    if (it >= a.max_iter) { status = 1; return MODE_FINAL; }
+    return MODE_P;
+  };
+  // p <- r + beta p for the own chunk, then a barrier so every workgroup sees p
+  auto update_p = [&](double beta) -> bool {
+    for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.p[j], a.r[j] + beta * ld_coh(&a.p[j]));
+    return grid_sync(ctx.gs);
+  };
+
+  if (a.use_x0) {
+    mode = MODE_X0;
+  } else {
+    double prr = 0.0, pgg = 0.0;
+    for (int64_t j = j0 + tid; j < j1; j += NT) {
+      st_coh(&a.x[j], 0.0);
+      const double gj = a.g[j];
+      a.r[j] = gj;
+      st_coh(&a.p[j], gj);
+      prr += gj * gj;
+      pgg += gj * gj;
+    }
+    ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg);
+    if (gg == 0.0) {
+      gg = 1.0;
+      rel_true = 0.0;
+      mode = MODE_DONE;
+    } else {
+      mode = decide();
+    }
+  }
+
+  while (ok && mode != MODE_DONE) {
+    const bool on_p = (mode == MODE_P);
+    if constexpr (K::kExactResidual) {
+      if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
+      else ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);
+    } else {
+      ok = K::template apply<false>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
+    }
+    if (!ok) break;
+    if (mode == MODE_P) {
+      double ppq = 0.0, pq;
+      for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * a.q[j];
+      if (!(ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy))) break;
+      if (!isfinite(pq)) { status = -4; break; }
+      if (!(pq > 0.0)) { status = 2; mode = MODE_FINAL; continue; }
+      const double alpha = rho / pq;
       double prr = 0.0;
-      for (int64_t j = j0 + tid; j < j1; j += kNT) {
+      for (int64_t j = j0 + tid; j < j1; j += NT) {
+        st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
+        const double rj = a.r[j] - alpha * a.q[j];
+        a.r[j] = rj;
+        prr += rj * rj;
+      }
+      it++;
+      if (a.refresh_every > 0 && it % a.refresh_every == 0) {
+        if (!(ok = grid_sync(ctx.gs))) break;      // x visible to the refresh product
+        mode = MODE_REFRESH;
+        continue;
+      }
+      double rho_new;
+      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
+      const double beta = rho_new / rho;
+      rho = rho_new;
+      if (!(ok = update_p(beta))) break;
+      mode = decide();
+    } else if (mode == MODE_REFRESH) {
+      double prr = 0.0, rho_new;
+      for (int64_t j = j0 + tid; j < j1; j += NT) {
+        const double rj = a.g[j] - a.q[j];
+        a.r[j] = rj;
+        prr += rj * rj;
+      }
+      refreshes++;
+      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
+      const double beta = a.restart_on_refresh ? 0.0 : rho_new / rho;
+      rho = rho_new;
+      if (!(ok = update_p(beta))) break;
+      mode = decide();
+    } else if (mode == MODE_X0) {
+      double prr = 0.0, pgg = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += NT) {
+        const double gj = a.g[j], rj = gj - a.q[j];
+        a.r[j] = rj;
+        st_coh(&a.p[j], rj);
+        prr += rj * rj;
+        pgg += gj * gj;
+      }
+      if (!(ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg))) break;
+      if (gg == 0.0) {
+        for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.x[j], 0.0);
+        gg = 1.0;
+        rho = 0.0;
+        rel_true = 0.0;
+        mode = MODE_DONE;
+      } else {
+        mode = decide();
+      }
+    } else {   // MODE_CONFIRM or MODE_FINAL: true residual g - A x
+      double prr = 0.0, tr;
+      for (int64_t j = j0 + tid; j < j1; j += NT) {
         const double t = a.g[j] - a.q[j];
-        a.r[j] = t;
+        if (mode == MODE_CONFIRM) a.r[j] = t;
         prr += t * t;
       }
-      double tr;
-      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy);
-      if (!ok) break;
+      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy))) break;
       rel_true = sqrt(tr / gg);
-      if (rel_true <= a.rtol) { status = 0; break; }
-      rho = tr;
-      refreshes++;
-      rel_true = -1.0;
-    }
-    if (it >= a.max_iter) { status = 1; break; }
-    ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
-    if (!ok) break;
-    double pq;
-    {
-      double ppq = 0.0;
-      for (int64_t j = j0 + tid; j < j1; j += kNT) ppq += ld_coh(&a.p[j]) * a.q[j];
-      ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy);
-      if (!ok) break;
-    }
-    if (!isfinite(pq)) { status = -4; break; }
-    if (!(pq > 0.0)) { status = 2; break; }
-    const double alpha = rho / pq;
-    for (int64_t j = j0 + tid; j < j1; j += kNT) {
-      st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
-      a.r[j] -= alpha * a.q[j];
-    }
-    it++;
-    if (a.refresh_every > 0 && it % a.refresh_every == 0) {
-      ok = grid_sync(ctx.gs);
-      if (!ok) break;
-      ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
-      if (!ok) break;
-      for (int64_t j = j0 + tid; j < j1; j += kNT) a.r[j] = a.g[j] - a.q[j];
-      refreshes++;
-      restart = a.restart_on_refresh != 0;
-    }
-    double rho_new;
-    {
-      double prr = 0.0;
-      for (int64_t j = j0 + tid; j < j1; j += kNT) prr += a.r[j] * a.r[j];
-      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy);
-      if (!ok) break;
-    }
-    const double beta = restart ? 0.0 : rho_new / rho;
-    restart = false;
-    rho = rho_new;
-    for (int64_t j = j0 + tid; j < j1; j += kNT) st_coh(&a.p[j], a.r[j] + beta * ld_coh(&a.p[j]));
-    ok = grid_sync(ctx.gs);
-    if (!ok) break;
-  }
-  // true residual for the report when the loop ended without confirming it
-  if (ok && rel_true < 0.0 && status >= 0) {
-    ok = grid_sync(ctx.gs);
-    if (ok) ok = K::template apply<K::kExactResidual>(a, ctx, a.x, a.q, j0, j1, products);
-    if (ok) {
-      double prr = 0.0;
-      for (int64_t j = j0 + tid; j < j1; j += kNT) {
-        const double t = a.g[j] - a.q[j];
-        prr += t * t;
+      if (mode == MODE_FINAL || rel_true <= a.rtol) {
+        mode = MODE_DONE;
+      } else if (it >= a.max_iter) {
+        status = 1;
+        mode = MODE_DONE;
+      } else {
+        // the recurrence residual drifted from the true one: continue from the true one
+        rho = tr;
+        refreshes++;
+        rel_true = -1.0;
+        mode = MODE_P;
       }
-      double tr;
-      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy);
-      if (ok) rel_true = sqrt(tr / gg);
     }
   }
-done:
   if (blockIdx.x == 0 && tid == 0) {
     a.info[0] = (double)it;
     a.info[1] = (double)refreshes;

@@ -3,11 +3,14 @@
 
 namespace sr {
 
-#define SR_REGISTER(NV, R, NB) \
-  {DT_F32, NV, R, NB, (const void *)&k_sv<DT_F32, NV, R, NB>, (const void *)&k_cg<DT_F32, NV, R, NB>, \
-   (const void *)&k_lm<DT_F32, NV, R, NB>},
+#define SR_REG_SR(NV, R, L, P, NT)                                                                   \
+  {DT_F32, NV, R, L, P, NT, 0, (const void *)&k_sv<DT_F32, NV, R, L, P, NT>,                        \
+   (const void *)&k_cg<DT_F32, NV, R, L, P, NT>, nullptr, Product<DT_F32, NV, R, 1, false, L, P, NT>::ring_bytes()},
+#define SR_REG_LM(NV, R, L, P, NT)                                                                   \
+  {DT_F32, NV, R, L, P, NT, 1, nullptr, nullptr, (const void *)&k_lm<DT_F32, NV, R, L, P, NT>,        \
+   Product<DT_F32, NV, R, 2, false, L, P, NT>::ring_bytes()},
 
-static const KernelEntry g_entries_f32[] = {SR_PRODUCT_CONFIGS_F32(SR_REGISTER)};
+static const KernelEntry g_entries_f32[] = {SR_SR_CONFIGS_F32(SR_REG_SR) SR_LM_CONFIGS(SR_REG_LM)};
 
 const KernelEntry *kernel_table_f32(int *count) {
   *count = (int)(sizeof(g_entries_f32) / sizeof(g_entries_f32[0]));

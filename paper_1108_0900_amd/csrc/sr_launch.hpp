@@ -66,16 +66,22 @@ struct QuantArgs {
   float *scale;
 };
 
-// Tile configurations (NV vectors per thread, R rows per tile, NB tile buffers) built for
-// each storage type.
-#define SR_PRODUCT_CONFIGS_F64(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
-#define SR_PRODUCT_CONFIGS_F32(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
-#define SR_PRODUCT_CONFIGS_BF16(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
-#define SR_PRODUCT_CONFIGS_F16(X) X(4, 2, 3) X(2, 4, 3) X(1, 4, 3)
+// Tile configurations (NV 16-byte vectors per data thread, R rows per tile) built for
+// each storage type: SR products (k_sv, k_cg) and linear-method products (k_lm, which
+// streams two matrices and so uses half the tile).
+// X(NV, R, LOOKAHEAD, POLL_ADVANCE, THREADS) per storage type; the first SR entry is the
+// default (chosen by the tile sweep on MI355X), the others are selectable for tuning.
+#define SR_SR_CONFIGS_F64(X) X(4, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(2, 1, 2, 2, 512) X(4, 2, 2, 2, 256)
+#define SR_SR_CONFIGS_F32(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
+#define SR_SR_CONFIGS_BF16(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
+#define SR_SR_CONFIGS_F16(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
+#define SR_LM_CONFIGS(X) X(2, 1, 2, 2, 512) X(4, 1, 2, 2, 256)
 
 struct KernelEntry {
-  int dt, nv, r, nb;
+  int dt, nv, r, look, poll, nt;
+  int kind;              // 0: SR (sv + cg), 1: LM
   const void *sv, *cg, *lm;
+  int ring_bytes;        // dynamic LDS of the launch
 };
 
 const KernelEntry *kernel_table(int dt, int *count);

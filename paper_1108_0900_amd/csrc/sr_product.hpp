@@ -2,18 +2,27 @@
 // Hamiltonian), Sec. II.A Eq. sr_multiply_2 and Sec. II.B Eq. linear_eigen.
 //
 // For each sample row k the method needs the scalar w_k = Oc_k . v before the row can be
-// accumulated into y = sum_k w_k Oc_k.  A row is kept in registers between the two uses,
-// so O is read from HBM exactly once per product:
+// accumulated into y = sum_k w_k Oc_k.  A row tile stays on chip between the two uses, so
+// O is read from HBM exactly once per product:
 //
-//   * The grid (one workgroup of 256 threads per CU, all co-resident) is split into
-//     RG row groups x C column groups.  Column group cg owns a slice of `wslice` columns;
-//     row group rg owns row tiles rg, rg+RG, rg+2RG, ... of R rows each.
-//   * Each thread owns NV 16-byte vectors of its slice (coalesced across the workgroup)
-//     and keeps v (times the column scale) and its y accumulators in registers.
-//   * Tile j: load -> partial dots (wave shuffles, then LDS across waves) -> if C > 1,
-//     publish the partial dots as tagged 64-bit words and read the other C-1 column
-//     groups' words one pipeline step later -> w -> y += w * tile.  NB tile buffers are
-//     in flight so HBM streaming continues while the exchange completes.
+//   * The grid (one workgroup per CU, all co-resident; NT = 256 or 512 threads, i.e. one
+//     or two waves per SIMD) is split into RG row groups x C column groups.  Column group cg owns a slice of `wslice` columns; row group rg owns
+//     row tiles rg, rg+RG, rg+2RG, ... of R rows each.
+//   * Each thread of the workgroup (NT threads) owns NV 16-byte vectors of the slice
+//     (coalesced across the workgroup) and keeps v (times the column scale) and its y accumulators
+//     in registers.
+//   * Row tiles stay in a ring of registers from their load (LOOK steps ahead) until they
+//     are accumulated LAG steps after their dots, so each tile is read from HBM once.
+//     Step t: issue the loads of tile t+LOOK; partial dots of tile t (wave shuffles, then
+//     LDS); accumulate tile t-LAG with the row weights w delivered by the exchange.  One
+//     barrier per step.  Every load is unconditional, so the compiler waits for exactly
+//     the tile a step consumes and leaves the later ones in flight.
+//   * Wave 0 also runs the exchange: after barrier t it combines the waves' partials and,
+//     with C > 1, publishes them as tagged 64-bit words.  The other column groups' words
+//     of step e are loaded at the start of step e+ADV (before that step's tile loads, so
+//     the in-order completion counter never makes the poll wait for newer tiles) and
+//     checked at the end of step e+ADV+1: the round trip through the coherent memory
+//     level overlaps more than a step of streaming.
 //   * Centering is folded in: each column group subtracts its share of obar . v from its
 //     partial dot, and the final y uses y_i = s_i (O^T w)_i - obar_i sum_k w_k.
 //   * Row-group partial y vectors (float64) go to a workspace; a grid barrier later lets
@@ -23,9 +32,8 @@
 
 namespace sr {
 
-constexpr int kNT = 256;            // threads per workgroup (4 waves)
-constexpr int kNW = kNT / 64;       // waves per workgroup
-constexpr int kRing = 4;            // exchange slots per row group (>= 3 needed)
+constexpr int kNT = 256;            // workgroup size of the column-statistics kernels
+constexpr int kRing = 16;           // exchange slots per row group (> 2 * poll delay + 1)
 
 struct ProdGeom {
   int G, C, RG;                     // grid size, column groups, row groups (G = C*RG)
@@ -91,24 +99,44 @@ template <int DT> struct AccOf<DT, true> { typedef double type; };
 
 // NDOT = 1: SR overlap product.  NDOT = 2: linear-method product (second operand D is
 // only dotted, never accumulated).
-template <int DT, int NV, int R, int NB, int NDOT, bool EXACT = false>
+//   NV    16-byte vectors per thread and row (slice width NV*VEC*NT columns)
+//   R     rows per tile
+//   LOOK  tiles whose loads are in flight ahead of the one being consumed
+//   ADV   the exchange of tile t is loaded at the start of step t + ADV (>= 2)
+//   NT    threads per workgroup
+template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int ADV = 2, int NT = 256>
 struct Product {
-  typedef Storage<DT> St;
+  static constexpr int NW = NT / 64;          // waves per workgroup
+  static constexpr int kLook = LOOK;
+  static constexpr int kAdv = ADV;
+  static constexpr int kLag = ADV + 2;        // tile t is accumulated at step t + kLag
+  // register ring: a tile lives from step t-LOOK to t+kLag; even size so the two poll
+  // buffers alternate with a compile-time index
+  static constexpr int kNBuf = ((LOOK + kLag + 1) + 1) / 2 * 2;
+  static_assert(ADV >= 2, "the poll of step e must start after every group published e");
+  // A workgroup publishing step t may meet a slower member of its row group still reading
+  // step t - ADV - 2; the exchange ring must keep those slots distinct.
+  static_assert(kRing > ADV + 3, "exchange ring too small for the poll advance");  typedef Storage<DT> St;
   typedef typename AccOf<DT, EXACT>::type acc_t;
   static constexpr int VEC = St::VEC;
   static constexpr int WPD = sizeof(acc_t) == 8 ? 2 : 1;   // exchange words per partial dot
   // exchange words per column group per tile; the ring is laid out for float64 partials
   // so that float32 and float64 products of the same launch can share it
   static constexpr int WORDS = NDOT * R * 2;
+  static constexpr int PW = NDOT * R * WPD;                  // polled words per column group
 
-  // --- per-thread state ---
-  int64_t colv[NV];                 // first column of each owned vector, or -1
-  u32x4 msk[NV];                    // element mask (vector straddling n_p)
+  // --- per-thread state (data threads) ---
+  int col0;                         // first column of vector 0; vector i starts at col0 + i*NT*VEC
+  int nvec;                         // owned vectors that start inside the slice (0..NV)
+  int n_p;                          // total columns (for the mask of a vector straddling n_p)
   acc_t vc[NDOT][NV][VEC];          // v_j * s_j per operand (0 outside the slice)
   acc_t yacc[NV][VEC];              // partial (O^T w)_j
-  u32x4 buf[NB][NDOT][R][NV];       // row-tile buffers
+  u32x4 buf[kNBuf][NDOT][R][NV];    // register ring of row tiles
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
+  // --- exchange state (wave 0) ---
+  u64 pw[2][PW];                    // words of column group `lane` for the two pending polls
+  double cshare;
 
   __device__ __forceinline__ static u32x4 elem_mask(int nvalid) {
     // keep the bytes of the first nvalid elements of a 16-byte vector
@@ -126,23 +154,29 @@ struct Product {
     return m;
   }
 
+  __device__ __forceinline__ int64_t colv(int i) const { return (int64_t)col0 + (int64_t)i * (NT * VEC); }
+
   // Load the owned coefficients; returns this workgroup's share of obar . v (operand 0).
   __device__ __forceinline__ double setup(const WgCtx &ctx, const ProdGeom &pg, const Operand *ops,
                                           const double *__restrict__ mean, const double *v) {
     const int tid = (int)threadIdx.x;
+    const bool data = true;
     double cpart = 0.0;
-    need_mask = false;
+    col0 = (int)(ctx.c0 + (int64_t)tid * VEC);
+    nvec = 0;
+    n_p = (int)pg.n_p;
+    bool straddles = false;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const int64_t col = ctx.c0 + ((int64_t)i * kNT + tid) * VEC;
-      colv[i] = (col < ctx.c1) ? col : -1;
+      const int64_t col = colv(i);
+      const bool in = data && col < ctx.c1;
       int nvalid = 0;
-      if (colv[i] >= 0) {
+      if (in) {
+        nvec = i + 1;
         const int64_t rem = pg.n_p - col;
         nvalid = rem >= VEC ? VEC : (int)rem;
+        if (nvalid < VEC) straddles = true;
       }
-      msk[i] = elem_mask(nvalid);
-      if (colv[i] >= 0 && nvalid < VEC) need_mask = true;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         double vj = 0.0;
@@ -161,11 +195,16 @@ struct Product {
     }
     s1 = 0.0;
     s2 = 0.0;
-    // need_mask is per thread; make it uniform (any thread) so branches stay uniform
-    need_mask = __syncthreads_or(need_mask ? 1 : 0) != 0;
-    return block_sum(cpart);
+    // uniform flag: does any thread own a straddling vector?
+    need_mask = __syncthreads_or(straddles ? 1 : 0) != 0;
+    cshare = block_sum(cpart);
+    return cshare;
   }
 
+  // Loads of tile j into buffer B.  Every load is issued unconditionally (rows past n_s
+  // and vectors past the slice read a valid address of the same matrix instead, and
+  // their row weights / coefficients are zero), so the compiler can wait for exactly the
+  // loads a step needs and leave the later tiles in flight.
   template <int B>
   __device__ __forceinline__ void issue(const WgCtx &ctx, const ProdGeom &pg, const Operand *ops, int j) {
     const int64_t row0 = ((int64_t)j * pg.RG + ctx.rg) * R;
@@ -173,18 +212,33 @@ struct Product {
     for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t row = row0 + r;
+        int64_t row = row0 + r;
+        row = row < pg.n_s ? row : pg.n_s - 1;
         const unsigned char *rowp = ops[d].O + row * ops[d].ldb;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-          if (row < pg.n_s && colv[i] >= 0) buf[B][d][r][i] = load_stream(rowp + colv[i] * St::BYTES);
-          else buf[B][d][r][i] = u32x4{0u, 0u, 0u, 0u};
+          const int64_t col = i < nvec ? colv(i) : 0;
+          buf[B][d][r][i] = load_stream(rowp + col * St::BYTES);
         }
       }
   }
 
   template <int B>
   __device__ __forceinline__ void dots(acc_t (&part)[NDOT][R]) {
+    if (need_mask) {
+      // zero the bytes past n_p (row padding may hold anything) before any use; the mask
+      // of each vector is computed, not looked up, so the tile stays in registers
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        int nv = n_p - (col0 + i * (NT * VEC));
+        nv = nv < 0 ? 0 : (nv > VEC ? VEC : nv);
+        const u32x4 m = elem_mask(nv);
+#pragma unroll
+        for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[B][d][r][i] &= m;
+      }
+    }
 #pragma unroll
     for (int d = 0; d < NDOT; ++d)
 #pragma unroll
@@ -192,37 +246,12 @@ struct Product {
         acc_t acc = (acc_t)0;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-          u32x4 x = buf[B][d][r][i];
-          if (need_mask) x &= msk[i];
+          const u32x4 x = buf[B][d][r][i];
 #pragma unroll
           for (int e = 0; e < VEC; ++e) acc += (acc_t)St::get(x, e) * vc[d][i][e];
         }
         part[d][r] = acc;
       }
-  }
-
-  // Workgroup reduction of the per-thread partial dots; result (minus the centering share
-  // for operand 0) in s_red[d][r] (float64, LDS) for every thread.
-  __device__ __forceinline__ void reduce(acc_t (&part)[NDOT][R], double cshare, double (&s_red)[NDOT][R],
-                                         double (&s_wave)[kNW][NDOT][R]) {
-    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 0; d < NDOT; ++d)
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        acc_t s = wave_sum(part[d][r]);
-        if (lane == 0) s_wave[wave][d][r] = (double)s;
-      }
-    __syncthreads();
-    if (threadIdx.x < NDOT * R) {
-      const int d = (int)threadIdx.x / R, r = (int)threadIdx.x % R;
-      double t = 0.0;
-#pragma unroll
-      for (int w = 0; w < kNW; ++w) t += s_wave[w][d][r];
-      if (d == 0) t -= cshare;
-      s_red[d][r] = t;
-    }
-    __syncthreads();
   }
 
   __device__ __forceinline__ u64 *slot_base(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
@@ -231,13 +260,15 @@ struct Product {
     return pb.xchg + (((int64_t)ctx.rg * kRing + slot) * pg.C) * WORDS;
   }
 
+  // Exchange wave: publish this column group's partial dots of exchange step `step`.
   __device__ __forceinline__ void publish(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx, uint32_t step,
-                                          const double (&s_red)[NDOT][R]) {
+                                          const double (&red)[NDOT][R]) {
     u64 *base = slot_base(pb, pg, ctx, step) + (int64_t)ctx.cg * WORDS;
     const u64 tag = (u64)(step / kRing + 1) << 32;
-    if (threadIdx.x < NDOT * R) {
-      const int d = (int)threadIdx.x / R, r = (int)threadIdx.x % R;
-      const double val = s_red[d][r];
+    const int lane = (int)threadIdx.x & 63;
+    if (lane < NDOT * R) {
+      const int d = lane / R, r = lane % R;
+      const double val = red[d][r];
       if (WPD == 1) {
         const float f = (float)val;
         st_coh64(&base[d * R + r], tag | (u64)__float_as_uint(f));
@@ -249,65 +280,110 @@ struct Product {
     }
   }
 
-  // Wait for all C column groups' words of `step` and sum them (fixed order, identical in
-  // every column group).  Result in s_tot[d][r].  Returns false on abort.
-  __device__ __forceinline__ bool collect(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx, uint32_t step,
-                                          double (&s_tot)[NDOT][R]) {
-    __shared__ int s_ok;
-    if (threadIdx.x < 64) {
-      const u64 *base = slot_base(pb, pg, ctx, step);
-      const uint32_t tag = step / kRing + 1;
-      const int lane = (int)threadIdx.x;
-      double acc[NDOT][R];
-      int ok = 1;
-      uint64_t spins = 0;
-      while (true) {
-        bool mine = true;
+  // Wave 0: issue the loads of column group `lane`'s words into poll buffer Q (no wait).
+  template <int Q>
+  __device__ __forceinline__ void poll_issue(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
+                                             uint32_t step) {
+    const int lane = (int)threadIdx.x & 63;
+    const u64 *wp = slot_base(pb, pg, ctx, step) + (int64_t)lane * WORDS;
+    if (lane < pg.C) {
 #pragma unroll
-        for (int d = 0; d < NDOT; ++d)
+      for (int k = 0; k < PW; ++k) pw[Q][k] = ld_coh64(&wp[k]);
+    } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) acc[d][r] = 0.0;
-        for (int c = lane; c < pg.C; c += 64) {
-          const u64 *wp = base + (int64_t)c * WORDS;
+      for (int k = 0; k < PW; ++k) pw[Q][k] = 0;
+    }
+  }
+
+  __device__ __forceinline__ static bool words_ok(const u64 *w, uint32_t tag) {
+    bool ok = true;
 #pragma unroll
-          for (int d = 0; d < NDOT; ++d)
+    for (int k = 0; k < PW; ++k) ok &= ((uint32_t)(w[k] >> 32) == tag);
+    return ok;
+  }
+  __device__ __forceinline__ static void words_add(const u64 *w, double (&acc)[NDOT][R]) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              if (WPD == 1) {
-                const u64 w = ld_coh64(&wp[d * R + r]);
-                mine &= ((uint32_t)(w >> 32) == tag);
-                acc[d][r] += (double)__uint_as_float((uint32_t)w);
-              } else {
-                const u64 lo = ld_coh64(&wp[(d * R + r) * 2 + 0]);
-                const u64 hi = ld_coh64(&wp[(d * R + r) * 2 + 1]);
-                mine &= ((uint32_t)(lo >> 32) == tag) && ((uint32_t)(hi >> 32) == tag);
-                acc[d][r] += __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
-              }
-            }
+    for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (WPD == 1) {
+          acc[d][r] += (double)__uint_as_float((uint32_t)w[d * R + r]);
+        } else {
+          const u64 lo = w[(d * R + r) * 2 + 0], hi = w[(d * R + r) * 2 + 1];
+          acc[d][r] += __longlong_as_double((long long)((hi << 32) | (lo & 0xFFFFFFFFull)));
         }
-        if (__all(mine)) break;
+      }
+  }
+
+  // Exchange wave: finish the poll of `step` (words already issued by poll_issue for the
+  // first 64 column groups), re-reading until every column group's words carry the
+  // step's tag; sum in a fixed order (lane, then butterfly) and store the row weights in
+  // tot[d][r].  Returns false if the wait gave up (abort).
+  template <int Q>
+  __device__ __forceinline__ bool poll_finish(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
+                                              uint32_t step, double (*tot)[R]) {
+    const int lane = (int)threadIdx.x & 63;
+    const uint32_t tag = step / kRing + 1;
+    const u64 *base = slot_base(pb, pg, ctx, step);
+    uint64_t spins = 0;
+    bool ok = true;
+    // first chunk: the words issued ahead.  The first check is kept out of the retry
+    // loop so that it waits only for those words, not for the tile loads issued after.
+    if (!__all(lane >= pg.C || words_ok(pw[Q], tag))) {
+      u64 w[PW];
+      while (true) {
+        if (lane < pg.C) {
+          const u64 *wp = base + (int64_t)lane * WORDS;
+#pragma unroll
+          for (int k = 0; k < PW; ++k) w[k] = ld_coh64(&wp[k]);
+        }
+        if (__all(lane >= pg.C || words_ok(w, tag))) break;
         if (++spins > kSpinLimit || ((spins & 255) == 0 && ld_coh32(ctx.gs.abort) != 0u)) {
-          if (lane == 0) st_coh32(ctx.gs.abort, 1u);
-          ok = 0;
+          ok = false;
           break;
         }
       }
 #pragma unroll
-      for (int d = 0; d < NDOT; ++d)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double t = wave_sum(acc[d][r]);
-          if (lane == 0) s_tot[d][r] = t;
-        }
-      if (lane == 0) s_ok = ok;
+      for (int k = 0; k < PW; ++k) pw[Q][k] = w[k];
     }
-    __syncthreads();
-    return s_ok != 0;
+    double acc[NDOT][R];
+#pragma unroll
+    for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[d][r] = 0.0;
+    if (lane < pg.C) words_add(pw[Q], acc);
+    // further chunks (C > 64): read synchronously
+    for (int c0 = 64; ok && c0 < pg.C; c0 += 64) {
+      const int c = c0 + lane;
+      u64 w[PW];
+      while (true) {
+        if (c < pg.C) {
+          const u64 *wp = base + (int64_t)c * WORDS;
+#pragma unroll
+          for (int k = 0; k < PW; ++k) w[k] = ld_coh64(&wp[k]);
+        }
+        if (__all(c >= pg.C || words_ok(w, tag))) break;
+        if (++spins > kSpinLimit || ((spins & 255) == 0 && ld_coh32(ctx.gs.abort) != 0u)) {
+          ok = false;
+          break;
+        }
+      }
+      if (c < pg.C) words_add(w, acc);
+    }
+    if (!ok && lane == 0) st_coh32(ctx.gs.abort, 1u);
+#pragma unroll
+    for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double t = wave_sum(acc[d][r]);
+        if (lane == 0) tot[d][r] = t;
+      }
+    return ok;
   }
 
-  // y += w * tile for tile j held in buffer B.
+  // y += w * tile for tile j, held in register buffer B.
   template <int B>
-  __device__ __forceinline__ void update(const ProdGeom &pg, const WgCtx &ctx, int j, const double (&tot)[NDOT][R],
+  __device__ __forceinline__ void update(const ProdGeom &pg, const WgCtx &ctx, int j, const double (*tot)[R],
                                          const double *__restrict__ E, double v0) {
     const int64_t row0 = ((int64_t)j * pg.RG + ctx.rg) * R;
     acc_t w[R];
@@ -333,86 +409,120 @@ struct Product {
     for (int i = 0; i < NV; ++i) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        u32x4 x = buf[B][0][r][i];
-        if (need_mask) x &= msk[i];
+        const u32x4 x = buf[B][0][r][i];
 #pragma unroll
         for (int e = 0; e < VEC; ++e) yacc[i][e] += (acc_t)St::get(x, e) * w[r];
       }
     }
   }
 
-  // One pipeline step for local tile j (buffer B = j % NB).
+  // One pipeline step t (register buffer B = t % kNBuf).
   template <int B>
-  __device__ __forceinline__ bool step(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
-                                       int j, int n_my, double cshare, const double *__restrict__ E, double v0,
-                                       double (&s_red)[NDOT][R], double (&s_wave)[kNW][NDOT][R],
-                                       double (&s_tot)[NDOT][R]) {
-    constexpr int BP = (B + NB - 1) % NB;   // buffer of tile j-1
-    if (pg.C == 1) {
-      if (j < n_my) {
-        acc_t part[NDOT][R];
-        dots<B>(part);
-        reduce(part, cshare, s_red, s_wave);
-        update<B>(pg, ctx, j, s_red, E, v0);
-        if (j + NB < n_my) issue<B>(ctx, pg, ops, j + NB);
-      }
-      return true;
+  __device__ __forceinline__ void step(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t,
+                                       int n_my, const double *__restrict__ E, double v0,
+                                       double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
+    constexpr int QI = ((B - kAdv) % 2 + 2) % 2;       // poll buffer of exchange t - kAdv
+    constexpr int QF = ((B - kAdv - 1) % 2 + 2) % 2;   // poll buffer of exchange t - kAdv - 1
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    // wave 0: start loading the exchange words of step t - kAdv (before any tile load of
+    // this step, so waiting for them later never waits for this step's tiles)
+    if (wave == 0 && pg.C > 1) {
+      const int e = t - kAdv;
+      if (e >= 0 && e < n_my && ok) poll_issue<QI>(pb, pg, ctx, ctx.xstep + (uint32_t)e);
     }
-    if (j < n_my) {
+    // streaming: unconditional in every step (tiles past n_my read clamped rows with zero
+    // weight), so the wait for tile t leaves tiles t+1..t+kLook in flight
+    issue<(B + kLook) % kNBuf>(ctx, pg, ops, t + kLook);
+    {
       acc_t part[NDOT][R];
       dots<B>(part);
-      reduce(part, cshare, s_red, s_wave);
-      publish(pb, pg, ctx, ctx.xstep + (uint32_t)j, s_red);
+#pragma unroll
+      for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const acc_t sw = wave_sum(part[d][r]);
+          if (lane == 0) s_part[t & 1][wave][d][r] = (double)sw;
+        }
     }
-    if (j >= 1 && j - 1 < n_my) {
-      if (!collect(pb, pg, ctx, ctx.xstep + (uint32_t)(j - 1), s_tot)) return false;
-      update<BP>(pg, ctx, j - 1, s_tot, E, v0);
-      __syncthreads();   // s_tot is rewritten by the next collect
+    const int u = t - kLag;
+    if (u >= 0 && u < n_my) update<(B + kNBuf - kLag) % kNBuf>(pg, ctx, u, s_tot[u % kNBuf], E, v0);
+    if (wave == 0 && pg.C > 1) {
+      // finish the poll started at the beginning of step t-1
+      const int e = t - kAdv - 1;
+      if (e >= 0 && e < n_my && ok) ok = poll_finish<QF>(pb, pg, ctx, ctx.xstep + (uint32_t)e, s_tot[e % kNBuf]);
     }
-    if (j - 1 + NB < n_my) issue<BP>(ctx, pg, ops, j - 1 + NB);
-    return true;
+    __syncthreads();
+    if (wave == 0 && t < n_my) {
+      double red[NDOT][R];
+#pragma unroll
+      for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double sm = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) sm += s_part[t & 1][w][d][r];
+          red[d][r] = (d == 0) ? sm - cshare : sm;
+        }
+      if (pg.C == 1) {
+        if (lane == 0) {
+#pragma unroll
+          for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+            for (int r = 0; r < R; ++r) s_tot[t % kNBuf][d][r] = red[d][r];
+        }
+      } else {
+        publish(pb, pg, ctx, ctx.xstep + (uint32_t)t, red);
+      }
+    }
   }
 
   // Accumulate this workgroup's share of O^T w over its row group's tiles.
   __device__ __forceinline__ bool accumulate(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
-                                             double cshare, const double *__restrict__ E, double v0) {
-    __shared__ double s_red[NDOT][R];
-    __shared__ double s_wave[kNW][NDOT][R];
-    __shared__ double s_tot[NDOT][R];
-    const int n_my = (ctx.rg < pg.n_tiles) ? (pg.n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
-    const int pre = (pg.C == 1) ? NB : NB - 1;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (b < pre && b < n_my) {
-        if (b == 0) issue<0>(ctx, pg, ops, 0);
-        if (NB > 1 && b == 1) issue<(1 % NB)>(ctx, pg, ops, 1);
-        if (NB > 2 && b == 2) issue<(2 % NB)>(ctx, pg, ops, 2);
-        if (NB > 3 && b == 3) issue<(3 % NB)>(ctx, pg, ops, 3);
-      }
-    }
-    const int last = (pg.C == 1) ? n_my : n_my + 1;   // exclusive bound of steps
+                                             double /*cshare*/, const double *__restrict__ E, double v0) {
+    __shared__ double s_part[2][NW][NDOT][R];
+    __shared__ double s_tot[kNBuf][NDOT][R];
+    __shared__ int s_ok;
+    const int n_tiles = (int)((pg.n_s + R - 1) / R);
+    const int n_my = (ctx.rg < n_tiles) ? (n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
+    static_assert(kNBuf <= 8, "unrolled for at most 8 tile buffers");
+    static_assert(kLook <= 4, "prologue issues at most 4 tiles");
+    issue<0>(ctx, pg, ops, 0);
+    if (kLook > 1) issue<(1 % kNBuf)>(ctx, pg, ops, 1);
+    if (kLook > 2) issue<(2 % kNBuf)>(ctx, pg, ops, 2);
+    if (kLook > 3) issue<(3 % kNBuf)>(ctx, pg, ops, 3);
     bool ok = true;
-    for (int j0 = 0; j0 < last && ok; j0 += NB) {
-      ok = step<0>(pg, pb, ctx, ops, j0, n_my, cshare, E, v0, s_red, s_wave, s_tot);
-      if (NB > 1 && ok && j0 + 1 < last)
-        ok = step<(1 % NB)>(pg, pb, ctx, ops, j0 + 1, n_my, cshare, E, v0, s_red, s_wave, s_tot);
-      if (NB > 2 && ok && j0 + 2 < last)
-        ok = step<(2 % NB)>(pg, pb, ctx, ops, j0 + 2, n_my, cshare, E, v0, s_red, s_wave, s_tot);
-      if (NB > 3 && ok && j0 + 3 < last)
-        ok = step<(3 % NB)>(pg, pb, ctx, ops, j0 + 3, n_my, cshare, E, v0, s_red, s_wave, s_tot);
+    // whole rounds of kNBuf steps: no step is skipped, so the loop body has no branch
+    // around loads (steps past n_my + kLag only stream clamped rows)
+    const int rounds = (n_my + kLag + kNBuf - 1) / kNBuf;
+    for (int q = 0; q < rounds; ++q) {
+      const int t0 = q * kNBuf;
+      step<0>(pg, pb, ctx, ops, t0, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 1) step<(1 % kNBuf)>(pg, pb, ctx, ops, t0 + 1, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 2) step<(2 % kNBuf)>(pg, pb, ctx, ops, t0 + 2, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 3) step<(3 % kNBuf)>(pg, pb, ctx, ops, t0 + 3, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 4) step<(4 % kNBuf)>(pg, pb, ctx, ops, t0 + 4, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 5) step<(5 % kNBuf)>(pg, pb, ctx, ops, t0 + 5, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 6) step<(6 % kNBuf)>(pg, pb, ctx, ops, t0 + 6, n_my, E, v0, s_part, s_tot, ok);
+      if (kNBuf > 7) step<(7 % kNBuf)>(pg, pb, ctx, ops, t0 + 7, n_my, E, v0, s_part, s_tot, ok);
     }
     ctx.xstep += (uint32_t)n_my;
-    return ok;
+    if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
+    __syncthreads();
+    return s_ok != 0;
   }
+
+  // Dynamic LDS of the launch (the tile ring lives in registers).
+  static constexpr int ring_bytes() { return 0; }
 
   // Store the row group's partial y (float64) and scalars, coherently.
   __device__ __forceinline__ void store_partials(const ProdGeom &pg, const ProdBufs &pb, const WgCtx &ctx) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      if (colv[i] < 0) continue;
+      if (i >= nvec) continue;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        const int64_t col = colv[i] + e;
+        const int64_t col = colv(i) + e;
         if (col < pg.n_p) st_coh(&pb.ypart[(int64_t)ctx.rg * pg.n_p + col], (double)yacc[i][e]);
       }
     }

@@ -51,6 +51,8 @@ PROTOTYPES = {
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
+    "sr_tile_configs": (ctypes.c_int, [_c_i32, _c_i32, ctypes.POINTER(ctypes.c_int32), _c_i32]),
+    "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sr_last_error": (ctypes.c_char_p, []),
     "sr_version": (ctypes.c_int, []),
@@ -257,6 +259,22 @@ def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, stream=None):
                            _ptr(s), _stream(stream))
     _check(st, "sr_quantize")
     return q[:, :n_p], s
+
+
+def tile_configs(dtype=torch.float64, kind: int = 0) -> list:
+    """Tile configurations (nv, rows, lookahead, poll_delay, threads) built for a storage
+    type; the first is the default."""
+    code = _TORCH_DT[dtype]
+    n = lib().sr_tile_configs(code, kind, None, 0)
+    arr = (ctypes.c_int32 * (5 * max(n, 1)))()
+    lib().sr_tile_configs(code, kind, arr, n)
+    return [tuple(arr[5 * i:5 * i + 5]) for i in range(n)]
+
+
+def set_tile_config(nv: int = 0, rows: int = 0, lookahead: int = 0, poll_delay: int = 0, threads: int = 0,
+                    col_groups: int = 0):
+    """Override the product tile configuration (nv = 0: automatic)."""
+    _check(lib().sr_set_tile_config(nv, rows, lookahead, poll_delay, threads, col_groups), "sr_set_tile_config")
 
 
 def release():

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     text = open(os.path.join(ROOT, "include", "sr.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:int|int64_t|char\s*\*|const char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|int32_t|int64_t|char\s*\*|const char\s*\*|void)\s*\*?\s*(\w+)\s*\(",
                        text, flags=re.M)
     return sorted(set(names))
 
@@ -130,3 +130,18 @@ def test_binding_raises_when_library_missing(monkeypatch, tmp_path):
     monkeypatch.setattr(sr, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         sr.lib()
+
+
+def test_tile_config_hooks():
+    import torch
+    for dt in (torch.float64, torch.float32, torch.bfloat16, torch.float16):
+        cfgs = sr.tile_configs(dt, 0)
+        assert cfgs and all(len(c) == 5 for c in cfgs)
+        assert sr.tile_configs(dt, 1)
+    cfg = sr.tile_configs(torch.float64, 0)[0]
+    sr.set_tile_config(*cfg)
+    sr.set_tile_config(0)
+    with pytest.raises(sr.SrError):
+        sr.set_tile_config(3, 3, 3, 3, 256)
+    with pytest.raises(sr.SrError):
+        sr.set_tile_config(*cfg, col_groups=3)
