@@ -65,6 +65,10 @@ typedef struct sr_matrix {
   int32_t dtype;             /* enum sr_dtype                                          */
   int32_t reserved;          /* must be 0                                              */
   const void *O;             /* [n_s][ld] device                                       */
+  const void *O_lo;          /* SR_BF16/SR_F16 only, optional: second code plane       */
+                             /* [n_s][ld] (same dtype and ld) holding the quantisation */
+                             /* remainder, so the stored value is s_j*(q_kj + lo_kj);   */
+                             /* NULL: single plane                                     */
   const float *col_scale;    /* [n_p] device; required for SR_BF16/SR_F16, else NULL   */
   const double *col_mean;    /* [n_p] device column means of the STORED values         */
                              /* (s_j*q_kj for scaled types); NULL: computed by the call */
@@ -110,7 +114,8 @@ int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean,
  * sr_sv_product: y = (S + eps I) v with S = (1/n_s) Oc^T Oc applied by interchanging the
  * sums over samples and parameters (Sec. II.A, Eq. sr_multiply_2): for each row,
  * w_k = Oc_k . v, then y = (1/n_s) sum_k w_k Oc_k + eps v.  O is read once.
- * v, y: [n_p] float64, must not overlap.  eps >= 0.
+ * v, y: [n_p] float64, must not overlap.  eps >= 0.  With a second code plane the
+ * product is that of the two-plane values, accumulated in float64.
  * ------------------------------------------------------------------------------------ */
 int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream);
 
@@ -124,7 +129,9 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
  * Residual refreshes and the exit check use products accumulated in float64 for every
  * storage type, so for bf16/f16 storage the iteration converges to the solution of the
  * stored (dequantized) system although its search-direction products accumulate in
- * float32 (mixed-precision residual replacement).
+ * float32 (mixed-precision residual replacement).  With a second code plane (O_lo) the
+ * stored system is the two-plane one: refreshes and the exit check read both planes,
+ * search-direction products read only the first (mixed-precision iterative refinement).
  * This call synchronizes `stream` before returning (it reads the outcome back).
  * Returns SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN or an error code.
  * ------------------------------------------------------------------------------------ */
@@ -138,7 +145,8 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x,
  *   t_k = Oc_k . v[1:],  u_k = D_k . v[1:],  z_k = E_k (v_0 + t_k) + u_k
  *   y_0 = E_mean v_0 + (1/n_s) sum_k (E_k t_k + u_k)
  *   y_i = (1/n_s) sum_k Oc_ki z_k                                       (i >= 1)
- * O and D: same n_s, n_p and dtype (their ld and scales may differ).  E: [n_s] float64.
+ * O and D: same n_s, n_p and dtype (their ld and scales may differ), single code plane
+ * (O_lo = NULL).  E: [n_s] float64.
  * v, y: [n_p + 1] float64, must not overlap.  The companion overlap is 1 (+) S.
  * ------------------------------------------------------------------------------------ */
 int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
@@ -151,10 +159,12 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
  *   q_kj = round-to-nearest-even of O_kj / s_j (the quotient taken in float64).
  * in: [n_s][ld_in] of in_dtype (SR_F64 or SR_F32).  q: [n_s][ld_out] of out_dtype
  * (columns n_p..ld_out-1 are set to zero).  scale: [n_p] float32.
+ * q_lo: NULL, or [n_s][ld_out] of out_dtype receiving the second plane, the nearest code
+ * of the remainder O_kj/s_j - q_kj (in float64).
  * Same alignment rules as sr_matrix for both matrices.
  * ------------------------------------------------------------------------------------ */
 int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
-                void *q, int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream);
+                void *q, void *q_lo, int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
  * Tuning hooks (not in the paper).  The fused product is built for a few tile

@@ -38,7 +38,7 @@ Functions and the passage each follows:
   cg_solve ............................... Sec. II.A, conjugate gradient (Hestenes-Stiefel)
   lm_matrices, lm_hv_dense ............... Sec. II.B, Eq. linear_eigen (H and S in Omega)
   lm_lowest_eigenpair .................... Sec. II.B, Eq. linear_eigen (dense generalized solve)
-  quantize_bf16/_f16, dequantize_* ....... precision form of the stored ratios (not in the paper)
+  quantize_bf16/_f16/_split, dequantize_* . precision form of the stored ratios (not in the paper)
   solve_adjoint_gradients ................ implicit-adjoint derivative of the solve (not in the paper)
 
 Every function is pinned by the CPU tests against something other than itself
@@ -55,7 +55,7 @@ __all__ = [
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
     "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense",
     "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
-    "solve_adjoint_gradients",
+    "quantize_split", "dequantize_split", "solve_adjoint_gradients",
 ]
 
 
@@ -308,6 +308,41 @@ def quantize_bf16(O):
     rounded = (fb.astype(np.uint64) + np.uint64(0x7FFF) + ((fb.astype(np.uint64) >> np.uint64(16)) & np.uint64(1)))
     q = (rounded >> np.uint64(16)).astype(np.uint16)
     return q, s
+
+
+def _rne_bf16_bits_from_f64(t: np.ndarray) -> np.ndarray:
+    fb = _f64_to_f32_round_to_odd(t).astype(np.uint64)
+    return ((fb + np.uint64(0x7FFF) + ((fb >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)).astype(np.uint16)
+
+
+def _bf16_bits_to_f64(q: np.ndarray) -> np.ndarray:
+    return (np.asarray(q, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
+def quantize_split(O, code: str = "bf16"):
+    """Two-plane codes: q_hi as in quantize_bf16/_f16, and q_lo = nearest-even code of the
+    remainder O_kj / s_j - q_hi_kj (in float64), so that s_j (q_hi + q_lo) represents O_kj
+    to about 2^-18 (bf16) of the column scale.  Returns (q_hi, q_lo, s)."""
+    O = np.asarray(O, dtype=np.float64)
+    q_hi, s = quantize_bf16(O) if code == "bf16" else quantize_f16(O)
+    t = O / s.astype(np.float64)[None, :]
+    hi = _bf16_bits_to_f64(q_hi) if code == "bf16" else q_hi.view(np.float16).astype(np.float64)
+    rem = t - hi
+    if code == "bf16":
+        q_lo = _rne_bf16_bits_from_f64(rem)
+    else:
+        q_lo = _f64_to_f32_round_to_odd(rem).view(np.float32).astype(np.float16).view(np.uint16)
+    return q_hi, q_lo, s
+
+
+def dequantize_split(q_hi, q_lo, s, code: str = "bf16") -> np.ndarray:
+    """Stored value s_j (q_hi + q_lo) lifted to float64 (the sum taken in float64)."""
+    if code == "bf16":
+        v = _bf16_bits_to_f64(q_hi) + _bf16_bits_to_f64(q_lo)
+    else:
+        v = (np.asarray(q_hi, dtype=np.uint16).view(np.float16).astype(np.float64)
+             + np.asarray(q_lo, dtype=np.uint16).view(np.float16).astype(np.float64))
+    return v * np.asarray(s, dtype=np.float32).astype(np.float64)[None, :]
 
 
 def quantize_f16(O):

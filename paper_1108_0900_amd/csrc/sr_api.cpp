@@ -70,6 +70,9 @@ int check_matrix(const sr_matrix *m, const char *name) {
     return fail(SR_ERR_INVALID, "%s: col_scale is required for bf16/f16 storage", name);
   if (!scaled(m->dtype) && m->col_scale != nullptr)
     return fail(SR_ERR_INVALID, "%s: col_scale must be NULL for f64/f32 storage", name);
+  if (m->O_lo != nullptr && !scaled(m->dtype))
+    return fail(SR_ERR_INVALID, "%s: a second code plane (O_lo) needs bf16/f16 storage", name);
+  if (((uintptr_t)m->O_lo) % 16 != 0) return fail(SR_ERR_INVALID, "%s: O_lo must be 16-byte aligned", name);
   return SR_OK;
 }
 
@@ -288,6 +291,7 @@ int launch_coop(const void *fn, int G, void *argp, hipStream_t s, int block = kN
 Operand make_operand(const sr_matrix *m) {
   Operand op;
   op.O = (const unsigned char *)m->O;
+  op.lo = (const unsigned char *)m->O_lo;
   op.ldb = m->ld * elem_bytes(m->dtype);
   op.scale = m->col_scale;
   return op;
@@ -511,6 +515,10 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   a.eps = eps;
   rc = zero_sync(w, stream);
   if (rc) return rc;
+  if (O->O_lo != nullptr) {
+    if (pl.ke->sv2 == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: no two-plane kernel for this configuration");
+    return launch_coop(pl.ke->sv2, pl.pg.G, &a, stream, pl.ke->nt, 0);
+  }
   return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
@@ -522,6 +530,8 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const
   if (rc) return rc;
   if (D->n_s != O->n_s || D->n_p != O->n_p || D->dtype != O->dtype)
     return fail(SR_ERR_INVALID, "lm_hv_product: O and D must have the same n_s, n_p and dtype");
+  if (O->O_lo != nullptr || D->O_lo != nullptr)
+    return fail(SR_ERR_INVALID, "lm_hv_product: a second code plane is not supported");
   if (E == nullptr || v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "lm_hv_product: null E, v or y");
   if (ranges_overlap(v, (O->n_p + 1) * 8, y, (O->n_p + 1) * 8))
     return fail(SR_ERR_INVALID, "lm_hv_product: v and y overlap");
@@ -646,14 +656,17 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   return status;
 }
 
-int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, void *q, int64_t ld_out,
-                int32_t out_dtype, float *scale, hipStream_t stream) {
+int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, void *q, void *q_lo,
+                int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream) {
   if (n_s < 1 || n_p < 1) return fail(SR_ERR_INVALID, "sr_quantize: n_s and n_p must be >= 1");
   if (in_dtype != SR_F64 && in_dtype != SR_F32) return fail(SR_ERR_INVALID, "sr_quantize: in_dtype must be f64 or f32");
   if (out_dtype != SR_BF16 && out_dtype != SR_F16) return fail(SR_ERR_INVALID, "sr_quantize: out_dtype must be bf16 or f16");
   if (in == nullptr || q == nullptr || scale == nullptr) return fail(SR_ERR_INVALID, "sr_quantize: null pointer");
   if (ld_in < n_p || ld_out < n_p) return fail(SR_ERR_INVALID, "sr_quantize: ld < n_p");
-  if (((uintptr_t)in) % 16 || ((uintptr_t)q) % 16) return fail(SR_ERR_INVALID, "sr_quantize: pointers must be 16-byte aligned");
+  if (((uintptr_t)in) % 16 || ((uintptr_t)q) % 16 || ((uintptr_t)q_lo) % 16)
+    return fail(SR_ERR_INVALID, "sr_quantize: pointers must be 16-byte aligned");
+  if (q_lo != nullptr && (ranges_overlap(q, n_s * ld_out * 2, q_lo, n_s * ld_out * 2)))
+    return fail(SR_ERR_INVALID, "sr_quantize: q and q_lo overlap");
   if ((ld_in * elem_bytes(in_dtype)) % 16 || (ld_out * 2) % 16)
     return fail(SR_ERR_INVALID, "sr_quantize: ld * element size must be a multiple of 16 bytes");
   int dev;
@@ -678,6 +691,7 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
   a.in = (const unsigned char *)in;
   a.ldb_in = ld_in * elem_bytes(in_dtype);
   a.out = (unsigned char *)q;
+  a.out_lo = (unsigned char *)q_lo;
   a.ld_out = ld_out;
   a.scale = scale;
   rc = zero_sync(w, stream);

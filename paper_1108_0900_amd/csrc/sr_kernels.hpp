@@ -31,17 +31,21 @@ __device__ __forceinline__ bool grid_allreduce2(double a, double b, double *red,
   return true;
 }
 
-__device__ __forceinline__ double load_decoded(const unsigned char *rowp, int64_t col, int dt, const float *scale) {
+__device__ __forceinline__ double code_value(const unsigned char *rowp, int64_t col, int dt) {
+  if (dt == DT_BF16) return (double)__uint_as_float((uint32_t)((const uint16_t *)rowp)[col] << 16);
+  return (double)(float)__builtin_bit_cast(_Float16, ((const uint16_t *)rowp)[col]);
+}
+
+// Stored value of element `col` of a row (both code planes when `lorow` is given).
+__device__ __forceinline__ double load_decoded(const unsigned char *rowp, const unsigned char *lorow, int64_t col,
+                                               int dt, const float *scale) {
   switch (dt) {
     case DT_F64: return ((const double *)rowp)[col];
     case DT_F32: return (double)((const float *)rowp)[col];
-    case DT_BF16: {
-      const uint32_t h = ((const uint16_t *)rowp)[col];
-      return (double)__uint_as_float(h << 16) * (double)scale[col];
-    }
     default: {
-      const uint16_t h = ((const uint16_t *)rowp)[col];
-      return (double)(float)__builtin_bit_cast(_Float16, h) * (double)scale[col];
+      double q = code_value(rowp, col, dt);
+      if (lorow != nullptr) q += code_value(lorow, col, dt);
+      return q * (double)scale[col];
     }
   }
 }
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       K[i][e] = 0.0;
-      if (colv[i] >= 0 && col + e < a.pg.n_p) K[i][e] = load_decoded(O, col + e, DT, a.op.scale);
+      if (colv[i] >= 0 && col + e < a.pg.n_p) K[i][e] = load_decoded(O, a.op.lo, col + e, DT, a.op.scale);
       sA[i][e] = sB[i][e] = sC[i][e] = 0.0;
     }
   }
@@ -99,8 +103,9 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
       sc[i][e] = (a.op.scale != nullptr && colv[i] >= 0 && col < a.pg.n_p) ? (double)a.op.scale[col] : 1.0;
     }
   const int64_t n_tiles = (a.pg.n_s + RT - 1) / RT;
+  const unsigned char *LO = a.op.lo;
   for (int64_t t = ctx.rg; t < n_tiles; t += a.pg.RG) {
-    u32x4 buf[RT][NV];
+    u32x4 buf[RT][NV], bufl[RT][NV];
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const int64_t row = t * RT + r;
@@ -108,6 +113,9 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
       for (int i = 0; i < NV; ++i) {
         if (row < a.pg.n_s && colv[i] >= 0) buf[r][i] = load_stream(O + row * a.op.ldb + colv[i] * St::BYTES);
         else buf[r][i] = u32x4{0u, 0u, 0u, 0u};
+        if (LO != nullptr && row < a.pg.n_s && colv[i] >= 0)
+          bufl[r][i] = load_stream(LO + row * a.op.ldb + colv[i] * St::BYTES);
+        else bufl[r][i] = u32x4{0u, 0u, 0u, 0u};
       }
     }
 #pragma unroll
@@ -119,7 +127,8 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
       for (int i = 0; i < NV; ++i)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const double x = (double)St::get(buf[r][i], e) * sc[i][e] - K[i][e];
+          const double q = (double)St::get(buf[r][i], e) + (double)St::get(bufl[r][i], e);
+          const double x = q * sc[i][e] - K[i][e];
           sA[i][e] += x;
           sB[i][e] = fma(x, x, sB[i][e]);
           sC[i][e] = fma(e_k, x, sC[i][e]);
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
       B += ld_coh(&base[a.pg.n_p + j]);
       Cg += ld_coh(&base[2 * a.pg.n_p + j]);
     }
-    const double Kj = load_decoded(O, j, DT, a.op.scale);
+    const double Kj = load_decoded(O, a.op.lo, j, DT, a.op.scale);
     const double dmean = A * inv_n;
     if (a.mean_out) a.mean_out[j] = Kj + dmean;
     if (a.diag_out) {
@@ -219,24 +228,32 @@ __global__ __launch_bounds__(kNT) void k_quantize(QuantArgs a) {
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t row = idx / nvec_row, c0 = (idx % nvec_row) * 8;
     const unsigned char *rin = a.in + row * a.ldb_in;
-    uint32_t w[4];
+    uint32_t w[4], wl[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-      uint32_t pair = 0;
+      uint32_t pair = 0, lpair = 0;
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int64_t col = c0 + 2 * h + e;
-        uint16_t code = 0;
+        uint16_t code = 0, lcode = 0;
         if (col < a.pg.n_p) {
           const double x = (IN_DT == DT_F64) ? ((const double *)rin)[col] : (double)((const float *)rin)[col];
           const double t = x / (double)a.scale[col];
           code = (OUT_DT == DT_BF16) ? rne_bf16(t) : rne_f16(t);
+          if (a.out_lo != nullptr) {
+            const double hv = (OUT_DT == DT_BF16) ? (double)__uint_as_float((uint32_t)code << 16)
+                                                  : (double)(float)__builtin_bit_cast(_Float16, code);
+            lcode = (OUT_DT == DT_BF16) ? rne_bf16(t - hv) : rne_f16(t - hv);
+          }
         }
         pair |= (uint32_t)code << (16 * e);
+        lpair |= (uint32_t)lcode << (16 * e);
       }
       w[h] = pair;
+      wl[h] = lpair;
     }
     *(u32x4 *)(a.out + row * a.ld_out * 2 + c0 * 2) = u32x4{w[0], w[1], w[2], w[3]};
+    if (a.out_lo != nullptr) *(u32x4 *)(a.out_lo + row * a.ld_out * 2 + c0 * 2) = u32x4{wl[0], wl[1], wl[2], wl[3]};
   }
 }
 
@@ -262,6 +279,28 @@ __global__ __launch_bounds__(NT) void k_sv(SvArgs a) {
     const double acc = finish_column(a.pb, a.pg, j);
     const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
     a.y[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
+  }
+}
+
+// (S + eps I) v for two code planes (stored value s_j (q + lo)), float64 accumulation.
+template <int DT, int NV, int NT>
+__global__ __launch_bounds__(NT) void k_sv2(SvArgs a) {
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  Product<DT, NV, 1, 1, true, 1, 2, NT, 2> P;
+  const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, a.v);
+  if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return;
+  P.store_partials(a.pg, a.pb, ctx);
+  if (!grid_sync(ctx.gs)) return;
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
+  const int G = (int)gridDim.x;
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
+    const double acc = finish_column(a.pb, a.pg, j);
+    a.y[j] = ((double)a.op.scale[j] * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
   }
 }
 
@@ -304,12 +343,12 @@ template <int DT, int NV, int R, int L, int P_, int NT>
 struct CgKernel {
   // q[j] = ((S + eps I) vin)_j for this workgroup's vector chunk [j0, j1).  EXACT selects
   // float64 accumulation (residual products of scaled storage).
-  template <bool EXACT>
+  template <bool EXACT, int PLANES = 1>
   __device__ __forceinline__ static bool apply(const CgArgs &a, WgCtx &ctx, const double *vin, double *q,
                                                int64_t j0, int64_t j1, int &products) {
     // the float64-accumulated residual product uses one-row tiles, one tile of lookahead
     // and the shortest poll advance (same column geometry, fewer registers)
-    Product<DT, NV, (EXACT ? 1 : R), 1, EXACT, (EXACT ? 1 : L), 2, NT> P;
+    Product<DT, NV, (EXACT ? 1 : R), 1, EXACT, (EXACT ? 1 : L), (EXACT ? 2 : P_), NT, PLANES> P;
     const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, vin);
     if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return false;
     P.store_partials(a.pg, a.pb, ctx);
@@ -393,7 +432,9 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   while (ok && mode != MODE_DONE) {
     const bool on_p = (mode == MODE_P);
     if constexpr (K::kExactResidual) {
+      // search directions: first code plane only; residuals: every plane, float64
       if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
+      else if (a.op.lo != nullptr) ok = K::template apply<true, 2>(a, ctx, a.x, a.q, j0, j1, products);
       else ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);
     } else {
       ok = K::template apply<false>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);

@@ -62,6 +62,7 @@ struct QuantArgs {
   const unsigned char *in;
   int64_t ldb_in;       // bytes
   unsigned char *out;
+  unsigned char *out_lo;  // second code plane or nullptr
   int64_t ld_out;       // elements (16-bit codes)
   float *scale;
 };
@@ -81,6 +82,7 @@ struct KernelEntry {
   int dt, nv, r, look, poll, nt;
   int kind;              // 0: SR (sv + cg), 1: LM
   const void *sv, *cg, *lm;
+  const void *sv2;       // two-code-plane product (scaled storage), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 

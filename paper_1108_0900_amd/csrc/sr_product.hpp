@@ -87,6 +87,7 @@ __device__ __forceinline__ void init_ctx(WgCtx &ctx, const ProdGeom &pg, uint32_
 // One matrix operand of the product.
 struct Operand {
   const unsigned char *O;           // base pointer
+  const unsigned char *lo;          // second code plane (same layout) or nullptr
   int64_t ldb;                      // row stride in bytes
   const float *scale;               // per-column scale (scaled storage) or nullptr
 };
@@ -104,8 +105,12 @@ template <int DT> struct AccOf<DT, true> { typedef double type; };
 //   LOOK  tiles whose loads are in flight ahead of the one being consumed
 //   ADV   the exchange of tile t is loaded at the start of step t + ADV (>= 2)
 //   NT    threads per workgroup
-template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int ADV = 2, int NT = 256>
+//   PLANES 2: the operand is s_j (q + lo) read from two code planes (NDOT = 1 only)
+template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int ADV = 2, int NT = 256,
+          int PLANES = 1>
 struct Product {
+  static_assert(PLANES == 1 || NDOT == 1, "two code planes only for the SR product");
+  static constexpr int NOPS = NDOT + PLANES - 1;   // loaded tiles per row (operands, planes)
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int kLook = LOOK;
   static constexpr int kAdv = ADV;
@@ -131,7 +136,7 @@ struct Product {
   int n_p;                          // total columns (for the mask of a vector straddling n_p)
   acc_t vc[NDOT][NV][VEC];          // v_j * s_j per operand (0 outside the slice)
   acc_t yacc[NV][VEC];              // partial (O^T w)_j
-  u32x4 buf[kNBuf][NDOT][R][NV];    // register ring of row tiles
+  u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
   // --- exchange state (wave 0) ---
@@ -209,12 +214,14 @@ struct Product {
   __device__ __forceinline__ void issue(const WgCtx &ctx, const ProdGeom &pg, const Operand *ops, int j) {
     const int64_t row0 = ((int64_t)j * pg.RG + ctx.rg) * R;
 #pragma unroll
-    for (int d = 0; d < NDOT; ++d)
+    for (int d = 0; d < NOPS; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int64_t row = row0 + r;
         row = row < pg.n_s ? row : pg.n_s - 1;
-        const unsigned char *rowp = ops[d].O + row * ops[d].ldb;
+        const Operand &op = ops[PLANES == 2 ? 0 : d];
+        const unsigned char *base = (PLANES == 2 && d == 1) ? op.lo : op.O;
+        const unsigned char *rowp = base + row * op.ldb;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const int64_t col = i < nvec ? colv(i) : 0;
@@ -234,7 +241,7 @@ struct Product {
         nv = nv < 0 ? 0 : (nv > VEC ? VEC : nv);
         const u32x4 m = elem_mask(nv);
 #pragma unroll
-        for (int d = 0; d < NDOT; ++d)
+        for (int d = 0; d < NOPS; ++d)
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[B][d][r][i] &= m;
       }
@@ -247,8 +254,15 @@ struct Product {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const u32x4 x = buf[B][d][r][i];
+          if (PLANES == 2) {
+            const u32x4 xl = buf[B][1][r][i];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) acc += (acc_t)St::get(x, e) * vc[d][i][e];
+            for (int e = 0; e < VEC; ++e)
+              acc += ((acc_t)St::get(x, e) + (acc_t)St::get(xl, e)) * vc[d][i][e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc += (acc_t)St::get(x, e) * vc[d][i][e];
+          }
         }
         part[d][r] = acc;
       }
@@ -410,8 +424,14 @@ struct Product {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const u32x4 x = buf[B][0][r][i];
+        if (PLANES == 2) {
+          const u32x4 xl = buf[B][NOPS - 1][r][i];
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) yacc[i][e] += (acc_t)St::get(x, e) * w[r];
+          for (int e = 0; e < VEC; ++e) yacc[i][e] += ((acc_t)St::get(x, e) + (acc_t)St::get(xl, e)) * w[r];
+        } else {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) yacc[i][e] += (acc_t)St::get(x, e) * w[r];
+        }
       }
     }
   }

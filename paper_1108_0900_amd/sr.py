@@ -30,7 +30,7 @@ _c_i64, _c_i32, _c_p, _c_d = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ct
 
 class SrMatrix(ctypes.Structure):
     _fields_ = [("n_s", _c_i64), ("n_p", _c_i64), ("ld", _c_i64), ("dtype", _c_i32), ("reserved", _c_i32),
-                ("O", _c_p), ("col_scale", _c_p), ("col_mean", _c_p)]
+                ("O", _c_p), ("O_lo", _c_p), ("col_scale", _c_p), ("col_mean", _c_p)]
 
 
 class SrCgOpts(ctypes.Structure):
@@ -49,7 +49,7 @@ PROTOTYPES = {
     "sr_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
                                    ctypes.POINTER(SrCgInfo), _c_p]),
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
-    "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
+    "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
     "sr_tile_configs": (ctypes.c_int, [_c_i32, _c_i32, ctypes.POINTER(ctypes.c_int32), _c_i32]),
     "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
@@ -106,6 +106,7 @@ class Matrix:
     n_p: int
     scale: torch.Tensor | None = None
     mean: torch.Tensor | None = None
+    lo: torch.Tensor | None = None   # second code plane, same layout as O
 
     @property
     def dtype_code(self) -> int:
@@ -126,12 +127,14 @@ class Matrix:
         m.dtype = self.dtype_code
         m.reserved = 0
         m.O = self.O.data_ptr()
+        m.O_lo = None if self.lo is None else self.lo.data_ptr()
         m.col_scale = None if self.scale is None else self.scale.data_ptr()
         m.col_mean = None if self.mean is None else self.mean.data_ptr()
         return m
 
 
-def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Tensor | None = None) -> Matrix:
+def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Tensor | None = None,
+              lo: torch.Tensor | None = None) -> Matrix:
     """Wrap a 2-D device tensor (float64/float32, or bfloat16/float16 codes with a float32
     column scale).  A copy with padded rows is made only when the layout rules of sr.h
     (16-byte aligned base, row stride a multiple of 16 bytes, unit column stride, rows
@@ -158,7 +161,15 @@ def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Te
         scale = scale.contiguous()
     if mean is not None:
         mean = mean.contiguous()
-    return Matrix(O=O, n_p=n_p, scale=scale, mean=mean)
+    if lo is not None:
+        if lo.shape != O.shape or lo.dtype != O.dtype:
+            raise ValueError("lo must have the shape and dtype of O")
+        if lo.stride() != O.stride() or lo.data_ptr() % 16:
+            ldo = O.stride(0) if n_s > 1 else ((n_p + vec - 1) // vec) * vec
+            L = torch.zeros(n_s, ldo, dtype=O.dtype, device=O.device)
+            L[:, :n_p] = lo
+            lo = L[:, :n_p]
+    return Matrix(O=O, n_p=n_p, scale=scale, mean=mean, lo=lo)
 
 
 def _vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
@@ -244,20 +255,24 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     return y
 
 
-def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, stream=None):
-    """bf16/f16 codes with per-column float32 scales (sr_quantize).  Returns (q, scale)
-    where q is an (n_s, ld) code tensor viewed as (n_s, n_p)."""
+def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, with_lo: bool = False, stream=None):
+    """bf16/f16 codes with per-column float32 scales (sr_quantize).  Returns (q, scale), or
+    (q, scale, lo) with the second code plane; codes are (n_s, ld) tensors viewed as
+    (n_s, n_p)."""
     if O.dtype not in (torch.float64, torch.float32) or O.dim() != 2:
         raise ValueError("O must be a 2-D float64/float32 tensor")
     Min = as_matrix(O)
     n_s, n_p = O.shape
     ld_out = ((n_p + 7) // 8) * 8
     q = torch.empty(n_s, ld_out, dtype=out_dtype, device=O.device)
+    qlo = torch.empty(n_s, ld_out, dtype=out_dtype, device=O.device) if with_lo else None
     s = torch.empty(n_p, dtype=torch.float32, device=O.device)
     ld_in = Min.ld
-    st = lib().sr_quantize(n_s, n_p, _ptr(Min.O), ld_in, Min.dtype_code, _ptr(q), ld_out, _TORCH_DT[out_dtype],
-                           _ptr(s), _stream(stream))
+    st = lib().sr_quantize(n_s, n_p, _ptr(Min.O), ld_in, Min.dtype_code, _ptr(q), _ptr(qlo), ld_out,
+                           _TORCH_DT[out_dtype], _ptr(s), _stream(stream))
     _check(st, "sr_quantize")
+    if with_lo:
+        return q[:, :n_p], s, qlo[:, :n_p]
     return q[:, :n_p], s
 
 

@@ -35,9 +35,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # sr_matrix: 3 int64 + 2 int32 + 3 pointers; sr_cg_opts: double + 4 int32 + pointer;
+    # sr_matrix: 3 int64 + 2 int32 + 4 pointers; sr_cg_opts: double + 4 int32 + pointer;
     # sr_cg_info: 4 int32 + 2 double
-    assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 3
+    assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 4
     assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8
     assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
 
@@ -50,10 +50,10 @@ def test_status_strings_and_version():
     assert L.sr_status_string(12345) == b"unknown status"
 
 
-def _mat(n_s=4, n_p=3, ld=4, dtype=sr.SR_F64, O=256, scale=None, mean=None, reserved=0):
+def _mat(n_s=4, n_p=3, ld=4, dtype=sr.SR_F64, O=256, scale=None, mean=None, reserved=0, lo=None):
     m = sr.SrMatrix()
     m.n_s, m.n_p, m.ld, m.dtype, m.reserved = n_s, n_p, ld, dtype, reserved
-    m.O, m.col_scale, m.col_mean = O, scale, mean
+    m.O, m.O_lo, m.col_scale, m.col_mean = O, lo, scale, mean
     return m
 
 
@@ -68,6 +68,8 @@ BAD = [
     ("f64 with scale", dict(scale=512)),
     ("bad dtype", dict(dtype=7)),
     ("reserved", dict(reserved=1)),
+    ("lo plane on f64", dict(lo=1024)),
+    ("misaligned lo plane", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo=1032)),
 ]
 
 
@@ -110,8 +112,12 @@ def test_invalid_scalars_rejected():
     E = ctypes.c_void_p(1 << 20)
     assert L.lm_hv_product(ctypes.byref(m), E, ctypes.byref(d), v, y, None) == sr.SR_ERR_INVALID
     # quantize
-    assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, 8, sr.SR_F32, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
-    assert L.sr_quantize(4, 3, v, 2, sr.SR_F64, y, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, None, 8, sr.SR_F32, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    assert L.sr_quantize(4, 3, v, 2, sr.SR_F64, y, None, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, y, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    # lm: a second code plane is rejected
+    mb = _mat(dtype=sr.SR_BF16, ld=8, scale=512, lo=1024)
+    assert L.lm_hv_product(ctypes.byref(mb), E, ctypes.byref(mb), v, y, None) == sr.SR_ERR_INVALID
 
 
 def test_no_device_reported_without_gpu():

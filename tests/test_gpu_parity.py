@@ -243,3 +243,65 @@ def test_abort_flag_not_set_on_normal_runs():
     for _ in range(5):
         y2 = sr.sr_sv_product(M, v, 0.1)
     assert torch.equal(y1, y2)      # deterministic reduction order
+
+
+# ------------------------------------------------------------------------------------------
+# Two code planes (quantisation remainder) for scaled storage
+# ------------------------------------------------------------------------------------------
+def _split(dtype):
+    return "bf16" if dtype == torch.bfloat16 else "f16"
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
+@pytest.mark.parametrize("shape", [(1, 3), (37, 1000), (600, 4099)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_quantize_two_planes_bit_exact(shape, dtype):
+    n_s, n_p = shape
+    O, _ = rand_dense(n_s, n_p, seed=70 + n_p)
+    q, s, lo = sr.sr_quantize(torch.from_numpy(O).to(DEV), out_dtype=dtype, with_lo=True)
+    qh, ql, so = orc.quantize_split(O, _split(dtype))
+    assert np.array_equal(to_np(s), so)
+    assert np.array_equal(q.contiguous().view(torch.int16).cpu().numpy().view(np.uint16), qh)
+    assert np.array_equal(lo.contiguous().view(torch.int16).cpu().numpy().view(np.uint16), ql)
+
+
+def _two_plane_matrix(O, dtype, with_mean=None):
+    q, s, lo = sr.sr_quantize(torch.from_numpy(O).to(DEV), out_dtype=dtype, with_lo=True)
+    return sr.as_matrix(q, scale=s, lo=lo, mean=with_mean)
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
+@pytest.mark.parametrize("shape", [(5, 7), (300, 2049), (129, 40000)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_two_plane_product_and_grad_match_oracle(shape, dtype):
+    n_s, n_p = shape
+    O, E = rand_dense(n_s, n_p, seed=80 + n_p, offset=0.5)
+    Os = orc.dequantize_split(*orc.quantize_split(O, _split(dtype)), _split(dtype))
+    M = _two_plane_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    np.testing.assert_allclose(to_np(st["mean"]), orc.sample_mean(Os), rtol=1e-12, atol=1e-12 * np.abs(Os).max())
+    gref = orc.energy_gradient(Os, E)
+    gmag = 2 * np.abs(orc.centred(Os)).T @ np.abs(E - E.mean()) / n_s
+    assert np.all(np.abs(to_np(st["g"]) - gref) <= 1e-12 * gmag + 1e-300)
+    M.mean = st["mean"]
+    v = np.random.default_rng(3).standard_normal(n_p)
+    y = to_np(sr.sr_sv_product(M, to_dev(v), 0.02))
+    ref = orc.sv_product_dense(Os, v, 0.02)
+    # float64 accumulation of the two-plane values
+    assert np.all(np.abs(y - ref) <= 1e-12 * magnitude_ref(Os, v, 0.02) + 1e-300)
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
+def test_cg_two_planes_reaches_float64_accuracy(dtype):
+    """Refinement: float32 single-plane search directions, float64 two-plane residuals."""
+    n_s, n_p = 2000, 1500
+    O, E = rand_dense(n_s, n_p, seed=31)
+    Os = orc.dequantize_split(*orc.quantize_split(O, _split(dtype)), _split(dtype))
+    M = _two_plane_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-10, refresh_every=20)
+    assert info["status"] == 0, info
+    x_split = orc.solve_dense(Os, orc.energy_gradient(Os, E), 1e-3 * orc.diag_overlap(Os).mean())
+    x_orig = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-3 * orc.diag_overlap(O).mean())
+    assert rel_err(to_np(x), x_split) <= 1e-8, rel_err(to_np(x), x_split)
+    assert rel_err(to_np(x), x_orig) <= 1e-4, rel_err(to_np(x), x_orig)

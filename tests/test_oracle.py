@@ -413,6 +413,26 @@ def test_quantize_f16_nearest_even_exact():
     assert np.array_equal(q2, ref.view(torch.int16).numpy().view(np.uint16))
 
 
+def test_quantize_split_two_planes():
+    """hi + lo planes: the lo code is the nearest code of the remainder, so the stored value
+    is within half a lo-ulp of O (about 2^-18 of the column scale for bf16, 2^-22 for f16)."""
+    rng = np.random.default_rng(23)
+    O = rng.standard_normal((40, 6)) * np.exp(rng.standard_normal(6))
+    O[:, 2] = 0.0
+    for code, nearest, bound in (("bf16", _nearest_bf16_fraction, 2.0 ** -17), ("f16", _nearest_f16_fraction, 2.0 ** -21)):
+        hi, lo, s = orc.quantize_split(O, code)
+        ref_hi, ref_s = (orc.quantize_bf16 if code == "bf16" else orc.quantize_f16)(O)
+        assert np.array_equal(hi, ref_hi) and np.array_equal(s, ref_s)
+        deq = orc.dequantize_split(hi, lo, s, code)
+        assert np.all(np.abs(deq - O) <= bound * s.astype(np.float64)[None, :])
+        # lo is the nearest code of the exact remainder (brute force on a few entries)
+        deq_hi = (orc.dequantize_bf16(hi, s) if code == "bf16" else orc.dequantize_f16(hi, s))
+        for (k, j) in [(0, 0), (5, 1), (17, 3), (39, 5)]:
+            rem = O[k, j] / float(s[j]) - deq_hi[k, j] / float(s[j])
+            assert (deq[k, j] - deq_hi[k, j]) / float(s[j]) == nearest(rem)
+        assert np.all(lo[:, 2] == 0)
+
+
 # ------------------------------------------------------------------------------------------
 # Adjoint derivatives
 # ------------------------------------------------------------------------------------------
