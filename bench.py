@@ -39,14 +39,14 @@ def elem_bytes(dt):
     return {torch.float64: 8, torch.float32: 4, torch.bfloat16: 2, torch.float16: 2}[dt]
 
 
-def product_bytes(n_s, n_p, dt, scaled):
-    """Algorithmic bytes of one product: one read of O plus the O(N_p) vectors (scale,
-    column mean, v, y)."""
-    return n_s * n_p * elem_bytes(dt) + n_p * ((4 if scaled else 0) + 3 * 8)
+def product_bytes(n_s, n_p, dt, scaled, planes=1):
+    """Algorithmic bytes of one product: one read of each code plane of O plus the O(N_p)
+    vectors (scale, column mean, v, y)."""
+    return planes * n_s * n_p * elem_bytes(dt) + n_p * ((4 if scaled else 0) + 3 * 8)
 
 
-def grad_bytes(n_s, n_p, dt, scaled):
-    return n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
+def grad_bytes(n_s, n_p, dt, scaled, planes=1):
+    return planes * n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
 
 
 def make_workload(name, device):
@@ -107,6 +107,11 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--rtol", type=float, default=None, help="CG tolerance of the timed bf16 solve")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison solve")
+    ap.add_argument("--one-plane", action="store_true",
+                    help="time the single-plane bf16 solve (no quantisation-remainder plane)")
+    ap.add_argument("--refine", action="store_true",
+                    help="search-direction products read the first plane only (iterative refinement)")
+    ap.add_argument("--refresh-drop", type=float, default=None)
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
@@ -127,63 +132,93 @@ def main():
 
     # ---- storage forms ----
     scaled = args.config == "c3"
+    planes, search_planes = 1, 1
     if scaled:
-        q, s = sr.sr_quantize(O64, out_dtype=torch.bfloat16)
+        q, s, lo = sr.sr_quantize(O64, out_dtype=torch.bfloat16, with_lo=True)
         torch.cuda.synchronize()
-        Mt = sr.as_matrix(q, scale=s)
+        M1 = sr.as_matrix(q, scale=s)                 # first code plane only
+        M2 = sr.as_matrix(q, scale=s, lo=lo)          # both planes (quantisation remainder)
+        Mt = M1 if args.one_plane else M2
+        planes = 1 if args.one_plane else 2
+        search_planes = 1 if (args.one_plane or args.refine) else 2
         dt_t, dtype_name = torch.bfloat16, "bf16"
-        rtol = args.rtol if args.rtol is not None else 1e-6
+        default_rtol = 1e-7 if args.refine else 1e-6
+        rtol = args.rtol if args.rtol is not None else default_rtol
     else:
         Mt = sr.as_matrix(O64)
         dt_t, dtype_name = O64.dtype, {torch.float64: "f64", torch.float32: "f32"}[O64.dtype]
         rtol = args.rtol if args.rtol is not None else cfg.rtol
     M64 = sr.as_matrix(O64)
+    drop = args.refresh_drop if args.refresh_drop is not None else (0.1 if args.refine else 0.0)
+    m_refresh = 0 if (args.refine and args.refresh_drop is None) else refresh
 
-    def step(M, tol):
+    def step(M, tol, refine=False):
         st = sr.sr_grad(M, E)
         M.mean = st["mean"]
         eps = 1e-3 * float(st["diag"].mean()) if cfg.eps_abs is None else cfg.eps_abs
-        (x, info), ms_cg = timed_events(lambda: sr.sr_cg_solve(M, st["g"], eps, rtol=tol, refresh_every=refresh))
+        kw = dict(refine=True, refresh_drop=drop, refresh_every=m_refresh) if refine else dict(refresh_every=refresh)
+        (x, info), ms_cg = timed_events(lambda: sr.sr_cg_solve(M, st["g"], eps, rtol=tol, **kw))
         if info["status"] != 0:
             raise RuntimeError(f"CG did not converge: {info}")
         return x, info, ms_cg, eps
 
-    # ---- float64 comparison solve (not timed as a step) ----
+    def solve_summary(info, ms, tol, planes_s, planes_r, dt):
+        it = info["iters"]
+        by = it * product_bytes(n_s, n_p, dt, dt in (torch.bfloat16, torch.float16), planes_s) + \
+            (info["products"] - it) * product_bytes(n_s, n_p, dt, dt in (torch.bfloat16, torch.float16), planes_r)
+        return {"solve_ms": round(ms, 3), "iters": it, "products": info["products"],
+                "rel_res_true": info["rel_res_true"], "rtol": tol, "GBps": round(by / ms / 1e6, 1)}
+
+    # ---- float64 solves of the same matrix (reference solution and time-to-accuracy) ----
     f64 = None
     x64 = None
     if scaled and not args.no_f64:
-        log("[bench] float64 comparison solve")
+        log("[bench] float64 solves")
         step(M64, 1e-10)      # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x64, info64, ms64, eps64 = step(M64, 1e-10)
-        torch.cuda.synchronize()
-        f64_step_ms = (time.perf_counter() - t0) * 1e3
-        f64 = {"solve_ms": round(ms64, 3), "step_ms": round(f64_step_ms, 3), "iters": info64["iters"],
-               "products": info64["products"], "rel_res_true": info64["rel_res_true"], "rtol": 1e-10,
-               "GBps": round(info64["products"] * product_bytes(n_s, n_p, torch.float64, False) / ms64 / 1e6, 1)}
+        x64, info64, ms64, _ = step(M64, 1e-10)
+        xr, infor, msr, _ = step(M64, rtol)
+        f64 = {"reference": solve_summary(info64, ms64, 1e-10, 1, 1, torch.float64),
+               "same_rtol": solve_summary(infor, msr, rtol, 1, 1, torch.float64)}
+        f64["same_rtol"]["err_vs_reference"] = float(torch.linalg.vector_norm(xr - x64) /
+                                                     torch.linalg.vector_norm(x64))
+        del xr
         log(f"[bench] f64: {f64}")
+
+    # ---- single-plane bf16 solve, for its error against float64 (not timed as a step) ----
+    err_one_plane = None
+    if scaled and planes == 2 and x64 is not None:
+        x1, info1, _, _ = step(M1, rtol)
+        err_one_plane = float(torch.linalg.vector_norm(x1 - x64) / torch.linalg.vector_norm(x64))
+        log(f"[bench] one-plane bf16 solve: {info1}, err vs f64 {err_one_plane:.3e}")
+        del x1
 
     # ---- timed steps ----
     log(f"[bench] warmup {args.warmup} step(s)")
     for _ in range(args.warmup):
-        step(Mt, rtol)
+        step(Mt, rtol, args.refine)
     torch.cuda.synchronize()
     cg_ms, infos = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x, info, ms_cg, eps = step(Mt, rtol)
+        x, info, ms_cg, eps = step(Mt, rtol, args.refine)
         cg_ms.append(ms_cg)
         infos.append(info)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     ms_per_step = wall_ms / args.steps
     products = sum(i["products"] for i in infos) / len(infos)
-    pb = product_bytes(n_s, n_p, dt_t, scaled)
-    step_bytes = grad_bytes(n_s, n_p, dt_t, scaled) + products * pb
+    # search-direction products read search_planes code planes; residual products
+    # (refreshes, exit checks) read every plane.  A converged solve makes one search
+    # product per iteration.
+    searches = sum(i["iters"] for i in infos) / len(infos)
+    residuals = products - searches
+    pb = product_bytes(n_s, n_p, dt_t, scaled, search_planes)
+    pb_res = product_bytes(n_s, n_p, dt_t, scaled, planes)
+    cg_bytes = searches * pb + residuals * pb_res
+    step_bytes = grad_bytes(n_s, n_p, dt_t, scaled, planes) + cg_bytes
     value = step_bytes / (ms_per_step * 1e6)
     cg_avg = sum(cg_ms) / len(cg_ms)
-    achieved = products * pb / (cg_avg * 1e6)
+    achieved = cg_bytes / (cg_avg * 1e6)
     log(f"[bench] {dtype_name}: {ms_per_step:.2f} ms/step, CG {cg_avg:.2f} ms, products {products}, "
         f"{value:.0f} GB/s step, {achieved:.0f} GB/s CG")
 
@@ -199,10 +234,15 @@ def main():
         ts.sort()
         return ts[len(ts) // 2]
     sv = {}
-    ms_t = sv_time(Mt)
-    sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb / ms_t / 1e6, 1),
-                      "frac": round(pb / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
+    ms_t = sv_time(M1 if scaled else Mt)
+    pb1 = product_bytes(n_s, n_p, dt_t, scaled)
+    sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb1 / ms_t / 1e6, 1),
+                      "frac": round(pb1 / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
     if scaled:
+        ms_2 = sv_time(M2)
+        b2 = product_bytes(n_s, n_p, dt_t, scaled, 2)
+        sv["bf16_two_planes"] = {"ms": round(ms_2, 3), "GBps": round(b2 / ms_2 / 1e6, 1),
+                                 "frac": round(b2 / ms_2 / 1e6 / HBM_PEAK_GBPS, 4)}
         ms_d = sv_time(M64)
         b64 = product_bytes(n_s, n_p, torch.float64, False)
         sv["f64"] = {"ms": round(ms_d, 3), "GBps": round(b64 / ms_d / 1e6, 1),
@@ -241,13 +281,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                      "kernel": "k_cg (persistent CG; products read O once each)",
-                     "bytes_per_launch": round(products * pb), "launch_ms": round(cg_avg, 3)},
+                     "bytes_per_launch": round(cg_bytes), "launch_ms": round(cg_avg, 3)},
         "cpu_baseline": cpu,
         "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
+                  "residual_products": residuals, "planes": planes, "search_planes": search_planes,
                   "rel_res_true": infos[-1]["rel_res_true"], "rtol": rtol, "eps": eps},
         "sv_product": sv,
         "f64_solve": f64,
         "err_vs_f64": err,
+        "err_vs_f64_one_plane": err_one_plane,
     }
     print(json.dumps(out), flush=True)
 

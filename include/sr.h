@@ -84,6 +84,12 @@ typedef struct sr_cg_opts {
   int32_t restart_on_refresh;/* 1: also reset p <- r at each refresh (restarted CG);   */
                              /* 0: keep p (residual replacement)                       */
   double *res_history;       /* optional device [max_iter+1]: ||r||/||g|| per iteration */
+  double refresh_drop;       /* in [0, 1): > 0 also refreshes as soon as ||r|| has      */
+                             /* fallen below refresh_drop times its value at the last   */
+                             /* refresh (or start); 0: periodic refreshes only          */
+  int32_t refine;            /* with O_lo only: 1: search-direction products read the  */
+                             /* first code plane only (iterative refinement); 0: they  */
+                             /* read both planes (float32 accumulation)                */
 } sr_cg_opts;
 
 /* CG outcome, written to host memory. */
@@ -116,6 +122,8 @@ int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean,
  * w_k = Oc_k . v, then y = (1/n_s) sum_k w_k Oc_k + eps v.  O is read once.
  * v, y: [n_p] float64, must not overlap.  eps >= 0.  With a second code plane the
  * product is that of the two-plane values, accumulated in float64.
+ * Asynchronous: if a cross-workgroup wait of the kernel gives up (SR_ERR_TIMEOUT in the
+ * synchronous calls) y is filled with NaN.  The same holds for lm_hv_product.
  * ------------------------------------------------------------------------------------ */
 int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream);
 
@@ -130,8 +138,13 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
  * storage type, so for bf16/f16 storage the iteration converges to the solution of the
  * stored (dequantized) system although its search-direction products accumulate in
  * float32 (mixed-precision residual replacement).  With a second code plane (O_lo) the
- * stored system is the two-plane one: refreshes and the exit check read both planes,
- * search-direction products read only the first (mixed-precision iterative refinement).
+ * stored system is the two-plane one and refreshes and the exit check read both planes.
+ * Search-direction products read both planes too unless opt->refine is set; then they
+ * read only the first (mixed-precision iterative refinement): the two operators differ,
+ * so every refresh also restarts the search direction (p <- r) whatever
+ * restart_on_refresh says, and a refresh_drop of about 0.1 keeps the refinement
+ * convergent on ill-conditioned systems.  Refinement leaves error along directions where
+ * S is nearly singular that the residual hardly sees: solve to a tighter rtol with it.
  * This call synchronizes `stream` before returning (it reads the outcome back).
  * Returns SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN or an error code.
  * ------------------------------------------------------------------------------------ */
@@ -169,8 +182,9 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
 /* ------------------------------------------------------------------------------------
  * Tuning hooks (not in the paper).  The fused product is built for a few tile
  * configurations: nv 16-byte vectors per thread and row, `rows` rows per tile, `lookahead`
- * tiles of loads in flight, a `poll_delay` of steps between publishing a tile's partial
- * dots and reading the other column groups' ones, and `threads` per workgroup.
+ * tiles of loads in flight, a `poll_delay` (poll depth) of steps between issuing the
+ * reads of the other column groups' partial dots of a tile and using them, and
+ * `threads` per workgroup.
  * sr_tile_configs: writes up to `max` configurations built for `dtype` (kind 0: SR
  * products and CG, kind 1: linear-method products) as int32 quintuples
  * (nv, rows, lookahead, poll_delay, threads) to the host array `out`; returns how many

@@ -53,7 +53,7 @@ import scipy.linalg as sla
 __all__ = [
     "sample_weights", "sample_mean", "centred", "overlap_matrix", "overlap_matrix_uncentred",
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
-    "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense",
+    "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense", "lm_hv_swapped",
     "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
     "quantize_split", "dequantize_split", "solve_adjoint_gradients",
 ]
@@ -264,6 +264,26 @@ def lm_hv_dense(O, E, D, v, w=None) -> np.ndarray:
     """H v with H from `lm_matrices`, formed explicitly."""
     H, _ = lm_matrices(O, E, D, w)
     return H @ np.asarray(v, dtype=np.float64)
+
+
+def lm_hv_swapped(O, E, D, v, w=None) -> np.ndarray:
+    """H v without forming H (the interchange of sums of Eq. sr_multiply_2 applied to the
+    blocks of `lm_matrices`): per sample t_k = Oc_k . v_rest, u_k = D_k . v_rest, then
+        (H v)_0 = <E> v_0 + sum_k w_k (E_k t_k + u_k)
+        (H v)_i = sum_k w_k Oc_ki (E_k (v_0 + t_k) + u_k),  i >= 1.
+    Used where H is too large to form."""
+    O = np.asarray(O, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    w = sample_weights(O.shape[0], w)
+    Oc = centred(O, w)
+    t = Oc @ v[1:]
+    u = D @ v[1:]
+    y = np.empty(O.shape[1] + 1)
+    y[0] = (w @ E) * v[0] + w @ (E * t + u)
+    y[1:] = Oc.T @ (w * (E * (v[0] + t) + u))
+    return y
 
 
 def lm_lowest_eigenpair(H, S):

@@ -254,6 +254,7 @@ void carve_prod(Carve &cv, const Plan &pl, int64_t ypart_doubles, ProdWs *w) {
   w->zero_base = (uint32_t *)(cv.base + start);
   w->zero_words = (int64_t)((end - start + 3) / 4);
   w->sb.red = cv.take<double>(4 * 2 * pg.G);
+  w->pb.sink = cv.take<u64>((int64_t)pg.G * (pl.words > 0 ? pl.words : 1));
   w->pb.ypart = cv.take<double>(ypart_doubles);
   w->pb.spart = cv.take<double>((int64_t)pg.RG * 2);
 }
@@ -266,6 +267,7 @@ size_t prod_ws_bytes(const Plan &pl, int64_t ypart_doubles) {
   add(64 * 4);
   add((size_t)pg.RG * kRing * pg.C * (pl.words > 0 ? pl.words : 1) * 8);
   add((size_t)4 * 2 * pg.G * 8);
+  add((size_t)pg.G * (pl.words > 0 ? pl.words : 1) * 8);
   add((size_t)ypart_doubles * 8);
   add((size_t)pg.RG * 2 * 8);
   return b + 256;
@@ -586,6 +588,9 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_every must be >= 0");
   if (o.restart_on_refresh != 0 && o.restart_on_refresh != 1)
     return fail(SR_ERR_INVALID, "sr_cg_solve: restart_on_refresh must be 0 or 1");
+  if (!(o.refresh_drop >= 0.0 && o.refresh_drop < 1.0))
+    return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_drop must be in [0, 1)");
+  if (o.refine != 0 && o.refine != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: refine must be 0 or 1");
   if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: use_x0 must be 0 or 1");
   int64_t max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
   if (max_iter > (1 << 30)) max_iter = 1 << 30;
@@ -629,7 +634,11 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.max_iter = (int)max_iter;
   a.refresh_every = o.refresh_every;
   a.use_x0 = o.use_x0;
-  a.restart_on_refresh = o.restart_on_refresh;
+  // refinement over two code planes: search directions and residuals use different
+  // operators, so a refresh must restart the direction
+  a.refine = (O->O_lo != nullptr && o.refine != 0) ? 1 : 0;
+  a.restart_on_refresh = (o.restart_on_refresh != 0 || a.refine) ? 1 : 0;
+  a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
   a.hist = o.res_history;
   rc = zero_sync(w, stream);
   if (rc) return rc;

@@ -266,15 +266,21 @@ __global__ __launch_bounds__(NT) void k_sv(SvArgs a) {
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
   Product<DT, NV, R, 1, false, L, P_, NT> P;
   const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, a.v);
-  if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return;
-  P.store_partials(a.pg, a.pb, ctx);
-  if (!grid_sync(ctx.gs)) return;
-  double S1, S2;
-  sum_row_scalars(a.pb, a.pg, S1, S2);
-  const double inv_n = 1.0 / (double)a.pg.n_s;
+  bool ok = P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0);
+  if (ok) {
+    P.store_partials(a.pg, a.pb, ctx);
+    ok = grid_sync(ctx.gs);
+  }
   const int G = (int)gridDim.x;
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  if (!ok) {   // a wait gave up: the result is NaN, never stale data
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) a.y[j] = __builtin_nan("");
+    return;
+  }
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
     const double acc = finish_column(a.pb, a.pg, j);
     const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
@@ -287,17 +293,23 @@ template <int DT, int NV, int NT>
 __global__ __launch_bounds__(NT) void k_sv2(SvArgs a) {
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
-  Product<DT, NV, 1, 1, true, 1, 2, NT, 2> P;
+  Product<DT, NV, 1, 1, true, 1, 1, NT, 2> P;
   const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, a.v);
-  if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return;
-  P.store_partials(a.pg, a.pb, ctx);
-  if (!grid_sync(ctx.gs)) return;
-  double S1, S2;
-  sum_row_scalars(a.pb, a.pg, S1, S2);
-  const double inv_n = 1.0 / (double)a.pg.n_s;
+  bool ok = P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0);
+  if (ok) {
+    P.store_partials(a.pg, a.pb, ctx);
+    ok = grid_sync(ctx.gs);
+  }
   const int G = (int)gridDim.x;
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  if (!ok) {   // a wait gave up: the result is NaN, never stale data
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) a.y[j] = __builtin_nan("");
+    return;
+  }
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
     const double acc = finish_column(a.pb, a.pg, j);
     a.y[j] = ((double)a.op.scale[j] * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
@@ -314,15 +326,22 @@ __global__ __launch_bounds__(NT) void k_lm(LmArgs a) {
   Product<DT, NV, R, 2, false, L, P_, NT> P;
   const double v0 = a.v[0];
   const double cshare = P.setup(ctx, a.pg, a.ops, a.mean, a.v + 1);
-  if (!P.accumulate(a.pg, a.pb, ctx, a.ops, cshare, a.E, v0)) return;
-  P.store_partials(a.pg, a.pb, ctx);
-  if (!grid_sync(ctx.gs)) return;
-  double S1, S2;
-  sum_row_scalars(a.pb, a.pg, S1, S2);
-  const double inv_n = 1.0 / (double)a.pg.n_s;
+  bool ok = P.accumulate(a.pg, a.pb, ctx, a.ops, cshare, a.E, v0);
+  if (ok) {
+    P.store_partials(a.pg, a.pb, ctx);
+    ok = grid_sync(ctx.gs);
+  }
   const int G = (int)gridDim.x;
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  if (!ok) {   // a wait gave up: the result is NaN, never stale data
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) a.y[1 + j] = __builtin_nan("");
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.y[0] = __builtin_nan("");
+    return;
+  }
+  double S1, S2;
+  sum_row_scalars(a.pb, a.pg, S1, S2);
+  const double inv_n = 1.0 / (double)a.pg.n_s;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
     const double acc = finish_column(a.pb, a.pg, j);
     const double s = a.ops[0].scale ? (double)a.ops[0].scale[j] : 1.0;
@@ -346,9 +365,10 @@ struct CgKernel {
   template <bool EXACT, int PLANES = 1>
   __device__ __forceinline__ static bool apply(const CgArgs &a, WgCtx &ctx, const double *vin, double *q,
                                                int64_t j0, int64_t j1, int &products) {
-    // the float64-accumulated residual product uses one-row tiles, one tile of lookahead
-    // and the shortest poll advance (same column geometry, fewer registers)
-    Product<DT, NV, (EXACT ? 1 : R), 1, EXACT, (EXACT ? 1 : L), (EXACT ? 2 : P_), NT, PLANES> P;
+    // the float64-accumulated and the two-plane products use one-row tiles, one tile of
+    // lookahead and the shortest poll depth (same column geometry, fewer registers)
+    constexpr bool kSmall = EXACT || PLANES == 2;
+    Product<DT, NV, (kSmall ? 1 : R), 1, EXACT, (kSmall ? 1 : L), (kSmall ? 1 : P_), NT, PLANES> P;
     const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, vin);
     if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return false;
     P.store_partials(a.pg, a.pb, ctx);
@@ -374,7 +394,8 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   // Conjugate gradient (Hestenes-Stiefel) as a state machine with one product per pass
   // through the loop, so the product code is instantiated once per accumulation type.
   //   MODE_P        q = A p, then alpha, x += alpha p, r -= alpha q
-  //   MODE_REFRESH  q = A x, r = g - q (every refresh_every iterations)
+  //   MODE_REFRESH  q = A x, r = g - q (every refresh_every iterations, or once the
+  //                 recurrence residual fell by refresh_drop since the last refresh)
   //   MODE_CONFIRM  q = A x when the recurrence residual meets rtol; accept or replace r
   //   MODE_FINAL    q = A x to report the true residual of an unconverged exit
   //   MODE_X0       q = A x0 for a warm start
@@ -389,6 +410,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   int nred = 0, products = 0, refreshes = 0, it = 0;
   int status = 0;       // SR_OK
   double rel_true = -1.0, rho = 0.0, gg = 1.0, dummy = 0.0;
+  double rho_ref = 0.0;  // rho at the start or the last refresh (drop-triggered refreshes)
   bool ok = true, restart = false;
   int mode;
 
@@ -420,6 +442,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       pgg += gj * gj;
     }
     ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg);
+    rho_ref = rho;
     if (gg == 0.0) {
       gg = 1.0;
       rel_true = 0.0;
@@ -432,8 +455,10 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   while (ok && mode != MODE_DONE) {
     const bool on_p = (mode == MODE_P);
     if constexpr (K::kExactResidual) {
-      // search directions: first code plane only; residuals: every plane, float64
-      if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
+      // residuals: every plane, float64 accumulation; search directions: float32
+      // accumulation over every plane, or the first plane only under refinement
+      if (on_p && a.op.lo != nullptr && !a.refine) ok = K::template apply<false, 2>(a, ctx, a.p, a.q, j0, j1, products);
+      else if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
       else if (a.op.lo != nullptr) ok = K::template apply<true, 2>(a, ctx, a.x, a.q, j0, j1, products);
       else ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);
     } else {
@@ -462,6 +487,12 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       }
       double rho_new;
       if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
+      if (rho_new <= a.refresh_drop2 * rho_ref && sqrt(rho_new / gg) > a.rtol) {
+        // the recurrence residual fell by the requested factor: refresh now (x is
+        // visible to every workgroup after the reduction's grid barrier)
+        mode = MODE_REFRESH;
+        continue;
+      }
       const double beta = rho_new / rho;
       rho = rho_new;
       if (!(ok = update_p(beta))) break;
@@ -477,6 +508,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
       const double beta = a.restart_on_refresh ? 0.0 : rho_new / rho;
       rho = rho_new;
+      rho_ref = rho_new;
       if (!(ok = update_p(beta))) break;
       mode = decide();
     } else if (mode == MODE_X0) {
@@ -489,6 +521,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
         pgg += gj * gj;
       }
       if (!(ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg))) break;
+      rho_ref = rho;
       if (gg == 0.0) {
         for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.x[j], 0.0);
         gg = 1.0;
@@ -515,8 +548,10 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       } else {
         // the recurrence residual drifted from the true one: continue from the true one
         rho = tr;
+        rho_ref = tr;
         refreshes++;
         rel_true = -1.0;
+        if (a.restart_on_refresh && !(ok = update_p(0.0))) break;
         mode = MODE_P;
       }
     }

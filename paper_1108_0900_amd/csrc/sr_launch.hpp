@@ -42,6 +42,8 @@ struct CgArgs {
   double *x, *r, *p, *q;
   double eps, rtol;
   int max_iter, refresh_every, use_x0, restart_on_refresh;
+  double refresh_drop2;       // squared relative drop that triggers a refresh; 0: off
+  int refine;                 // two planes: search products read the first plane only
   double *hist;         // [max_iter + 1] or nullptr
   double *info;         // [8]
 };
@@ -72,11 +74,13 @@ struct QuantArgs {
 // streams two matrices and so uses half the tile).
 // X(NV, R, LOOKAHEAD, POLL_ADVANCE, THREADS) per storage type; the first SR entry is the
 // default (chosen by the tile sweep on MI355X), the others are selectable for tuning.
-#define SR_SR_CONFIGS_F64(X) X(4, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(2, 1, 2, 2, 512) X(4, 2, 2, 2, 256)
-#define SR_SR_CONFIGS_F32(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
-#define SR_SR_CONFIGS_BF16(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
-#define SR_SR_CONFIGS_F16(X) X(2, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 2, 2, 2, 256)
-#define SR_LM_CONFIGS(X) X(2, 1, 2, 2, 512) X(4, 1, 2, 2, 256)
+#define SR_SR_CONFIGS_F64(X) X(4, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 2, 2, 1, 256) \
+  X(4, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 1, 1, 3, 512)
+#define SR_SR_CONFIGS_F32(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 3, 512)
+#define SR_SR_CONFIGS_BF16(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 2, 512) \
+  X(2, 1, 2, 3, 512) X(2, 1, 2, 5, 512)
+#define SR_SR_CONFIGS_F16(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 3, 512)
+#define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)
 
 struct KernelEntry {
   int dt, nv, r, look, poll, nt;

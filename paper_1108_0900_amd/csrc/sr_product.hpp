@@ -28,6 +28,7 @@
 //   * Row-group partial y vectors (float64) go to a workspace; a grid barrier later lets
 //     any workgroup finish a column range with a fixed-order sum over row groups.
 #pragma once
+#include <utility>
 #include "sr_device.hpp"
 
 namespace sr {
@@ -45,6 +46,7 @@ struct ProdBufs {
   double *ypart;                    // [RG][n_p]   row-group partial O^T w
   double *spart;                    // [RG][2]     row-group scalars
   u64 *xchg;                        // [RG][kRing][C][words]
+  u64 *sink;                        // [G][words]  target of the tail steps' publishes
 };
 
 struct WgCtx {
@@ -103,25 +105,32 @@ template <int DT> struct AccOf<DT, true> { typedef double type; };
 //   NV    16-byte vectors per thread and row (slice width NV*VEC*NT columns)
 //   R     rows per tile
 //   LOOK  tiles whose loads are in flight ahead of the one being consumed
-//   ADV   the exchange of tile t is loaded at the start of step t + ADV (>= 2)
+//   PD    poll depth: the other column groups' partial dots of tile t are loaded at the
+//         start of step t + 2 and used at the end of step t + 2 + PD, so PD steps of
+//         streaming cover the latency of those coherent loads
 //   NT    threads per workgroup
 //   PLANES 2: the operand is s_j (q + lo) read from two code planes (NDOT = 1 only)
-template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int ADV = 2, int NT = 256,
+template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int PD = 1, int NT = 256,
           int PLANES = 1>
 struct Product {
   static_assert(PLANES == 1 || NDOT == 1, "two code planes only for the SR product");
   static constexpr int NOPS = NDOT + PLANES - 1;   // loaded tiles per row (operands, planes)
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int kLook = LOOK;
-  static constexpr int kAdv = ADV;
-  static constexpr int kLag = ADV + 2;        // tile t is accumulated at step t + kLag
-  // register ring: a tile lives from step t-LOOK to t+kLag; even size so the two poll
-  // buffers alternate with a compile-time index
-  static constexpr int kNBuf = ((LOOK + kLag + 1) + 1) / 2 * 2;
-  static_assert(ADV >= 2, "the poll of step e must start after every group published e");
-  // A workgroup publishing step t may meet a slower member of its row group still reading
-  // step t - ADV - 2; the exchange ring must keep those slots distinct.
-  static_assert(kRing > ADV + 3, "exchange ring too small for the poll advance");  typedef Storage<DT> St;
+  static constexpr int kAdv = 2;              // the poll of tile t starts at step t + kAdv
+  static constexpr int kPD = PD;
+  static constexpr int kNPoll = PD + 1;       // poll buffers in flight
+  static constexpr int kLag = kAdv + PD + 1;  // tile t is accumulated at step t + kLag
+  // register ring: a tile lives from step t-LOOK to t+kLag; its size is a multiple of the
+  // number of poll buffers so that both rings are indexed at compile time
+  static constexpr int kNBuf = ((LOOK + kLag + 1) + kNPoll - 1) / kNPoll * kNPoll;
+  static_assert(PD >= 1, "a poll is used at the earliest one step after it was issued");
+  // A workgroup at step t has seen every member of its row group publish step
+  // t - 1 - kAdv - PD, so each member is at step >= t - kAdv - PD and may still be
+  // (re)reading step t - 2 (kAdv + PD).  Those slots must stay distinct from the one
+  // step t publishes to.
+  static_assert(kRing > 2 * (kAdv + PD), "exchange ring too small for the poll depth");
+  typedef Storage<DT> St;
   typedef typename AccOf<DT, EXACT>::type acc_t;
   static constexpr int VEC = St::VEC;
   static constexpr int WPD = sizeof(acc_t) == 8 ? 2 : 1;   // exchange words per partial dot
@@ -140,7 +149,7 @@ struct Product {
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
   // --- exchange state (wave 0) ---
-  u64 pw[2][PW];                    // words of column group `lane` for the two pending polls
+  u64 pw[kNPoll][PW];               // words of column group `lane` for the pending polls
   double cshare;
 
   __device__ __forceinline__ static u32x4 elem_mask(int nvalid) {
@@ -275,38 +284,45 @@ struct Product {
   }
 
   // Exchange wave: publish this column group's partial dots of exchange step `step`.
+  // Every lane stores (lane l writes word l mod PW, the same value as the lanes it
+  // shares the word with), so the store is issued unconditionally and the compiler's
+  // count of outstanding memory operations stays exact.
+  // Tail steps (tile >= n_my) publish to this workgroup's sink words instead: after its
+  // last poll a workgroup runs its tail steps without waiting for the others, and a
+  // publish into the ring could then overwrite a slot a slower member still reads.
   __device__ __forceinline__ void publish(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx, uint32_t step,
-                                          const double (&red)[NDOT][R]) {
-    u64 *base = slot_base(pb, pg, ctx, step) + (int64_t)ctx.cg * WORDS;
+                                          bool tail, const double (&red)[NDOT][R]) {
+    u64 *base = tail ? pb.sink + (int64_t)blockIdx.x * WORDS
+                     : slot_base(pb, pg, ctx, step) + (int64_t)ctx.cg * WORDS;
     const u64 tag = (u64)(step / kRing + 1) << 32;
-    const int lane = (int)threadIdx.x & 63;
-    if (lane < NDOT * R) {
-      const int d = lane / R, r = lane % R;
-      const double val = red[d][r];
-      if (WPD == 1) {
-        const float f = (float)val;
-        st_coh64(&base[d * R + r], tag | (u64)__float_as_uint(f));
-      } else {
-        const u64 b = (u64)__double_as_longlong(val);
-        st_coh64(&base[(d * R + r) * 2 + 0], tag | (b & 0xFFFFFFFFull));
-        st_coh64(&base[(d * R + r) * 2 + 1], tag | (b >> 32));
-      }
+    const int k = ((int)threadIdx.x & 63) % PW;     // word written by this lane
+    const int dr = k / WPD;                          // which partial dot
+    double val = red[0][0];
+#pragma unroll
+    for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+      for (int r = 0; r < R; ++r) val = (dr == d * R + r) ? red[d][r] : val;
+    u64 word;
+    if (WPD == 1) {
+      word = tag | (u64)__float_as_uint((float)val);
+    } else {
+      const u64 b = (u64)__double_as_longlong(val);
+      word = tag | ((k % 2) == 0 ? (b & 0xFFFFFFFFull) : (b >> 32));
     }
+    st_coh64(&base[k], word);
   }
 
-  // Wave 0: issue the loads of column group `lane`'s words into poll buffer Q (no wait).
+  // Exchange wave: issue the loads of column group `lane`'s words into poll buffer Q (no
+  // wait).  Issued unconditionally: lanes past C read column group 0's words and steps
+  // outside the product read a valid slot; neither result is used.
   template <int Q>
   __device__ __forceinline__ void poll_issue(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
                                              uint32_t step) {
     const int lane = (int)threadIdx.x & 63;
-    const u64 *wp = slot_base(pb, pg, ctx, step) + (int64_t)lane * WORDS;
-    if (lane < pg.C) {
+    const int c = lane < pg.C ? lane : 0;
+    const u64 *wp = slot_base(pb, pg, ctx, step) + (int64_t)c * WORDS;
 #pragma unroll
-      for (int k = 0; k < PW; ++k) pw[Q][k] = ld_coh64(&wp[k]);
-    } else {
-#pragma unroll
-      for (int k = 0; k < PW; ++k) pw[Q][k] = 0;
-    }
+    for (int k = 0; k < PW; ++k) pw[Q][k] = ld_coh64(&wp[k]);
   }
 
   __device__ __forceinline__ static bool words_ok(const u64 *w, uint32_t tag) {
@@ -404,18 +420,19 @@ struct Product {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t row = row0 + r;
-      double wr = 0.0;
-      if (row < pg.n_s) {
-        if (NDOT == 1) {
-          wr = tot[0][r];
-          s1 += wr;
-        } else {
-          const double t = tot[0][r], u = tot[1][r];
-          const double e = E[row];
-          wr = e * (v0 + t) + u;
-          s1 += wr;
-          s2 += e * t + u;
-        }
+      const bool valid = row < pg.n_s;
+      double wr;
+      if (NDOT == 1) {
+        wr = valid ? tot[0][r] : 0.0;
+        s1 += wr;
+      } else {
+        // the load is unconditional (clamped row) so that no memory operation sits in a
+        // branch; the row's weight is zero past n_s
+        const double e = E[valid ? row : pg.n_s - 1];
+        const double t = tot[0][r], u = tot[1][r];
+        wr = valid ? e * (v0 + t) + u : 0.0;
+        s1 += wr;
+        s2 += valid ? e * t + u : 0.0;
       }
       w[r] = (acc_t)wr;
     }
@@ -436,21 +453,21 @@ struct Product {
     }
   }
 
-  // One pipeline step t (register buffer B = t % kNBuf).
-  template <int B>
+  // One pipeline step t (register buffer B = t % kNBuf).  X: this is the exchange wave
+  // (wave 0 when there are several column groups); the other waves run the same steps
+  // without the exchange.  Inside a step no memory operation is conditional, so the
+  // compiler waits for exactly the loads each use needs.
+  template <int B, bool X>
   __device__ __forceinline__ void step(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t,
                                        int n_my, const double *__restrict__ E, double v0,
                                        double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
-    constexpr int QI = ((B - kAdv) % 2 + 2) % 2;       // poll buffer of exchange t - kAdv
-    constexpr int QF = ((B - kAdv - 1) % 2 + 2) % 2;   // poll buffer of exchange t - kAdv - 1
+    constexpr int QI = ((B - kAdv) % kNPoll + kNPoll) % kNPoll;        // exchange t - kAdv
+    constexpr int QF = ((B - kAdv - PD) % kNPoll + kNPoll) % kNPoll;   // exchange t - kAdv - PD
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    // wave 0: start loading the exchange words of step t - kAdv (before any tile load of
-    // this step, so waiting for them later never waits for this step's tiles)
-    if (wave == 0 && pg.C > 1) {
-      const int e = t - kAdv;
-      if (e >= 0 && e < n_my && ok) poll_issue<QI>(pb, pg, ctx, ctx.xstep + (uint32_t)e);
-    }
+    // exchange wave: start loading the words of step t - kAdv (before this step's tile
+    // loads, so waiting for them later never waits for this step's tiles)
+    if constexpr (X) poll_issue<QI>(pb, pg, ctx, ctx.xstep + (uint32_t)(t - kAdv));
     // streaming: unconditional in every step (tiles past n_my read clamped rows with zero
     // weight), so the wait for tile t leaves tiles t+1..t+kLook in flight
     issue<(B + kLook) % kNBuf>(ctx, pg, ops, t + kLook);
@@ -467,13 +484,13 @@ struct Product {
     }
     const int u = t - kLag;
     if (u >= 0 && u < n_my) update<(B + kNBuf - kLag) % kNBuf>(pg, ctx, u, s_tot[u % kNBuf], E, v0);
-    if (wave == 0 && pg.C > 1) {
-      // finish the poll started at the beginning of step t-1
-      const int e = t - kAdv - 1;
+    if constexpr (X) {
+      // finish the poll started at the beginning of step t - PD
+      const int e = t - kAdv - PD;
       if (e >= 0 && e < n_my && ok) ok = poll_finish<QF>(pb, pg, ctx, ctx.xstep + (uint32_t)e, s_tot[e % kNBuf]);
     }
     __syncthreads();
-    if (wave == 0 && t < n_my) {
+    if (wave == 0 && (X || t < n_my)) {
       double red[NDOT][R];
 #pragma unroll
       for (int d = 0; d < NDOT; ++d)
@@ -484,17 +501,45 @@ struct Product {
           for (int w = 0; w < NW; ++w) sm += s_part[t & 1][w][d][r];
           red[d][r] = (d == 0) ? sm - cshare : sm;
         }
-      if (pg.C == 1) {
+      if constexpr (X) {
+        // every step publishes (the tail steps past n_my into the sink), so the store is
+        // not conditional
+        publish(pb, pg, ctx, ctx.xstep + (uint32_t)t, t >= n_my, red);
+      } else {
         if (lane == 0) {
 #pragma unroll
           for (int d = 0; d < NDOT; ++d)
 #pragma unroll
             for (int r = 0; r < R; ++r) s_tot[t % kNBuf][d][r] = red[d][r];
         }
-      } else {
-        publish(pb, pg, ctx, ctx.xstep + (uint32_t)t, red);
       }
     }
+  }
+
+  // Steps t0 .. t0 + kNBuf - 1, one per register buffer, fully unrolled.
+  template <bool X, int... Bs>
+  __device__ __forceinline__ void round_of_steps(std::integer_sequence<int, Bs...>, const ProdGeom &pg,
+                                                 const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t0, int n_my,
+                                                 const double *__restrict__ E, double v0,
+                                                 double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
+    (step<Bs, X>(pg, pb, ctx, ops, t0 + Bs, n_my, E, v0, s_part, s_tot, ok), ...);
+  }
+
+  // The whole streaming loop of one wave (X: the exchange wave).  Both loops execute the
+  // same number of barriers.
+  template <bool X>
+  __device__ __forceinline__ bool stream_rows(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
+                                              int n_my, int rounds, const double *__restrict__ E, double v0,
+                                              double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R]) {
+    issue<0>(ctx, pg, ops, 0);
+    if (kLook > 1) issue<(1 % kNBuf)>(ctx, pg, ops, 1);
+    if (kLook > 2) issue<(2 % kNBuf)>(ctx, pg, ops, 2);
+    if (kLook > 3) issue<(3 % kNBuf)>(ctx, pg, ops, 3);
+    bool ok = true;
+    for (int q = 0; q < rounds; ++q)
+      round_of_steps<X>(std::make_integer_sequence<int, kNBuf>{}, pg, pb, ctx, ops, q * kNBuf, n_my, E, v0, s_part,
+                        s_tot, ok);
+    return ok;
   }
 
   // Accumulate this workgroup's share of O^T w over its row group's tiles.
@@ -505,28 +550,18 @@ struct Product {
     __shared__ int s_ok;
     const int n_tiles = (int)((pg.n_s + R - 1) / R);
     const int n_my = (ctx.rg < n_tiles) ? (n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
-    static_assert(kNBuf <= 8, "unrolled for at most 8 tile buffers");
     static_assert(kLook <= 4, "prologue issues at most 4 tiles");
-    issue<0>(ctx, pg, ops, 0);
-    if (kLook > 1) issue<(1 % kNBuf)>(ctx, pg, ops, 1);
-    if (kLook > 2) issue<(2 % kNBuf)>(ctx, pg, ops, 2);
-    if (kLook > 3) issue<(3 % kNBuf)>(ctx, pg, ops, 3);
-    bool ok = true;
     // whole rounds of kNBuf steps: no step is skipped, so the loop body has no branch
     // around loads (steps past n_my + kLag only stream clamped rows)
     const int rounds = (n_my + kLag + kNBuf - 1) / kNBuf;
-    for (int q = 0; q < rounds; ++q) {
-      const int t0 = q * kNBuf;
-      step<0>(pg, pb, ctx, ops, t0, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 1) step<(1 % kNBuf)>(pg, pb, ctx, ops, t0 + 1, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 2) step<(2 % kNBuf)>(pg, pb, ctx, ops, t0 + 2, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 3) step<(3 % kNBuf)>(pg, pb, ctx, ops, t0 + 3, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 4) step<(4 % kNBuf)>(pg, pb, ctx, ops, t0 + 4, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 5) step<(5 % kNBuf)>(pg, pb, ctx, ops, t0 + 5, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 6) step<(6 % kNBuf)>(pg, pb, ctx, ops, t0 + 6, n_my, E, v0, s_part, s_tot, ok);
-      if (kNBuf > 7) step<(7 % kNBuf)>(pg, pb, ctx, ops, t0 + 7, n_my, E, v0, s_part, s_tot, ok);
-    }
-    ctx.xstep += (uint32_t)n_my;
+    const bool xwave = (threadIdx.x >> 6) == 0 && pg.C > 1;    // uniform per wave
+    bool ok;
+    if (xwave) ok = stream_rows<true>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
+    else ok = stream_rows<false>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
+    // the next product starts on a fresh block of kRing steps, so no word this product
+    // left in the ring carries one of its tags (products may differ in words per slot)
+    const uint32_t used = ctx.xstep + (uint32_t)n_my;
+    ctx.xstep = (used + kRing - 1) / kRing * kRing;
     if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
     __syncthreads();
     return s_ok != 0;

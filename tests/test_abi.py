@@ -35,10 +35,11 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # sr_matrix: 3 int64 + 2 int32 + 4 pointers; sr_cg_opts: double + 4 int32 + pointer;
+    # sr_matrix: 3 int64 + 2 int32 + 4 pointers; sr_cg_opts: double + 4 int32 + pointer + double
+    # + int32 (padded);
     # sr_cg_info: 4 int32 + 2 double
     assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 4
-    assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8
+    assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
 
 
@@ -105,6 +106,14 @@ def test_invalid_scalars_rejected():
     opts.refresh_every = 0
     opts.use_x0 = 2
     assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.use_x0 = 0
+    for drop in (-0.1, 1.0, float("nan")):
+        opts.refresh_drop = drop
+        assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.refresh_drop = 0.0
+    opts.refine = 2
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.refine = 0
     # grad: g without E
     assert L.sr_grad(ctypes.byref(m), None, v, None, None, None, None) == sr.SR_ERR_INVALID
     # lm: mismatched D

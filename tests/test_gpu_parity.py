@@ -305,3 +305,97 @@ def test_cg_two_planes_reaches_float64_accuracy(dtype):
     x_orig = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-3 * orc.diag_overlap(O).mean())
     assert rel_err(to_np(x), x_split) <= 1e-8, rel_err(to_np(x), x_split)
     assert rel_err(to_np(x), x_orig) <= 1e-4, rel_err(to_np(x), x_orig)
+
+
+def test_cg_two_planes_ill_conditioned_cps_with_refresh_drop():
+    """CPS-shaped system with N_p > N_s: the one-plane solution is far from the float64 one;
+    refinement with drop-triggered, restarting refreshes recovers it."""
+    d = synth.small_cps_inputs(seed=21, n_s=2048, n_corr=16, n_states=240, n_dense=530)
+    O, E = d["O"].numpy(), d["E"].numpy()
+    M = _two_plane_matrix(O, torch.bfloat16)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-9, refresh_every=0, refresh_drop=0.1)
+    assert info["status"] == 0, info
+    x_orig = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-3 * orc.diag_overlap(O).mean())
+    assert rel_err(to_np(x), x_orig) <= 1e-4, rel_err(to_np(x), x_orig)
+
+
+# ------------------------------------------------------------------------------------------
+# Every built tile configuration on wide matrices with few rows per row group: many
+# column groups exchange partial dots and the pipeline's tail steps are a large part of
+# the run.  Each call is made twice on one stream (workspace and exchange ring reuse).
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16, torch.float16], ids=_dname)
+@pytest.mark.parametrize("shape", [(37, 300001), (1000, 70001)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_every_tile_config_product(shape, dtype):
+    n_s, n_p = shape
+    O, _ = rand_dense(n_s, n_p, seed=91 + n_s, offset=0.25)
+    Os = stored_dense(O, dtype)
+    v = np.random.default_rng(4).standard_normal(n_p)
+    ref = orc.sv_product_swapped(Os, v, 0.07)
+    mag = magnitude_ref(Os, v, 0.07, dtype)
+    M = device_matrix(O, dtype)
+    vd = to_dev(v)
+    try:
+        for cfg in sr.tile_configs(dtype, 0):
+            print(f"[tile] {n_s}x{n_p} {dtype} {cfg}", flush=True)
+            sr.set_tile_config(*cfg)
+            for _ in range(2):
+                y = to_np(sr.sr_sv_product(M, vd, 0.07))
+                assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * mag + 1e-300), \
+                    (cfg, float(np.max(np.abs(y - ref) / mag)))
+    finally:
+        sr.set_tile_config(0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.bfloat16], ids=_dname)
+def test_every_tile_config_lm_product(dtype):
+    n_s, n_p = 53, 200001
+    O, E = rand_dense(n_s, n_p, seed=93, offset=0.1)
+    Os = stored_dense(O, dtype)
+    rng = np.random.default_rng(5)
+    D = 0.1 * rng.standard_normal((n_s, n_p))
+    Ds = stored_dense(D, dtype)
+    v = rng.standard_normal(n_p + 1)
+    ref = orc.lm_hv_swapped(Os, E, Ds, v)
+    Oa, Da = np.abs(Os), np.abs(Ds)
+    t = Oa @ np.abs(v[1:])
+    z = np.abs(E) * (abs(v[0]) + t) + Da @ np.abs(v[1:])
+    mag = np.concatenate([[abs(E.mean() * v[0]) + (np.abs(E) @ t + (Da @ np.abs(v[1:])).sum()) / n_s],
+                          (Oa.T @ z + np.abs(orc.sample_mean(Os)) * z.sum()) / n_s])
+    M, Dm = device_matrix(O, dtype), device_matrix(D, dtype)
+    Ed, vd = to_dev(E), to_dev(v)
+    try:
+        for cfg in sr.tile_configs(dtype, 1):
+            print(f"[tile-lm] {n_s}x{n_p} {dtype} {cfg}", flush=True)
+            sr.set_tile_config(*cfg)
+            for _ in range(2):
+                y = to_np(sr.lm_hv_product(M, Ed, Dm, vd))
+                assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * mag + 1e-300), \
+                    (cfg, float(np.max(np.abs(y - ref) / mag)))
+    finally:
+        sr.set_tile_config(0)
+
+
+def test_every_tile_config_cg_wide():
+    """CG (several products per launch, float64) with each configuration on a wide matrix:
+    same solution as the oracle's matrix-free CG."""
+    n_s, n_p = 301, 90001
+    O, E = rand_dense(n_s, n_p, seed=95)
+    g = orc.energy_gradient(O, E)
+    eps = 1e-2 * orc.diag_overlap(O).mean()
+    x_ref, _, _ = orc.cg_solve(lambda u: orc.sv_product_swapped(O, u, eps), g, rtol=1e-13, max_iter=2000)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    try:
+        for cfg in sr.tile_configs(torch.float64, 0):
+            print(f"[tile-cg] {cfg}", flush=True)
+            sr.set_tile_config(*cfg)
+            x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-12, refresh_every=10)
+            assert info["status"] == 0, (cfg, info)
+            assert rel_err(to_np(x), x_ref) <= 1e-9, (cfg, rel_err(to_np(x), x_ref))
+    finally:
+        sr.set_tile_config(0)

@@ -183,6 +183,18 @@ def test_lm_matrices_exact_enumeration():
     np.testing.assert_allclose(orc.lm_hv_dense(O, E, D, v, w), Hx @ v, rtol=1e-11, atol=1e-12)
 
 
+def test_lm_matrix_free_product_equals_dense():
+    """The matrix-free H v equals H v with H formed (weighted and uniform samples)."""
+    rng = np.random.default_rng(17)
+    O = rng.standard_normal((40, 7)) + 0.3
+    E = rng.standard_normal(40) - 2.0
+    D = 0.1 * rng.standard_normal((40, 7))
+    v = rng.standard_normal(8)
+    for w in (None, rng.random(40)):
+        np.testing.assert_allclose(orc.lm_hv_swapped(O, E, D, v, w), orc.lm_hv_dense(O, E, D, v, w),
+                                   rtol=1e-12, atol=1e-13)
+
+
 def test_lm_eigenvalue_variational_and_exact_when_complete():
     """Lowest LM eigenvalue >= ground-state energy; equal when Omega spans the whole space."""
     H, psi, dpsi = _tiny_space(M=4, P=3, seed=5)       # 1 + 3 = 4 = M: Omega is complete
