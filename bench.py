@@ -149,6 +149,16 @@ def main():
         dt_t, dtype_name = O64.dtype, {torch.float64: "f64", torch.float32: "f32"}[O64.dtype]
         rtol = args.rtol if args.rtol is not None else cfg.rtol
     M64 = sr.as_matrix(O64)
+
+    # ---- tile autotuning (not timed): every built configuration on these matrices ----
+    from paper_1108_0900_amd import tune
+    tiles = {}
+    for name, M in (("f64", M64), (dtype_name, M1 if scaled else Mt)):
+        if name in tiles:
+            continue
+        res = tune.autotune(M, kind=0, reps=3)
+        tiles[name] = {"best": list(res["best"]), "ms": {str(list(k)): round(v, 3) for k, v in res["ms"].items()}}
+        log(f"[bench] tuned {name}: {res['best']}  {tiles[name]['ms']}")
     drop = args.refresh_drop if args.refresh_drop is not None else (0.1 if args.refine else 0.0)
     m_refresh = 0 if (args.refine and args.refresh_drop is None) else refresh
 
@@ -287,6 +297,7 @@ def main():
                   "residual_products": residuals, "planes": planes, "search_planes": search_planes,
                   "rel_res_true": infos[-1]["rel_res_true"], "rtol": rtol, "eps": eps},
         "sv_product": sv,
+        "tiles": tiles,
         "f64_solve": f64,
         "err_vs_f64": err,
         "err_vs_f64_one_plane": err_one_plane,

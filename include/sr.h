@@ -190,14 +190,15 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
  * (nv, rows, lookahead, poll_delay, threads) to the host array `out`; returns how many
  * exist.  The first one listed is the default.
  * sr_set_tile_config: process-wide override of the automatic choice for every later call
- * (nv = 0 restores it); col_groups = 0 keeps the automatic number of column groups,
- * otherwise it must be a power of two (used when larger than the minimum).  Not
- * synchronized with calls running on other threads.  SR_ERR_INVALID if no kernel has
- * that configuration.
+ * with storage type `dtype` and product kind `kind` (nv = 0 restores the automatic
+ * choice; dtype = -1 with nv = 0 restores it for all); col_groups = 0 keeps the
+ * automatic number of column groups, otherwise it must be a power of two (used when
+ * larger than the minimum).  Not synchronized with calls running on other threads.
+ * SR_ERR_INVALID if no kernel of that type and kind has that configuration.
  * ------------------------------------------------------------------------------------ */
 int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max);
-int sr_set_tile_config(int32_t nv, int32_t rows, int32_t lookahead, int32_t poll_delay, int32_t threads,
-                       int32_t col_groups);
+int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
+                       int32_t poll_delay, int32_t threads, int32_t col_groups);
 
 /* Frees every workspace the library holds (all devices, all streams).  Must not be
  * called while library work is pending on any stream. */

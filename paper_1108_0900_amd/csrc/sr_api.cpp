@@ -177,21 +177,13 @@ struct Plan {
   int words = 0;   // exchange words per column group per tile
 };
 
-// Optional override "nv,r,look,poll,threads[,c]" from the SR_TILE environment variable
-// (tile sweeps): tile shape, pipeline depths, workgroup size and, optionally, a larger
-// power-of-two number of column groups.
-int g_force_nv = 0, g_force_r = 0, g_force_look = 0, g_force_poll = 0, g_force_nt = 0, g_force_c = 0;
-
-void read_env_override() {
-  static bool done = false;
-  if (done) return;
-  done = true;
-  if (g_force_nv > 0) return;   // set through sr_set_tile_config
-  const char *e = std::getenv("SR_TILE");
-  if (e) std::sscanf(e, "%d,%d,%d,%d,%d,%d", &g_force_nv, &g_force_r, &g_force_look, &g_force_poll, &g_force_nt,
-                     &g_force_c);
-  if (g_force_c & (g_force_c - 1)) g_force_c = 0;   // column groups must be a power of two
-}
+// Tile overrides per (storage type, product kind) set by sr_set_tile_config (tuning):
+// tile shape, pipeline depths, workgroup size and, optionally, a larger power-of-two
+// number of column groups.  nv = 0: automatic.
+struct TileForce {
+  int nv, r, look, poll, nt, c;
+};
+TileForce g_force[4][2] = {};
 
 int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg) {
   int64_t C = pow2_ceil(cdiv(n_p, cols_per_wg));
@@ -209,16 +201,16 @@ int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, i
 }
 
 int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
-  read_env_override();
   int count = 0;
   const KernelEntry *tab = kernel_table(dt, &count);
   const int vec = vec_of(dt);
   const int kind = ndot == 1 ? 0 : 1;
+  const TileForce &f = g_force[dt][kind];
   const KernelEntry *pick = nullptr;
-  if (g_force_nv > 0) {
+  if (f.nv > 0) {
     for (int i = 0; i < count; ++i)
-      if (tab[i].kind == kind && tab[i].nv == g_force_nv && tab[i].r == g_force_r &&
-          tab[i].look == g_force_look && tab[i].poll == g_force_poll && tab[i].nt == g_force_nt)
+      if (tab[i].kind == kind && tab[i].nv == f.nv && tab[i].r == f.r && tab[i].look == f.look &&
+          tab[i].poll == f.poll && tab[i].nt == f.nt)
         pick = &tab[i];
   }
   if (pick == nullptr) {
@@ -229,7 +221,7 @@ int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
   }
   plan->ke = pick;
   const int cols = pick->nv * vec * pick->nt;
-  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, g_force_c, &plan->pg);
+  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg);
   if (rc) return rc;
   plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
   return SR_OK;
@@ -414,33 +406,32 @@ int sr_release(void) {
   return rc;
 }
 
-int sr_set_tile_config(int32_t nv, int32_t rows, int32_t lookahead, int32_t poll_delay, int32_t threads,
-                       int32_t col_groups) {
+int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
+                       int32_t poll_delay, int32_t threads, int32_t col_groups) {
+  if (nv == 0 && dtype == -1) {
+    for (auto &row : g_force)
+      for (auto &f : row) f = TileForce{};
+    return SR_OK;
+  }
+  if (dtype < SR_F64 || dtype > SR_F16 || (kind != 0 && kind != 1))
+    return fail(SR_ERR_INVALID, "sr_set_tile_config: bad dtype or kind");
   if (nv == 0) {
-    g_force_nv = g_force_r = g_force_look = g_force_poll = g_force_nt = g_force_c = 0;
+    g_force[dtype][kind] = TileForce{};
     return SR_OK;
   }
   if (col_groups < 0 || (col_groups & (col_groups - 1)))
     return fail(SR_ERR_INVALID, "sr_set_tile_config: col_groups must be 0 or a power of two");
   bool found = false;
-  for (int dt = SR_F64; dt <= SR_F16 && !found; ++dt) {
-    int count = 0;
-    const KernelEntry *tab = kernel_table(dt, &count);
-    for (int i = 0; i < count; ++i)
-      if (tab[i].nv == nv && tab[i].r == rows && tab[i].look == lookahead && tab[i].poll == poll_delay &&
-          tab[i].nt == threads)
-        found = true;
-  }
+  int count = 0;
+  const KernelEntry *tab = kernel_table(dtype, &count);
+  for (int i = 0; i < count; ++i)
+    if (tab[i].kind == kind && tab[i].nv == nv && tab[i].r == rows && tab[i].look == lookahead &&
+        tab[i].poll == poll_delay && tab[i].nt == threads)
+      found = true;
   if (!found)
-    return fail(SR_ERR_INVALID, "sr_set_tile_config: no kernel built for (%d, %d, %d, %d, %d)", nv, rows, lookahead,
-                poll_delay, threads);
-  read_env_override();
-  g_force_nv = nv;
-  g_force_r = rows;
-  g_force_look = lookahead;
-  g_force_poll = poll_delay;
-  g_force_nt = threads;
-  g_force_c = col_groups;
+    return fail(SR_ERR_INVALID, "sr_set_tile_config: no kernel built for (%d, %d, %d, %d, %d) of this type and kind",
+                nv, rows, lookahead, poll_delay, threads);
+  g_force[dtype][kind] = TileForce{nv, rows, lookahead, poll_delay, threads, col_groups};
   return SR_OK;
 }
 
@@ -642,7 +633,9 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.hist = o.res_history;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  rc = launch_coop(pl.ke->cg, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+  const void *cg_fn = O->O_lo == nullptr ? pl.ke->cg : (a.refine ? pl.ke->cgr : pl.ke->cg2);
+  if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no two-plane CG kernel for this configuration");
+  rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
   if (rc) return rc;
   double hinfo[8];
   uint32_t habort = 0;

@@ -389,7 +389,14 @@ struct CgKernel {
   static constexpr bool kExactResidual = (DT == DT_BF16 || DT == DT_F16);
 };
 
-template <int DT, int NV, int R, int L, int P_, int NT>
+// CGM selects the products of the solve, so that each kernel holds only the two it uses:
+//   kCgOnePlane   one code plane: search directions in the storage type's accumulation,
+//                 residuals float64-accumulated for scaled storage
+//   kCgTwoPlanes  two code planes everywhere, float64 accumulation
+//   kCgRefine     search directions on the first plane, residuals on both (refinement)
+enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgRefine = 2 };
+
+template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane>
 __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   // Conjugate gradient (Hestenes-Stiefel) as a state machine with one product per pass
   // through the loop, so the product code is instantiated once per accumulation type.
@@ -454,12 +461,15 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
 
   while (ok && mode != MODE_DONE) {
     const bool on_p = (mode == MODE_P);
-    if constexpr (K::kExactResidual) {
-      // residuals: every plane, float64 accumulation; search directions: float32
-      // accumulation over every plane, or the first plane only under refinement
-      if (on_p && a.op.lo != nullptr && !a.refine) ok = K::template apply<false, 2>(a, ctx, a.p, a.q, j0, j1, products);
-      else if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
-      else if (a.op.lo != nullptr) ok = K::template apply<true, 2>(a, ctx, a.x, a.q, j0, j1, products);
+    if constexpr (CGM == kCgTwoPlanes) {
+      // one product code for search directions and residuals: float64 accumulation
+      // (measured faster here than float32 with the two planes in one kernel)
+      ok = K::template apply<true, 2>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
+    } else if constexpr (CGM == kCgRefine) {
+      if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
+      else ok = K::template apply<true, 2>(a, ctx, a.x, a.q, j0, j1, products);
+    } else if constexpr (K::kExactResidual) {
+      if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
       else ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);
     } else {
       ok = K::template apply<false>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);

@@ -72,14 +72,14 @@ struct QuantArgs {
 // Tile configurations (NV 16-byte vectors per data thread, R rows per tile) built for
 // each storage type: SR products (k_sv, k_cg) and linear-method products (k_lm, which
 // streams two matrices and so uses half the tile).
-// X(NV, R, LOOKAHEAD, POLL_ADVANCE, THREADS) per storage type; the first SR entry is the
+// X(NV, R, LOOKAHEAD, POLL_DEPTH, THREADS) per storage type; the first SR entry is the
 // default (chosen by the tile sweep on MI355X), the others are selectable for tuning.
-#define SR_SR_CONFIGS_F64(X) X(4, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 2, 2, 1, 256) \
-  X(4, 1, 2, 2, 512) X(4, 1, 1, 2, 512) X(4, 1, 1, 3, 512)
-#define SR_SR_CONFIGS_F32(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 3, 512)
-#define SR_SR_CONFIGS_BF16(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 2, 512) \
-  X(2, 1, 2, 3, 512) X(2, 1, 2, 5, 512)
-#define SR_SR_CONFIGS_F16(X) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512) X(4, 2, 2, 1, 256) X(2, 1, 2, 3, 512)
+#define SR_SR_CONFIGS_F64(X) X(4, 1, 1, 1, 512) X(4, 1, 2, 1, 512) X(2, 1, 2, 1, 512) X(2, 2, 1, 1, 512) \
+  X(4, 1, 1, 2, 512) X(4, 1, 3, 2, 512)
+#define SR_SR_CONFIGS_F32(X) X(2, 1, 2, 1, 512) X(2, 2, 1, 1, 512) X(4, 1, 1, 1, 512) X(4, 1, 2, 1, 512)
+#define SR_SR_CONFIGS_BF16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(2, 1, 3, 1, 512) X(4, 1, 1, 1, 512) \
+  X(2, 2, 2, 1, 512) X(1, 4, 1, 1, 512)
+#define SR_SR_CONFIGS_F16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512)
 #define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)
 
 struct KernelEntry {
@@ -87,6 +87,7 @@ struct KernelEntry {
   int kind;              // 0: SR (sv + cg), 1: LM
   const void *sv, *cg, *lm;
   const void *sv2;       // two-code-plane product (scaled storage), or nullptr
+  const void *cg2, *cgr; // CG over two code planes / refinement (scaled storage), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 

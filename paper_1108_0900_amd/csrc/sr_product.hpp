@@ -149,7 +149,8 @@ struct Product {
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
   // --- exchange state (wave 0) ---
-  u64 pw[kNPoll][PW];               // words of column group `lane` for the pending polls
+  static constexpr int kCh = 2;     // column groups per lane read ahead (C <= 128 asynchronously)
+  u64 pw[kNPoll][kCh][PW];          // words of column groups lane, lane + 64 for the pending polls
   double cshare;
 
   __device__ __forceinline__ static u32x4 elem_mask(int nvalid) {
@@ -312,17 +313,20 @@ struct Product {
     st_coh64(&base[k], word);
   }
 
-  // Exchange wave: issue the loads of column group `lane`'s words into poll buffer Q (no
-  // wait).  Issued unconditionally: lanes past C read column group 0's words and steps
-  // outside the product read a valid slot; neither result is used.
+  // Exchange wave: issue the loads of column groups lane and lane + 64 into poll buffer Q
+  // (no wait).  Issued unconditionally: column groups past C read group 0's words and
+  // steps outside the product read a valid slot; neither result is used.
   template <int Q>
   __device__ __forceinline__ void poll_issue(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
                                              uint32_t step) {
     const int lane = (int)threadIdx.x & 63;
-    const int c = lane < pg.C ? lane : 0;
-    const u64 *wp = slot_base(pb, pg, ctx, step) + (int64_t)c * WORDS;
+    const u64 *base = slot_base(pb, pg, ctx, step);
 #pragma unroll
-    for (int k = 0; k < PW; ++k) pw[Q][k] = ld_coh64(&wp[k]);
+    for (int h = 0; h < kCh; ++h) {
+      const int c = lane + 64 * h < pg.C ? lane + 64 * h : 0;
+#pragma unroll
+      for (int k = 0; k < PW; ++k) pw[Q][h][k] = ld_coh64(&base[(int64_t)c * WORDS + k]);
+    }
   }
 
   __device__ __forceinline__ static bool words_ok(const u64 *w, uint32_t tag) {
@@ -345,10 +349,10 @@ struct Product {
       }
   }
 
-  // Exchange wave: finish the poll of `step` (words already issued by poll_issue for the
-  // first 64 column groups), re-reading until every column group's words carry the
-  // step's tag; sum in a fixed order (lane, then butterfly) and store the row weights in
-  // tot[d][r].  Returns false if the wait gave up (abort).
+  // Exchange wave: finish the poll of `step` (words of the first 128 column groups
+  // already issued by poll_issue), re-reading until every column group's words carry the
+  // step's tag; sum in a fixed order (lane's groups in order, then butterfly) and store
+  // the row weights in tot[d][r].  Returns false if the wait gave up (abort).
   template <int Q>
   __device__ __forceinline__ bool poll_finish(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
                                               uint32_t step, double (*tot)[R]) {
@@ -357,33 +361,44 @@ struct Product {
     const u64 *base = slot_base(pb, pg, ctx, step);
     uint64_t spins = 0;
     bool ok = true;
-    // first chunk: the words issued ahead.  The first check is kept out of the retry
-    // loop so that it waits only for those words, not for the tile loads issued after.
-    if (!__all(lane >= pg.C || words_ok(pw[Q], tag))) {
-      u64 w[PW];
-      while (true) {
-        if (lane < pg.C) {
-          const u64 *wp = base + (int64_t)lane * WORDS;
+    auto lane_ok = [&](const u64 (&w)[kCh][PW]) {
+      bool good = true;
 #pragma unroll
-          for (int k = 0; k < PW; ++k) w[k] = ld_coh64(&wp[k]);
+      for (int h = 0; h < kCh; ++h) good &= (lane + 64 * h >= pg.C) || words_ok(w[h], tag);
+      return good;
+    };
+    // the words issued ahead.  The first check is kept out of the retry loop so that it
+    // waits only for those words, not for the tile loads issued after them.
+    if (!__all(lane_ok(pw[Q]))) {
+      u64 w[kCh][PW];
+      while (true) {
+#pragma unroll
+        for (int h = 0; h < kCh; ++h) {
+          const int c = lane + 64 * h < pg.C ? lane + 64 * h : 0;
+#pragma unroll
+          for (int k = 0; k < PW; ++k) w[h][k] = ld_coh64(&base[(int64_t)c * WORDS + k]);
         }
-        if (__all(lane >= pg.C || words_ok(w, tag))) break;
+        if (__all(lane_ok(w))) break;
         if (++spins > kSpinLimit || ((spins & 255) == 0 && ld_coh32(ctx.gs.abort) != 0u)) {
           ok = false;
           break;
         }
       }
 #pragma unroll
-      for (int k = 0; k < PW; ++k) pw[Q][k] = w[k];
+      for (int h = 0; h < kCh; ++h)
+#pragma unroll
+        for (int k = 0; k < PW; ++k) pw[Q][h][k] = w[h][k];
     }
     double acc[NDOT][R];
 #pragma unroll
     for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[d][r] = 0.0;
-    if (lane < pg.C) words_add(pw[Q], acc);
-    // further chunks (C > 64): read synchronously
-    for (int c0 = 64; ok && c0 < pg.C; c0 += 64) {
+#pragma unroll
+    for (int h = 0; h < kCh; ++h)
+      if (lane + 64 * h < pg.C) words_add(pw[Q][h], acc);
+    // further column groups (C > 128): read synchronously
+    for (int c0 = 64 * kCh; ok && c0 < pg.C; c0 += 64) {
       const int c = c0 + lane;
       u64 w[PW];
       while (true) {
@@ -453,11 +468,18 @@ struct Product {
     }
   }
 
-  // One pipeline step t (register buffer B = t % kNBuf).  X: this is the exchange wave
-  // (wave 0 when there are several column groups); the other waves run the same steps
-  // without the exchange.  Inside a step no memory operation is conditional, so the
-  // compiler waits for exactly the loads each use needs.
-  template <int B, bool X>
+  // Roles of the waves when there are several column groups: wave 0 polls the other
+  // groups' partial dots (kPoll), wave 1 combines the waves' partial dots and publishes
+  // them (kPublish), the others only stream (kPlain).  Splitting the two halves the
+  // serial work any one wave adds between barriers; for 2-byte storage (short steps)
+  // that pays, for 4- and 8-byte storage wave 0 does both (kBoth) (measured on MI355X).
+  enum { kPlain = 0, kPoll = 1, kPublish = 2, kBoth = 3 };
+  static constexpr bool kSplit = St::BYTES == 2;
+
+  // One pipeline step t (register buffer B = t % kNBuf) of a wave with role X.  Inside a
+  // step no memory operation is conditional, so the compiler waits for exactly the loads
+  // each use needs.
+  template <int B, int X>
   __device__ __forceinline__ void step(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t,
                                        int n_my, const double *__restrict__ E, double v0,
                                        double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
@@ -465,9 +487,9 @@ struct Product {
     constexpr int QF = ((B - kAdv - PD) % kNPoll + kNPoll) % kNPoll;   // exchange t - kAdv - PD
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    // exchange wave: start loading the words of step t - kAdv (before this step's tile
+    // polling wave: start loading the words of step t - kAdv (before this step's tile
     // loads, so waiting for them later never waits for this step's tiles)
-    if constexpr (X) poll_issue<QI>(pb, pg, ctx, ctx.xstep + (uint32_t)(t - kAdv));
+    if constexpr ((X & kPoll) != 0) poll_issue<QI>(pb, pg, ctx, ctx.xstep + (uint32_t)(t - kAdv));
     // streaming: unconditional in every step (tiles past n_my read clamped rows with zero
     // weight), so the wait for tile t leaves tiles t+1..t+kLook in flight
     issue<(B + kLook) % kNBuf>(ctx, pg, ops, t + kLook);
@@ -484,13 +506,13 @@ struct Product {
     }
     const int u = t - kLag;
     if (u >= 0 && u < n_my) update<(B + kNBuf - kLag) % kNBuf>(pg, ctx, u, s_tot[u % kNBuf], E, v0);
-    if constexpr (X) {
+    if constexpr ((X & kPoll) != 0) {
       // finish the poll started at the beginning of step t - PD
       const int e = t - kAdv - PD;
       if (e >= 0 && e < n_my && ok) ok = poll_finish<QF>(pb, pg, ctx, ctx.xstep + (uint32_t)e, s_tot[e % kNBuf]);
     }
     __syncthreads();
-    if (wave == 0 && (X || t < n_my)) {
+    if ((X & kPublish) != 0 || (X == kPlain && pg.C == 1 && wave == 0 && t < n_my)) {
       double red[NDOT][R];
 #pragma unroll
       for (int d = 0; d < NDOT; ++d)
@@ -501,7 +523,7 @@ struct Product {
           for (int w = 0; w < NW; ++w) sm += s_part[t & 1][w][d][r];
           red[d][r] = (d == 0) ? sm - cshare : sm;
         }
-      if constexpr (X) {
+      if constexpr ((X & kPublish) != 0) {
         // every step publishes (the tail steps past n_my into the sink), so the store is
         // not conditional
         publish(pb, pg, ctx, ctx.xstep + (uint32_t)t, t >= n_my, red);
@@ -517,7 +539,7 @@ struct Product {
   }
 
   // Steps t0 .. t0 + kNBuf - 1, one per register buffer, fully unrolled.
-  template <bool X, int... Bs>
+  template <int X, int... Bs>
   __device__ __forceinline__ void round_of_steps(std::integer_sequence<int, Bs...>, const ProdGeom &pg,
                                                  const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t0, int n_my,
                                                  const double *__restrict__ E, double v0,
@@ -525,9 +547,9 @@ struct Product {
     (step<Bs, X>(pg, pb, ctx, ops, t0 + Bs, n_my, E, v0, s_part, s_tot, ok), ...);
   }
 
-  // The whole streaming loop of one wave (X: the exchange wave).  Both loops execute the
-  // same number of barriers.
-  template <bool X>
+  // The whole streaming loop of one wave with role X.  Every role executes the same
+  // number of barriers.
+  template <int X>
   __device__ __forceinline__ bool stream_rows(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
                                               int n_my, int rounds, const double *__restrict__ E, double v0,
                                               double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R]) {
@@ -554,10 +576,15 @@ struct Product {
     // whole rounds of kNBuf steps: no step is skipped, so the loop body has no branch
     // around loads (steps past n_my + kLag only stream clamped rows)
     const int rounds = (n_my + kLag + kNBuf - 1) / kNBuf;
-    const bool xwave = (threadIdx.x >> 6) == 0 && pg.C > 1;    // uniform per wave
+    static_assert(NW >= 2, "the exchange roles need two waves");
+    const int wave = (int)(threadIdx.x >> 6);
     bool ok;
-    if (xwave) ok = stream_rows<true>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
-    else ok = stream_rows<false>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
+    if (pg.C > 1 && wave == 0)
+      ok = stream_rows<(kSplit ? kPoll : kBoth)>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
+    else if (kSplit && pg.C > 1 && wave == 1)
+      ok = stream_rows<kPublish>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
+    else
+      ok = stream_rows<kPlain>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
     // the next product starts on a fresh block of kRing steps, so no word this product
     // left in the ring carries one of its tags (products may differ in words per slot)
     const uint32_t used = ctx.xstep + (uint32_t)n_my;

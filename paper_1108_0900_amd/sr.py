@@ -53,7 +53,7 @@ PROTOTYPES = {
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
     "sr_tile_configs": (ctypes.c_int, [_c_i32, _c_i32, ctypes.POINTER(ctypes.c_int32), _c_i32]),
-    "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
+    "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sr_last_error": (ctypes.c_char_p, []),
     "sr_version": (ctypes.c_int, []),
@@ -289,10 +289,14 @@ def tile_configs(dtype=torch.float64, kind: int = 0) -> list:
     return [tuple(arr[5 * i:5 * i + 5]) for i in range(n)]
 
 
-def set_tile_config(nv: int = 0, rows: int = 0, lookahead: int = 0, poll_delay: int = 0, threads: int = 0,
-                    col_groups: int = 0):
-    """Override the product tile configuration (nv = 0: automatic)."""
-    _check(lib().sr_set_tile_config(nv, rows, lookahead, poll_delay, threads, col_groups), "sr_set_tile_config")
+def set_tile_config(dtype=None, kind: int = 0, nv: int = 0, rows: int = 0, lookahead: int = 0,
+                    poll_delay: int = 0, threads: int = 0, col_groups: int = 0):
+    """Override the product tile configuration for one storage type and product kind
+    (nv = 0: automatic).  set_tile_config() with no arguments restores every automatic
+    choice."""
+    code = -1 if dtype is None else _TORCH_DT[dtype]
+    _check(lib().sr_set_tile_config(code, kind, nv, rows, lookahead, poll_delay, threads, col_groups),
+           "sr_set_tile_config")
 
 
 def release():

@@ -1,0 +1,118 @@
+"""Tile-configuration autotuner for the fused products.
+
+libsr is built with several tile configurations per storage type (16-byte vectors per
+thread, rows per tile, lookahead, poll depth, threads; `sr.tile_configs`).  Which one is
+fastest depends on the matrix shape: the number of column groups that exchange partial
+dots per row, the rows per row group, and the bytes per element.  `autotune` times every
+configuration on the caller's own matrix with HIP events and selects the fastest for
+that storage type and product kind, process-wide (`sr.set_tile_config`).  Results can
+be cached in a JSON file keyed by device, storage type, shape and product kind, so a
+later process reuses them without timing.  The CG solve uses the configuration of the SR product (kind 0).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import sr
+
+CACHE_ENV = "SR_TUNE_CACHE"
+
+
+def _key(M: sr.Matrix, kind: int) -> str:
+    dev = torch.cuda.get_device_name(M.O.device)
+    return f"{dev}|{str(M.O.dtype).split('.')[-1]}|{M.O.shape[0]}|{M.n_p}|kind{kind}"
+
+
+def _load(path):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def _save(path, table):
+    if not path:
+        return
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _median_ms(fn, reps: int, warm: int = 1) -> float:
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    stream = torch.cuda.current_stream()
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None = None,
+             E: torch.Tensor | None = None, D: sr.Matrix | None = None, apply: bool = True) -> dict:
+    """Time every built configuration of the product of `kind` (0: (S + eps I) v,
+    1: linear-method H v, which needs E and D) on M; select the fastest if `apply`.
+
+    Returns {"best": (nv, rows, lookahead, poll_depth, threads), "ms": {config: ms},
+    "cached": bool}.  A configuration whose call fails (for example, one that cannot hold
+    n_p columns) is skipped.  M's column means are computed first if missing.
+    """
+    if kind not in (0, 1):
+        raise ValueError("kind must be 0 (SR product) or 1 (linear-method product)")
+    if kind == 1 and (E is None or D is None):
+        raise ValueError("the linear-method product needs E and D")
+    if M.lo is not None:
+        raise ValueError("tune the first code plane alone (two-plane products use a fixed tile)")
+    cache_path = cache_path or os.environ.get(CACHE_ENV)
+    table = _load(cache_path)
+    key = _key(M, kind)
+    if key in table:
+        best = tuple(table[key]["best"])
+        if apply:
+            sr.set_tile_config(M.O.dtype, kind, *best)
+        return {"best": best, "ms": {tuple(json.loads(k)): v for k, v in table[key]["ms"].items()}, "cached": True}
+
+    if M.mean is None:
+        M.mean = sr.sr_grad(M, None)["mean"]
+    gen = torch.Generator(device=M.O.device)
+    gen.manual_seed(0)
+    n = M.n_p + (1 if kind == 1 else 0)
+    v = torch.randn(n, generator=gen, dtype=torch.float64, device=M.O.device)
+    y = torch.empty_like(v)
+    if kind == 0:
+        def call():
+            sr.sr_sv_product(M, v, 0.1, out=y)
+    else:
+        def call():
+            sr.lm_hv_product(M, E, D, v, out=y)
+
+    times = {}
+    try:
+        for cfg in sr.tile_configs(M.O.dtype, kind):
+            sr.set_tile_config(M.O.dtype, kind, *cfg)
+            try:
+                times[cfg] = _median_ms(call, reps)
+            except sr.SrError:
+                continue
+    finally:
+        sr.set_tile_config(M.O.dtype, kind)
+    if not times:
+        raise RuntimeError("no tile configuration could run this product")
+    best = min(times, key=times.get)
+    if apply:
+        sr.set_tile_config(M.O.dtype, kind, *best)
+    table[key] = {"best": list(best), "ms": {json.dumps(list(k)): v for k, v in times.items()}}
+    _save(cache_path, table)
+    return {"best": best, "ms": times, "cached": False}

@@ -154,9 +154,12 @@ def test_tile_config_hooks():
         assert cfgs and all(len(c) == 5 for c in cfgs)
         assert sr.tile_configs(dt, 1)
     cfg = sr.tile_configs(torch.float64, 0)[0]
-    sr.set_tile_config(*cfg)
-    sr.set_tile_config(0)
+    sr.set_tile_config(torch.float64, 0, *cfg)
+    sr.set_tile_config(torch.float64, 0)
+    sr.set_tile_config()
     with pytest.raises(sr.SrError):
-        sr.set_tile_config(3, 3, 3, 3, 256)
+        sr.set_tile_config(torch.float64, 0, 3, 3, 3, 3, 256)
     with pytest.raises(sr.SrError):
-        sr.set_tile_config(*cfg, col_groups=3)
+        sr.set_tile_config(torch.float64, 0, *cfg, col_groups=3)
+    with pytest.raises(sr.SrError):
+        sr.set_tile_config(torch.float64, 2, *cfg)

@@ -341,13 +341,13 @@ def test_every_tile_config_product(shape, dtype):
     try:
         for cfg in sr.tile_configs(dtype, 0):
             print(f"[tile] {n_s}x{n_p} {dtype} {cfg}", flush=True)
-            sr.set_tile_config(*cfg)
+            sr.set_tile_config(dtype, 0, *cfg)
             for _ in range(2):
                 y = to_np(sr.sr_sv_product(M, vd, 0.07))
                 assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * mag + 1e-300), \
                     (cfg, float(np.max(np.abs(y - ref) / mag)))
     finally:
-        sr.set_tile_config(0)
+        sr.set_tile_config()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.bfloat16], ids=_dname)
@@ -370,13 +370,13 @@ def test_every_tile_config_lm_product(dtype):
     try:
         for cfg in sr.tile_configs(dtype, 1):
             print(f"[tile-lm] {n_s}x{n_p} {dtype} {cfg}", flush=True)
-            sr.set_tile_config(*cfg)
+            sr.set_tile_config(dtype, 1, *cfg)
             for _ in range(2):
                 y = to_np(sr.lm_hv_product(M, Ed, Dm, vd))
                 assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * mag + 1e-300), \
                     (cfg, float(np.max(np.abs(y - ref) / mag)))
     finally:
-        sr.set_tile_config(0)
+        sr.set_tile_config()
 
 
 def test_every_tile_config_cg_wide():
@@ -393,9 +393,36 @@ def test_every_tile_config_cg_wide():
     try:
         for cfg in sr.tile_configs(torch.float64, 0):
             print(f"[tile-cg] {cfg}", flush=True)
-            sr.set_tile_config(*cfg)
+            sr.set_tile_config(torch.float64, 0, *cfg)
             x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-12, refresh_every=10)
             assert info["status"] == 0, (cfg, info)
             assert rel_err(to_np(x), x_ref) <= 1e-9, (cfg, rel_err(to_np(x), x_ref))
     finally:
-        sr.set_tile_config(0)
+        sr.set_tile_config()
+
+
+def test_autotuner_selects_a_built_config_and_caches(tmp_path):
+    from paper_1108_0900_amd import tune
+    n_s, n_p = 400, 150001
+    O, E = rand_dense(n_s, n_p, seed=97)
+    cache = str(tmp_path / "tune.json")
+    try:
+        for dtype in (torch.float64, torch.bfloat16):
+            M = device_matrix(O, dtype)
+            res = tune.autotune(M, kind=0, reps=2, cache_path=cache)
+            assert res["best"] in sr.tile_configs(dtype, 0) and not res["cached"]
+            assert res["ms"][res["best"]] == min(res["ms"].values())
+            again = tune.autotune(M, kind=0, cache_path=cache)
+            assert again["cached"] and again["best"] == res["best"]
+            # the selected configuration computes the same product
+            Os = stored_dense(O, dtype)
+            v = np.random.default_rng(9).standard_normal(n_p)
+            y = to_np(sr.sr_sv_product(M, to_dev(v), 0.3))
+            ref = orc.sv_product_swapped(Os, v, 0.3)
+            assert np.all(np.abs(y - ref) <= TOL_PRODUCT[dtype] * magnitude_ref(Os, v, 0.3, dtype) + 1e-300)
+        D = device_matrix(0.1 * np.random.default_rng(3).standard_normal((n_s, n_p)), torch.float64)
+        M = device_matrix(O, torch.float64)
+        res = tune.autotune(M, kind=1, reps=2, E=to_dev(E), D=D)
+        assert res["best"] in sr.tile_configs(torch.float64, 1)
+    finally:
+        sr.set_tile_config()
