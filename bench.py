@@ -49,6 +49,34 @@ def grad_bytes(n_s, n_p, dt, scaled, planes=1):
     return planes * n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
 
 
+KERNEL_SOURCES = ("sr_device.hpp", "sr_product.hpp", "sr_kernels.hpp", "sr_launch.hpp", "sr_kernels_bf16.hip")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_bf16x2_cps500k_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 of the device sources of the bf16 kernels (to tell whether a counter record
+    still describes the built kernel)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1108_0900_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel_name):
+    """HBM bytes per launch of the CG kernel from the committed FETCH_SIZE / WRITE_SIZE
+    record, or None if there is none for this kernel or its sources changed since."""
+    try:
+        text = open(TRAFFIC_RECORD).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel_name or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
 def make_workload(name, device):
     import synth
     from synth.configs import CONFIGS
@@ -114,6 +142,12 @@ def main():
     ap.add_argument("--refresh-drop", type=float, default=None)
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--quick", action="store_true",
+                    help="timed steps only (for profiler passes): no tuning, float64 solves, standalone "
+                         "products or CPU baseline")
+    ap.add_argument("--copy-gb", type=float, default=0.0,
+                    help="after the steps, copy a buffer of this many GB three times (a plain kernel of "
+                         "known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
@@ -154,7 +188,7 @@ def main():
     from paper_1108_0900_amd import tune
     tiles = {}
     for name, M in (("f64", M64), (dtype_name, M1 if scaled else Mt)):
-        if name in tiles:
+        if name in tiles or args.quick:
             continue
         res = tune.autotune(M, kind=0, reps=3)
         tiles[name] = {"best": list(res["best"]), "ms": {str(list(k)): round(v, 3) for k, v in res["ms"].items()}}
@@ -182,7 +216,7 @@ def main():
     # ---- float64 solves of the same matrix (reference solution and time-to-accuracy) ----
     f64 = None
     x64 = None
-    if scaled and not args.no_f64:
+    if scaled and not args.no_f64 and not args.quick:
         log("[bench] float64 solves")
         step(M64, 1e-10)      # warm
         x64, info64, ms64, _ = step(M64, 1e-10)
@@ -244,27 +278,49 @@ def main():
         ts.sort()
         return ts[len(ts) // 2]
     sv = {}
-    ms_t = sv_time(M1 if scaled else Mt)
-    pb1 = product_bytes(n_s, n_p, dt_t, scaled)
-    sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb1 / ms_t / 1e6, 1),
-                      "frac": round(pb1 / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
-    if scaled:
-        ms_2 = sv_time(M2)
-        b2 = product_bytes(n_s, n_p, dt_t, scaled, 2)
-        sv["bf16_two_planes"] = {"ms": round(ms_2, 3), "GBps": round(b2 / ms_2 / 1e6, 1),
-                                 "frac": round(b2 / ms_2 / 1e6 / HBM_PEAK_GBPS, 4)}
-        ms_d = sv_time(M64)
-        b64 = product_bytes(n_s, n_p, torch.float64, False)
-        sv["f64"] = {"ms": round(ms_d, 3), "GBps": round(b64 / ms_d / 1e6, 1),
-                     "frac": round(b64 / ms_d / 1e6 / HBM_PEAK_GBPS, 4)}
+    if args.copy_gb > 0:
+        nbytes = int(args.copy_gb * 1e9) // 16 * 16
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes (read {nbytes}, write {nbytes} each)")
+        del src, dst
+    if args.quick:
+        sv = None
+    else:
+        ms_t = sv_time(M1 if scaled else Mt)
+        pb1 = product_bytes(n_s, n_p, dt_t, scaled)
+        sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb1 / ms_t / 1e6, 1),
+                          "frac": round(pb1 / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
+        if scaled:
+            ms_2 = sv_time(M2)
+            b2 = product_bytes(n_s, n_p, dt_t, scaled, 2)
+            sv["bf16_two_planes"] = {"ms": round(ms_2, 3), "GBps": round(b2 / ms_2 / 1e6, 1),
+                                     "frac": round(b2 / ms_2 / 1e6 / HBM_PEAK_GBPS, 4)}
+            ms_d = sv_time(M64)
+            b64 = product_bytes(n_s, n_p, torch.float64, False)
+            sv["f64"] = {"ms": round(ms_d, 3), "GBps": round(b64 / ms_d / 1e6, 1),
+                         "frac": round(b64 / ms_d / 1e6 / HBM_PEAK_GBPS, 4)}
 
     err = None
     if x64 is not None:
         err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
 
     # ---- CPU baseline (oracle, bounded sample) ----
-    log("[bench] cpu baseline")
-    cpu = cpu_baseline(O64, min(args.cpu_rows, n_s), eps, args.cpu_budget)
+    cpu = None
+    if not args.quick:
+        log("[bench] cpu baseline")
+        cpu = cpu_baseline(O64, min(args.cpu_rows, n_s), eps, args.cpu_budget)
+
+    # HBM traffic of the CG launch from the committed counter record (same kernel build and
+    # same algorithmic bytes per launch), else null
+    traffic = None
+    rec = traffic_record("void sr::k_cg<2, 2, 1, 1, 1, 512, 1>(sr::CgArgs)") if (scaled and planes == 2
+                                                                                 and not args.refine) else None
+    if rec is not None and abs(rec["algorithmic_bytes"] - cg_bytes) <= 1e-6 * cg_bytes:
+        traffic = round(rec["traffic_bytes"] / 1e9, 1)
 
     out = {
         "metric": METRIC,
@@ -289,9 +345,10 @@ def main():
             "n_s": n_s, "n_p": n_p, "seed": cfg.seed, "parallelism": "single GPU",
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_cg (persistent CG; products read O once each)",
-                     "bytes_per_launch": round(cg_bytes), "launch_ms": round(cg_avg, 3)},
+                     "algorithmic_GB_per_launch": round(cg_bytes / 1e9, 1), "launch_ms": round(cg_avg, 3)},
         "cpu_baseline": cpu,
         "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
                   "residual_products": residuals, "planes": planes, "search_planes": search_planes,
