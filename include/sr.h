@@ -166,6 +166,25 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
                   const double *v, double *y, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * sr_adjoint: gradients of a loss L(x) through the SR solve x = (S + eps I)^{-1} g with
+ * S and g the sampled quantities of sr_grad (Sec. II.A, Eq. sr_overlap and the right-hand
+ * side of Eq. sr_lin_eq), given x and lambda = (S + eps I)^{-1} dL/dx (a second
+ * sr_cg_solve).  One read of O gives p1 = Oc x and p2 = Oc lambda; then
+ *   dE_k      = (2/n_s) p2_k                                              [n_s]
+ *   dO_kj     = (1/n_s) [ (2 (E_k - E_mean) - p1_k) lambda_j - p2_k x_j ]   [n_s][ld_dO]
+ * (dL/dg = lambda and dL/deps = -lambda . x need no kernel).  The derivative is taken
+ * with respect to the stored values of O (s_j q_kj for scaled storage), the column means
+ * depending on O included.
+ * O: single code plane (O_lo = NULL); col_mean may be NULL (computed).  E, x, lam:
+ * device float64 [n_s], [n_p], [n_p].  dE: device [n_s] float64 or NULL.  dO: device,
+ * dO_dtype SR_F64 or SR_F32, row stride ld_dO >= n_p elements with 16-byte aligned rows,
+ * or NULL (columns >= n_p are not written).  p12: device [2 n_s] float64 (p1 then p2) or
+ * NULL.  Outputs must not overlap the inputs.  Asynchronous on `stream`.
+ * ------------------------------------------------------------------------------------ */
+int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const double *lam, double *dE,
+               void *dO, int32_t dO_dtype, int64_t ld_dO, double *p12, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * sr_quantize: storage conversion of a float64 or float32 matrix to SR_BF16 or SR_F16
  * codes with per-column float32 scales (not in the paper; the precision form):
  *   s_j = float32(max_k |O_kj|)  (1 for an all-zero column)

@@ -515,6 +515,98 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
+int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const double *lam, double *dE, void *dO,
+               int32_t dO_dtype, int64_t ld_dO, double *p12, hipStream_t stream) {
+  int rc = check_matrix(O, "sr_adjoint");
+  if (rc) return rc;
+  if (O->O_lo != nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: a second code plane is not supported");
+  if (E == nullptr || x == nullptr || lam == nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: null E, x or lam");
+  const int64_t n_s = O->n_s, n_p = O->n_p;
+  if (dO != nullptr) {
+    if (dO_dtype != SR_F64 && dO_dtype != SR_F32)
+      return fail(SR_ERR_INVALID, "sr_adjoint: dO_dtype must be SR_F64 or SR_F32");
+    const int64_t eb = dO_dtype == SR_F64 ? 8 : 4;
+    if (ld_dO < n_p || ((uintptr_t)dO % 16) != 0 || (ld_dO * eb) % 16 != 0)
+      return fail(SR_ERR_INVALID, "sr_adjoint: dO needs ld_dO >= n_p and 16-byte aligned rows");
+    const int64_t nb = ((n_s - 1) * ld_dO + n_p) * eb;
+    if (ranges_overlap(dO, nb, O->O, n_s * O->ld * elem_bytes(O->dtype)) || ranges_overlap(dO, nb, x, n_p * 8) ||
+        ranges_overlap(dO, nb, lam, n_p * 8) || ranges_overlap(dO, nb, E, n_s * 8) ||
+        (dE != nullptr && ranges_overlap(dO, nb, dE, n_s * 8)))
+      return fail(SR_ERR_INVALID, "sr_adjoint: dO overlaps another argument");
+  }
+  if (dE != nullptr && (ranges_overlap(dE, n_s * 8, E, n_s * 8) || ranges_overlap(dE, n_s * 8, x, n_p * 8) ||
+                        ranges_overlap(dE, n_s * 8, lam, n_p * 8)))
+    return fail(SR_ERR_INVALID, "sr_adjoint: dE overlaps another argument");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  double *mscr = nullptr;
+  if (!O->col_mean) {
+    rc = get_mean_scratch(dev, stream, n_p, &mscr);
+    if (rc) return rc;
+  }
+  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
+  if (rc) return rc;
+  // row dots: column groups of NV 16-byte vectors per thread, about 2048 workgroups
+  const int vec = vec_of(O->dtype), nt = adjoint_threads(), rr = adjoint_rows_per_block();
+  const int nv = n_p >= (int64_t)4 * vec * nt * 8 ? 4 : (n_p >= (int64_t)2 * vec * nt * 8 ? 2 : 1);
+  const int64_t cols = (int64_t)nv * vec * nt;
+  const int C = (int)std::min<int64_t>(cdiv(n_p, cols), 1 << 20);
+  const int RG = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_s, rr), std::max<int64_t>(1, 2048 / C)));
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, (size_t)C * n_s * 16 + (size_t)n_s * 16 + 1024, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  RowDotsArgs ra{};
+  ra.O = (const unsigned char *)O->O;
+  ra.ldb = O->ld * elem_bytes(O->dtype);
+  ra.scale = O->col_scale;
+  ra.mean = mean;
+  ra.x = x;
+  ra.lam = lam;
+  ra.n_s = n_s;
+  ra.n_p = n_p;
+  ra.wslice = round_up(cdiv(n_p, C), vec);
+  ra.C = C;
+  ra.RG = RG;
+  ra.part = cv.take<double>((int64_t)C * n_s * 2);
+  {
+    void *args[] = {&ra};
+    HIP_TRY(hipLaunchKernel(rowdots_kernel(O->dtype, nv), dim3((unsigned)((int64_t)C * RG)), dim3(nt), args, 0,
+                            stream));
+  }
+  AdjFinishArgs fa{};
+  fa.E = E;
+  fa.part = ra.part;
+  fa.n_s = n_s;
+  fa.C = C;
+  fa.coef = cv.take<double>(2 * n_s);
+  fa.dE = dE;
+  fa.p12 = p12;
+  {
+    void *args[] = {&fa};
+    HIP_TRY(hipLaunchKernel(adjoint_finish_kernel(), dim3(1), dim3(1024), args, 0, stream));
+  }
+  if (dO != nullptr) {
+    Rank2Args wa{};
+    wa.coef = fa.coef;
+    wa.lam = lam;
+    wa.x = x;
+    wa.n_s = n_s;
+    wa.n_p = n_p;
+    wa.ld = ld_dO;
+    wa.dO = dO;
+    const int W = dO_dtype == SR_F64 ? 2 : 4;
+    const unsigned bx = (unsigned)cdiv(n_p, (int64_t)nt * W);
+    const unsigned by = (unsigned)std::min<int64_t>(n_s, std::max<int64_t>(1, 16384 / (int64_t)bx));
+    void *args[] = {&wa};
+    HIP_TRY(hipLaunchKernel(rank2_kernel(dO_dtype), dim3(bx, by), dim3(nt), args, 0, stream));
+  }
+  return SR_OK;
+}
+
 int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const double *v, double *y,
                   hipStream_t stream) {
   int rc = check_matrix(O, "lm_hv_product(O)");

@@ -82,6 +82,33 @@ struct QuantArgs {
 #define SR_SR_CONFIGS_F16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512)
 #define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)
 
+// Adjoint backward (row dots, finish, rank-2 write).
+struct RowDotsArgs {
+  const unsigned char *O;
+  int64_t ldb;                       // row stride in bytes
+  const float *scale;                // column scales (scaled storage) or nullptr
+  const double *mean, *x, *lam;
+  int64_t n_s, n_p, wslice;
+  int C, RG;
+  double *part;                      // [C][n_s][2]
+};
+struct AdjFinishArgs {
+  const double *E, *part;
+  int64_t n_s;
+  int C;
+  double *coef, *dE, *p12;
+};
+struct Rank2Args {
+  const double *coef, *lam, *x;
+  int64_t n_s, n_p, ld;              // ld in elements of the output type
+  void *dO;
+};
+const void *rowdots_kernel(int dt, int nv);
+const void *adjoint_finish_kernel();
+const void *rank2_kernel(int out_dt);
+int adjoint_threads();
+int adjoint_rows_per_block();
+
 struct KernelEntry {
   int dt, nv, r, look, poll, nt;
   int kind;              // 0: SR (sv + cg), 1: LM

@@ -52,6 +52,8 @@ PROTOTYPES = {
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
+    "sr_adjoint": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, ctypes.c_int64,
+                                  _c_p, _c_p]),
     "sr_tile_configs": (ctypes.c_int, [_c_i32, _c_i32, ctypes.POINTER(ctypes.c_int32), _c_i32]),
     "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -256,6 +258,31 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
            "lm_hv_product")
     return y
+
+
+def sr_adjoint(M: Matrix, E: torch.Tensor, x: torch.Tensor, lam: torch.Tensor, dO_dtype=torch.float32,
+               want_dE: bool = True, want_p12: bool = False, stream=None):
+    """Gradients through the SR solve (sr_adjoint): returns (dO, dE, p12); dO is an
+    (n_s, n_p) tensor of dO_dtype (None if dO_dtype is None), dE [n_s] float64 or None,
+    p12 [2, n_s] float64 (p1 = Oc x, p2 = Oc lambda) or None."""
+    n_s = M.O.shape[0]
+    E = _vec(E, n_s, "E")
+    x = _vec(x, M.n_p, "x")
+    lam = _vec(lam, M.n_p, "lam")
+    dO = dO_arg = None
+    code, ld = 0, 0
+    if dO_dtype is not None:
+        code = _TORCH_DT[dO_dtype]
+        vec = 16 // _ELEM[code]
+        ld = ((M.n_p + vec - 1) // vec) * vec
+        dO_arg = torch.empty(n_s, ld, dtype=dO_dtype, device=E.device)
+        dO = dO_arg[:, :M.n_p]
+    dE = torch.empty(n_s, dtype=torch.float64, device=E.device) if want_dE else None
+    p12 = torch.empty(2, n_s, dtype=torch.float64, device=E.device) if want_p12 else None
+    m = M.c()
+    _check(lib().sr_adjoint(ctypes.byref(m), _ptr(E), _ptr(x), _ptr(lam), _ptr(dE), _ptr(dO_arg), code, ld,
+                            _ptr(p12), _stream(stream)), "sr_adjoint")
+    return dO, dE, p12
 
 
 def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, with_lo: bool = False, stream=None):

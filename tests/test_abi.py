@@ -22,7 +22,7 @@ def _declared_functions():
 
 def test_header_declares_the_entry_points():
     names = _declared_functions()
-    for n in ("sr_grad", "sr_sv_product", "sr_cg_solve", "lm_hv_product", "sr_quantize", "sr_release",
+    for n in ("sr_grad", "sr_sv_product", "sr_cg_solve", "lm_hv_product", "sr_quantize", "sr_adjoint", "sr_release",
               "sr_status_string", "sr_last_error", "sr_version"):
         assert n in names, n
 
@@ -124,9 +124,19 @@ def test_invalid_scalars_rejected():
     assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, None, 8, sr.SR_F32, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
     assert L.sr_quantize(4, 3, v, 2, sr.SR_F64, y, None, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
     assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, y, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
+    # adjoint
+    assert L.sr_adjoint(ctypes.byref(m), None, v, v, None, None, 0, 0, None, None) == sr.SR_ERR_INVALID
+    dO = ctypes.c_void_p(1 << 24)
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_BF16, 4, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_F64, 2, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p((1 << 24) + 8), sr.SR_F64, 4, None,
+                        None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p(4096), sr.SR_F64, 4, None,
+                        None) == sr.SR_ERR_INVALID          # overlaps v
     # lm: a second code plane is rejected
     mb = _mat(dtype=sr.SR_BF16, ld=8, scale=512, lo=1024)
     assert L.lm_hv_product(ctypes.byref(mb), E, ctypes.byref(mb), v, y, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(mb), E, v, v, None, None, 0, 0, None, None) == sr.SR_ERR_INVALID
 
 
 def test_no_device_reported_without_gpu():
