@@ -166,6 +166,41 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
                   const double *v, double *y, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Several right-hand sides and batches of systems (the batched form; the paper solves
+ * one system at a time).  Up to SR_BATCH_MAX_RHS columns share every read of O:
+ *   Y = (S + diag(eps)) V,  i.e. W = Oc V, Y = (1/n_s) Oc^T W + V diag(eps).
+ * sr_svk_product: V, Y: device [k][n_p] float64 (column i at V + i n_p), must not
+ * overlap; eps: host [k].  exact = 1 accumulates in float64 (otherwise float32 storage
+ * accumulates in float32).  Storage SR_F64 or SR_F32, one code plane.  Synchronizes
+ * `stream` (its launch descriptor is copied from host memory).
+ * sr_cg_solve_batched: n_sys independent systems (each its own O, k right-hand sides g
+ * and shifts eps), all solved in one persistent launch, system after system; within a
+ * system the k CG iterations share each product.  Each column stops when its true
+ * residual reaches opt->rtol (checked with a float64-accumulated product whenever its
+ * recurrence residual gets there, every opt->refresh_every iterations and at max_iter).
+ * sys: host [n_sys]; every O has the same dtype (SR_F64 or SR_F32).  info: host
+ * [n_sys * k] (system-major) or NULL; its `refreshes` is 0 and rel_res_recur repeats
+ * rel_res_true.  With SR_F32 storage the search products accumulate in float32: a
+ * refresh is also taken once a column's residual fell by opt->refresh_drop (0: 1e-3)
+ * since the last one, and every refresh restarts the search directions (inexact
+ * iterative refinement).  opt->use_x0, restart_on_refresh, refine and res_history are
+ * not used.  Synchronizes `stream`.  Returns SR_OK if every column converged, else
+ * SR_NOT_CONVERGED / SR_BREAKDOWN (the first such status met) or an error code.
+ * ------------------------------------------------------------------------------------ */
+#define SR_BATCH_MAX_RHS 8
+typedef struct sr_batch_system {
+  sr_matrix O;               /* the system's matrix; col_mean may be NULL (computed)    */
+  const double *g;           /* device [k][n_p] right-hand sides                        */
+  double *x;                 /* device [k][n_p] solutions                               */
+  double eps[SR_BATCH_MAX_RHS]; /* shift of each right-hand side, >= 0                 */
+} sr_batch_system;
+
+int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double *eps, double *Y, int32_t exact,
+                   hipStream_t stream);
+int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, const sr_cg_opts *opt,
+                        sr_cg_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * sr_adjoint: gradients of a loss L(x) through the SR solve x = (S + eps I)^{-1} g with
  * S and g the sampled quantities of sr_grad (Sec. II.A, Eq. sr_overlap and the right-hand
  * side of Eq. sr_lin_eq), given x and lambda = (S + eps I)^{-1} dL/dx (a second

@@ -132,9 +132,10 @@ int device_check(int *dev_out, DeviceInfo *info_out) {
 
 // Workspace of at least `bytes` for (dev, stream); grows by reallocation (after the
 // stream has drained).
-int get_workspace(int dev, hipStream_t s, size_t bytes, void **out) {
+int get_workspace(int dev, hipStream_t s, size_t bytes, void **out,
+                  std::map<std::pair<int, hipStream_t>, Workspace> &table = g_ws) {
   std::lock_guard<std::mutex> lk(g_mu);
-  Workspace &w = g_ws[std::make_pair(dev, s)];
+  Workspace &w = table[std::make_pair(dev, s)];
   if (w.bytes < bytes) {
     if (w.ptr) {
       HIP_TRY(hipStreamSynchronize(s));
@@ -338,6 +339,9 @@ int ensure_mean(const sr_matrix *m, double *scratch, const double **mean_out, in
 // Separate small allocation for means computed on behalf of the caller, so they survive
 // the workspace being re-carved by the product launch that follows.
 std::map<std::pair<int, hipStream_t>, Workspace> g_mean_ws;
+// Buffers of the batched calls (kept apart from g_ws, which the prepare passes they
+// launch first carve for themselves).
+std::map<std::pair<int, hipStream_t>, Workspace> g_batch_ws;
 
 int get_mean_scratch(int dev, hipStream_t s, int64_t n, double **out) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -391,7 +395,7 @@ const char *sr_status_string(int status) {
 int sr_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = SR_OK;
-  for (auto *mp : {&g_ws, &g_mean_ws}) {
+  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws}) {
     for (auto &kv : *mp) {
       if (kv.second.ptr) {
         int cur = 0;
@@ -513,6 +517,246 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
     return launch_coop(pl.ke->sv2, pl.pg.G, &a, stream, pl.ke->nt, 0);
   }
   return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+}
+
+// ------------------------------------------------------------------------------------
+// Several right-hand sides, batches of systems
+// ------------------------------------------------------------------------------------
+int check_batch_matrix(const sr_matrix *m, const char *where) {
+  int rc = check_matrix(m, where);
+  if (rc) return rc;
+  if (m->dtype != SR_F64 && m->dtype != SR_F32)
+    return fail(SR_ERR_INVALID, "%s: storage must be SR_F64 or SR_F32", where);
+  if (m->O_lo != nullptr) return fail(SR_ERR_INVALID, "%s: a second code plane is not supported", where);
+  return SR_OK;
+}
+
+int fill_zero(void *p, int64_t words, hipStream_t s) {
+  uint32_t v = 0;
+  uint32_t *q = (uint32_t *)p;
+  void *args[] = {&q, &words, &v};
+  const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(words, 256)));
+  HIP_TRY(hipLaunchKernel(fill_kernel(), dim3(blocks), dim3(256), args, 0, s));
+  return SR_OK;
+}
+
+// Carves the buffers every batched launch uses; the zeroed part (barrier flags, abort
+// word, exchange ring) is cleared by a fill kernel.
+struct BatchWs {
+  BatchArgs a{};
+  uint32_t *zero_base = nullptr;
+  int64_t zero_words = 0;
+};
+size_t batch_ws_bytes(int G, int64_t vstride, int64_t ypart_doubles) {
+  const int K = kBatchK, words = K * 2;   // R = 1 tiles, float64-sized exchange words
+  size_t b = 0;
+  auto add = [&](size_t n) { b = (size_t)round_up((int64_t)b, 256) + n; };
+  add(G * 4);
+  add(64 * 4);
+  add((size_t)G * kRing * words * 8);
+  add((size_t)G * words * 8);
+  add((size_t)4 * K * G * 8);
+  add((size_t)ypart_doubles * 8);
+  add((size_t)2 * G * (K + 1) * 8);
+  for (int i = 0; i < 4; ++i) add((size_t)K * vstride * 8);
+  return b + 256;
+}
+void carve_batch(Carve &cv, int G, int64_t vstride, int64_t ypart_doubles, BatchWs *w) {
+  const int K = kBatchK, words = K * 2;
+  const size_t start = (size_t)round_up((int64_t)cv.off, 256);
+  w->a.sb.flags = cv.take<uint32_t>(G);
+  w->a.sb.abort = cv.take<uint32_t>(64);
+  w->a.pb.xchg = cv.take<u64>((int64_t)G * kRing * words);
+  const size_t end = cv.off;
+  w->zero_base = (uint32_t *)(cv.base + start);
+  w->zero_words = (int64_t)((end - start + 3) / 4);
+  w->a.pb.sink = cv.take<u64>((int64_t)G * words);
+  w->a.red = cv.take<double>((int64_t)4 * K * G);
+  w->a.pb.ypart = cv.take<double>(ypart_doubles);
+  w->a.pb.spart = cv.take<double>((int64_t)2 * G * (K + 1));   // two halves (BatchKernel::apply)
+  w->a.x = cv.take<double>((int64_t)K * vstride);
+  w->a.r = cv.take<double>((int64_t)K * vstride);
+  w->a.p = cv.take<double>((int64_t)K * vstride);
+  w->a.q = cv.take<double>((int64_t)K * vstride);
+  w->a.vstride = vstride;
+}
+
+int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double *eps, double *Y, int32_t exact,
+                   hipStream_t stream) {
+  int rc = check_batch_matrix(O, "sr_svk_product");
+  if (rc) return rc;
+  if (k < 1 || k > kBatchK) return fail(SR_ERR_INVALID, "sr_svk_product: k must be in [1, %d]", kBatchK);
+  if (V == nullptr || Y == nullptr || eps == nullptr) return fail(SR_ERR_INVALID, "sr_svk_product: null V, Y or eps");
+  if (exact != 0 && exact != 1) return fail(SR_ERR_INVALID, "sr_svk_product: exact must be 0 or 1");
+  const int64_t n_p = O->n_p;
+  if (ranges_overlap(V, k * n_p * 8, Y, k * n_p * 8)) return fail(SR_ERR_INVALID, "sr_svk_product: V and Y overlap");
+  for (int i = 0; i < k; ++i)
+    if (!(eps[i] >= 0.0) || !std::isfinite(eps[i]))
+      return fail(SR_ERR_INVALID, "sr_svk_product: eps must be finite and >= 0");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  double *mscr = nullptr;
+  if (!O->col_mean) {
+    rc = get_mean_scratch(dev, stream, n_p, &mscr);
+    if (rc) return rc;
+  }
+  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
+  if (rc) return rc;
+  const BatchEntry *be = batched_entry(O->dtype);
+  BatchSys S{};
+  const int vec = vec_of(O->dtype);
+  rc = geometry(di.grid, O->n_s, n_p, be->nv * vec * be->nt, vec, be->r, 0, &S.pg);
+  if (rc) return rc;
+  S.op = make_operand(O);
+  S.mean = mean;
+  S.k = k;
+  for (int i = 0; i < kBatchK; ++i) S.eps[i] = i < k ? eps[i] : 0.0;
+  void *base = nullptr;
+  const int64_t yp = (int64_t)kBatchK * S.pg.RG * n_p;
+  rc = get_workspace(dev, stream, batch_ws_bytes(di.grid, n_p, yp) + 1024, &base, g_batch_ws);
+  if (rc) return rc;
+  Carve cv(base);
+  BatchWs w;
+  carve_batch(cv, di.grid, n_p, yp, &w);
+  BatchSys *table = cv.take<BatchSys>(1);
+  // V padded to kBatchK columns in the p buffer, the result in q
+  S.g = w.a.p;
+  HIP_TRY(hipMemcpyAsync(w.a.p, V, (size_t)k * n_p * 8, hipMemcpyDeviceToDevice, stream));
+  if (k < kBatchK) {
+    rc = fill_zero(w.a.p + (int64_t)k * n_p, (int64_t)(kBatchK - k) * n_p * 2, stream);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipMemcpyAsync(table, &S, sizeof(S), hipMemcpyHostToDevice, stream));
+  w.a.sys = table;
+  w.a.n_sys = 1;
+  w.a.refresh_every = exact;     // k_svk: 1 selects float64 accumulation
+  rc = fill_zero(w.zero_base, w.zero_words, stream);
+  if (rc) return rc;
+  rc = launch_coop(be->sv, di.grid, &w.a, stream, be->nt, 0);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(Y, w.a.q, (size_t)k * n_p * 8, hipMemcpyDeviceToDevice, stream));
+  // the host copy of the table must outlive the copy above: wait for it
+  HIP_TRY(hipStreamSynchronize(stream));
+  return SR_OK;
+}
+
+int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, const sr_cg_opts *opt,
+                        sr_cg_info *info, hipStream_t stream) {
+  if (n_sys < 1 || sys == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: need n_sys >= 1 systems");
+  if (k < 1 || k > kBatchK) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: k must be in [1, %d]", kBatchK);
+  int64_t max_np = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    const sr_batch_system &b = sys[s];
+    int rc = check_batch_matrix(&b.O, "sr_cg_solve_batched");
+    if (rc) return rc;
+    if (b.O.dtype != sys[0].O.dtype) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: systems differ in dtype");
+    if (b.g == nullptr || b.x == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: null g or x");
+    if (ranges_overlap(b.g, k * b.O.n_p * 8, b.x, k * b.O.n_p * 8))
+      return fail(SR_ERR_INVALID, "sr_cg_solve_batched: g and x overlap");
+    for (int i = 0; i < k; ++i)
+      if (!(b.eps[i] >= 0.0) || !std::isfinite(b.eps[i]))
+        return fail(SR_ERR_INVALID, "sr_cg_solve_batched: eps must be finite and >= 0");
+    max_np = std::max<int64_t>(max_np, b.O.n_p);
+  }
+  sr_cg_opts o{};
+  o.rtol = 1e-10;
+  if (opt) o = *opt;
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: bad rtol");
+  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve_batched: refresh_every must be >= 0");
+  int64_t max_iter = o.max_iter > 0 ? o.max_iter : max_np + 100;
+  if (max_iter > (1 << 30)) max_iter = 1 << 30;
+  int dev;
+  DeviceInfo di;
+  int rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const int dt = sys[0].O.dtype, vec = vec_of(dt);
+  const BatchEntry *be = batched_entry(dt);
+  std::vector<BatchSys> host(n_sys);
+  int64_t yp = 0, mean_total = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    rc = geometry(di.grid, sys[s].O.n_s, sys[s].O.n_p, be->nv * vec * be->nt, vec, be->r, 0, &host[s].pg);
+    if (rc) return rc;
+    yp = std::max<int64_t>(yp, (int64_t)kBatchK * host[s].pg.RG * sys[s].O.n_p);
+    if (!sys[s].O.col_mean) mean_total += round_up(sys[s].O.n_p, 32);
+  }
+  const size_t info_n = (size_t)n_sys * kBatchK * 4 + 1;
+  const size_t bytes = batch_ws_bytes(di.grid, max_np, yp) + (size_t)mean_total * 8 + info_n * 8 +
+                       (size_t)n_sys * sizeof(BatchSys) + 4096;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, bytes, &base, g_batch_ws);
+  if (rc) return rc;
+  Carve cv(base);
+  double *means = cv.take<double>(std::max<int64_t>(mean_total, 1));
+  BatchSys *table = cv.take<BatchSys>(n_sys);
+  double *dinfo = cv.take<double>((int64_t)info_n);
+  BatchWs w;
+  carve_batch(cv, di.grid, max_np, yp, &w);
+  int64_t moff = 0;
+  for (int s = 0; s < n_sys; ++s) {
+    const sr_batch_system &b = sys[s];
+    BatchSys &S = host[s];
+    S.op = make_operand(&b.O);
+    if (b.O.col_mean) {
+      S.mean = b.O.col_mean;
+    } else {
+      double *m = means + moff;
+      moff += round_up(b.O.n_p, 32);
+      rc = run_grad(&b.O, nullptr, nullptr, nullptr, m, nullptr, dev, di, stream);
+      if (rc) return rc;
+      S.mean = m;
+    }
+    S.g = b.g;
+    S.x = b.x;
+    S.k = k;
+    for (int i = 0; i < kBatchK; ++i) S.eps[i] = i < k ? b.eps[i] : 0.0;
+  }
+  HIP_TRY(hipMemcpyAsync(table, host.data(), (size_t)n_sys * sizeof(BatchSys), hipMemcpyHostToDevice, stream));
+  w.a.sys = table;
+  w.a.n_sys = n_sys;
+  w.a.rtol = o.rtol;
+  w.a.max_iter = (int)max_iter;
+  w.a.refresh_every = o.refresh_every;
+  // float32 storage: search products accumulate in float32; refresh (and restart) once
+  // the residual fell by refresh_drop (default 1e-3, above that rounding level)
+  if (!(o.refresh_drop >= 0.0 && o.refresh_drop < 1.0))
+    return fail(SR_ERR_INVALID, "sr_cg_solve_batched: refresh_drop must be in [0, 1)");
+  const double drop = o.refresh_drop > 0.0 ? o.refresh_drop : (dt == SR_F32 ? 1e-3 : 0.0);
+  w.a.refresh_drop2 = drop * drop;
+  w.a.info = dinfo;
+  rc = fill_zero(w.zero_base, w.zero_words, stream);
+  if (rc) return rc;
+  rc = fill_zero(dinfo, (int64_t)info_n * 2, stream);
+  if (rc) return rc;
+  rc = launch_coop(be->cg, di.grid, &w.a, stream, be->nt, 0);
+  if (rc) return rc;
+  std::vector<double> hinfo(info_n);
+  uint32_t habort = 0;
+  HIP_TRY(hipMemcpyAsync(hinfo.data(), dinfo, info_n * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&habort, w.a.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (habort != 0u || hinfo[info_n - 1] == 0.0)
+    return fail(SR_ERR_TIMEOUT, "sr_cg_solve_batched: a cross-workgroup wait timed out");
+  int status = SR_OK;
+  for (int s = 0; s < n_sys; ++s)
+    for (int i = 0; i < k; ++i) {
+      const double *h = &hinfo[((size_t)s * kBatchK + i) * 4];
+      const int st = (int)h[1];
+      if (info) {
+        sr_cg_info &ci = info[(size_t)s * k + i];
+        ci.iters = (int32_t)h[0];
+        ci.refreshes = 0;
+        ci.status = st;
+        ci.products = (int32_t)h[3];
+        ci.rel_res_recur = h[2];
+        ci.rel_res_true = h[2];
+      }
+      if (status == SR_OK && st != SR_OK) status = st;
+    }
+  if (status < 0) return fail(status, "sr_cg_solve_batched: a column reported %s", sr_status_string(status));
+  return status;
 }
 
 int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const double *lam, double *dE, void *dO,

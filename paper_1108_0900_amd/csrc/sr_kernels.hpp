@@ -577,4 +577,343 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   }
 }
 
+// ======================================================================================
+// Several right-hand sides: Y = (S + diag(eps)) V for the K columns of V, one read of O
+// ======================================================================================
+// Sum of N values per workgroup over the grid, the same in every workgroup (fixed order).
+// red: [4][N][G] slots used round-robin (a set is reused only after three more
+// reductions, each of which contains a grid barrier).
+template <int N>
+__device__ __forceinline__ bool grid_allreduce_n(const double (&in)[N], double *red, int &nred, GridSync &gs,
+                                                 double (&out)[N]) {
+  __shared__ double s_w[16][N];
+  __shared__ double s_o[N];
+  const int G = (int)gridDim.x, set = nred & 3;
+  const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  nred++;
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    const double w = wave_sum(in[n]);
+    if (lane == 0) s_w[wave][n] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += s_w[w][threadIdx.x];
+    st_coh(&red[((int64_t)set * N + threadIdx.x) * G + blockIdx.x], t);
+  }
+  if (!grid_sync(gs)) return false;
+  if (wave < N) {      // wave n sums value n over the grid
+    double acc = 0.0;
+    for (int i = lane; i < G; i += 64) acc += ld_coh(&red[((int64_t)set * N + wave) * G + i]);
+    acc = wave_sum(acc);
+    if (lane == 0) s_o[wave] = acc;
+  }
+  if (N > 16) {        // more values than waves: the remaining ones by wave 0
+    for (int n = 16; n < N; ++n) {
+      if (wave == 0) {
+        double acc = 0.0;
+        for (int i = lane; i < G; i += 64) acc += ld_coh(&red[((int64_t)set * N + n) * G + i]);
+        acc = wave_sum(acc);
+        if (lane == 0) s_o[n] = acc;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < N; ++n) out[n] = s_o[n];
+  __syncthreads();
+  return true;
+}
+
+template <int DT, int NV, int R, int L, int P_, int NT>
+struct BatchKernel {
+  static constexpr int K = kBatchK;
+  // Columns per read of O: all K for the float32-accumulated products of 4-byte storage;
+  // the float64-accumulated ones (and 8-byte storage) take them in halves, whose
+  // coefficients and accumulators fit in registers.
+  template <bool EXACT>
+  static constexpr int kPer = (!EXACT && Storage<DT>::BYTES == 4) ? K : K / 2;
+  // float32-accumulated search products differ from the float64 residual products by
+  // their rounding: a refresh then restarts the search direction (inexact iterative
+  // refinement), since continuing it with a replaced residual is unstable
+  static constexpr bool kRestart = Storage<DT>::BYTES == 4;
+
+  // Columns [k0, k0 + KP): q_k = (S + eps_k I) v_k for this workgroup's chunk.  The
+  // halves of one apply use separate partial buffers (pb): a workgroup may start the
+  // second half while others still sum the first half's partials.
+  template <bool EXACT, int KP>
+  __device__ __forceinline__ static bool apply_cols(const BatchArgs &a, const BatchSys &S, WgCtx &ctx,
+                                                    const ProdBufs &pb, const double *vin, double *q, int64_t j0,
+                                                    int64_t j1, int k0) {
+    Product<DT, NV, (EXACT ? 1 : R), 1, EXACT, (EXACT ? 1 : L), (EXACT ? 1 : P_), NT, 1, KP> P;
+    const double *v = vin + (int64_t)k0 * a.vstride;
+    const double cshare = P.setup(ctx, S.pg, &S.op, S.mean, v, a.vstride);
+    if (!P.accumulate(S.pg, pb, ctx, &S.op, cshare, nullptr, 0.0)) return false;
+    P.store_partials(S.pg, pb, ctx);
+    if (!grid_sync(ctx.gs)) return false;
+    double S1[KP];
+    sum_row_scalars_k<KP>(pb, S.pg, S1);
+    const double inv_n = 1.0 / (double)S.pg.n_s;
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT) {
+      const double s = S.op.scale ? (double)S.op.scale[j] : 1.0;
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const double acc = finish_column(pb, S.pg, j, k);
+        st_coh(&q[(k0 + k) * a.vstride + j],
+               (s * acc - S.mean[j] * S1[k]) * inv_n + S.eps[k0 + k] * ld_coh(&v[k * a.vstride + j]));
+      }
+    }
+    return true;
+  }
+
+  // q_k = ((S + eps_k I) v_k) for all K columns.  EXACT: float64 accumulation
+  // (refreshes and exit checks).
+  template <bool EXACT>
+  __device__ __forceinline__ static bool apply(const BatchArgs &a, const BatchSys &S, WgCtx &ctx, const double *vin,
+                                               double *q, int64_t j0, int64_t j1) {
+    constexpr int KP = kPer<EXACT>;
+#pragma unroll
+    for (int h = 0; h < K / KP; ++h) {
+      ProdBufs pb = a.pb;
+      pb.ypart += (int64_t)h * KP * S.pg.RG * S.pg.n_p;
+      pb.spart += (int64_t)h * S.pg.G * (kBatchK + 1);
+      if (!apply_cols<EXACT, KP>(a, S, ctx, pb, vin, q, j0, j1, h * KP)) return false;
+    }
+    return true;
+  }
+};
+
+// Batched CG: for each system in turn, K independent CG iterations (one per right-hand
+// side and shift) whose products share every read of O.  A column that has converged
+// stops moving (step length zero) while the others continue.  All residuals are
+// recomputed from x with float64-accumulated products every refresh_every iterations,
+// whenever a column's recurrence residual reaches rtol (its convergence is confirmed by
+// the true residual, or it continues from it) and at max_iter.  Scalars are float64 and
+// the same in every workgroup (fixed-order reductions), so all take the same branches.
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_cg_batched(BatchArgs a) {
+  typedef BatchKernel<DT, NV, R, L, P_, NT> BK;
+  constexpr int K = kBatchK;
+  // The vectors x, r, p, q are split over the workgroups by each system's n_p, so a
+  // workgroup's share moves between systems: every access to them is coherent (a plain
+  // load could hit a line another workgroup's share left in this CU's cache).
+  // Per-column CG state is the same in every thread of the workgroup: it lives in LDS
+  // (thread 0 writes it, a barrier publishes it) so that no register holds it across
+  // the products.
+  __shared__ double s_rho[K], s_gg[K], s_rel[K], s_ref[K];
+  __shared__ int s_status[K], s_iters[K], s_done[K];
+  WgCtx ctx;
+  init_ctx(ctx, a.sys[0].pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  const int64_t vs = a.vstride;
+  double *const X = a.x;
+  int nred = 0;
+  bool ok = true;
+  for (int sidx = 0; sidx < a.n_sys && ok; ++sidx) {
+    const BatchSys &S = a.sys[sidx];
+    // every workgroup has finished the previous system (its results are copied out of the
+    // shared vectors) before this one overwrites them
+    if (sidx > 0 && !(ok = grid_sync(ctx.gs))) break;
+    // this system's geometry; the exchange step counter and barrier epochs carry on
+    map_workgroup((int)blockIdx.x, S.pg.G, S.pg.C, ctx.rg, ctx.cg);
+    ctx.c0 = min((int64_t)ctx.cg * S.pg.wslice, S.pg.n_p);
+    ctx.c1 = min(ctx.c0 + S.pg.wslice, S.pg.n_p);
+    const int64_t n = S.pg.n_p;
+    const int64_t ch = (n + G - 1) / G;
+    const int64_t j0 = min(n, (int64_t)blockIdx.x * ch), j1 = min(n, j0 + ch);
+    const int kuse = S.k;
+    {
+      // x = 0, r = p = g; columns >= k are zero and done from the start
+      double part[K], gg[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) part[k] = 0.0;
+      for (int64_t j = j0 + tid; j < j1; j += NT) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double gj = k < kuse ? S.g[k * n + j] : 0.0;
+          st_coh(&X[k * vs + j], 0.0);
+          st_coh(&a.r[k * vs + j], gj);
+          st_coh(&a.p[k * vs + j], gj);
+          part[k] += gj * gj;
+        }
+      }
+      if (!(ok = grid_allreduce_n<K>(part, a.red, nred, ctx.gs, gg))) break;
+      if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          s_rho[k] = gg[k];
+          s_ref[k] = gg[k];
+          s_gg[k] = gg[k] == 0.0 ? 1.0 : gg[k];
+          s_status[k] = 0;
+          s_iters[k] = 0;
+          s_done[k] = (k >= kuse || gg[k] == 0.0) ? 1 : 0;
+          s_rel[k] = s_done[k] ? 0.0 : -1.0;
+        }
+      }
+      __syncthreads();
+    }
+    int it = 0, products = 0;
+    bool refreshed = false;
+    while (true) {
+      bool any = false, check = false;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (s_done[k]) continue;
+        any = true;
+        check |= !isfinite(s_rho[k]) || sqrt(s_rho[k] / s_gg[k]) <= a.rtol || s_rho[k] <= a.refresh_drop2 * s_ref[k];
+      }
+      if (!any) break;
+      const bool at_limit = it >= a.max_iter;
+      const bool periodic = a.refresh_every > 0 && it > 0 && it % a.refresh_every == 0 && !refreshed;
+      if (check || at_limit || periodic) {
+        // true residuals of every column: r = g - (S + eps) x, float64 accumulation
+        if (!(ok = grid_sync(ctx.gs))) break;                     // x visible to all
+        if (!(ok = BK::template apply<true>(a, S, ctx, X, a.q, j0, j1))) break;
+        products += BK::template kPer<true> == K ? 1 : 2;
+        double part[K], red[K];
+        int done_mask = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          part[k] = 0.0;
+          done_mask |= s_done[k] ? (1 << k) : 0;
+        }
+        for (int64_t j = j0 + tid; j < j1; j += NT) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const double t = (k < kuse ? S.g[k * n + j] : 0.0) - ld_coh(&a.q[k * vs + j]);
+            if (!((done_mask >> k) & 1)) {
+              st_coh(&a.r[k * vs + j], t);
+              if (BK::kRestart) st_coh(&a.p[k * vs + j], t);   // visible after the reduction
+            }
+            part[k] += t * t;
+          }
+        }
+        if (!(ok = grid_allreduce_n<K>(part, a.red, nred, ctx.gs, red))) break;
+        if (tid == 0) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (s_done[k]) continue;
+            const double rt = sqrt(red[k] / s_gg[k]);
+            if (rt <= a.rtol || at_limit || !isfinite(rt)) {
+              s_rel[k] = rt;
+              s_status[k] = !isfinite(rt) ? -4 : (rt <= a.rtol ? 0 : 1);
+              s_done[k] = 1;
+              s_iters[k] = it;
+            } else {
+              s_rho[k] = red[k];       // continue from the true residual (p kept or restarted)
+              s_ref[k] = red[k];
+            }
+          }
+        }
+        __syncthreads();
+        refreshed = true;
+        continue;
+      }
+      // search step for every column (done ones do not move)
+      if (!(ok = BK::template apply<false>(a, S, ctx, a.p, a.q, j0, j1))) break;
+      products += BK::template kPer<false> == K ? 1 : 2;
+      {
+        double part[K], red[K], alpha[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k] = 0.0;
+        for (int64_t j = j0 + tid; j < j1; j += NT) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) part[k] += ld_coh(&a.p[k * vs + j]) * ld_coh(&a.q[k * vs + j]);
+        }
+        if (!(ok = grid_allreduce_n<K>(part, a.red, nred, ctx.gs, red))) break;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const bool live = !s_done[k] && isfinite(red[k]) && red[k] > 0.0;
+          alpha[k] = live ? s_rho[k] / red[k] : 0.0;
+        }
+        __syncthreads();        // every thread has read s_done / s_rho before thread 0 writes
+        if (tid == 0) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            if (s_done[k]) continue;
+            if (!isfinite(red[k])) {
+              s_status[k] = -4;
+              s_done[k] = 1;
+              s_iters[k] = it;
+            } else if (!(red[k] > 0.0)) {
+              s_status[k] = 2;           // breakdown: p . A p <= 0
+              s_done[k] = 1;
+              s_iters[k] = it;
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k] = 0.0;
+        for (int64_t j = j0 + tid; j < j1; j += NT) {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            double rj = ld_coh(&a.r[k * vs + j]);
+            if (alpha[k] != 0.0) {
+              st_coh(&X[k * vs + j], ld_coh(&X[k * vs + j]) + alpha[k] * ld_coh(&a.p[k * vs + j]));
+              rj -= alpha[k] * ld_coh(&a.q[k * vs + j]);
+              st_coh(&a.r[k * vs + j], rj);
+            }
+            part[k] += rj * rj;
+          }
+        }
+        if (!(ok = grid_allreduce_n<K>(part, a.red, nred, ctx.gs, red))) break;
+        // (the reduction's barriers published thread 0's writes above)
+        double beta[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) beta[k] = (!s_done[k] && s_rho[k] > 0.0) ? red[k] / s_rho[k] : 0.0;
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            if (!s_done[k]) s_rho[k] = red[k];
+        }
+        for (int64_t j = j0 + tid; j < j1; j += NT) {
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            st_coh(&a.p[k * vs + j], ld_coh(&a.r[k * vs + j]) + beta[k] * ld_coh(&a.p[k * vs + j]));
+        }
+      }
+      if (!(ok = grid_sync(ctx.gs))) break;                       // p visible to all (and s_rho)
+      it++;
+      refreshed = false;
+    }
+    if (!ok) break;
+    // results of this system
+    for (int64_t j = j0 + tid; j < j1; j += NT) {
+      for (int k = 0; k < kuse; ++k) S.x[k * n + j] = ld_coh(&X[k * vs + j]);
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      for (int k = 0; k < K; ++k) {
+        double *inf = a.info + ((int64_t)sidx * K + k) * 4;
+        inf[0] = (double)s_iters[k];
+        inf[1] = (double)s_status[k];
+        inf[2] = s_rel[k];
+        inf[3] = (double)products;
+      }
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && tid == 0) a.info[(int64_t)a.n_sys * K * 4] = ok ? 1.0 : 0.0;
+}
+
+// Standalone K-right-hand-side product (tests, timing): Y = (S + diag(eps)) V.
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_svk(BatchArgs a) {
+  typedef BatchKernel<DT, NV, R, L, P_, NT> BK;
+  const BatchSys &S = a.sys[0];
+  WgCtx ctx;
+  init_ctx(ctx, S.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  const int G = (int)gridDim.x;
+  const int64_t n = S.pg.n_p, ch = (n + G - 1) / G;
+  const int64_t j0 = min(n, (int64_t)blockIdx.x * ch), j1 = min(n, j0 + ch);
+  // V = g (stride vstride), Y = q (stride vstride); exact when refresh_every == 1
+  const bool ok = a.refresh_every == 1 ? BK::template apply<true>(a, S, ctx, S.g, a.q, j0, j1)
+                                       : BK::template apply<false>(a, S, ctx, S.g, a.q, j0, j1);
+  if (!ok) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += NT)
+      for (int k = 0; k < kBatchK; ++k) a.q[k * a.vstride + j] = __builtin_nan("");
+  }
+}
+
 }  // namespace sr

@@ -13,6 +13,17 @@ const KernelEntry *kernel_table_f32(int *count);
 const KernelEntry *kernel_table_bf16(int *count);
 const KernelEntry *kernel_table_f16(int *count);
 
+const BatchEntry *batched_entry_f64();
+const BatchEntry *batched_entry_f32();
+
+const BatchEntry *batched_entry(int dt) {
+  switch (dt) {
+    case DT_F64: return batched_entry_f64();
+    case DT_F32: return batched_entry_f32();
+    default: return nullptr;
+  }
+}
+
 const KernelEntry *kernel_table(int dt, int *count) {
   switch (dt) {
     case DT_F64: return kernel_table_f64(count);

@@ -82,6 +82,40 @@ struct QuantArgs {
 #define SR_SR_CONFIGS_F16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512)
 #define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)
 
+// Batched solves: K right-hand sides per system, systems one after another in one
+// persistent launch.
+constexpr int kBatchK = 8;           // right-hand sides per product of the batched kernels
+struct BatchSys {
+  Operand op;
+  const double *mean;                // [n_p] column means
+  const double *g;                   // [k][n_p] right-hand sides
+  double *x;                         // [k][n_p] solutions
+  ProdGeom pg;                       // geometry of this system's products
+  int k;                             // right-hand sides in use (<= kBatchK)
+  double eps[kBatchK];               // shift of each right-hand side
+};
+struct BatchArgs {
+  const BatchSys *sys;               // [n_sys] device table
+  int n_sys;
+  ProdBufs pb;                       // ypart [K][RG][n_p] and spart [RG][K + 1] of the largest system
+  SyncBufs sb;
+  double *red;                       // [4][2K][G] grid reductions
+  double *x, *r, *p, *q;             // [K][vstride]
+  int64_t vstride;                   // max n_p (stride of the K vectors)
+  double rtol;
+  int max_iter, refresh_every;
+  double refresh_drop2;              // squared residual drop that triggers a refresh; 0: off
+  double *info;                      // [n_sys][K][4]: iterations, status, rel. true residual,
+                                     // products; then [1]: 1 if no wait gave up
+};
+
+// The batched kernels of a storage type (float64 and float32 only).
+struct BatchEntry {
+  const void *cg, *sv;
+  int nv, r, nt;
+};
+const BatchEntry *batched_entry(int dt);   // nullptr if the type has none
+
 // Adjoint backward (row dots, finish, rank-2 write).
 struct RowDotsArgs {
   const unsigned char *O;

@@ -44,6 +44,13 @@ class SrCgInfo(ctypes.Structure):
                 ("rel_res_recur", _c_d), ("rel_res_true", _c_d)]
 
 
+BATCH_MAX_RHS = 8
+
+
+class SrBatchSystem(ctypes.Structure):
+    _fields_ = [("O", SrMatrix), ("g", _c_p), ("x", _c_p), ("eps", _c_d * BATCH_MAX_RHS)]
+
+
 PROTOTYPES = {
     "sr_grad": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "sr_sv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_d, _c_p]),
@@ -54,6 +61,10 @@ PROTOTYPES = {
     "sr_release": (ctypes.c_int, []),
     "sr_adjoint": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, ctypes.c_int64,
                                   _c_p, _c_p]),
+    "sr_svk_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_i32, _c_p, ctypes.POINTER(_c_d), _c_p, _c_i32,
+                                      _c_p]),
+    "sr_cg_solve_batched": (ctypes.c_int, [_c_i32, ctypes.POINTER(SrBatchSystem), _c_i32, ctypes.POINTER(SrCgOpts),
+                                           ctypes.POINTER(SrCgInfo), _c_p]),
     "sr_tile_configs": (ctypes.c_int, [_c_i32, _c_i32, ctypes.POINTER(ctypes.c_int32), _c_i32]),
     "sr_set_tile_config": (ctypes.c_int, [_c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32, _c_i32]),
     "sr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -258,6 +269,72 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
            "lm_hv_product")
     return y
+
+
+def _rhs_block(V: torch.Tensor, n_p: int, name: str) -> torch.Tensor:
+    if V.dtype != torch.float64 or V.dim() != 2 or V.shape[1] != n_p or not 1 <= V.shape[0] <= BATCH_MAX_RHS:
+        raise ValueError(f"{name} must be a float64 (k, {n_p}) tensor with 1 <= k <= {BATCH_MAX_RHS}")
+    return V.contiguous()
+
+
+def sr_svk_product(M: Matrix, V: torch.Tensor, eps, exact: bool = False, out: torch.Tensor | None = None,
+                   stream=None) -> torch.Tensor:
+    """Y = (S + diag(eps)) V for the k rows of V (k <= 8 right-hand sides, one read of O)."""
+    V = _rhs_block(V, M.n_p, "V")
+    k = V.shape[0]
+    eps = [float(e) for e in eps]
+    if len(eps) != k:
+        raise ValueError("one eps per right-hand side")
+    Y = torch.empty_like(V) if out is None else out
+    arr = (_c_d * k)(*eps)
+    m = M.c()
+    _check(lib().sr_svk_product(ctypes.byref(m), k, _ptr(V), arr, _ptr(Y), 1 if exact else 0, _stream(stream)),
+           "sr_svk_product")
+    return Y
+
+
+def sr_cg_solve_batched(systems, rtol: float = 1e-10, max_iter: int = 0, refresh_every: int = 0,
+                        refresh_drop: float = 0.0,
+                        raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT),
+                        stream=None):
+    """Solve many systems in one launch (sr_cg_solve_batched).  `systems` is a list of
+    (Matrix, G, eps) with G a float64 (k, n_p) tensor of right-hand sides and eps a list of
+    k shifts; k must be the same for all.  Returns (list of X tensors (k, n_p), list of
+    per-system lists of per-column info dicts, status)."""
+    k = None
+    descs = (SrBatchSystem * len(systems))()
+    keep, xs = [], []
+    for i, (M, G, eps) in enumerate(systems):
+        G = _rhs_block(G, M.n_p, "G")
+        if k is None:
+            k = G.shape[0]
+        elif G.shape[0] != k:
+            raise ValueError("every system needs the same number of right-hand sides")
+        if len(eps) != k:
+            raise ValueError("one eps per right-hand side")
+        X = torch.empty_like(G)
+        descs[i].O = M.c()
+        descs[i].g = G.data_ptr()
+        descs[i].x = X.data_ptr()
+        for j in range(BATCH_MAX_RHS):
+            descs[i].eps[j] = float(eps[j]) if j < k else 0.0
+        keep.append(G)
+        xs.append(X)
+    opts = SrCgOpts()
+    opts.rtol = float(rtol)
+    opts.max_iter = int(max_iter)
+    opts.refresh_every = int(refresh_every)
+    opts.refresh_drop = float(refresh_drop)
+    infos = (SrCgInfo * (len(systems) * k))()
+    st = lib().sr_cg_solve_batched(len(systems), descs, k, ctypes.byref(opts), infos, _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "sr_cg_solve_batched")
+    out = []
+    for i in range(len(systems)):
+        out.append([{"iters": infos[i * k + j].iters, "status": infos[i * k + j].status,
+                     "products": infos[i * k + j].products, "rel_res_true": infos[i * k + j].rel_res_true}
+                    for j in range(k)])
+    return xs, out, st
 
 
 def sr_adjoint(M: Matrix, E: torch.Tensor, x: torch.Tensor, lam: torch.Tensor, dO_dtype=torch.float32,
