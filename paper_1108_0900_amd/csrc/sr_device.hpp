@@ -73,32 +73,40 @@ template <> struct Storage<DT_F16> {
   }
 };
 
-// Streaming 16-byte load of stored ratios (read once per product: non-temporal).
+// Streaming 16-byte load of stored ratios (read once per product: non-temporal).  The
+// pointer is cast to the global address space: a pointer the kernel read from memory
+// (a table of systems) would otherwise be generic, and generic (flat) loads also count
+// against the LDS wait counter, so every LDS wait would drain the tile prefetch.
+typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
 __device__ __forceinline__ u32x4 load_stream(const void *p) {
-  return __builtin_nontemporal_load((const u32x4 *)p);
+  return __builtin_nontemporal_load((global_u32x4 *)p);
 }
 
 // ------------------------------------------------------------------------------------
 // Coherent (device-scope) accesses for data shared between workgroups of one launch
 // ------------------------------------------------------------------------------------
+// (all of them address global memory: the casts keep pointers read from memory from
+// turning into generic accesses)
+typedef __attribute__((address_space(1))) u64 global_u64;
+typedef __attribute__((address_space(1))) uint32_t global_u32;
 __device__ __forceinline__ void st_coh(double *p, double v) {
-  __hip_atomic_store((u64 *)p, (u64)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((global_u64 *)p, (u64)__double_as_longlong(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double ld_coh(const double *p) {
   return __longlong_as_double(
-      (long long)__hip_atomic_load((u64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      (long long)__hip_atomic_load((global_u64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 __device__ __forceinline__ void st_coh64(u64 *p, u64 v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((global_u64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ u64 ld_coh64(const u64 *p) {
-  return __hip_atomic_load((u64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((global_u64 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_coh32(uint32_t *p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store((global_u32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t ld_coh32(const uint32_t *p) {
-  return __hip_atomic_load((uint32_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load((global_u32 *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Wait until this wave's outstanding vector-memory operations (including coherent stores)
 // have completed, so that a flag written afterwards is observed after them.
@@ -110,6 +118,34 @@ __device__ __forceinline__ void wait_vmem() { asm volatile("s_waitcnt vmcnt(0)" 
 template <typename T> __device__ __forceinline__ T wave_sum(T x) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
+constexpr int log2_exact(int n) { return n <= 1 ? 0 : 1 + log2_exact(n / 2); }
+
+// Sums of N values (N a power of two <= 64) over the 64 lanes of a wave by recursive
+// halving: at each of the first log2(N) exchange stages a lane keeps half of its values
+// and adds its partner's copies of them, so N sums cost N - 1 + 6 - log2(N) exchanges
+// instead of 6 N.  On return lane l holds the sum of value l >> (6 - log2(N)).
+template <int N, typename T> __device__ __forceinline__ T multi_wave_sum(T (&v)[N], int lane) {
+  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
+  constexpr int L = log2_exact(N);
+#pragma unroll
+  for (int s = 0; s < L; ++s) {
+    const int off = 32 >> s;
+    const int half = N >> (s + 1);
+    const bool upper = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const T send = upper ? v[i] : v[i + half];
+      const T keep = upper ? v[i + half] : v[i];
+      v[i] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  T x = v[0];
+#pragma unroll
+  for (int off = 32 >> L; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
 

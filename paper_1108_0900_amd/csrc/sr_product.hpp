@@ -434,13 +434,25 @@ struct Product {
       if (c < pg.C) words_add(w, acc);
     }
     if (!ok && lane == 0) st_coh32(ctx.gs.abort, 1u);
+    // fixed-order sums over the lanes (column groups)
+    if constexpr (ND * R <= 2) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+      for (int d = 0; d < ND; ++d)
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double t = wave_sum(acc[d][r]);
-        if (lane == 0) tot[d][r] = t;
-      }
+        for (int r = 0; r < R; ++r) {
+          const double t = wave_sum(acc[d][r]);
+          if (lane == 0) tot[d][r] = t;
+        }
+    } else {
+      // all ND * R values at once (recursive halving)
+      constexpr int NP2 = pow2_at_least(ND * R), SH = 6 - log2_exact(NP2);
+      double flat[NP2];
+#pragma unroll
+      for (int q = 0; q < NP2; ++q) flat[q] = q < ND * R ? acc[q / R][q % R] : 0.0;
+      const double t = multi_wave_sum<NP2>(flat, lane);
+      const int q = lane >> SH;
+      if ((lane & ((1 << SH) - 1)) == 0 && q < ND * R) tot[q / R][q % R] = t;
+    }
     return ok;
   }
 
@@ -540,13 +552,25 @@ struct Product {
     {
       acc_t part[ND][R];
       dots<B>(part);
+      if constexpr (ND * R <= 2) {
+        // one or two values: separate butterflies (measured faster here)
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+        for (int d = 0; d < ND; ++d)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const acc_t sw = wave_sum(part[d][r]);
-          if (lane == 0) s_part[t & 1][wave][d][r] = (double)sw;
-        }
+          for (int r = 0; r < R; ++r) {
+            const acc_t sw = wave_sum(part[d][r]);
+            if (lane == 0) s_part[t & 1][wave][d][r] = (double)sw;
+          }
+      } else {
+        // all ND * R partial dots of the wave summed at once (recursive halving)
+        constexpr int NP2 = pow2_at_least(ND * R), SH = 6 - log2_exact(NP2);
+        acc_t flat[NP2];
+#pragma unroll
+        for (int q = 0; q < NP2; ++q) flat[q] = q < ND * R ? part[q / R][q % R] : (acc_t)0;
+        const acc_t sw = multi_wave_sum<NP2>(flat, lane);
+        const int q = lane >> SH;
+        if ((lane & ((1 << SH) - 1)) == 0 && q < ND * R) s_part[t & 1][wave][q / R][q % R] = (double)sw;
+      }
     }
     const int u = t - kLag;
     if (u >= 0 && u < n_my) update<(B + kNBuf - kLag) % kNBuf>(pg, ctx, u, s_tot[u % kNBuf], E, v0);
