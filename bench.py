@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="timed steps only (for profiler passes): no tuning, float64 solves, standalone "
                          "products or CPU baseline")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--batched-systems", type=int, default=64,
+                    help="systems of the batched workload timed in one launch (its first n)")
     ap.add_argument("--copy-gb", type=float, default=0.0,
                     help="after the steps, copy a buffer of this many GB three times (a plain kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -153,11 +156,81 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
               f"in DESIGN.md and is not built in this repository.", file=sys.stderr)
         sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    out = measure_single(args)
+    torch.cuda.empty_cache()
+    out["batched"] = None if (args.quick or args.no_batched) else measure_batched(args)
+    print(json.dumps(out), flush=True)
 
+
+def measure_batched(args):
+    """The batched form: many independent systems, 8 shifts each, one persistent launch
+    (float32 O, two-pass products shared by the 8 columns).  Also times the same work for
+    one system as 8 separate single-column solves, and the 8-column product alone."""
+    import torch
+    import synth
+    from paper_1108_0900_amd import sr
+    dev = "cuda:0"
+    cfg = synth.CONFIGS["c4"]
+    shapes = synth.batched_shapes(seed=cfg.seed)[: args.batched_systems]
+    shifts = synth.relative_shifts(8)
+    systems = []
+    for s_i, (ns, npar) in enumerate(shapes):
+        d = synth.dense_inputs(ns, npar, cfg.seed * 1000 + s_i, device=dev, dtype=torch.float32)
+        M = sr.as_matrix(d["O"])
+        st = sr.sr_grad(M, d["E"])
+        M.mean = st["mean"]
+        dS = float(st["diag"].mean())
+        systems.append((M, st["g"].unsqueeze(0).repeat(8, 1).contiguous(), [dS * r for r in shifts]))
+        del d
+        if s_i % 8 == 7:
+            log(f"[bench] batched workload: {s_i + 1} systems built")
+    gb_o = [M.O.numel() * 4 / 1e9 for M, _, _ in systems]
+    sr.sr_cg_solve_batched(systems[:2], rtol=cfg.rtol, refresh_every=20)      # warm
+    log("[bench] batched: one launch over all systems")
+    (res, ms) = timed_events(lambda: sr.sr_cg_solve_batched(systems, rtol=cfg.rtol, refresh_every=20))
+    X, info, status = res
+    prods = [i[0]["products"] for i in info]
+    worst = max(c["rel_res_true"] for i in info for c in i)
+    # every product streams O twice (row dots, then the update pass)
+    passes_gb = sum(2 * p * g for p, g in zip(prods, gb_o))
+    out = {"workload": "%d independent systems, N_p in [1000, 60000], N_s in [4096, 32768], dense float32 O "
+                       "N(0,1) x lognormal(0, 0.5) column scales, 8 shifts 1e-4..1e-1 of mean(diag S) each, CG "
+                       "to rel. true residual %g, refresh every 20" % (len(systems), cfg.rtol),
+           "O_GB": round(sum(gb_o), 1), "launch_ms": round(ms, 1), "status": status,
+           "column_solves": 8 * len(systems), "products": sum(prods), "worst_rel_res_true": worst,
+           "O_stream_GBps": round(passes_gb / ms * 1e3, 1)}
+    del X
+    # the same 8 columns of the first system: one batched launch vs 8 single solves
+    M, G, eps = systems[0]
+    (res1, ms1) = timed_events(lambda: sr.sr_cg_solve_batched([systems[0]], rtol=cfg.rtol, refresh_every=20))
+    t_single = 0.0
+    for i in range(8):
+        (r, ms_i) = timed_events(lambda: sr.sr_cg_solve(M, G[i], eps[i], rtol=cfg.rtol, refresh_every=20))
+        t_single += ms_i
+    out["system0"] = {"n_s": M.O.shape[0], "n_p": M.n_p, "batched_ms": round(ms1, 2),
+                      "eight_single_solves_ms": round(t_single, 2), "speedup": round(t_single / ms1, 2)}
+    # the 8-column product alone on the largest system
+    big = max(range(len(systems)), key=lambda k: gb_o[k])
+    Mb = systems[big][0]
+    V = torch.randn(8, Mb.n_p, dtype=torch.float64, device=dev)
+    sr.sr_svk_product(Mb, V, [0.1] * 8)
+    ts = sorted(timed_events(lambda: sr.sr_svk_product(Mb, V, [0.1] * 8))[1] for _ in range(5))
+    ms_k = ts[2]
+    ts1 = sorted(timed_events(lambda: sr.sr_sv_product(Mb, V[0], 0.1))[1] for _ in range(5))
+    out["svk_product"] = {"n_s": Mb.O.shape[0], "n_p": Mb.n_p, "ms_8_columns": round(ms_k, 3),
+                          "ms_1_column": round(ts1[2], 3),
+                          "O_stream_GBps": round(2 * gb_o[big] / ms_k * 1e3, 1),
+                          "columns_per_O_read_equivalent": round(8 * ts1[2] / ms_k, 2)}
+    log(f"[bench] batched: {out}")
+    return out
+
+
+def measure_single(args):
     import torch
     from paper_1108_0900_amd import sr
     dev = "cuda:0"
-    torch.cuda.set_device(0)
 
     cfg, d = make_workload(args.config, dev)
     O64, E = d["O"], d["E"]
@@ -359,7 +432,7 @@ def main():
         "err_vs_f64": err,
         "err_vs_f64_one_plane": err_one_plane,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 if __name__ == "__main__":

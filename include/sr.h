@@ -167,24 +167,25 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
 
 /* ------------------------------------------------------------------------------------
  * Several right-hand sides and batches of systems (the batched form; the paper solves
- * one system at a time).  Up to SR_BATCH_MAX_RHS columns share every read of O:
- *   Y = (S + diag(eps)) V,  i.e. W = Oc V, Y = (1/n_s) Oc^T W + V diag(eps).
+ * one system at a time).  Up to SR_BATCH_MAX_RHS columns share each product:
+ *   Y = (S + diag(eps)) V,  i.e. W = Oc V, Y = (1/n_s) Oc^T W + V diag(eps),
+ * computed in two passes over O (the row dots W by row blocks, then Oc^T W by column
+ * blocks), every sum accumulated in float64.
  * sr_svk_product: V, Y: device [k][n_p] float64 (column i at V + i n_p), must not
- * overlap; eps: host [k].  exact = 1 accumulates in float64 (otherwise float32 storage
- * accumulates in float32).  Storage SR_F64 or SR_F32, one code plane.  Synchronizes
- * `stream` (its launch descriptor is copied from host memory).
+ * overlap; eps: host [k].  exact must be 0 or 1; both accumulate in float64 (the flag
+ * is kept so that a faster inexact product can be added behind it).  Storage SR_F64 or
+ * SR_F32, one code plane.  Synchronizes `stream` (its launch descriptor is copied from
+ * host memory).
  * sr_cg_solve_batched: n_sys independent systems (each its own O, k right-hand sides g
  * and shifts eps), all solved in one persistent launch, system after system; within a
  * system the k CG iterations share each product.  Each column stops when its true
- * residual reaches opt->rtol (checked with a float64-accumulated product whenever its
- * recurrence residual gets there, every opt->refresh_every iterations and at max_iter).
+ * residual reaches opt->rtol (checked with a product from x whenever its recurrence
+ * residual gets there, every opt->refresh_every iterations, once it fell by
+ * opt->refresh_drop since the last check if refresh_drop > 0, and at max_iter).
  * sys: host [n_sys]; every O has the same dtype (SR_F64 or SR_F32).  info: host
  * [n_sys * k] (system-major) or NULL; its `refreshes` is 0 and rel_res_recur repeats
- * rel_res_true.  With SR_F32 storage the search products accumulate in float32: a
- * refresh is also taken once a column's residual fell by opt->refresh_drop (0: 1e-3)
- * since the last one, and every refresh restarts the search directions (inexact
- * iterative refinement).  opt->use_x0, restart_on_refresh, refine and res_history are
- * not used.  Synchronizes `stream`.  Returns SR_OK if every column converged, else
+ * rel_res_true.  opt->use_x0, restart_on_refresh, refine and res_history are not used.
+ * Synchronizes `stream`.  Returns SR_OK if every column converged, else
  * SR_NOT_CONVERGED / SR_BREAKDOWN (the first such status met) or an error code.
  * ------------------------------------------------------------------------------------ */
 #define SR_BATCH_MAX_RHS 8

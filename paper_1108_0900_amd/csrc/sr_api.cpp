@@ -540,45 +540,77 @@ int fill_zero(void *p, int64_t words, hipStream_t s) {
   return SR_OK;
 }
 
+// Geometry of one system's two-pass products (see BatchProduct): about two tasks per
+// workgroup in each pass where the shape allows.
+BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
+  BatchGeom g{};
+  g.n_s = n_s;
+  g.n_p = n_p;
+  const int nw = kBatchNT / 64;
+  const int64_t cw = 64 * (int64_t)vec, bw = (int64_t)kBatchNT * vec;
+  g.n_rb = cdiv(n_s, (int64_t)nw * kBatchRows);
+  const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));   // parts of >= 4 chunks
+  const int64_t parts = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
+  g.pw = round_up(cdiv(n_p, parts), cw);
+  g.P = (int)cdiv(n_p, g.pw);
+  g.C = (int)cdiv(n_p, bw);
+  const int64_t sp = std::max<int64_t>(cdiv(n_s, kBatchSplitRows),
+                                       std::min<int64_t>(cdiv(2 * (int64_t)G, g.C), cdiv(n_s, 64)));
+  g.rs = cdiv(n_s, sp);
+  g.SP = (int)cdiv(n_s, g.rs);
+  return g;
+}
+
+// Buffer sizes of a batched launch (the largest system sets each).
+struct BatchSizes {
+  int64_t vstride = 0, wp = 0, yp = 0, swp = 0;
+  void add(const BatchGeom &g) {
+    vstride = std::max<int64_t>(vstride, g.n_p);
+    wp = std::max<int64_t>(wp, (int64_t)g.P * g.n_s * kBatchK);
+    yp = std::max<int64_t>(yp, (int64_t)g.SP * kBatchK * g.n_p);
+    swp = std::max<int64_t>(swp, (int64_t)g.SP * kBatchK);
+  }
+};
+
 // Carves the buffers every batched launch uses; the zeroed part (barrier flags, abort
-// word, exchange ring) is cleared by a fill kernel.
+// word) is cleared by a fill kernel.
 struct BatchWs {
   BatchArgs a{};
   uint32_t *zero_base = nullptr;
   int64_t zero_words = 0;
 };
-size_t batch_ws_bytes(int G, int64_t vstride, int64_t ypart_doubles) {
-  const int K = kBatchK, words = K * 2;   // R = 1 tiles, float64-sized exchange words
+size_t batch_ws_bytes(int G, const BatchSizes &z) {
+  const int K = kBatchK;
   size_t b = 0;
   auto add = [&](size_t n) { b = (size_t)round_up((int64_t)b, 256) + n; };
   add(G * 4);
   add(64 * 4);
-  add((size_t)G * kRing * words * 8);
-  add((size_t)G * words * 8);
   add((size_t)4 * K * G * 8);
-  add((size_t)ypart_doubles * 8);
-  add((size_t)2 * G * (K + 1) * 8);
-  for (int i = 0; i < 4; ++i) add((size_t)K * vstride * 8);
+  add((size_t)K * z.vstride * 8);
+  add((size_t)z.wp * 8);
+  add((size_t)z.yp * 8);
+  add((size_t)z.swp * 8);
+  for (int i = 0; i < 4; ++i) add((size_t)K * z.vstride * 8);
   return b + 256;
 }
-void carve_batch(Carve &cv, int G, int64_t vstride, int64_t ypart_doubles, BatchWs *w) {
-  const int K = kBatchK, words = K * 2;
+void carve_batch(Carve &cv, int G, const BatchSizes &z, BatchWs *w) {
+  const int K = kBatchK;
   const size_t start = (size_t)round_up((int64_t)cv.off, 256);
   w->a.sb.flags = cv.take<uint32_t>(G);
   w->a.sb.abort = cv.take<uint32_t>(64);
-  w->a.pb.xchg = cv.take<u64>((int64_t)G * kRing * words);
   const size_t end = cv.off;
   w->zero_base = (uint32_t *)(cv.base + start);
   w->zero_words = (int64_t)((end - start + 3) / 4);
-  w->a.pb.sink = cv.take<u64>((int64_t)G * words);
   w->a.red = cv.take<double>((int64_t)4 * K * G);
-  w->a.pb.ypart = cv.take<double>(ypart_doubles);
-  w->a.pb.spart = cv.take<double>((int64_t)2 * G * (K + 1));   // two halves (BatchKernel::apply)
-  w->a.x = cv.take<double>((int64_t)K * vstride);
-  w->a.r = cv.take<double>((int64_t)K * vstride);
-  w->a.p = cv.take<double>((int64_t)K * vstride);
-  w->a.q = cv.take<double>((int64_t)K * vstride);
-  w->a.vstride = vstride;
+  w->a.vs = cv.take<double>((int64_t)K * z.vstride);
+  w->a.wp = cv.take<double>(z.wp);
+  w->a.yp = cv.take<double>(z.yp);
+  w->a.swp = cv.take<double>(z.swp);
+  w->a.x = cv.take<double>((int64_t)K * z.vstride);
+  w->a.r = cv.take<double>((int64_t)K * z.vstride);
+  w->a.p = cv.take<double>((int64_t)K * z.vstride);
+  w->a.q = cv.take<double>((int64_t)K * z.vstride);
+  w->a.vstride = z.vstride;
 }
 
 int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double *eps, double *Y, int32_t exact,
@@ -607,23 +639,21 @@ int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double 
   if (rc) return rc;
   const BatchEntry *be = batched_entry(O->dtype);
   BatchSys S{};
-  const int vec = vec_of(O->dtype);
-  rc = geometry(di.grid, O->n_s, n_p, be->nv * vec * be->nt, vec, be->r, 0, &S.pg);
-  if (rc) return rc;
+  S.bg = batch_geometry(di.grid, O->n_s, n_p, vec_of(O->dtype));
+  BatchSizes z;
+  z.add(S.bg);
   S.op = make_operand(O);
   S.mean = mean;
   S.k = k;
   for (int i = 0; i < kBatchK; ++i) S.eps[i] = i < k ? eps[i] : 0.0;
   void *base = nullptr;
-  const int64_t yp = (int64_t)kBatchK * S.pg.RG * n_p;
-  rc = get_workspace(dev, stream, batch_ws_bytes(di.grid, n_p, yp) + 1024, &base, g_batch_ws);
+  rc = get_workspace(dev, stream, batch_ws_bytes(di.grid, z) + 1024, &base, g_batch_ws);
   if (rc) return rc;
   Carve cv(base);
   BatchWs w;
-  carve_batch(cv, di.grid, n_p, yp, &w);
+  carve_batch(cv, di.grid, z, &w);
   BatchSys *table = cv.take<BatchSys>(1);
   // V padded to kBatchK columns in the p buffer, the result in q
-  S.g = w.a.p;
   HIP_TRY(hipMemcpyAsync(w.a.p, V, (size_t)k * n_p * 8, hipMemcpyDeviceToDevice, stream));
   if (k < kBatchK) {
     rc = fill_zero(w.a.p + (int64_t)k * n_p, (int64_t)(kBatchK - k) * n_p * 2, stream);
@@ -632,7 +662,6 @@ int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double 
   HIP_TRY(hipMemcpyAsync(table, &S, sizeof(S), hipMemcpyHostToDevice, stream));
   w.a.sys = table;
   w.a.n_sys = 1;
-  w.a.refresh_every = exact;     // k_svk: 1 selects float64 accumulation
   rc = fill_zero(w.zero_base, w.zero_words, stream);
   if (rc) return rc;
   rc = launch_coop(be->sv, di.grid, &w.a, stream, be->nt, 0);
@@ -675,15 +704,15 @@ int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, co
   const int dt = sys[0].O.dtype, vec = vec_of(dt);
   const BatchEntry *be = batched_entry(dt);
   std::vector<BatchSys> host(n_sys);
-  int64_t yp = 0, mean_total = 0;
+  BatchSizes z;
+  int64_t mean_total = 0;
   for (int s = 0; s < n_sys; ++s) {
-    rc = geometry(di.grid, sys[s].O.n_s, sys[s].O.n_p, be->nv * vec * be->nt, vec, be->r, 0, &host[s].pg);
-    if (rc) return rc;
-    yp = std::max<int64_t>(yp, (int64_t)kBatchK * host[s].pg.RG * sys[s].O.n_p);
+    host[s].bg = batch_geometry(di.grid, sys[s].O.n_s, sys[s].O.n_p, vec);
+    z.add(host[s].bg);
     if (!sys[s].O.col_mean) mean_total += round_up(sys[s].O.n_p, 32);
   }
   const size_t info_n = (size_t)n_sys * kBatchK * 4 + 1;
-  const size_t bytes = batch_ws_bytes(di.grid, max_np, yp) + (size_t)mean_total * 8 + info_n * 8 +
+  const size_t bytes = batch_ws_bytes(di.grid, z) + (size_t)mean_total * 8 + info_n * 8 +
                        (size_t)n_sys * sizeof(BatchSys) + 4096;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base, g_batch_ws);
@@ -693,7 +722,7 @@ int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, co
   BatchSys *table = cv.take<BatchSys>(n_sys);
   double *dinfo = cv.take<double>((int64_t)info_n);
   BatchWs w;
-  carve_batch(cv, di.grid, max_np, yp, &w);
+  carve_batch(cv, di.grid, z, &w);
   int64_t moff = 0;
   for (int s = 0; s < n_sys; ++s) {
     const sr_batch_system &b = sys[s];
@@ -719,12 +748,10 @@ int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, co
   w.a.rtol = o.rtol;
   w.a.max_iter = (int)max_iter;
   w.a.refresh_every = o.refresh_every;
-  // float32 storage: search products accumulate in float32; refresh (and restart) once
-  // the residual fell by refresh_drop (default 1e-3, above that rounding level)
+  // optional extra refreshes once the residual fell by refresh_drop since the last one
   if (!(o.refresh_drop >= 0.0 && o.refresh_drop < 1.0))
     return fail(SR_ERR_INVALID, "sr_cg_solve_batched: refresh_drop must be in [0, 1)");
-  const double drop = o.refresh_drop > 0.0 ? o.refresh_drop : (dt == SR_F32 ? 1e-3 : 0.0);
-  w.a.refresh_drop2 = drop * drop;
+  w.a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
   w.a.info = dinfo;
   rc = fill_zero(w.zero_base, w.zero_words, stream);
   if (rc) return rc;

@@ -15,8 +15,8 @@ static const KernelEntry g_entries_f32[] = {SR_SR_CONFIGS_F32(SR_REG_SR) SR_LM_C
 
 // Batched solves: one tile configuration (K = 8 right-hand sides need the registers of
 // one 16-byte vector per thread).
-static const BatchEntry g_batch_f32 = {(const void *)&k_cg_batched<DT_F32, 1, 1, 2, 1, 512>,
-                                           (const void *)&k_svk<DT_F32, 1, 1, 2, 1, 512>, 1, 1, 512};
+static const BatchEntry g_batch_f32 = {(const void *)&k_cg_batched<DT_F32, kBatchNT>,
+                                           (const void *)&k_svk<DT_F32, kBatchNT>, kBatchNT};
 const BatchEntry *batched_entry_f32() { return &g_batch_f32; }
 
 const KernelEntry *kernel_table_f32(int *count) {

@@ -15,8 +15,8 @@ static const KernelEntry g_entries_f64[] = {SR_SR_CONFIGS_F64(SR_REG_SR) SR_LM_C
 
 // Batched solves: one tile configuration (K = 8 right-hand sides need the registers of
 // one 16-byte vector per thread).
-static const BatchEntry g_batch_f64 = {(const void *)&k_cg_batched<DT_F64, 1, 1, 2, 1, 512>,
-                                           (const void *)&k_svk<DT_F64, 1, 1, 2, 1, 512>, 1, 1, 512};
+static const BatchEntry g_batch_f64 = {(const void *)&k_cg_batched<DT_F64, kBatchNT>,
+                                           (const void *)&k_svk<DT_F64, kBatchNT>, kBatchNT};
 const BatchEntry *batched_entry_f64() { return &g_batch_f64; }
 
 const KernelEntry *kernel_table_f64(int *count) {

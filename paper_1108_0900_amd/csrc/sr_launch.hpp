@@ -83,23 +83,41 @@ struct QuantArgs {
 #define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)
 
 // Batched solves: K right-hand sides per system, systems one after another in one
-// persistent launch.
+// persistent launch.  A product (S + diag(eps)) V takes two passes over O: row dots
+// W = O_c V by row blocks (V staged through LDS chunk by chunk), then O^T W by column
+// blocks and row splits (the split's rows of W held in LDS).
 constexpr int kBatchK = 8;           // right-hand sides per product of the batched kernels
+constexpr int kBatchRows = 4;        // rows per wave in the row-dot pass
+constexpr int kBatchSplitRows = 1024;   // most rows per split of the update pass
+constexpr int kBatchNT = 512;        // threads per workgroup of the batched kernels
+
+struct BatchGeom {
+  int64_t n_s, n_p;
+  int64_t n_rb;                      // row blocks of the row-dot pass (waves * kBatchRows rows)
+  int64_t pw;                        // columns per part of the row-dot pass (chunk multiple)
+  int P;                             // column parts of the row-dot pass
+  int C;                             // column blocks of the update pass (threads * VEC columns)
+  int SP;                            // row splits of the update pass
+  int64_t rs;                        // rows per split (<= kBatchSplitRows)
+};
 struct BatchSys {
   Operand op;
   const double *mean;                // [n_p] column means
   const double *g;                   // [k][n_p] right-hand sides
   double *x;                         // [k][n_p] solutions
-  ProdGeom pg;                       // geometry of this system's products
+  BatchGeom bg;                      // geometry of this system's products
   int k;                             // right-hand sides in use (<= kBatchK)
   double eps[kBatchK];               // shift of each right-hand side
 };
 struct BatchArgs {
   const BatchSys *sys;               // [n_sys] device table
   int n_sys;
-  ProdBufs pb;                       // ypart [K][RG][n_p] and spart [RG][K + 1] of the largest system
   SyncBufs sb;
-  double *red;                       // [4][2K][G] grid reductions
+  double *red;                       // [4][K][G] grid reductions
+  double *vs;                        // [K][vstride] scaled operand s_j v_kj
+  double *wp;                        // [P][n_s][K] row dots per column part (largest system)
+  double *yp;                        // [SP][K][n_p] update-pass partials (largest system)
+  double *swp;                       // [SP][K] sums of the centred row dots per split
   double *x, *r, *p, *q;             // [K][vstride]
   int64_t vstride;                   // max n_p (stride of the K vectors)
   double rtol;
@@ -112,7 +130,7 @@ struct BatchArgs {
 // The batched kernels of a storage type (float64 and float32 only).
 struct BatchEntry {
   const void *cg, *sv;
-  int nv, r, nt;
+  int nt;
 };
 const BatchEntry *batched_entry(int dt);   // nullptr if the type has none
 

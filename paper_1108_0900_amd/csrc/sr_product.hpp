@@ -154,14 +154,24 @@ struct Product {
   acc_t vc[ND][NV][VEC];            // v_j * s_j per operand / right-hand side (0 outside the slice)
   acc_t yacc[K][NV][VEC];           // partial (O^T w)_j per right-hand side
   u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
-  double s1[K], s2;                 // row-group scalars (SR: sum w per right-hand side; LM: sum z, sum(E t + u))
+  // row-group scalars (SR: sum w; LM: sum z, sum(E t + u)).  With several right-hand
+  // sides the K sums of w live in LDS (thread 0 accumulates them; it alone stores them)
+  // to keep registers for the tiles.
+  static constexpr int KS1 = K > 1 ? 1 : K;
+  double s1[KS1], s2;
   bool need_mask;
   // --- exchange state (wave 0) ---
   // column groups per lane read ahead (C <= 128 asynchronously; C <= 64 with several
   // right-hand sides, whose words take more registers)
   static constexpr int kCh = K > 1 ? 1 : 2;
   u64 pw[kNPoll][kCh][PW];          // words of column groups lane, lane + 64 for the pending polls
-  double cshare[K];                 // this workgroup's share of obar . v per right-hand side
+  // this workgroup's share of obar . v per right-hand side (the same in every thread; in
+  // LDS with several right-hand sides)
+  double cshare[KS1];
+  __device__ __forceinline__ static double *lds_k() {
+    __shared__ double s_k[2][K];     // [0]: cshare, [1]: sum of w (several right-hand sides)
+    return &s_k[0][0];
+  }
 
   __device__ __forceinline__ static u32x4 elem_mask(int nvalid) {
     // keep the bytes of the first nvalid elements of a 16-byte vector
@@ -225,13 +235,26 @@ struct Product {
       }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) s1[k] = 0.0;
+    for (int k = 0; k < KS1; ++k) s1[k] = 0.0;
     s2 = 0.0;
     // uniform flag: does any thread own a straddling vector?
     need_mask = __syncthreads_or(straddles ? 1 : 0) != 0;
+    double c0 = 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) cshare[k] = block_sum(cpart[k]);
-    return cshare[0];
+    for (int k = 0; k < K; ++k) {
+      const double c = block_sum(cpart[k]);   // (its barriers order the LDS writes below)
+      if (k == 0) c0 = c;
+      if constexpr (K > 1) {
+        if (threadIdx.x == 0) {
+          lds_k()[k] = c;
+          lds_k()[K + k] = 0.0;
+        }
+      } else {
+        cshare[0] = c;
+      }
+    }
+    if constexpr (K > 1) __syncthreads();
+    return c0;
   }
 
   // Loads of tile j into buffer B.  Every load is issued unconditionally (rows past n_s
@@ -469,7 +492,7 @@ struct Product {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const double wr = valid ? tot[k][r] : 0.0;
-          s1[k] += wr;
+          if (threadIdx.x == 0) lds_k()[K + k] += wr;
           wk[k][r] = (acc_t)wr;
         }
       }
@@ -589,7 +612,10 @@ struct Product {
           double sm = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) sm += s_part[t & 1][w][d][r];
-          red[d][r] = (d < K) ? sm - cshare[d] : sm;   // centring of operand 0's dots
+          double cs = 0.0;       // centring of operand 0's dots
+          if constexpr (K > 1) cs = lds_k()[d < K ? d : 0];
+          else cs = cshare[0];
+          red[d][r] = (d < K) ? sm - cs : sm;
         }
       if constexpr ((X & kPublish) != 0) {
         // every step publishes (the tail steps past n_my into the sink), so the store is
@@ -686,7 +712,7 @@ struct Product {
       }
     if (ctx.cg == 0 && threadIdx.x == 0) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) st_coh(&pb.spart[ctx.rg * (K + 1) + k], s1[k]);
+      for (int k = 0; k < K; ++k) st_coh(&pb.spart[ctx.rg * (K + 1) + k], K > 1 ? lds_k()[K + k] : s1[0]);
       st_coh(&pb.spart[ctx.rg * (K + 1) + K], s2);
     }
   }

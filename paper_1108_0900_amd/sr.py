@@ -279,7 +279,8 @@ def _rhs_block(V: torch.Tensor, n_p: int, name: str) -> torch.Tensor:
 
 def sr_svk_product(M: Matrix, V: torch.Tensor, eps, exact: bool = False, out: torch.Tensor | None = None,
                    stream=None) -> torch.Tensor:
-    """Y = (S + diag(eps)) V for the k rows of V (k <= 8 right-hand sides, one read of O)."""
+    """Y = (S + diag(eps)) V for the k rows of V (k <= 8 right-hand sides sharing two passes
+    over O, float64-accumulated; `exact` is accepted for either value)."""
     V = _rhs_block(V, M.n_p, "V")
     k = V.shape[0]
     eps = [float(e) for e in eps]
