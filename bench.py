@@ -421,7 +421,8 @@ def measure_single(args):
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_cg (persistent CG; products read O once each)",
-                     "algorithmic_GB_per_launch": round(cg_bytes / 1e9, 1), "launch_ms": round(cg_avg, 3)},
+                     "algorithmic_GB_per_launch": round(cg_bytes / 1e9, 1),
+                     "algorithmic_bytes_per_launch": int(round(cg_bytes)), "launch_ms": round(cg_avg, 3)},
         "cpu_baseline": cpu,
         "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
                   "residual_products": residuals, "planes": planes, "search_planes": search_planes,

@@ -121,36 +121,6 @@ template <typename T> __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
-constexpr int log2_exact(int n) { return n <= 1 ? 0 : 1 + log2_exact(n / 2); }
-
-// Sums of N values (N a power of two <= 64) over the 64 lanes of a wave by recursive
-// halving: at each of the first log2(N) exchange stages a lane keeps half of its values
-// and adds its partner's copies of them, so N sums cost N - 1 + 6 - log2(N) exchanges
-// instead of 6 N.  On return lane l holds the sum of value l >> (6 - log2(N)).
-template <int N, int STAGE, typename T> __device__ __forceinline__ void multi_wave_stage(T (&v)[N], int lane) {
-  if constexpr ((N >> STAGE) > 1) {
-    constexpr int off = 32 >> STAGE, half = N >> (STAGE + 1);
-    const bool upper = (lane & off) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const T send = upper ? v[i] : v[i + half];
-      const T keep = upper ? v[i + half] : v[i];
-      v[i] = keep + __shfl_xor(send, off, 64);
-    }
-    multi_wave_stage<N, STAGE + 1>(v, lane);   // (stages as template arguments: every index is static)
-  }
-}
-template <int N, typename T> __device__ __forceinline__ T multi_wave_sum(T (&v)[N], int lane) {
-  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N must be a power of two <= 64");
-  constexpr int L = log2_exact(N);
-  multi_wave_stage<N, 0>(v, lane);
-  T x = v[0];
-#pragma unroll
-  for (int off = 32 >> L; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
 // ------------------------------------------------------------------------------------
 // Grid barrier and abort flag
 // ------------------------------------------------------------------------------------

@@ -1,5 +1,5 @@
 // Product, CG and linear-method kernels for DT_F32 storage.
-#include "sr_kernels.hpp"
+#include "sr_batch.hpp"
 
 namespace sr {
 

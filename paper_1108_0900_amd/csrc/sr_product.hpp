@@ -28,7 +28,6 @@
 //   * Row-group partial y vectors (float64) go to a workspace; a grid barrier later lets
 //     any workgroup finish a column range with a fixed-order sum over row groups.
 #pragma once
-#include <type_traits>
 #include <utility>
 #include "sr_device.hpp"
 
@@ -111,15 +110,11 @@ template <int DT> struct AccOf<DT, true> { typedef double type; };
 //         streaming cover the latency of those coherent loads
 //   NT    threads per workgroup
 //   PLANES 2: the operand is s_j (q + lo) read from two code planes (NDOT = 1 only)
-//   K     right-hand sides of an SR product sharing each read of O (NDOT = 1, one plane):
-//         W = Oc V, Y = Oc^T W for the K columns of V, K partial dots per row
 template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int PD = 1, int NT = 256,
-          int PLANES = 1, int K = 1>
+          int PLANES = 1>
 struct Product {
   static_assert(PLANES == 1 || NDOT == 1, "two code planes only for the SR product");
-  static_assert(K == 1 || (NDOT == 1 && PLANES == 1), "several right-hand sides only for the one-plane SR product");
   static constexpr int NOPS = NDOT + PLANES - 1;   // loaded tiles per row (operands, planes)
-  static constexpr int ND = NDOT * K;              // partial dots per row
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int kLook = LOOK;
   static constexpr int kAdv = 2;              // the poll of tile t starts at step t + kAdv
@@ -136,42 +131,27 @@ struct Product {
   // step t publishes to.
   static_assert(kRing > 2 * (kAdv + PD), "exchange ring too small for the poll depth");
   typedef Storage<DT> St;
-  // several right-hand sides over float32 storage accumulate in float32 (the float64
-  // refresh products carry the accuracy); otherwise as AccOf
-  typedef typename std::conditional<(K > 1 && !EXACT && St::BYTES == 4), float,
-                                    typename AccOf<DT, EXACT>::type>::type acc_t;
+  typedef typename AccOf<DT, EXACT>::type acc_t;
   static constexpr int VEC = St::VEC;
   static constexpr int WPD = sizeof(acc_t) == 8 ? 2 : 1;   // exchange words per partial dot
   // exchange words per column group per tile; the ring is laid out for float64 partials
   // so that float32 and float64 products of the same launch can share it
-  static constexpr int WORDS = ND * R * 2;
-  static constexpr int PW = ND * R * WPD;                    // polled words per column group
+  static constexpr int WORDS = NDOT * R * 2;
+  static constexpr int PW = NDOT * R * WPD;                  // polled words per column group
 
   // --- per-thread state (data threads) ---
   int col0;                         // first column of vector 0; vector i starts at col0 + i*NT*VEC
   int nvec;                         // owned vectors that start inside the slice (0..NV)
   int n_p;                          // total columns (for the mask of a vector straddling n_p)
-  acc_t vc[ND][NV][VEC];            // v_j * s_j per operand / right-hand side (0 outside the slice)
-  acc_t yacc[K][NV][VEC];           // partial (O^T w)_j per right-hand side
+  acc_t vc[NDOT][NV][VEC];          // v_j * s_j per operand (0 outside the slice)
+  acc_t yacc[NV][VEC];              // partial (O^T w)_j
   u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
-  // row-group scalars (SR: sum w; LM: sum z, sum(E t + u)).  With several right-hand
-  // sides the K sums of w live in LDS (thread 0 accumulates them; it alone stores them)
-  // to keep registers for the tiles.
-  static constexpr int KS1 = K > 1 ? 1 : K;
-  double s1[KS1], s2;
+  double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
   // --- exchange state (wave 0) ---
-  // column groups per lane read ahead (C <= 128 asynchronously; C <= 64 with several
-  // right-hand sides, whose words take more registers)
-  static constexpr int kCh = K > 1 ? 1 : 2;
+  static constexpr int kCh = 2;     // column groups per lane read ahead (C <= 128 asynchronously)
   u64 pw[kNPoll][kCh][PW];          // words of column groups lane, lane + 64 for the pending polls
-  // this workgroup's share of obar . v per right-hand side (the same in every thread; in
-  // LDS with several right-hand sides)
-  double cshare[KS1];
-  __device__ __forceinline__ static double *lds_k() {
-    __shared__ double s_k[2][K];     // [0]: cshare, [1]: sum of w (several right-hand sides)
-    return &s_k[0][0];
-  }
+  double cshare;
 
   __device__ __forceinline__ static u32x4 elem_mask(int nvalid) {
     // keep the bytes of the first nvalid elements of a 16-byte vector
@@ -191,15 +171,12 @@ struct Product {
 
   __device__ __forceinline__ int64_t colv(int i) const { return (int64_t)col0 + (int64_t)i * (NT * VEC); }
 
-  // Load the owned coefficients (v: K right-hand sides, vstride apart); returns this
-  // workgroup's share of obar . v of the first right-hand side.
+  // Load the owned coefficients; returns this workgroup's share of obar . v (operand 0).
   __device__ __forceinline__ double setup(const WgCtx &ctx, const ProdGeom &pg, const Operand *ops,
-                                          const double *__restrict__ mean, const double *v, int64_t vstride = 0) {
+                                          const double *__restrict__ mean, const double *v) {
     const int tid = (int)threadIdx.x;
     const bool data = true;
-    double cpart[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) cpart[k] = 0.0;
+    double cpart = 0.0;
     col0 = (int)(ctx.c0 + (int64_t)tid * VEC);
     nvec = 0;
     n_p = (int)pg.n_p;
@@ -217,44 +194,26 @@ struct Product {
       }
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          double vj = 0.0;
-          if (e < nvalid) {
-            vj = ld_coh(&v[k * vstride + col + e]);
-            cpart[k] += mean[col + e] * vj;
-          }
-#pragma unroll
-          for (int d = 0; d < NDOT; ++d) {
-            double s = 1.0;
-            if (ops[d].scale != nullptr && e < nvalid) s = (double)ops[d].scale[col + e];
-            vc[d * K + k][i][e] = (acc_t)(vj * s);
-          }
-          yacc[k][i][e] = (acc_t)0;
+        double vj = 0.0;
+        if (e < nvalid) {
+          vj = ld_coh(&v[col + e]);
+          cpart += mean[col + e] * vj;
         }
+#pragma unroll
+        for (int d = 0; d < NDOT; ++d) {
+          double s = 1.0;
+          if (ops[d].scale != nullptr && e < nvalid) s = (double)ops[d].scale[col + e];
+          vc[d][i][e] = (acc_t)(vj * s);
+        }
+        yacc[i][e] = (acc_t)0;
       }
     }
-#pragma unroll
-    for (int k = 0; k < KS1; ++k) s1[k] = 0.0;
+    s1 = 0.0;
     s2 = 0.0;
     // uniform flag: does any thread own a straddling vector?
     need_mask = __syncthreads_or(straddles ? 1 : 0) != 0;
-    double c0 = 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double c = block_sum(cpart[k]);   // (its barriers order the LDS writes below)
-      if (k == 0) c0 = c;
-      if constexpr (K > 1) {
-        if (threadIdx.x == 0) {
-          lds_k()[k] = c;
-          lds_k()[K + k] = 0.0;
-        }
-      } else {
-        cshare[0] = c;
-      }
-    }
-    if constexpr (K > 1) __syncthreads();
-    return c0;
+    cshare = block_sum(cpart);
+    return cshare;
   }
 
   // Loads of tile j into buffer B.  Every load is issued unconditionally (rows past n_s
@@ -282,7 +241,7 @@ struct Product {
   }
 
   template <int B>
-  __device__ __forceinline__ void dots(acc_t (&part)[ND][R]) {
+  __device__ __forceinline__ void dots(acc_t (&part)[NDOT][R]) {
     if (need_mask) {
       // zero the bytes past n_p (row padding may hold anything) before any use; the mask
       // of each vector is computed, not looked up, so the tile stays in registers
@@ -298,13 +257,13 @@ struct Product {
       }
     }
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         acc_t acc = (acc_t)0;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-          const u32x4 x = buf[B][K > 1 ? 0 : d][r][i];
+          const u32x4 x = buf[B][d][r][i];
           if (PLANES == 2) {
             const u32x4 xl = buf[B][1][r][i];
 #pragma unroll
@@ -333,7 +292,7 @@ struct Product {
   // last poll a workgroup runs its tail steps without waiting for the others, and a
   // publish into the ring could then overwrite a slot a slower member still reads.
   __device__ __forceinline__ void publish(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx, uint32_t step,
-                                          bool tail, const double (&red)[ND][R]) {
+                                          bool tail, const double (&red)[NDOT][R]) {
     u64 *base = tail ? pb.sink + (int64_t)blockIdx.x * WORDS
                      : slot_base(pb, pg, ctx, step) + (int64_t)ctx.cg * WORDS;
     const u64 tag = (u64)(step / kRing + 1) << 32;
@@ -341,7 +300,7 @@ struct Product {
     const int dr = k / WPD;                          // which partial dot
     double val = red[0][0];
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) val = (dr == d * R + r) ? red[d][r] : val;
     u64 word;
@@ -376,9 +335,9 @@ struct Product {
     for (int k = 0; k < PW; ++k) ok &= ((uint32_t)(w[k] >> 32) == tag);
     return ok;
   }
-  __device__ __forceinline__ static void words_add(const u64 *w, double (&acc)[ND][R]) {
+  __device__ __forceinline__ static void words_add(const u64 *w, double (&acc)[NDOT][R]) {
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (WPD == 1) {
@@ -430,9 +389,9 @@ struct Product {
 #pragma unroll
         for (int k = 0; k < PW; ++k) pw[Q][h][k] = w[h][k];
     }
-    double acc[ND][R];
+    double acc[NDOT][R];
 #pragma unroll
-    for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < NDOT; ++d)
 #pragma unroll
       for (int r = 0; r < R; ++r) acc[d][r] = 0.0;
 #pragma unroll
@@ -457,25 +416,13 @@ struct Product {
       if (c < pg.C) words_add(w, acc);
     }
     if (!ok && lane == 0) st_coh32(ctx.gs.abort, 1u);
-    // fixed-order sums over the lanes (column groups)
-    if constexpr (ND * R <= 2) {
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+    for (int d = 0; d < NDOT; ++d)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double t = wave_sum(acc[d][r]);
-          if (lane == 0) tot[d][r] = t;
-        }
-    } else {
-      // all ND * R values at once (recursive halving)
-      constexpr int NP2 = pow2_at_least(ND * R), SH = 6 - log2_exact(NP2);
-      double flat[NP2];
-#pragma unroll
-      for (int q = 0; q < NP2; ++q) flat[q] = q < ND * R ? acc[q / R][q % R] : 0.0;
-      const double t = multi_wave_sum<NP2>(flat, lane);
-      const int q = lane >> SH;
-      if ((lane & ((1 << SH) - 1)) == 0 && q < ND * R) tot[q / R][q % R] = t;
-    }
+      for (int r = 0; r < R; ++r) {
+        const double t = wave_sum(acc[d][r]);
+        if (lane == 0) tot[d][r] = t;
+      }
     return ok;
   }
 
@@ -484,32 +431,6 @@ struct Product {
   __device__ __forceinline__ void update(const ProdGeom &pg, const WgCtx &ctx, int j, const double (*tot)[R],
                                          const double *__restrict__ E, double v0) {
     const int64_t row0 = ((int64_t)j * pg.RG + ctx.rg) * R;
-    if constexpr (K > 1) {
-      acc_t wk[K][R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const bool valid = row0 + r < pg.n_s;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const double wr = valid ? tot[k][r] : 0.0;
-          if (threadIdx.x == 0) lds_k()[K + k] += wr;
-          wk[k][r] = (acc_t)wr;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const u32x4 x = buf[B][0][r][i];
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) {
-            const acc_t o = (acc_t)St::get(x, e);
-#pragma unroll
-            for (int k = 0; k < K; ++k) yacc[k][i][e] += o * wk[k][r];
-          }
-        }
-      return;
-    }
     acc_t w[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -518,14 +439,14 @@ struct Product {
       double wr;
       if (NDOT == 1) {
         wr = valid ? tot[0][r] : 0.0;
-        s1[0] += wr;
+        s1 += wr;
       } else {
         // the load is unconditional (clamped row) so that no memory operation sits in a
         // branch; the row's weight is zero past n_s
         const double e = E[valid ? row : pg.n_s - 1];
         const double t = tot[0][r], u = tot[1][r];
         wr = valid ? e * (v0 + t) + u : 0.0;
-        s1[0] += wr;
+        s1 += wr;
         s2 += valid ? e * t + u : 0.0;
       }
       w[r] = (acc_t)wr;
@@ -538,10 +459,10 @@ struct Product {
         if (PLANES == 2) {
           const u32x4 xl = buf[B][NOPS - 1][r][i];
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) yacc[0][i][e] += ((acc_t)St::get(x, e) + (acc_t)St::get(xl, e)) * w[r];
+          for (int e = 0; e < VEC; ++e) yacc[i][e] += ((acc_t)St::get(x, e) + (acc_t)St::get(xl, e)) * w[r];
         } else {
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) yacc[0][i][e] += (acc_t)St::get(x, e) * w[r];
+          for (int e = 0; e < VEC; ++e) yacc[i][e] += (acc_t)St::get(x, e) * w[r];
         }
       }
     }
@@ -561,7 +482,7 @@ struct Product {
   template <int B, int X>
   __device__ __forceinline__ void step(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t,
                                        int n_my, const double *__restrict__ E, double v0,
-                                       double (*s_part)[NW][ND][R], double (*s_tot)[ND][R], bool &ok) {
+                                       double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
     constexpr int QI = ((B - kAdv) % kNPoll + kNPoll) % kNPoll;        // exchange t - kAdv
     constexpr int QF = ((B - kAdv - PD) % kNPoll + kNPoll) % kNPoll;   // exchange t - kAdv - PD
     const int tid = (int)threadIdx.x;
@@ -573,27 +494,15 @@ struct Product {
     // weight), so the wait for tile t leaves tiles t+1..t+kLook in flight
     issue<(B + kLook) % kNBuf>(ctx, pg, ops, t + kLook);
     {
-      acc_t part[ND][R];
+      acc_t part[NDOT][R];
       dots<B>(part);
-      if constexpr (ND * R <= 2) {
-        // one or two values: separate butterflies (measured faster here)
 #pragma unroll
-        for (int d = 0; d < ND; ++d)
+      for (int d = 0; d < NDOT; ++d)
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const acc_t sw = wave_sum(part[d][r]);
-            if (lane == 0) s_part[t & 1][wave][d][r] = (double)sw;
-          }
-      } else {
-        // all ND * R partial dots of the wave summed at once (recursive halving)
-        constexpr int NP2 = pow2_at_least(ND * R), SH = 6 - log2_exact(NP2);
-        acc_t flat[NP2];
-#pragma unroll
-        for (int q = 0; q < NP2; ++q) flat[q] = q < ND * R ? part[q / R][q % R] : (acc_t)0;
-        const acc_t sw = multi_wave_sum<NP2>(flat, lane);
-        const int q = lane >> SH;
-        if ((lane & ((1 << SH) - 1)) == 0 && q < ND * R) s_part[t & 1][wave][q / R][q % R] = (double)sw;
-      }
+        for (int r = 0; r < R; ++r) {
+          const acc_t sw = wave_sum(part[d][r]);
+          if (lane == 0) s_part[t & 1][wave][d][r] = (double)sw;
+        }
     }
     const int u = t - kLag;
     if (u >= 0 && u < n_my) update<(B + kNBuf - kLag) % kNBuf>(pg, ctx, u, s_tot[u % kNBuf], E, v0);
@@ -604,18 +513,15 @@ struct Product {
     }
     __syncthreads();
     if ((X & kPublish) != 0 || (X == kPlain && pg.C == 1 && wave == 0 && t < n_my)) {
-      double red[ND][R];
+      double red[NDOT][R];
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+      for (int d = 0; d < NDOT; ++d)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           double sm = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) sm += s_part[t & 1][w][d][r];
-          double cs = 0.0;       // centring of operand 0's dots
-          if constexpr (K > 1) cs = lds_k()[d < K ? d : 0];
-          else cs = cshare[0];
-          red[d][r] = (d < K) ? sm - cs : sm;
+          red[d][r] = (d == 0) ? sm - cshare : sm;
         }
       if constexpr ((X & kPublish) != 0) {
         // every step publishes (the tail steps past n_my into the sink), so the store is
@@ -624,7 +530,7 @@ struct Product {
       } else {
         if (lane == 0) {
 #pragma unroll
-          for (int d = 0; d < ND; ++d)
+          for (int d = 0; d < NDOT; ++d)
 #pragma unroll
             for (int r = 0; r < R; ++r) s_tot[t % kNBuf][d][r] = red[d][r];
         }
@@ -637,7 +543,7 @@ struct Product {
   __device__ __forceinline__ void round_of_steps(std::integer_sequence<int, Bs...>, const ProdGeom &pg,
                                                  const ProdBufs &pb, WgCtx &ctx, const Operand *ops, int t0, int n_my,
                                                  const double *__restrict__ E, double v0,
-                                                 double (*s_part)[NW][ND][R], double (*s_tot)[ND][R], bool &ok) {
+                                                 double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R], bool &ok) {
     (step<Bs, X>(pg, pb, ctx, ops, t0 + Bs, n_my, E, v0, s_part, s_tot, ok), ...);
   }
 
@@ -646,7 +552,7 @@ struct Product {
   template <int X>
   __device__ __forceinline__ bool stream_rows(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
                                               int n_my, int rounds, const double *__restrict__ E, double v0,
-                                              double (*s_part)[NW][ND][R], double (*s_tot)[ND][R]) {
+                                              double (*s_part)[NW][NDOT][R], double (*s_tot)[NDOT][R]) {
     issue<0>(ctx, pg, ops, 0);
     if (kLook > 1) issue<(1 % kNBuf)>(ctx, pg, ops, 1);
     if (kLook > 2) issue<(2 % kNBuf)>(ctx, pg, ops, 2);
@@ -661,8 +567,8 @@ struct Product {
   // Accumulate this workgroup's share of O^T w over its row group's tiles.
   __device__ __forceinline__ bool accumulate(const ProdGeom &pg, const ProdBufs &pb, WgCtx &ctx, const Operand *ops,
                                              double /*cshare*/, const double *__restrict__ E, double v0) {
-    __shared__ double s_part[2][NW][ND][R];
-    __shared__ double s_tot[kNBuf][ND][R];
+    __shared__ double s_part[2][NW][NDOT][R];
+    __shared__ double s_tot[kNBuf][NDOT][R];
     __shared__ int s_ok;
     const int n_tiles = (int)((pg.n_s + R - 1) / R);
     const int n_my = (ctx.rg < n_tiles) ? (n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
@@ -680,12 +586,8 @@ struct Product {
     else
       ok = stream_rows<kPlain>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
     // the next product starts on a fresh block of kRing steps, so no word this product
-    // left in the ring carries one of its tags (products may differ in words per slot).
-    // The counter advances by the largest row group's tile count, the same in every
-    // workgroup: a later product with another geometry regroups the workgroups, and the
-    // members of a row group must agree on its step numbers.
-    const int n_max = (n_tiles + pg.RG - 1) / pg.RG;
-    const uint32_t used = ctx.xstep + (uint32_t)n_max;
+    // left in the ring carries one of its tags (products may differ in words per slot)
+    const uint32_t used = ctx.xstep + (uint32_t)n_my;
     ctx.xstep = (used + kRing - 1) / kRing * kRing;
     if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
     __syncthreads();
@@ -695,54 +597,30 @@ struct Product {
   // Dynamic LDS of the launch (the tile ring lives in registers).
   static constexpr int ring_bytes() { return 0; }
 
-  // Store the row group's partial y (float64; [K][RG][n_p]) and scalars ([RG][K + 1]),
-  // coherently.
+  // Store the row group's partial y (float64) and scalars, coherently.
   __device__ __forceinline__ void store_partials(const ProdGeom &pg, const ProdBufs &pb, const WgCtx &ctx) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+    for (int i = 0; i < NV; ++i) {
+      if (i >= nvec) continue;
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        if (i >= nvec) continue;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const int64_t col = colv(i) + e;
-          if (col < pg.n_p)
-            st_coh(&pb.ypart[((int64_t)k * pg.RG + ctx.rg) * pg.n_p + col], (double)yacc[k][i][e]);
-        }
+      for (int e = 0; e < VEC; ++e) {
+        const int64_t col = colv(i) + e;
+        if (col < pg.n_p) st_coh(&pb.ypart[(int64_t)ctx.rg * pg.n_p + col], (double)yacc[i][e]);
       }
+    }
     if (ctx.cg == 0 && threadIdx.x == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) st_coh(&pb.spart[ctx.rg * (K + 1) + k], K > 1 ? lds_k()[K + k] : s1[0]);
-      st_coh(&pb.spart[ctx.rg * (K + 1) + K], s2);
+      st_coh(&pb.spart[ctx.rg * 2 + 0], s1);
+      st_coh(&pb.spart[ctx.rg * 2 + 1], s2);
     }
   }
 };
 
 // Column j of the finished product: (s_j * sum_rg ypart[rg][j] - mean_j * S1) with
 // S1 = sum_rg spart[rg][0]; a fixed summation order over row groups.
-__device__ __forceinline__ double finish_column(const ProdBufs &pb, const ProdGeom &pg, int64_t j, int k = 0) {
+__device__ __forceinline__ double finish_column(const ProdBufs &pb, const ProdGeom &pg, int64_t j) {
   double acc = 0.0;
-  for (int rg = 0; rg < pg.RG; ++rg) acc += ld_coh(&pb.ypart[((int64_t)k * pg.RG + rg) * pg.n_p + j]);
+  for (int rg = 0; rg < pg.RG; ++rg) acc += ld_coh(&pb.ypart[(int64_t)rg * pg.n_p + j]);
   return acc;
-}
-
-// Row-group sums of the K scalars sum_k w (spart [RG][K + 1]); every thread gets them.
-template <int K>
-__device__ __forceinline__ void sum_row_scalars_k(const ProdBufs &pb, const ProdGeom &pg, double (&S1)[K]) {
-  __shared__ double s_s[K];
-  if (threadIdx.x < 64) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double a = 0.0;
-      for (int rg = (int)threadIdx.x; rg < pg.RG; rg += 64) a += ld_coh(&pb.spart[rg * (K + 1) + k]);
-      a = wave_sum(a);
-      if (threadIdx.x == 0) s_s[k] = a;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) S1[k] = s_s[k];
-  __syncthreads();
 }
 
 __device__ __forceinline__ void sum_row_scalars(const ProdBufs &pb, const ProdGeom &pg, double &S1, double &S2) {
