@@ -146,6 +146,7 @@ def main():
                     help="timed steps only (for profiler passes): no tuning, float64 solves, standalone "
                          "products or CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation-form measurement")
     ap.add_argument("--batched-systems", type=int, default=64,
                     help="systems of the batched workload timed in one launch (its first n)")
     ap.add_argument("--copy-gb", type=float, default=0.0,
@@ -161,7 +162,52 @@ def main():
     out = measure_single(args)
     torch.cuda.empty_cache()
     out["batched"] = None if (args.quick or args.no_batched) else measure_batched(args)
+    torch.cuda.empty_cache()
+    out["adjoint"] = None if (args.quick or args.no_adjoint) else measure_adjoint(args)
     print(json.dumps(out), flush=True)
+
+
+def measure_adjoint(args):
+    """The differentiation form on dense float32 O 16384 x 16384, eps = 1e-3, L = w . x:
+    forward (prepare pass + CG) and backward (adjoint CG + sr_adjoint) through
+    torch.autograd, and sr_adjoint alone (one read of O, one write of dL/dO)."""
+    import torch
+    import synth
+    from paper_1108_0900_amd import sr
+    from paper_1108_0900_amd.autograd import sr_solve
+    dev = "cuda:0"
+    cfg = synth.CONFIGS["c5"]
+    d = synth.dense_inputs(cfg.n_s, cfg.n_p, cfg.seed, device=dev, dtype=torch.float32)
+    O, E = d["O"], d["E"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(55)
+    w = torch.randn(cfg.n_p, generator=gen, dtype=torch.float64, device=dev)
+    rtol = 1e-9
+
+    def fwd_bwd():
+        Ot = O.clone().requires_grad_(True)
+        Et = E.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        x, ms_f = timed_events(lambda: sr_solve(Ot, Et, cfg.eps_abs, rtol, 20))
+        _, ms_b = timed_events(lambda: (x * w).sum().backward())
+        return ms_f, ms_b
+    fwd_bwd()                                                   # warm
+    ms_f, ms_b = fwd_bwd()
+    M = sr.as_matrix(O)
+    st = sr.sr_grad(M, E)
+    M.mean = st["mean"]
+    x, info_x = sr.sr_cg_solve(M, st["g"], cfg.eps_abs, rtol=rtol, refresh_every=20)
+    lam, info_l = sr.sr_cg_solve(M, w, cfg.eps_abs, rtol=rtol, refresh_every=20)
+    sr.sr_adjoint(M, E, x, lam, dO_dtype=torch.float32)
+    ts = sorted(timed_events(lambda: sr.sr_adjoint(M, E, x, lam, dO_dtype=torch.float32))[1] for _ in range(5))
+    gb = 2 * O.numel() * 4 / 1e9
+    out = {"workload": "dense float32 O %d x %d N(0,1) x lognormal(0, 0.5), eps = %g, L = w . x, CG to %g, "
+                       "refresh every 20" % (cfg.n_s, cfg.n_p, cfg.eps_abs, rtol),
+           "forward_ms": round(ms_f, 2), "backward_ms": round(ms_b, 2),
+           "forward_products": info_x["products"], "adjoint_cg_products": info_l["products"],
+           "sr_adjoint_ms": round(ts[2], 3), "sr_adjoint_GBps": round(gb / ts[2] * 1e3, 1)}
+    log(f"[bench] adjoint: {out}")
+    return out
 
 
 def measure_batched(args):
