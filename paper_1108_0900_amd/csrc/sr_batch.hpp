@@ -91,8 +91,8 @@ __device__ __forceinline__ bool grid_allreduce_n(const double (&in)[N], double *
 //   0. vs_k = s_j v_kj (scaled operand) and c_k = obar . v_k (grid sum).
 //   1. Row dots: a workgroup takes a block of NW * kBatchRows rows (kBatchRows per wave)
 //      and one column part; it walks the part in chunks of 64 * VEC columns, the chunk of
-//      vs staged in LDS (double-buffered, next chunk's vs and tiles loaded during the
-//      current one), and writes wp[part][row][k] (c_k taken off in part 0).
+//      vs staged in LDS (double-buffered; tiles are loaded two chunks ahead, vs one), and
+//      writes wp[part][row][k] (c_k taken off in part 0).
 //   2. Updates: a workgroup takes threads * VEC columns and one split of the rows; the
 //      split's centred row dots (summed over parts) sit in LDS, each thread accumulates
 //      sum_rows O_rj w[row][k] for its VEC columns and all k, rows kBatchU at a time.
@@ -122,13 +122,15 @@ struct BatchProduct {
     return in ? (double)St::get(t, e) : 0.0;
   }
 
+  // Loads (unconditional: clamped address, masked value) of chunk [c0, c0 + CW) of vs.
   __device__ __forceinline__ static void stage_load(const BatchArgs &a, double (&vr)[KPT], int64_t c0, int64_t ce) {
 #pragma unroll
     for (int m = 0; m < KPT; ++m) {
       const int idx = (int)threadIdx.x + m * NT;
       const int k = idx / CW, jj = idx % CW;
       const int64_t col = c0 + jj;
-      vr[m] = col < ce ? ld_coh(&a.vs[k * a.vstride + col]) : 0.0;
+      const double v = ld_coh(&a.vs[k * a.vstride + (col < ce ? col : 0)]);
+      vr[m] = col < ce ? v : 0.0;
     }
   }
   __device__ __forceinline__ static void stage_store(double *buf, const double (&vr)[KPT]) {
@@ -139,6 +141,42 @@ struct BatchProduct {
                                                     int64_t col) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) t[r] = load_stream(rowp[r] + col * St::BYTES);
+  }
+
+  // One chunk step of the row-dot pass (chunk i, B = i % 3): start the loads of chunk
+  // i + 2, accumulate chunk i (tiles t[B], vs in LDS buffer i & 1), stage chunk i + 1's vs
+  // (loaded one step earlier) into the other LDS buffer.  Tiles are in flight two steps,
+  // vs one step.  A lane past the part's end reads the part's first vector (masked).
+  template <int B>
+  __device__ __forceinline__ static void rd_step(const BatchArgs &a, double *sv, u32x4 (&t)[3][RB],
+                                                 double (&vr)[3][KPT], double (&acc)[RB][K],
+                                                 const unsigned char *const (&rowp)[RB], int i, int64_t cs,
+                                                 int64_t ce, int lane) {
+    constexpr int BN = (B + 2) % 3, B1 = (B + 1) % 3;
+    const int64_t cn = cs + (int64_t)(i + 2) * CW;
+    tiles_load(t[BN], rowp, cn + lane * VEC < ce ? cn + lane * VEC : cs);
+    stage_load(a, vr[BN], cn, ce);
+    const double *vb = sv + (i & 1) * (K * CW) + lane * VEC;
+    const int64_t col = cs + (int64_t)i * CW + lane * VEC;
+    double o[RB][VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const bool in = col + e < ce;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) o[r][e] = elem(t[B][r], e, in);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v[e] = vb[k * CW + e];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[r][k] += o[r][e] * v[e];
+    }
+    stage_store(sv + ((i + 1) & 1) * (K * CW), vr[B1]);
+    __syncthreads();
   }
 
   // Pass 1 over this workgroup's tasks.
@@ -160,46 +198,23 @@ struct BatchProduct {
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[r][k] = 0.0;
+      // whole rounds of three steps (steps past the part's end are fully masked)
       const int nch = (int)((ce - cs + CW - 1) / CW);
-      double vr[KPT];
-      u32x4 cur[RB], nxt[RB];
-      // a lane past the part's end reads the part's first vector (masked below)
+      const int rounds = (nch + 2) / 3;
+      u32x4 t[3][RB];
+      double vr[3][KPT];
       auto lane_col = [&](int64_t c0) { return c0 + lane * VEC < ce ? c0 + lane * VEC : cs; };
-      stage_load(a, vr, cs, ce);
-      tiles_load(cur, rowp, lane_col(cs));
+      tiles_load(t[0], rowp, lane_col(cs));
+      stage_load(a, vr[0], cs, ce);
+      tiles_load(t[1], rowp, lane_col(cs + CW));
+      stage_load(a, vr[1], cs + CW, ce);
       __syncthreads();                       // the previous task's readers of sv are done
-      stage_store(sv, vr);
+      stage_store(sv, vr[0]);
       __syncthreads();
-      for (int i = 0; i < nch; ++i) {
-        const int64_t c0 = cs + (int64_t)i * CW;
-        const bool more = i + 1 < nch;
-        if (more) {
-          stage_load(a, vr, c0 + CW, ce);
-          tiles_load(nxt, rowp, lane_col(c0 + CW));
-        }
-        const double *vb = sv + (i & 1) * (K * CW) + lane * VEC;
-        const int64_t col = c0 + lane * VEC;
-        double o[RB][VEC];
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const bool in = col + e < ce;
-#pragma unroll
-          for (int r = 0; r < RB; ++r) o[r][e] = elem(cur[r], e, in);
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          double v[VEC];
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) v[e] = vb[k * CW + e];
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) acc[r][k] += o[r][e] * v[e];
-        }
-        if (more) stage_store(sv + ((i + 1) & 1) * (K * CW), vr);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RB; ++r) cur[r] = nxt[r];
+      for (int q = 0; q < rounds; ++q) {
+        rd_step<0>(a, sv, t, vr, acc, rowp, 3 * q, cs, ce, lane);
+        rd_step<1>(a, sv, t, vr, acc, rowp, 3 * q + 1, cs, ce, lane);
+        rd_step<2>(a, sv, t, vr, acc, rowp, 3 * q + 2, cs, ce, lane);
       }
       double flat[RB * K];
 #pragma unroll
