@@ -248,8 +248,11 @@ def measure_batched(args):
            "column_solves": 8 * len(systems), "products": sum(prods), "worst_rel_res_true": worst,
            "O_stream_GBps": round(passes_gb / ms * 1e3, 1)}
     del X
-    # the same 8 columns of the first system: one batched launch vs 8 single solves
+    # the same 8 columns of the first system: one batched launch vs 8 single solves (the
+    # single-column product's tiles tuned on this matrix first)
     M, G, eps = systems[0]
+    from paper_1108_0900_amd import tune
+    tune.autotune(M, kind=0, reps=3)
     (res1, ms1) = timed_events(lambda: sr.sr_cg_solve_batched([systems[0]], rtol=cfg.rtol, refresh_every=20))
     t_single = 0.0
     for i in range(8):

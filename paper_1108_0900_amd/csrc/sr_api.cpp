@@ -540,8 +540,25 @@ int fill_zero(void *p, int64_t words, hipStream_t s) {
   return SR_OK;
 }
 
-// Geometry of one system's two-pass products (see BatchProduct): about two tasks per
-// workgroup in each pass where the shape allows.
+// Of the multipliers m in [lo, hi], the one whose task count units * m spreads best over G
+// workgroups (least ceil(t / G) / (t / G): the busiest workgroup sets the pass time);
+// ties go to the smaller m.
+int64_t balanced_multiplier(int64_t units, int G, int64_t lo, int64_t hi) {
+  int64_t best = lo;
+  double best_q = 1e300;
+  for (int64_t m = lo; m <= hi; ++m) {
+    const double t = (double)(units * m);
+    const double q = std::ceil(t / G) / (t / G);
+    if (q < best_q - 1e-9) {
+      best_q = q;
+      best = m;
+    }
+  }
+  return best;
+}
+
+// Geometry of one system's two-pass products (see BatchProduct): two to six tasks per
+// workgroup in each pass where the shape allows, the count chosen to balance.
 BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
   BatchGeom g{};
   g.n_s = n_s;
@@ -549,13 +566,20 @@ BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
   const int nw = kBatchNT / 64;
   const int64_t cw = 64 * (int64_t)vec, bw = (int64_t)kBatchNT * vec;
   g.n_rb = cdiv(n_s, (int64_t)nw * kBatchRows);
-  const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));   // parts of >= 4 chunks
-  const int64_t parts = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
+  // column parts of the row-dot pass, each at least 4 chunks wide
+  const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));
+  const int64_t p_lo = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
+  const int64_t p_hi = std::min<int64_t>(max_parts, std::max<int64_t>(p_lo, cdiv(6 * (int64_t)G, g.n_rb)));
+  const int64_t parts = balanced_multiplier(g.n_rb, G, p_lo, p_hi);
   g.pw = round_up(cdiv(n_p, parts), cw);
   g.P = (int)cdiv(n_p, g.pw);
   g.C = (int)cdiv(n_p, bw);
-  const int64_t sp = std::max<int64_t>(cdiv(n_s, kBatchSplitRows),
-                                       std::min<int64_t>(cdiv(2 * (int64_t)G, g.C), cdiv(n_s, 64)));
+  // row splits of the update pass, each at least 64 rows (their partials,
+  // SP x 8 x N_p float64, stay small next to O)
+  const int64_t sp_max = std::max<int64_t>(1, cdiv(n_s, 64));
+  const int64_t s_lo = std::min<int64_t>(sp_max, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.C)));
+  const int64_t s_hi = std::min<int64_t>(sp_max, std::max<int64_t>(s_lo, cdiv(6 * (int64_t)G, g.C)));
+  const int64_t sp = balanced_multiplier(g.C, G, s_lo, s_hi);
   g.rs = cdiv(n_s, sp);
   g.SP = (int)cdiv(n_s, g.rs);
   return g;

@@ -94,8 +94,9 @@ __device__ __forceinline__ bool grid_allreduce_n(const double (&in)[N], double *
 //      vs staged in LDS (double-buffered; tiles are loaded two chunks ahead, vs one), and
 //      writes wp[part][row][k] (c_k taken off in part 0).
 //   2. Updates: a workgroup takes threads * VEC columns and one split of the rows; the
-//      split's centred row dots (summed over parts) sit in LDS, each thread accumulates
-//      sum_rows O_rj w[row][k] for its VEC columns and all k, rows kBatchU at a time.
+//      split's centred row dots (summed over parts) pass through LDS in windows of
+//      kBatchSplitRows rows, each thread accumulates sum_rows O_rj w[row][k] for its VEC
+//      columns and all k, rows kBatchU at a time.
 //   3. Finish: y_kj = (s_j sum_sp yp - obar_j sum_rows w_k) / N + eps_k v_kj.
 // Buffers written in one pass and read by other workgroups in the next are accessed
 // coherently; a grid barrier separates the passes.
@@ -241,29 +242,6 @@ struct BatchProduct {
     for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
       const int cb = (int)(task % g.C), sp = (int)(task / g.C);
       const int64_t rs0 = (int64_t)sp * g.rs, rs1 = min(g.n_s, rs0 + g.rs);
-      const int nrow = (int)(rs1 - rs0);
-      __syncthreads();                       // the previous task's readers of sw are done
-      for (int idx = tid; idx < nrow * K; idx += NT) {
-        const int64_t row = rs0 + idx / K;
-        const int k = idx % K;
-        double t = 0.0;
-        for (int p = 0; p < g.P; ++p) t += ld_coh(&a.wp[((int64_t)p * g.n_s + row) * K + k]);
-        sw[idx] = t;
-      }
-      __syncthreads();
-      if (cb == 0 && tid < 64) {             // this split's sums of the centred row dots
-        double ps[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) ps[k] = 0.0;
-        for (int r = tid; r < nrow; r += 64)
-#pragma unroll
-          for (int k = 0; k < K; ++k) ps[k] += sw[r * K + k];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const double t = wave_sum(ps[k]);
-          if (tid == 0) st_coh(&a.swp[(int64_t)sp * K + k], t);
-        }
-      }
       const int64_t col = (int64_t)cb * BW + (int64_t)tid * VEC;
       const bool live = col < g.n_p;
       const int64_t colc = live ? col : 0;
@@ -271,37 +249,66 @@ struct BatchProduct {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) in[e] = live && col + e < g.n_p;
       const unsigned char *base = S.op.O + colc * St::BYTES;
-      double y[K][VEC];
+      double y[K][VEC], ps[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k) {
+        ps[k] = 0.0;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) y[k][e] = 0.0;
-      u32x4 cur[kBatchU], nxt[kBatchU];
-#pragma unroll
-      for (int u = 0; u < kBatchU; ++u) cur[u] = load_stream(base + min(rs0 + u, rs1 - 1) * S.op.ldb);
-      for (int64_t r = rs0; r < rs1; r += kBatchU) {
-        const bool more = r + kBatchU < rs1;
-        if (more) {
-#pragma unroll
-          for (int u = 0; u < kBatchU; ++u) nxt[u] = load_stream(base + min(r + kBatchU + u, rs1 - 1) * S.op.ldb);
+      }
+      // the split's rows in windows of kBatchSplitRows, their centred row dots (summed
+      // over the column parts) staged in LDS
+      for (int64_t w0 = rs0; w0 < rs1; w0 += kBatchSplitRows) {
+        const int64_t w1 = min(rs1, w0 + (int64_t)kBatchSplitRows);
+        const int nrow = (int)(w1 - w0);
+        __syncthreads();                     // the previous window's readers of sw are done
+        for (int idx = tid; idx < nrow * K; idx += NT) {
+          const int64_t row = w0 + idx / K;
+          const int k = idx % K;
+          double t = 0.0;
+          for (int p = 0; p < g.P; ++p) t += ld_coh(&a.wp[((int64_t)p * g.n_s + row) * K + k]);
+          sw[idx] = t;
         }
+        __syncthreads();
+        if (cb == 0 && tid < 64) {           // running sums of the centred row dots
+          for (int r = tid; r < nrow; r += 64)
 #pragma unroll
-        for (int u = 0; u < kBatchU; ++u) {
-          if (r + u < rs1) {
-            const double *wr = sw + (r + u - rs0) * K;
-            double w[K];
+            for (int k = 0; k < K; ++k) ps[k] += sw[r * K + k];
+        }
+        u32x4 cur[kBatchU], nxt[kBatchU];
 #pragma unroll
-            for (int k = 0; k < K; ++k) w[k] = wr[k];
+        for (int u = 0; u < kBatchU; ++u) cur[u] = load_stream(base + min(w0 + u, w1 - 1) * S.op.ldb);
+        for (int64_t r = w0; r < w1; r += kBatchU) {
+          const bool more = r + kBatchU < w1;
+          if (more) {
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) {
-              const double o = elem(cur[u], e, in[e]);
+            for (int u = 0; u < kBatchU; ++u) nxt[u] = load_stream(base + min(r + kBatchU + u, w1 - 1) * S.op.ldb);
+          }
 #pragma unroll
-              for (int k = 0; k < K; ++k) y[k][e] += o * w[k];
+          for (int u = 0; u < kBatchU; ++u) {
+            if (r + u < w1) {
+              const double *wr = sw + (r + u - w0) * K;
+              double w[K];
+#pragma unroll
+              for (int k = 0; k < K; ++k) w[k] = wr[k];
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) {
+                const double o = elem(cur[u], e, in[e]);
+#pragma unroll
+                for (int k = 0; k < K; ++k) y[k][e] += o * w[k];
+              }
             }
           }
-        }
 #pragma unroll
-        for (int u = 0; u < kBatchU; ++u) cur[u] = nxt[u];
+          for (int u = 0; u < kBatchU; ++u) cur[u] = nxt[u];
+        }
+      }
+      if (cb == 0 && tid < 64) {             // this split's sums of the centred row dots
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double t = wave_sum(ps[k]);
+          if (tid == 0) st_coh(&a.swp[(int64_t)sp * K + k], t);
+        }
       }
 #pragma unroll
       for (int k = 0; k < K; ++k)

@@ -85,10 +85,10 @@ struct QuantArgs {
 // Batched solves: K right-hand sides per system, systems one after another in one
 // persistent launch.  A product (S + diag(eps)) V takes two passes over O: row dots
 // W = O_c V by row blocks (V staged through LDS chunk by chunk), then O^T W by column
-// blocks and row splits (the split's rows of W held in LDS).
+// blocks and row splits (the split's rows of W pass through LDS in windows).
 constexpr int kBatchK = 8;           // right-hand sides per product of the batched kernels
 constexpr int kBatchRows = 4;        // rows per wave in the row-dot pass
-constexpr int kBatchSplitRows = 1024;   // most rows per split of the update pass
+constexpr int kBatchSplitRows = 1024;   // rows per LDS window of the update pass
 constexpr int kBatchNT = 512;        // threads per workgroup of the batched kernels
 
 struct BatchGeom {
@@ -98,7 +98,7 @@ struct BatchGeom {
   int P;                             // column parts of the row-dot pass
   int C;                             // column blocks of the update pass (threads * VEC columns)
   int SP;                            // row splits of the update pass
-  int64_t rs;                        // rows per split (<= kBatchSplitRows)
+  int64_t rs;                        // rows per split
 };
 struct BatchSys {
   Operand op;

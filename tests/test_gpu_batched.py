@@ -57,6 +57,28 @@ def test_multi_rhs_product_matches_oracle(shape, dtype, k, exact):
         assert np.all(np.abs(Y[i] - ref) <= tol * mag + 1e-300), (i, float(np.max(np.abs(Y[i] - ref) / mag)))
 
 
+def test_multi_rhs_product_long_splits_match_single_products():
+    """A shape whose row splits span several LDS windows of the update pass (12000 rows,
+    140000 columns: 69 column blocks, 8 splits of 1500 rows): every column of the 8-column
+    product equals the one-column float64 product (a different kernel, itself checked
+    against the oracle) to 1e-12 of the magnitude reference."""
+    n_s, n_p = 12000, 140000
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(91)
+    O = (torch.randn(n_s, n_p, generator=gen, device=DEV, dtype=torch.float32) + 0.3)
+    M = sr.as_matrix(O)
+    M.mean = sr.sr_grad(M, None)["mean"]
+    V = torch.randn(8, n_p, generator=gen, device=DEV, dtype=torch.float64)
+    eps = [10.0 ** (-i) for i in range(8)]
+    Y = sr.sr_svk_product(M, V, eps)
+    A = (O - M.mean.float()).abs().double()
+    for i in range(8):
+        y1 = sr.sr_sv_product(M, V[i], eps[i])
+        mag = (A.T @ (A @ V[i].abs())) / n_s + eps[i] * V[i].abs()
+        assert float(((Y[i] - y1).abs() / mag).max()) <= 1e-12, i
+    del O, A
+
+
 def _batch_case(dtype, shapes, k, seed):
     systems, refs = [], []
     for s, (n_s, n_p) in enumerate(shapes):
