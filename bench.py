@@ -184,20 +184,23 @@ def measure_adjoint(args):
     w = torch.randn(cfg.n_p, generator=gen, dtype=torch.float64, device=dev)
     rtol = 1e-9
 
-    def fwd_bwd():
+    def fwd_bwd(precond=False):
         Ot = O.clone().requires_grad_(True)
         Et = E.clone().requires_grad_(True)
         torch.cuda.synchronize()
-        x, ms_f = timed_events(lambda: sr_solve(Ot, Et, cfg.eps_abs, rtol, 20))
+        x, ms_f = timed_events(lambda: sr_solve(Ot, Et, cfg.eps_abs, rtol, 20, precond))
         _, ms_b = timed_events(lambda: (x * w).sum().backward())
-        return ms_f, ms_b
+        return ms_f, ms_b, x.detach()
     fwd_bwd()                                                   # warm
-    ms_f, ms_b = fwd_bwd()
+    ms_f, ms_b, x_plain = fwd_bwd()
+    ms_fj, ms_bj, x_jac = fwd_bwd(True)
     M = sr.as_matrix(O)
     st = sr.sr_grad(M, E)
     M.mean = st["mean"]
     x, info_x = sr.sr_cg_solve(M, st["g"], cfg.eps_abs, rtol=rtol, refresh_every=20)
     lam, info_l = sr.sr_cg_solve(M, w, cfg.eps_abs, rtol=rtol, refresh_every=20)
+    _, info_xj = sr.sr_cg_solve(M, st["g"], cfg.eps_abs, rtol=rtol, refresh_every=20, precond=True)
+    _, info_lj = sr.sr_cg_solve(M, w, cfg.eps_abs, rtol=rtol, refresh_every=20, precond=True)
     sr.sr_adjoint(M, E, x, lam, dO_dtype=torch.float32)
     ts = sorted(timed_events(lambda: sr.sr_adjoint(M, E, x, lam, dO_dtype=torch.float32))[1] for _ in range(5))
     gb = 2 * O.numel() * 4 / 1e9
@@ -205,6 +208,10 @@ def measure_adjoint(args):
                        "refresh every 20" % (cfg.n_s, cfg.n_p, cfg.eps_abs, rtol),
            "forward_ms": round(ms_f, 2), "backward_ms": round(ms_b, 2),
            "forward_products": info_x["products"], "adjoint_cg_products": info_l["products"],
+           "jacobi": {"forward_ms": round(ms_fj, 2), "backward_ms": round(ms_bj, 2),
+                      "forward_products": info_xj["products"], "adjoint_cg_products": info_lj["products"],
+                      "x_rel_diff_vs_plain": float(torch.linalg.vector_norm(x_jac - x_plain) /
+                                                   torch.linalg.vector_norm(x_plain))},
            "sr_adjoint_ms": round(ts[2], 3), "sr_adjoint_GBps": round(gb / ts[2] * 1e3, 1)}
     log(f"[bench] adjoint: {out}")
     return out

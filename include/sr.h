@@ -90,6 +90,9 @@ typedef struct sr_cg_opts {
   int32_t refine;            /* with O_lo only: 1: search-direction products read the  */
                              /* first code plane only (iterative refinement); 0: they  */
                              /* read both planes (float32 accumulation)                */
+  int32_t precond;           /* 1: Jacobi preconditioner, z = r / (diag S + eps) (one  */
+                             /* extra prepare pass computes diag S); SR_F64 / SR_F32    */
+                             /* storage only; 0: none                                  */
 } sr_cg_opts;
 
 /* CG outcome, written to host memory. */
@@ -184,7 +187,8 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
  * opt->refresh_drop since the last check if refresh_drop > 0, and at max_iter).
  * sys: host [n_sys]; every O has the same dtype (SR_F64 or SR_F32).  info: host
  * [n_sys * k] (system-major) or NULL; its `refreshes` is 0 and rel_res_recur repeats
- * rel_res_true.  opt->use_x0, restart_on_refresh, refine and res_history are not used.
+ * rel_res_true.  opt->use_x0, restart_on_refresh, refine, precond and res_history are
+ * not used.
  * Synchronizes `stream`.  Returns SR_OK if every column converged, else
  * SR_NOT_CONVERGED / SR_BREAKDOWN (the first such status met) or an error code.
  * ------------------------------------------------------------------------------------ */

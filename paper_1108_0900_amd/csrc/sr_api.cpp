@@ -540,25 +540,10 @@ int fill_zero(void *p, int64_t words, hipStream_t s) {
   return SR_OK;
 }
 
-// Of the multipliers m in [lo, hi], the one whose task count units * m spreads best over G
-// workgroups (least ceil(t / G) / (t / G): the busiest workgroup sets the pass time);
-// ties go to the smaller m.
-int64_t balanced_multiplier(int64_t units, int G, int64_t lo, int64_t hi) {
-  int64_t best = lo;
-  double best_q = 1e300;
-  for (int64_t m = lo; m <= hi; ++m) {
-    const double t = (double)(units * m);
-    const double q = std::ceil(t / G) / (t / G);
-    if (q < best_q - 1e-9) {
-      best_q = q;
-      best = m;
-    }
-  }
-  return best;
-}
-
-// Geometry of one system's two-pass products (see BatchProduct): two to six tasks per
-// workgroup in each pass where the shape allows, the count chosen to balance.
+// Geometry of one system's two-pass products (see BatchProduct): about two tasks per
+// workgroup in each pass where the shape allows.  The update pass's splits hold at most
+// kBatchSplitRows rows (their partials, SP x 8 x N_p float64, stay near 1.6 % of a
+// float32 O); shorter splits cost more partial traffic than their balance gains.
 BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
   BatchGeom g{};
   g.n_s = n_s;
@@ -566,20 +551,13 @@ BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
   const int nw = kBatchNT / 64;
   const int64_t cw = 64 * (int64_t)vec, bw = (int64_t)kBatchNT * vec;
   g.n_rb = cdiv(n_s, (int64_t)nw * kBatchRows);
-  // column parts of the row-dot pass, each at least 4 chunks wide
-  const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));
-  const int64_t p_lo = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
-  const int64_t p_hi = std::min<int64_t>(max_parts, std::max<int64_t>(p_lo, cdiv(6 * (int64_t)G, g.n_rb)));
-  const int64_t parts = balanced_multiplier(g.n_rb, G, p_lo, p_hi);
+  const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));   // parts of >= 4 chunks
+  const int64_t parts = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
   g.pw = round_up(cdiv(n_p, parts), cw);
   g.P = (int)cdiv(n_p, g.pw);
   g.C = (int)cdiv(n_p, bw);
-  // row splits of the update pass, each at least 64 rows (their partials,
-  // SP x 8 x N_p float64, stay small next to O)
-  const int64_t sp_max = std::max<int64_t>(1, cdiv(n_s, 64));
-  const int64_t s_lo = std::min<int64_t>(sp_max, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.C)));
-  const int64_t s_hi = std::min<int64_t>(sp_max, std::max<int64_t>(s_lo, cdiv(6 * (int64_t)G, g.C)));
-  const int64_t sp = balanced_multiplier(g.C, G, s_lo, s_hi);
+  const int64_t sp = std::max<int64_t>(cdiv(n_s, kBatchSplitRows),
+                                       std::min<int64_t>(cdiv(2 * (int64_t)G, g.C), cdiv(n_s, 64)));
   g.rs = cdiv(n_s, sp);
   g.SP = (int)cdiv(n_s, g.rs);
   return g;
@@ -970,6 +948,9 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_drop must be in [0, 1)");
   if (o.refine != 0 && o.refine != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: refine must be 0 or 1");
   if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: use_x0 must be 0 or 1");
+  if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: precond must be 0 or 1");
+  if (o.precond && (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32)))
+    return fail(SR_ERR_INVALID, "sr_cg_solve: the Jacobi preconditioner needs SR_F64 or SR_F32 storage, one plane");
   int64_t max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
   if (max_iter > (1 << 30)) max_iter = 1 << 30;
   int dev;
@@ -977,13 +958,23 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   rc = device_check(&dev, &di);
   if (rc) return rc;
   const double *mean = nullptr;
-  double *mscr = nullptr;
-  if (!O->col_mean) {
-    rc = get_mean_scratch(dev, stream, O->n_p, &mscr);
+  double *mscr = nullptr, *diag = nullptr;
+  if (o.precond) {
+    // one prepare pass gives diag S (and the column means, used unless the caller gave them)
+    rc = get_mean_scratch(dev, stream, 2 * round_up(O->n_p, 32), &mscr);
+    if (rc) return rc;
+    diag = mscr + round_up(O->n_p, 32);
+    rc = run_grad(O, nullptr, nullptr, nullptr, mscr, diag, dev, di, stream);
+    if (rc) return rc;
+    mean = O->col_mean ? O->col_mean : mscr;
+  } else {
+    if (!O->col_mean) {
+      rc = get_mean_scratch(dev, stream, O->n_p, &mscr);
+      if (rc) return rc;
+    }
+    rc = ensure_mean(O, mscr, &mean, dev, di, stream);
     if (rc) return rc;
   }
-  rc = ensure_mean(O, mscr, &mean, dev, di, stream);
-  if (rc) return rc;
   Plan pl;
   rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl);
   if (rc) return rc;
@@ -1018,9 +1009,11 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.restart_on_refresh = (o.restart_on_refresh != 0 || a.refine) ? 1 : 0;
   a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
   a.hist = o.res_history;
+  a.diag = diag;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  const void *cg_fn = O->O_lo == nullptr ? pl.ke->cg : (a.refine ? pl.ke->cgr : pl.ke->cg2);
+  const void *cg_fn =
+      O->O_lo == nullptr ? (o.precond ? pl.ke->cgj : pl.ke->cg) : (a.refine ? pl.ke->cgr : pl.ke->cg2);
   if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no two-plane CG kernel for this configuration");
   rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
   if (rc) return rc;

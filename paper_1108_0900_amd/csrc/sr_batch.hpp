@@ -91,12 +91,12 @@ __device__ __forceinline__ bool grid_allreduce_n(const double (&in)[N], double *
 //   0. vs_k = s_j v_kj (scaled operand) and c_k = obar . v_k (grid sum).
 //   1. Row dots: a workgroup takes a block of NW * kBatchRows rows (kBatchRows per wave)
 //      and one column part; it walks the part in chunks of 64 * VEC columns, the chunk of
-//      vs staged in LDS (double-buffered; tiles are loaded two chunks ahead, vs one), and
-//      writes wp[part][row][k] (c_k taken off in part 0).
-//   2. Updates: a workgroup takes threads * VEC columns and one split of the rows; the
-//      split's centred row dots (summed over parts) pass through LDS in windows of
-//      kBatchSplitRows rows, each thread accumulates sum_rows O_rj w[row][k] for its VEC
-//      columns and all k, rows kBatchU at a time.
+//      vs staged in LDS (double-buffered, next chunk's vs and tiles loaded during the
+//      current one), and writes wp[part][row][k] (c_k taken off in part 0).
+//   2. Updates: a workgroup takes threads * VEC columns and one split of at most
+//      kBatchSplitRows rows; the split's centred row dots (summed over parts) sit in LDS,
+//      each thread accumulates sum_rows O_rj w[row][k] for its VEC columns and all k,
+//      rows kBatchU at a time.
 //   3. Finish: y_kj = (s_j sum_sp yp - obar_j sum_rows w_k) / N + eps_k v_kj.
 // Buffers written in one pass and read by other workgroups in the next are accessed
 // coherently; a grid barrier separates the passes.
@@ -123,15 +123,13 @@ struct BatchProduct {
     return in ? (double)St::get(t, e) : 0.0;
   }
 
-  // Loads (unconditional: clamped address, masked value) of chunk [c0, c0 + CW) of vs.
   __device__ __forceinline__ static void stage_load(const BatchArgs &a, double (&vr)[KPT], int64_t c0, int64_t ce) {
 #pragma unroll
     for (int m = 0; m < KPT; ++m) {
       const int idx = (int)threadIdx.x + m * NT;
       const int k = idx / CW, jj = idx % CW;
       const int64_t col = c0 + jj;
-      const double v = ld_coh(&a.vs[k * a.vstride + (col < ce ? col : 0)]);
-      vr[m] = col < ce ? v : 0.0;
+      vr[m] = col < ce ? ld_coh(&a.vs[k * a.vstride + col]) : 0.0;
     }
   }
   __device__ __forceinline__ static void stage_store(double *buf, const double (&vr)[KPT]) {
@@ -142,42 +140,6 @@ struct BatchProduct {
                                                     int64_t col) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) t[r] = load_stream(rowp[r] + col * St::BYTES);
-  }
-
-  // One chunk step of the row-dot pass (chunk i, B = i % 3): start the loads of chunk
-  // i + 2, accumulate chunk i (tiles t[B], vs in LDS buffer i & 1), stage chunk i + 1's vs
-  // (loaded one step earlier) into the other LDS buffer.  Tiles are in flight two steps,
-  // vs one step.  A lane past the part's end reads the part's first vector (masked).
-  template <int B>
-  __device__ __forceinline__ static void rd_step(const BatchArgs &a, double *sv, u32x4 (&t)[3][RB],
-                                                 double (&vr)[3][KPT], double (&acc)[RB][K],
-                                                 const unsigned char *const (&rowp)[RB], int i, int64_t cs,
-                                                 int64_t ce, int lane) {
-    constexpr int BN = (B + 2) % 3, B1 = (B + 1) % 3;
-    const int64_t cn = cs + (int64_t)(i + 2) * CW;
-    tiles_load(t[BN], rowp, cn + lane * VEC < ce ? cn + lane * VEC : cs);
-    stage_load(a, vr[BN], cn, ce);
-    const double *vb = sv + (i & 1) * (K * CW) + lane * VEC;
-    const int64_t col = cs + (int64_t)i * CW + lane * VEC;
-    double o[RB][VEC];
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const bool in = col + e < ce;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) o[r][e] = elem(t[B][r], e, in);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double v[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) v[e] = vb[k * CW + e];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[r][k] += o[r][e] * v[e];
-    }
-    stage_store(sv + ((i + 1) & 1) * (K * CW), vr[B1]);
-    __syncthreads();
   }
 
   // Pass 1 over this workgroup's tasks.
@@ -199,23 +161,46 @@ struct BatchProduct {
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[r][k] = 0.0;
-      // whole rounds of three steps (steps past the part's end are fully masked)
       const int nch = (int)((ce - cs + CW - 1) / CW);
-      const int rounds = (nch + 2) / 3;
-      u32x4 t[3][RB];
-      double vr[3][KPT];
+      double vr[KPT];
+      u32x4 cur[RB], nxt[RB];
+      // a lane past the part's end reads the part's first vector (masked below)
       auto lane_col = [&](int64_t c0) { return c0 + lane * VEC < ce ? c0 + lane * VEC : cs; };
-      tiles_load(t[0], rowp, lane_col(cs));
-      stage_load(a, vr[0], cs, ce);
-      tiles_load(t[1], rowp, lane_col(cs + CW));
-      stage_load(a, vr[1], cs + CW, ce);
+      stage_load(a, vr, cs, ce);
+      tiles_load(cur, rowp, lane_col(cs));
       __syncthreads();                       // the previous task's readers of sv are done
-      stage_store(sv, vr[0]);
+      stage_store(sv, vr);
       __syncthreads();
-      for (int q = 0; q < rounds; ++q) {
-        rd_step<0>(a, sv, t, vr, acc, rowp, 3 * q, cs, ce, lane);
-        rd_step<1>(a, sv, t, vr, acc, rowp, 3 * q + 1, cs, ce, lane);
-        rd_step<2>(a, sv, t, vr, acc, rowp, 3 * q + 2, cs, ce, lane);
+      for (int i = 0; i < nch; ++i) {
+        const int64_t c0 = cs + (int64_t)i * CW;
+        const bool more = i + 1 < nch;
+        if (more) {
+          stage_load(a, vr, c0 + CW, ce);
+          tiles_load(nxt, rowp, lane_col(c0 + CW));
+        }
+        const double *vb = sv + (i & 1) * (K * CW) + lane * VEC;
+        const int64_t col = c0 + lane * VEC;
+        double o[RB][VEC];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const bool in = col + e < ce;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) o[r][e] = elem(cur[r], e, in);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          double v[VEC];
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[e] = vb[k * CW + e];
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc[r][k] += o[r][e] * v[e];
+        }
+        if (more) stage_store(sv + ((i + 1) & 1) * (K * CW), vr);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RB; ++r) cur[r] = nxt[r];
       }
       double flat[RB * K];
 #pragma unroll
@@ -242,6 +227,29 @@ struct BatchProduct {
     for (int64_t task = blockIdx.x; task < ntask; task += gridDim.x) {
       const int cb = (int)(task % g.C), sp = (int)(task / g.C);
       const int64_t rs0 = (int64_t)sp * g.rs, rs1 = min(g.n_s, rs0 + g.rs);
+      const int nrow = (int)(rs1 - rs0);
+      __syncthreads();                       // the previous task's readers of sw are done
+      for (int idx = tid; idx < nrow * K; idx += NT) {
+        const int64_t row = rs0 + idx / K;
+        const int k = idx % K;
+        double t = 0.0;
+        for (int p = 0; p < g.P; ++p) t += ld_coh(&a.wp[((int64_t)p * g.n_s + row) * K + k]);
+        sw[idx] = t;
+      }
+      __syncthreads();
+      if (cb == 0 && tid < 64) {             // this split's sums of the centred row dots
+        double ps[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) ps[k] = 0.0;
+        for (int r = tid; r < nrow; r += 64)
+#pragma unroll
+          for (int k = 0; k < K; ++k) ps[k] += sw[r * K + k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double t = wave_sum(ps[k]);
+          if (tid == 0) st_coh(&a.swp[(int64_t)sp * K + k], t);
+        }
+      }
       const int64_t col = (int64_t)cb * BW + (int64_t)tid * VEC;
       const bool live = col < g.n_p;
       const int64_t colc = live ? col : 0;
@@ -249,66 +257,37 @@ struct BatchProduct {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) in[e] = live && col + e < g.n_p;
       const unsigned char *base = S.op.O + colc * St::BYTES;
-      double y[K][VEC], ps[K];
+      double y[K][VEC];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        ps[k] = 0.0;
+      for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) y[k][e] = 0.0;
-      }
-      // the split's rows in windows of kBatchSplitRows, their centred row dots (summed
-      // over the column parts) staged in LDS
-      for (int64_t w0 = rs0; w0 < rs1; w0 += kBatchSplitRows) {
-        const int64_t w1 = min(rs1, w0 + (int64_t)kBatchSplitRows);
-        const int nrow = (int)(w1 - w0);
-        __syncthreads();                     // the previous window's readers of sw are done
-        for (int idx = tid; idx < nrow * K; idx += NT) {
-          const int64_t row = w0 + idx / K;
-          const int k = idx % K;
-          double t = 0.0;
-          for (int p = 0; p < g.P; ++p) t += ld_coh(&a.wp[((int64_t)p * g.n_s + row) * K + k]);
-          sw[idx] = t;
+      u32x4 cur[kBatchU], nxt[kBatchU];
+#pragma unroll
+      for (int u = 0; u < kBatchU; ++u) cur[u] = load_stream(base + min(rs0 + u, rs1 - 1) * S.op.ldb);
+      for (int64_t r = rs0; r < rs1; r += kBatchU) {
+        const bool more = r + kBatchU < rs1;
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < kBatchU; ++u) nxt[u] = load_stream(base + min(r + kBatchU + u, rs1 - 1) * S.op.ldb);
         }
-        __syncthreads();
-        if (cb == 0 && tid < 64) {           // running sums of the centred row dots
-          for (int r = tid; r < nrow; r += 64)
 #pragma unroll
-            for (int k = 0; k < K; ++k) ps[k] += sw[r * K + k];
-        }
-        u32x4 cur[kBatchU], nxt[kBatchU];
+        for (int u = 0; u < kBatchU; ++u) {
+          if (r + u < rs1) {
+            const double *wr = sw + (r + u - rs0) * K;
+            double w[K];
 #pragma unroll
-        for (int u = 0; u < kBatchU; ++u) cur[u] = load_stream(base + min(w0 + u, w1 - 1) * S.op.ldb);
-        for (int64_t r = w0; r < w1; r += kBatchU) {
-          const bool more = r + kBatchU < w1;
-          if (more) {
+            for (int k = 0; k < K; ++k) w[k] = wr[k];
 #pragma unroll
-            for (int u = 0; u < kBatchU; ++u) nxt[u] = load_stream(base + min(r + kBatchU + u, w1 - 1) * S.op.ldb);
-          }
+            for (int e = 0; e < VEC; ++e) {
+              const double o = elem(cur[u], e, in[e]);
 #pragma unroll
-          for (int u = 0; u < kBatchU; ++u) {
-            if (r + u < w1) {
-              const double *wr = sw + (r + u - w0) * K;
-              double w[K];
-#pragma unroll
-              for (int k = 0; k < K; ++k) w[k] = wr[k];
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) {
-                const double o = elem(cur[u], e, in[e]);
-#pragma unroll
-                for (int k = 0; k < K; ++k) y[k][e] += o * w[k];
-              }
+              for (int k = 0; k < K; ++k) y[k][e] += o * w[k];
             }
           }
-#pragma unroll
-          for (int u = 0; u < kBatchU; ++u) cur[u] = nxt[u];
         }
-      }
-      if (cb == 0 && tid < 64) {             // this split's sums of the centred row dots
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const double t = wave_sum(ps[k]);
-          if (tid == 0) st_coh(&a.swp[(int64_t)sp * K + k], t);
-        }
+        for (int u = 0; u < kBatchU; ++u) cur[u] = nxt[u];
       }
 #pragma unroll
       for (int k = 0; k < K; ++k)

@@ -394,7 +394,9 @@ struct CgKernel {
 //                 residuals float64-accumulated for scaled storage
 //   kCgTwoPlanes  two code planes everywhere, float64 accumulation
 //   kCgRefine     search directions on the first plane, residuals on both (refinement)
-enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgRefine = 2 };
+//   kCgJacobi     one plane, Jacobi-preconditioned: z = r / (diag S + eps), rho = r . z
+//                 (the convergence test stays on ||r|| / ||g||)
+enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgRefine = 2, kCgJacobi = 3 };
 
 template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane>
 __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
@@ -408,6 +410,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   //   MODE_X0       q = A x0 for a warm start
   typedef CgKernel<DT, NV, R, L, P_, NT> K;
   enum { MODE_P, MODE_REFRESH, MODE_CONFIRM, MODE_FINAL, MODE_X0, MODE_DONE };
+  constexpr bool kJac = CGM == kCgJacobi;
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
   const int G = (int)gridDim.x, tid = (int)threadIdx.x;
@@ -418,6 +421,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   int status = 0;       // SR_OK
   double rel_true = -1.0, rho = 0.0, gg = 1.0, dummy = 0.0;
   double rho_ref = 0.0;  // rho at the start or the last refresh (drop-triggered refreshes)
+  double rz = 0.0;       // r . z with z = r / (diag S + eps) (Jacobi; rho = r . r stays the test)
   bool ok = true, restart = false;
   int mode;
 
@@ -430,25 +434,34 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
     if (it >= a.max_iter) { status = 1; return MODE_FINAL; }
     return MODE_P;
   };
-  // p <- r + beta p for the own chunk, then a barrier so every workgroup sees p
+  // preconditioned residual component (z = r without preconditioning)
+  auto zof = [&](int64_t j, double rj) -> double {
+    if constexpr (kJac) return rj / (a.diag[j] + a.eps);
+    else return rj;
+  };
+  // p <- z + beta p for the own chunk, then a barrier so every workgroup sees p
   auto update_p = [&](double beta) -> bool {
-    for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.p[j], a.r[j] + beta * ld_coh(&a.p[j]));
+    for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.p[j], zof(j, a.r[j]) + beta * ld_coh(&a.p[j]));
     return grid_sync(ctx.gs);
   };
 
   if (a.use_x0) {
     mode = MODE_X0;
   } else {
-    double prr = 0.0, pgg = 0.0;
+    double prr = 0.0, pgg = 0.0, prz = 0.0;
     for (int64_t j = j0 + tid; j < j1; j += NT) {
       st_coh(&a.x[j], 0.0);
-      const double gj = a.g[j];
+      const double gj = a.g[j], zj = zof(j, gj);
       a.r[j] = gj;
-      st_coh(&a.p[j], gj);
+      st_coh(&a.p[j], zj);
       prr += gj * gj;
       pgg += gj * gj;
+      if constexpr (kJac) prz += gj * zj;
     }
     ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg);
+    if constexpr (kJac) {
+      if (ok) ok = grid_allreduce2(prz, 0.0, a.sb.red, nred, ctx.gs, rz, dummy);
+    }
     rho_ref = rho;
     if (gg == 0.0) {
       gg = 1.0;
@@ -481,13 +494,14 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       if (!(ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy))) break;
       if (!isfinite(pq)) { status = -4; break; }
       if (!(pq > 0.0)) { status = 2; mode = MODE_FINAL; continue; }
-      const double alpha = rho / pq;
-      double prr = 0.0;
+      const double alpha = (kJac ? rz : rho) / pq;
+      double prr = 0.0, prz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
         st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
         const double rj = a.r[j] - alpha * a.q[j];
         a.r[j] = rj;
         prr += rj * rj;
+        if constexpr (kJac) prz += rj * zof(j, rj);
       }
       it++;
       if (a.refresh_every > 0 && it % a.refresh_every == 0) {
@@ -495,42 +509,51 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
         mode = MODE_REFRESH;
         continue;
       }
-      double rho_new;
-      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
+      double rho_new, rz_new = 0.0;
+      if (!(ok = grid_allreduce2(prr, kJac ? prz : 0.0, a.sb.red, nred, ctx.gs, rho_new, kJac ? rz_new : dummy)))
+        break;
       if (rho_new <= a.refresh_drop2 * rho_ref && sqrt(rho_new / gg) > a.rtol) {
         // the recurrence residual fell by the requested factor: refresh now (x is
         // visible to every workgroup after the reduction's grid barrier)
         mode = MODE_REFRESH;
         continue;
       }
-      const double beta = rho_new / rho;
+      const double beta = kJac ? rz_new / rz : rho_new / rho;
       rho = rho_new;
+      if constexpr (kJac) rz = rz_new;
       if (!(ok = update_p(beta))) break;
       mode = decide();
     } else if (mode == MODE_REFRESH) {
-      double prr = 0.0, rho_new;
+      double prr = 0.0, prz = 0.0, rho_new, rz_new = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
         const double rj = a.g[j] - a.q[j];
         a.r[j] = rj;
         prr += rj * rj;
+        if constexpr (kJac) prz += rj * zof(j, rj);
       }
       refreshes++;
-      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy))) break;
-      const double beta = a.restart_on_refresh ? 0.0 : rho_new / rho;
+      if (!(ok = grid_allreduce2(prr, kJac ? prz : 0.0, a.sb.red, nred, ctx.gs, rho_new, kJac ? rz_new : dummy)))
+        break;
+      const double beta = a.restart_on_refresh ? 0.0 : (kJac ? rz_new / rz : rho_new / rho);
       rho = rho_new;
+      if constexpr (kJac) rz = rz_new;
       rho_ref = rho_new;
       if (!(ok = update_p(beta))) break;
       mode = decide();
     } else if (mode == MODE_X0) {
-      double prr = 0.0, pgg = 0.0;
+      double prr = 0.0, pgg = 0.0, prz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
-        const double gj = a.g[j], rj = gj - a.q[j];
+        const double gj = a.g[j], rj = gj - a.q[j], zj = zof(j, rj);
         a.r[j] = rj;
-        st_coh(&a.p[j], rj);
+        st_coh(&a.p[j], zj);
         prr += rj * rj;
         pgg += gj * gj;
+        if constexpr (kJac) prz += rj * zj;
       }
       if (!(ok = grid_allreduce2(prr, pgg, a.sb.red, nred, ctx.gs, rho, gg))) break;
+      if constexpr (kJac) {
+        if (!(ok = grid_allreduce2(prz, 0.0, a.sb.red, nred, ctx.gs, rz, dummy))) break;
+      }
       rho_ref = rho;
       if (gg == 0.0) {
         for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.x[j], 0.0);
@@ -542,13 +565,14 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
         mode = decide();
       }
     } else {   // MODE_CONFIRM or MODE_FINAL: true residual g - A x
-      double prr = 0.0, tr;
+      double prr = 0.0, prz = 0.0, tr, trz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
         const double t = a.g[j] - a.q[j];
         if (mode == MODE_CONFIRM) a.r[j] = t;
         prr += t * t;
+        if constexpr (kJac) prz += t * zof(j, t);
       }
-      if (!(ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, tr, dummy))) break;
+      if (!(ok = grid_allreduce2(prr, kJac ? prz : 0.0, a.sb.red, nred, ctx.gs, tr, kJac ? trz : dummy))) break;
       rel_true = sqrt(tr / gg);
       if (mode == MODE_FINAL || rel_true <= a.rtol) {
         mode = MODE_DONE;
@@ -559,6 +583,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
         // the recurrence residual drifted from the true one: continue from the true one
         rho = tr;
         rho_ref = tr;
+        if constexpr (kJac) rz = trz;
         refreshes++;
         rel_true = -1.0;
         if (a.restart_on_refresh && !(ok = update_p(0.0))) break;

@@ -46,6 +46,7 @@ struct CgArgs {
   int refine;                 // two planes: search products read the first plane only
   double *hist;         // [max_iter + 1] or nullptr
   double *info;         // [8]
+  const double *diag;   // [n_p] diag S (Jacobi-preconditioned CG), else nullptr
 };
 
 struct GradArgs {
@@ -85,10 +86,10 @@ struct QuantArgs {
 // Batched solves: K right-hand sides per system, systems one after another in one
 // persistent launch.  A product (S + diag(eps)) V takes two passes over O: row dots
 // W = O_c V by row blocks (V staged through LDS chunk by chunk), then O^T W by column
-// blocks and row splits (the split's rows of W pass through LDS in windows).
+// blocks and row splits (the split's rows of W held in LDS).
 constexpr int kBatchK = 8;           // right-hand sides per product of the batched kernels
 constexpr int kBatchRows = 4;        // rows per wave in the row-dot pass
-constexpr int kBatchSplitRows = 1024;   // rows per LDS window of the update pass
+constexpr int kBatchSplitRows = 1024;   // most rows per split of the update pass (LDS)
 constexpr int kBatchNT = 512;        // threads per workgroup of the batched kernels
 
 struct BatchGeom {
@@ -98,7 +99,7 @@ struct BatchGeom {
   int P;                             // column parts of the row-dot pass
   int C;                             // column blocks of the update pass (threads * VEC columns)
   int SP;                            // row splits of the update pass
-  int64_t rs;                        // rows per split
+  int64_t rs;                        // rows per split (<= kBatchSplitRows)
 };
 struct BatchSys {
   Operand op;
@@ -167,6 +168,7 @@ struct KernelEntry {
   const void *sv, *cg, *lm;
   const void *sv2;       // two-code-plane product (scaled storage), or nullptr
   const void *cg2, *cgr; // CG over two code planes / refinement (scaled storage), or nullptr
+  const void *cgj;       // Jacobi-preconditioned CG (float64 / float32 storage), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 

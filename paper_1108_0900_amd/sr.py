@@ -36,7 +36,7 @@ class SrMatrix(ctypes.Structure):
 class SrCgOpts(ctypes.Structure):
     _fields_ = [("rtol", _c_d), ("max_iter", _c_i32), ("refresh_every", _c_i32), ("use_x0", _c_i32),
                 ("restart_on_refresh", _c_i32), ("res_history", _c_p), ("refresh_drop", _c_d),
-                ("refine", _c_i32)]
+                ("refine", _c_i32), ("precond", _c_i32)]
 
 
 class SrCgInfo(ctypes.Structure):
@@ -225,7 +225,7 @@ def sr_sv_product(M: Matrix, v: torch.Tensor, eps: float = 0.0, out: torch.Tenso
 def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max_iter: int = 0,
                 refresh_every: int = 0, x0: torch.Tensor | None = None, history: bool = False,
                 restart_on_refresh: bool = False, refresh_drop: float = 0.0, refine: bool = False,
-                out: torch.Tensor | None = None, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP,
+                precond: bool = False, out: torch.Tensor | None = None, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP,
                                                            SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
     """CG solve of (S + eps I) x = g (sr_cg_solve).  Returns (x, info dict)."""
     g = _vec(g, M.n_p, "g")
@@ -241,6 +241,7 @@ def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max
     opts.restart_on_refresh = 1 if restart_on_refresh else 0
     opts.refresh_drop = float(refresh_drop)
     opts.refine = 1 if refine else 0
+    opts.precond = 1 if precond else 0
     hist = None
     if history:
         mi = max_iter if max_iter > 0 else M.n_p + 100

@@ -114,6 +114,12 @@ def test_invalid_scalars_rejected():
     opts.refine = 2
     assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
     opts.refine = 0
+    opts.precond = 2
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.precond = 1          # Jacobi needs float64 / float32 storage, one plane
+    mq = _mat(dtype=sr.SR_BF16, ld=8, scale=512)
+    assert L.sr_cg_solve(ctypes.byref(mq), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.precond = 0
     # grad: g without E
     assert L.sr_grad(ctypes.byref(m), None, v, None, None, None, None) == sr.SR_ERR_INVALID
     # lm: mismatched D

@@ -85,7 +85,8 @@ def test_adjoint_padded_rows_with_nan_padding():
     assert np.all(np.abs(to_np(dO) - ref["dO"]) <= 1e-12 * mag)
 
 
-def test_srsolve_autograd_matches_oracle_f64():
+@pytest.mark.parametrize("precond", [False, True], ids=["plain", "jacobi"])
+def test_srsolve_autograd_matches_oracle_f64(precond):
     n_s, n_p = 400, 300
     O, E = rand_dense(n_s, n_p, seed=21)
     w = np.random.default_rng(5).standard_normal(n_p)
@@ -93,7 +94,7 @@ def test_srsolve_autograd_matches_oracle_f64():
     Ot = to_dev(O).requires_grad_(True)
     Et = to_dev(E).requires_grad_(True)
     epst = torch.tensor(eps0, dtype=torch.float64, requires_grad=True)
-    x = sr_solve(Ot, Et, epst, 1e-13, 20)
+    x = sr_solve(Ot, Et, epst, 1e-13, 20, precond)
     loss = (x * to_dev(w)).sum()
     loss.backward()
     ref = orc.solve_adjoint_gradients(O, E, eps0, w)

@@ -119,6 +119,46 @@ def test_cg_matches_cholesky(shape, dtype):
     assert info["rel_res_true"] <= 1e-13
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=_dname)
+@pytest.mark.parametrize("shape", [(50, 9), (1500, 1200), (3000, 5000), (6000, 2000)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_cg_jacobi_matches_cholesky(shape, dtype):
+    """Jacobi-preconditioned CG (z = r / (diag S + eps)) reaches the dense solution of the
+    stored system like plain CG; with more samples than parameters it needs fewer
+    products."""
+    n_s, n_p = shape
+    print(f"[cg-jacobi] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=23 + n_p)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-13, refresh_every=20, precond=True)
+    assert info["status"] == 0, info
+    x_ref = orc.solve_dense(Os, orc.energy_gradient(Os, E), 1e-3 * orc.diag_overlap(Os).mean())
+    assert rel_err(to_np(x), x_ref) <= 1e-10, (rel_err(to_np(x), x_ref), info)
+    assert info["rel_res_true"] <= 1e-13
+    if n_s >= 2 * n_p:
+        _, plain = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-13, refresh_every=20)
+        assert info["products"] < plain["products"], (info, plain)
+
+
+def test_cg_jacobi_warm_start_and_history():
+    n_s, n_p = 2500, 800
+    O, E = rand_dense(n_s, n_p, seed=29)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x_ref = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-3 * orc.diag_overlap(O).mean())
+    x1, i1 = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-5, precond=True, history=True)
+    assert i1["status"] == 0
+    h = to_np(i1["history"])[: i1["iters"] + 1]
+    assert h[0] == pytest.approx(1.0) and h[-1] <= 1e-5
+    x2, i2 = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-13, x0=x1, refresh_every=10, precond=True)
+    assert i2["status"] == 0 and rel_err(to_np(x2), x_ref) <= 1e-10, i2
+
+
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
 def test_cg_scaled_storage_matches_dequantized_oracle(dtype):
     n_s, n_p = 2000, 1500
