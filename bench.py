@@ -11,7 +11,14 @@ Prints ONE JSON line on stdout (progress goes to stderr).
               per product) / step time, inputs resident in HBM
   roofline    the CG kernel (the step's dominant kernel): algorithmic bytes per launch /
               its duration measured with HIP events on its stream, against 8 TB/s
-  cpu_baseline  the CPU oracle's matrix-free product on a bounded row sample, same unit
+  cpu_baseline  the CPU oracle's matrix-free product on a bounded row sample, same unit;
+              with the smaller workloads also the oracle's dense solve of the 8192 x 4000
+              matrix on the host cores
+  batched     64 independent float32 systems x 8 shifts in one launch; one system against
+              8 single-column solves; the 8-column product alone
+  adjoint     forward and backward of the differentiable solve on 16384 x 16384 float32,
+              plain and Jacobi-preconditioned; sr_adjoint alone
+  other_configs  dense 8192 x 4000 float64 and CPS 65536 x 24512 float64 / float32 solves
 """
 from __future__ import annotations
 
@@ -147,6 +154,8 @@ def main():
                          "products or CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation-form measurement")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the dense 8192 x 4000 and CPS 65536 x 24512 solves")
     ap.add_argument("--batched-systems", type=int, default=64,
                     help="systems of the batched workload timed in one launch (its first n)")
     ap.add_argument("--copy-gb", type=float, default=0.0,
@@ -164,7 +173,86 @@ def main():
     out["batched"] = None if (args.quick or args.no_batched) else measure_batched(args)
     torch.cuda.empty_cache()
     out["adjoint"] = None if (args.quick or args.no_adjoint) else measure_adjoint(args)
+    torch.cuda.empty_cache()
+    out["other_configs"] = None
+    if not (args.quick or args.no_small):
+        out["other_configs"], dense_case = measure_other_configs(args)
+        if out["cpu_baseline"] is not None:
+            out["cpu_baseline"]["dense_solve"] = cpu_baseline_dense(*dense_case)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_dense(O, E, x_gpu):
+    """The oracle's dense solve (explicit S, Cholesky, float64 on the host cores) of the
+    dense 8192 x 4000 workload, and the GPU solution's error against it."""
+    import numpy as np
+    import oracle as orc
+    t0 = time.perf_counter()
+    x_ref = orc.solve_dense(O, orc.energy_gradient(O, E), 1e-3 * orc.diag_overlap(O).mean())
+    t = time.perf_counter() - t0
+    return {"workload": "dense float64 O 8192 x 4000, eps = 1e-3 mean(diag S)", "kind": "oracle",
+            "method": "form S, Cholesky (numpy/OpenBLAS)", "seconds": round(t, 3),
+            "gpu_cg_err_vs_oracle": float(np.linalg.norm(x_gpu - x_ref) / np.linalg.norm(x_ref))}
+
+
+def measure_other_configs(args):
+    """Solves of the two smaller workloads: dense 8192 x 4000 float64 (CG to 1e-10, plain
+    and Jacobi-preconditioned; on rank 0 also the oracle's dense solve on the host cores,
+    as the CPU reference and for the error) and CPS 65536 x 24512 in float64 and float32
+    (CG to 1e-8, error of float32 against float64).  Returns the record and the dense
+    case's host arrays (O, E, x) for the CPU baseline."""
+    import torch
+    from paper_1108_0900_amd import sr, tune
+    dev = "cuda:0"
+    res = {}
+    cfg, d = make_workload("c1", dev)
+    O, E = d["O"], d["E"]
+    n_s, n_p = O.shape
+    M = sr.as_matrix(O)
+    tune.autotune(M, kind=0, reps=3)
+
+    def solve(M, tol, precond=False):
+        st = sr.sr_grad(M, E)
+        M.mean = st["mean"]
+        eps = 1e-3 * float(st["diag"].mean())
+        sr.sr_cg_solve(M, st["g"], eps, rtol=tol, refresh_every=20, precond=precond)      # warm
+        (x, info), ms = timed_events(lambda: sr.sr_cg_solve(M, st["g"], eps, rtol=tol, refresh_every=20,
+                                                            precond=precond))
+        if info["status"] != 0:
+            raise RuntimeError(f"CG did not converge: {info}")
+        return x, info, ms, eps
+    x, info, ms, eps = solve(M, cfg.rtol)
+    xj, infoj, msj, _ = solve(M, cfg.rtol, True)
+    pb = product_bytes(n_s, n_p, torch.float64, False)
+    c1 = {"workload": "dense float64 O 8192 x 4000 N(0,1) x lognormal(0, 0.5), eps = 1e-3 mean(diag S), CG to 1e-10",
+          "cg_ms": round(ms, 2), "iters": info["iters"], "products": info["products"],
+          "GBps": round(info["products"] * pb / ms / 1e6, 1),
+          "jacobi": {"cg_ms": round(msj, 2), "iters": infoj["iters"], "products": infoj["products"],
+                     "x_rel_diff_vs_plain": float(torch.linalg.vector_norm(xj - x) / torch.linalg.vector_norm(x))}}
+    res["dense_8192x4000_f64"] = c1
+    dense_case = (O.cpu().numpy(), E.cpu().numpy(), x.cpu().numpy())
+    del d, O, M, x, xj
+    torch.cuda.empty_cache()
+
+    cfg, d = make_workload("c2", dev)
+    O64, E = d["O"], d["E"]
+    n_s, n_p = O64.shape
+    out2 = {"workload": "CPS-shaped O 65536 x 24512 (64 correlators x 256 states + 8128 dense pairing columns), "
+                        "eps = 1e-3 mean(diag S), CG to 1e-8"}
+    xs = {}
+    for name, Ot, dt in (("f64", O64, torch.float64), ("f32", O64.float(), torch.float32)):
+        M = sr.as_matrix(Ot)
+        tune.autotune(M, kind=0, reps=3)
+        x, info, ms, _ = solve(M, cfg.rtol)
+        xs[name] = x
+        out2[name] = {"cg_ms": round(ms, 2), "iters": info["iters"], "products": info["products"],
+                      "GBps": round(info["products"] * product_bytes(n_s, n_p, dt, False) / ms / 1e6, 1)}
+        del M, Ot
+    out2["f32_err_vs_f64"] = float(torch.linalg.vector_norm(xs["f32"] - xs["f64"]) /
+                                   torch.linalg.vector_norm(xs["f64"]))
+    res["cps_65536x24512"] = out2
+    log(f"[bench] other configs: {res}")
+    return res, dense_case
 
 
 def measure_adjoint(args):
