@@ -139,7 +139,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--config", default="cps_32768x500000",
+                    choices=["dense_8192x4000", "cps_65536x24512", "cps_32768x500000", "dense_16384"])
     ap.add_argument("--rtol", type=float, default=None, help="CG tolerance of the timed bf16 solve")
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison solve")
     ap.add_argument("--one-plane", action="store_true",
@@ -163,8 +164,8 @@ def main():
                          "known traffic, to calibrate hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is a design "
-              f"in DESIGN.md and is not built in this repository.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding over several GPUs is "
+              f"designed but not built in this repository.", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
@@ -205,7 +206,7 @@ def measure_other_configs(args):
     from paper_1108_0900_amd import sr, tune
     dev = "cuda:0"
     res = {}
-    cfg, d = make_workload("c1", dev)
+    cfg, d = make_workload("dense_8192x4000", dev)
     O, E = d["O"], d["E"]
     n_s, n_p = O.shape
     M = sr.as_matrix(O)
@@ -234,7 +235,7 @@ def measure_other_configs(args):
     del d, O, M, x, xj
     torch.cuda.empty_cache()
 
-    cfg, d = make_workload("c2", dev)
+    cfg, d = make_workload("cps_65536x24512", dev)
     O64, E = d["O"], d["E"]
     n_s, n_p = O64.shape
     out2 = {"workload": "CPS-shaped O 65536 x 24512 (64 correlators x 256 states + 8128 dense pairing columns), "
@@ -264,7 +265,7 @@ def measure_adjoint(args):
     from paper_1108_0900_amd import sr
     from paper_1108_0900_amd.autograd import sr_solve
     dev = "cuda:0"
-    cfg = synth.CONFIGS["c5"]
+    cfg = synth.CONFIGS["dense_16384"]
     d = synth.dense_inputs(cfg.n_s, cfg.n_p, cfg.seed, device=dev, dtype=torch.float32)
     O, E = d["O"], d["E"]
     gen = torch.Generator(device=dev)
@@ -313,7 +314,7 @@ def measure_batched(args):
     import synth
     from paper_1108_0900_amd import sr
     dev = "cuda:0"
-    cfg = synth.CONFIGS["c4"]
+    cfg = synth.CONFIGS["batched_64sys"]
     shapes = synth.batched_shapes(seed=cfg.seed)[: args.batched_systems]
     shifts = synth.relative_shifts(8)
     systems = []
@@ -382,7 +383,7 @@ def measure_single(args):
     refresh = cfg.refresh_every or 20
 
     # ---- storage forms ----
-    scaled = args.config == "c3"
+    scaled = args.config == "cps_32768x500000"
     planes, search_planes = 1, 1
     if scaled:
         q, s, lo = sr.sr_quantize(O64, out_dtype=torch.bfloat16, with_lo=True)
@@ -553,12 +554,12 @@ def measure_single(args):
         "dtype": dtype_name,
         "data": "synthetic",
         "config": {
-            "workload": {"c3": "CPS-shaped O, 32768 samples x 500000 parameters (2048 correlators x 240 states + "
+            "workload": {"cps_32768x500000": "CPS-shaped O, 32768 samples x 500000 parameters (2048 correlators x 240 states + "
                                "8480 dense pairing columns), bf16 codes + float32 column scales; prepare pass + "
                                "CG to rel. residual %g, float64 residual refresh every %d" % (rtol, refresh),
-                         "c1": "dense O 8192 x 4000 float64; prepare pass + CG to %g" % rtol,
-                         "c2": "CPS-shaped O 65536 x 24512 float64; prepare pass + CG to %g" % rtol,
-                         "c5": "dense O 16384 x 16384 float32; prepare pass + CG to %g" % rtol}[args.config],
+                         "dense_8192x4000": "dense O 8192 x 4000 float64; prepare pass + CG to %g" % rtol,
+                         "cps_65536x24512": "CPS-shaped O 65536 x 24512 float64; prepare pass + CG to %g" % rtol,
+                         "dense_16384": "dense O 16384 x 16384 float32; prepare pass + CG to %g" % rtol}[args.config],
             "n_s": n_s, "n_p": n_p, "seed": cfg.seed, "parallelism": "single GPU",
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

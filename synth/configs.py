@@ -37,18 +37,18 @@ class Config:
 
 CONFIGS = {
     # dense O 8192 x 4000 float64 (4,048-parameter scale of the hydrogen lattice, Sec. III.C)
-    "c1": Config("c1", "dense", 8192, 4000, 1, ("f64",), 1e-10, eps_rel=1e-3),
+    "dense_8192x4000": Config("dense_8192x4000", "dense", 8192, 4000, 1, ("f64",), 1e-10, eps_rel=1e-3),
     # CPS-shaped: 64 plaquettes x 256 states + 8128 pairing columns (8x8 lattice, Sec. III.B)
-    "c2": Config("c2", "cps", 65536, 64 * 256 + 8128, 2, ("f64", "f32"), 1e-8, eps_rel=1e-3,
+    "cps_65536x24512": Config("cps_65536x24512", "cps", 65536, 64 * 256 + 8128, 2, ("f64", "f32"), 1e-8, eps_rel=1e-3,
                  n_corr=64, n_states=256, n_dense=8128),
     # CPS-shaped, 500,000 parameters (524,784-parameter scale of Sec. III.A), bf16 vs f64
-    "c3": Config("c3", "cps", 32768, 2048 * 240 + 8480, 3, ("bf16", "f64"), 1e-10, eps_rel=1e-3,
+    "cps_32768x500000": Config("cps_32768x500000", "cps", 32768, 2048 * 240 + 8480, 3, ("bf16", "f64"), 1e-10, eps_rel=1e-3,
                  n_corr=2048, n_states=240, n_dense=8480, refresh_every=20),
     # 64 independent systems, 8 relative shifts each
-    "c4": Config("c4", "batched", 0, 0, 4, ("f32",), 1e-8, extra={"n_sys": 64, "n_shift": 8,
+    "batched_64sys": Config("batched_64sys", "batched", 0, 0, 4, ("f32",), 1e-8, extra={"n_sys": 64, "n_shift": 8,
                  "n_p_range": (1000, 60000), "n_s_range": (4096, 32768)}),
     # differentiation case, f32 O, absolute eps
-    "c5": Config("c5", "dense", 16384, 16384, 5, ("f32",), 1e-10, eps_abs=1e-3),
+    "dense_16384": Config("dense_16384", "dense", 16384, 16384, 5, ("f32",), 1e-10, eps_abs=1e-3),
 }
 
 

@@ -162,7 +162,7 @@ def test_adjoint_full_size_differentiation_case():
     Checked where the oracle can compute one by one: lambda's residual through the
     matrix-free product, and sampled rows of dL/dO and dL/dE recomputed in float64 from
     the same O, x and lambda; dL/deps = -lambda . x."""
-    cfg = synth.CONFIGS["c5"]
+    cfg = synth.CONFIGS["dense_16384"]
     d = synth.dense_inputs(cfg.n_s, cfg.n_p, cfg.seed, device=DEV, dtype=torch.float32)
     O, E = d["O"], d["E"]
     n_s, n_p = O.shape

@@ -146,7 +146,7 @@ def test_batched_full_size_workload():
     1e-4..1e-1 of mean(diag S) each, g the SR gradient, one launch.  Every column must
     end converged; its residual is re-checked with the one-column float64 product (a
     different kernel), and on the smallest systems with the CPU oracle."""
-    cfg = synth.CONFIGS["c4"]
+    cfg = synth.CONFIGS["batched_64sys"]
     shapes = synth.batched_shapes(seed=cfg.seed)
     shifts = synth.relative_shifts(8)
     systems, grads = [], []
