@@ -18,7 +18,8 @@ Prints ONE JSON line on stdout (progress goes to stderr).
               8 single-column solves; the 8-column product alone
   adjoint     forward and backward of the differentiable solve on 16384 x 16384 float32,
               plain and Jacobi-preconditioned; sr_adjoint alone
-  other_configs  dense 8192 x 4000 float64 and CPS 65536 x 24512 float64 / float32 solves
+  other_configs  dense 8192 x 4000 float64 and CPS 65536 x 24512 float64 / float32 solves;
+              the linear method's Davidson eigensolve on the dense samples
 """
 from __future__ import annotations
 
@@ -198,11 +199,12 @@ def cpu_baseline_dense(O, E, x_gpu):
 
 def measure_other_configs(args):
     """Solves of the two smaller workloads: dense 8192 x 4000 float64 (CG to 1e-10, plain
-    and Jacobi-preconditioned; on rank 0 also the oracle's dense solve on the host cores,
-    as the CPU reference and for the error) and CPS 65536 x 24512 in float64 and float32
-    (CG to 1e-8, error of float32 against float64).  Returns the record and the dense
+    and Jacobi-preconditioned; the linear method's Davidson eigensolve and H product on
+    the same samples) and CPS 65536 x 24512 in float64 and float32 (CG to 1e-8, error of
+    float32 against float64).  Returns the record and the dense
     case's host arrays (O, E, x) for the CPU baseline."""
     import torch
+    import synth
     from paper_1108_0900_amd import sr, tune
     dev = "cuda:0"
     res = {}
@@ -232,6 +234,25 @@ def measure_other_configs(args):
                      "x_rel_diff_vs_plain": float(torch.linalg.vector_norm(xj - x) / torch.linalg.vector_norm(x))}}
     res["dense_8192x4000_f64"] = c1
     dense_case = (O.cpu().numpy(), E.cpu().numpy(), x.cpu().numpy())
+    # the linear method on the same samples: D = 0.1 N(0,1) s_j, lowest eigenpair of
+    # H c = theta S c by generalized Davidson (one H and one S product per iteration), and
+    # the H product alone
+    Dt = synth.lm_derivatives(n_s, d["col_scale"], device=dev)
+    Md = sr.as_matrix(Dt)
+    M.mean = sr.sr_grad(M, None)["mean"]
+    sr.lm_davidson(M, E, Md, tol=1e-8, max_sub=40)                          # warm
+    (th, cvec, dinfo), ms_d = timed_events(lambda: sr.lm_davidson(M, E, Md, tol=1e-8, max_sub=40))
+    v = torch.randn(n_p + 1, dtype=torch.float64, device=dev)
+    sr.lm_hv_product(M, E, Md, v)
+    ts = sorted(timed_events(lambda: sr.lm_hv_product(M, E, Md, v))[1] for _ in range(7))
+    res["lm_davidson_8192x4000_f64"] = {
+        "workload": "dense float64 O and D = 0.1 N(0,1) s_j, 8192 x 4000; lowest eigenpair to "
+                    "||H c - theta S c|| <= 1e-8 |theta|, subspace 40",
+        "ms": round(ms_d, 2), "iters": dinfo["iters"], "restarts": dinfo["restarts"], "theta": th,
+        "res_norm": dinfo["res_norm"], "status": dinfo["status"],
+        "lm_hv_product_ms": round(ts[3], 4),
+        "lm_hv_product_GBps": round(2 * n_s * n_p * 8 / ts[3] / 1e6, 1)}
+    del Dt, Md
     del d, O, M, x, xj
     torch.cuda.empty_cache()
 

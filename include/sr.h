@@ -225,6 +225,41 @@ int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const doubl
                void *dO, int32_t dO_dtype, int64_t ld_dO, double *p12, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * lm_davidson: lowest eigenpair of the linear method's generalized eigenproblem
+ * H c = theta S c (Sec. II.B, Eq. linear_eigen; the paper solves it with a generalized
+ * Davidson method on H.x and S.x products), with H the sampled matrix of lm_hv_product and
+ * S = 1 (+) S_c (the overlap in the basis {Psi, Psi^i - <O_i> Psi}).  Each iteration takes
+ * one H product (lm_hv_product, one read of O and D) and one S product (sr_sv_product,
+ * one read of O); the subspace basis is S-orthonormal (classical Gram-Schmidt, twice),
+ * the projected matrix is solved on the host (Hessenberg QR), the new direction is the
+ * Ritz residual H c - theta S c, and the subspace restarts from the Ritz vector when it
+ * reaches opt->max_sub vectors.  The start vector is Psi itself, c = (1, 0, ..., 0).
+ * O, D, E: as lm_hv_product (same n_s, n_p, dtype; single code plane).  c: device
+ * [n_p + 1] float64, receives the Ritz vector (S-normalized, c^T S c = 1).  info: host,
+ * required.  opt: NULL for the defaults (tol 1e-8, max_iter 1000, max_sub 40); converged
+ * when ||H c - theta S c|| <= tol |theta|.  Needs S positive definite on the explored
+ * subspace (a direction of S-norm <= 1e-28 relative ends the iteration).  Synchronizes
+ * `stream`.  Returns SR_OK when converged, SR_NOT_CONVERGED otherwise (c then holds the
+ * last Ritz vector), SR_BREAKDOWN if the projected eigenproblem's QR iteration did not
+ * converge, or an error code.
+ * ------------------------------------------------------------------------------------ */
+typedef struct lm_davidson_opts {
+  double tol;                /* > 0 */
+  int32_t max_iter;          /* H products, >= 1 */
+  int32_t max_sub;           /* subspace size before a restart, in [2, 64] */
+} lm_davidson_opts;
+typedef struct lm_davidson_info {
+  int32_t iters;             /* iterations (each one H and one S product) */
+  int32_t restarts;
+  int32_t status;
+  int32_t reserved;
+  double theta;              /* Ritz value */
+  double res_norm;           /* ||H c - theta S c|| */
+} lm_davidson_info;
+int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const lm_davidson_opts *opt,
+                double *c, lm_davidson_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * sr_quantize: storage conversion of a float64 or float32 matrix to SR_BF16 or SR_F16
  * codes with per-column float32 scales (not in the paper; the precision form):
  *   s_j = float32(max_k |O_kj|)  (1 for an all-zero column)

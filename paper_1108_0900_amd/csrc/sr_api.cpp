@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -366,6 +367,223 @@ int get_mean_scratch(int dev, hipStream_t s, int64_t n, double **out) {
   return SR_OK;
 }
 
+// Buffers of the Davidson solver (its products carve g_ws for themselves).
+std::map<std::pair<int, hipStream_t>, Workspace> g_lm_ws;
+
+// ------------------------------------------------------------------------------------
+// Small dense eigenproblem of the Davidson subspace (host)
+// ------------------------------------------------------------------------------------
+typedef std::complex<double> cplx;
+
+// Eigenvalues of the real m x m matrix A (row-major): Householder reduction to upper
+// Hessenberg form, then single-shift QR in complex arithmetic with Wilkinson shifts
+// (Givens rotations on the active block, deflation at negligible subdiagonals).
+bool hessenberg_qr_eigenvalues(const std::vector<double> &A, int m, std::vector<cplx> &ev) {
+  std::vector<cplx> H(A.begin(), A.end());
+  auto h = [&](int i, int j) -> cplx & { return H[(size_t)i * m + j]; };
+  for (int k = 0; k + 2 < m; ++k) {
+    double alpha = 0.0;
+    for (int i = k + 1; i < m; ++i) alpha += std::norm(h(i, k));
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    std::vector<cplx> v(m, 0.0);
+    const cplx x0 = h(k + 1, k);
+    const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
+    for (int i = k + 1; i < m; ++i) v[i] = h(i, k);
+    v[k + 1] += ph * alpha;
+    double vn = 0.0;
+    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    // H <- P H P with P = I - 2 v v^H / (v^H v)
+    for (int j = 0; j < m; ++j) {
+      cplx d = 0.0;
+      for (int i = k + 1; i < m; ++i) d += std::conj(v[i]) * h(i, j);
+      d *= 2.0 / vn;
+      for (int i = k + 1; i < m; ++i) h(i, j) -= v[i] * d;
+    }
+    for (int i = 0; i < m; ++i) {
+      cplx d = 0.0;
+      for (int j = k + 1; j < m; ++j) d += h(i, j) * v[j];
+      d *= 2.0 / vn;
+      for (int j = k + 1; j < m; ++j) h(i, j) -= d * std::conj(v[j]);
+    }
+  }
+  const double ulp = 2.220446049250313e-16;
+  int hi = m - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    if (std::abs(h(hi, hi - 1)) <= ulp * (std::abs(h(hi, hi)) + std::abs(h(hi - 1, hi - 1)))) {
+      h(hi, hi - 1) = 0.0;
+      --hi;
+      iter = 0;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::abs(h(lo, lo - 1)) > ulp * (std::abs(h(lo, lo)) + std::abs(h(lo - 1, lo - 1)))) --lo;
+    const cplx a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+    const cplx tr = a + d, det = a * d - b * c, disc = std::sqrt(tr * tr / 4.0 - det);
+    const cplx m1 = tr / 2.0 + disc, m2 = tr / 2.0 - disc;
+    cplx mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    if (iter > 0 && iter % 10 == 0) mu += std::abs(h(hi, hi - 1));     // exceptional shift
+    for (int k = lo; k <= hi; ++k) h(k, k) -= mu;
+    std::vector<double> cs(m);
+    std::vector<cplx> sn(m);
+    for (int k = lo; k < hi; ++k) {           // H - mu I = Q R
+      const cplx x = h(k, k), y = h(k + 1, k);
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      double cc;
+      cplx ss;
+      if (r == 0.0) {
+        cc = 1.0;
+        ss = 0.0;
+      } else if (std::abs(x) == 0.0) {
+        cc = 0.0;
+        ss = std::conj(y) / std::abs(y);
+      } else {
+        cc = std::abs(x) / r;
+        ss = (x / std::abs(x)) * std::conj(y) / r;
+      }
+      cs[k] = cc;
+      sn[k] = ss;
+      for (int j = k; j <= hi; ++j) {
+        const cplx p = h(k, j), q = h(k + 1, j);
+        h(k, j) = cc * p + ss * q;
+        h(k + 1, j) = -std::conj(ss) * p + cc * q;
+      }
+    }
+    for (int k = lo; k < hi; ++k) {           // R Q
+      const double cc = cs[k];
+      const cplx ss = sn[k];
+      for (int i = lo; i <= std::min(k + 1, hi); ++i) {
+        const cplx p = h(i, k), q = h(i, k + 1);
+        h(i, k) = p * cc + q * std::conj(ss);
+        h(i, k + 1) = -p * ss + q * cc;
+      }
+    }
+    for (int k = lo; k <= hi; ++k) h(k, k) += mu;
+    ++iter;
+    if (++total > 200 * m) return false;
+  }
+  ev.resize(m);
+  for (int i = 0; i < m; ++i) ev[i] = h(i, i);
+  return true;
+}
+
+// Eigenvector of A for the eigenvalue theta by inverse iteration (complex LU with partial
+// pivoting of A - theta I, nudged off exact singularity); real part, unit norm, sign fixed
+// by the largest component.
+void inverse_iteration(const std::vector<double> &A, int m, cplx theta, std::vector<double> &y) {
+  double scale = 0.0;
+  for (double v : A) scale = std::max(scale, std::abs(v));
+  const cplx shift = theta + cplx(1e-13 * std::max(scale, 1e-300), 0.0);
+  std::vector<cplx> L((size_t)m * m);
+  std::vector<int> piv(m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) L[(size_t)i * m + j] = A[(size_t)i * m + j] - (i == j ? shift : cplx(0.0));
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::abs(L[(size_t)i * m + k]) > std::abs(L[(size_t)p * m + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < m; ++j) std::swap(L[(size_t)k * m + j], L[(size_t)p * m + j]);
+    if (std::abs(L[(size_t)k * m + k]) == 0.0) L[(size_t)k * m + k] = 1e-300;
+    for (int i = k + 1; i < m; ++i) {
+      const cplx f = L[(size_t)i * m + k] / L[(size_t)k * m + k];
+      L[(size_t)i * m + k] = f;
+      for (int j = k + 1; j < m; ++j) L[(size_t)i * m + j] -= f * L[(size_t)k * m + j];
+    }
+  }
+  std::vector<cplx> z(m, cplx(1.0 / std::sqrt((double)m)));
+  for (int sweep = 0; sweep < 3; ++sweep) {
+    for (int k = 0; k < m; ++k) std::swap(z[k], z[piv[k]]);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < i; ++j) z[i] -= L[(size_t)i * m + j] * z[j];
+    for (int i = m - 1; i >= 0; --i) {
+      for (int j = i + 1; j < m; ++j) z[i] -= L[(size_t)i * m + j] * z[j];
+      z[i] /= L[(size_t)i * m + i];
+    }
+    double nz = 0.0;
+    for (const cplx &v : z) nz += std::norm(v);
+    nz = std::sqrt(nz);
+    for (cplx &v : z) v /= nz;
+  }
+  int big = 0;
+  for (int i = 1; i < m; ++i)
+    if (std::abs(z[i]) > std::abs(z[big])) big = i;
+  const cplx ph = std::conj(z[big]) / std::abs(z[big]);
+  y.assign(m, 0.0);
+  double ny = 0.0;
+  for (int i = 0; i < m; ++i) {
+    y[i] = std::real(z[i] * ph);
+    ny += y[i] * y[i];
+  }
+  ny = std::sqrt(ny);
+  for (double &v : y) v /= ny;
+}
+
+// The lowest eigenvalue of A (least real part; real ones preferred) and its vector.
+bool lowest_eigenpair(const std::vector<double> &A, int m, double *theta, std::vector<double> &y) {
+  std::vector<cplx> ev;
+  if (!hessenberg_qr_eigenvalues(A, m, ev)) return false;
+  double scale = 0.0;
+  for (const cplx &e : ev) scale = std::max(scale, std::abs(e));
+  int best = -1;
+  for (int pass = 0; pass < 2 && best < 0; ++pass)
+    for (int i = 0; i < m; ++i) {
+      if (pass == 0 && std::abs(std::imag(ev[i])) > 1e-10 * std::max(scale, 1e-300)) continue;
+      if (best < 0 || std::real(ev[i]) < std::real(ev[best])) best = i;
+    }
+  inverse_iteration(A, m, ev[best], y);
+  *theta = std::real(ev[best]);
+  return true;
+}
+
+// ------------------------------------------------------------------------------------
+// Device vector operations of the Davidson solver
+// ------------------------------------------------------------------------------------
+struct LmBufs {
+  double *part, *dots;             // [nb][kLmMaxSub], [kLmMaxSub]
+  int nb;
+};
+// out_host[i] = X[i] . w for i < m (device reduction in fixed order, then a copy).
+int lm_mdot(const LmBufs &b, const double *X, int64_t ld, int m, const double *w, int64_t n, double *out_host,
+            hipStream_t s) {
+  MdotArgs a{};
+  a.X = X;
+  a.ld = ld;
+  a.n = n;
+  a.m = m;
+  a.nb = b.nb;
+  a.w = w;
+  a.part = b.part;
+  a.out = b.dots;
+  void *args[] = {&a};
+  HIP_TRY(hipLaunchKernel(mdot_part_kernel(), dim3(b.nb), dim3(lm_threads()), args, 0, s));
+  HIP_TRY(hipLaunchKernel(mdot_final_kernel(), dim3(1), dim3(64), args, 0, s));
+  HIP_TRY(hipMemcpyAsync(out_host, b.dots, (size_t)m * 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SR_OK;
+}
+// out = beta out + sum_i ca[i] X[i] + sum_i cz[i] Z[i].
+int lm_lincomb(const double *X, const double *ca, int mx, const double *Z, const double *cz, int mz, int64_t ld,
+               double beta, double *out, int64_t n, hipStream_t s) {
+  LincombArgs a{};
+  a.X = X;
+  a.Z = Z;
+  a.mx = mx;
+  a.mz = mz;
+  a.ld = ld;
+  a.n = n;
+  a.beta = beta;
+  a.out = out;
+  for (int i = 0; i < mx; ++i) a.ca[i] = ca[i];
+  for (int i = 0; i < mz; ++i) a.cz[i] = cz[i];
+  void *args[] = {&a};
+  const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, lm_threads())));
+  HIP_TRY(hipLaunchKernel(lincomb_kernel(), dim3(blocks), dim3(lm_threads()), args, 0, s));
+  return SR_OK;
+}
+
 }  // namespace
 
 // ======================================================================================
@@ -395,7 +613,7 @@ const char *sr_status_string(int status) {
 int sr_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = SR_OK;
-  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws}) {
+  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws, &g_lm_ws}) {
     for (auto &kv : *mp) {
       if (kv.second.ptr) {
         int cur = 0;
@@ -785,6 +1003,174 @@ int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, co
       if (status == SR_OK && st != SR_OK) status = st;
     }
   if (status < 0) return fail(status, "sr_cg_solve_batched: a column reported %s", sr_status_string(status));
+  return status;
+}
+
+int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const lm_davidson_opts *opt, double *c,
+                lm_davidson_info *info, hipStream_t stream) {
+  int rc = check_matrix(O, "lm_davidson(O)");
+  if (rc) return rc;
+  rc = check_matrix(D, "lm_davidson(D)");
+  if (rc) return rc;
+  if (D->n_s != O->n_s || D->n_p != O->n_p || D->dtype != O->dtype)
+    return fail(SR_ERR_INVALID, "lm_davidson: O and D must have the same n_s, n_p and dtype");
+  if (O->O_lo != nullptr || D->O_lo != nullptr)
+    return fail(SR_ERR_INVALID, "lm_davidson: a second code plane is not supported");
+  if (E == nullptr || c == nullptr || info == nullptr) return fail(SR_ERR_INVALID, "lm_davidson: null E, c or info");
+  lm_davidson_opts o{1e-8, 1000, 40};
+  if (opt) o = *opt;
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(SR_ERR_INVALID, "lm_davidson: tol must be finite and > 0");
+  if (o.max_iter < 1) return fail(SR_ERR_INVALID, "lm_davidson: max_iter must be >= 1");
+  if (o.max_sub < 2 || o.max_sub > kLmMaxSub)
+    return fail(SR_ERR_INVALID, "lm_davidson: max_sub must be in [2, %d]", kLmMaxSub);
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const int64_t n_p = O->n_p, n = n_p + 1, ld = round_up(n, 32);
+  const int ms = o.max_sub;
+  const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n, 4096)));
+  // V, HV, SV [ms][ld]; r, c-temporaries [3][ld]; column means [ld]; reduction buffers
+  const size_t bytes = ((size_t)3 * ms + 4) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 4096;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, bytes, &base, g_lm_ws);
+  if (rc) return rc;
+  Carve cv(base);
+  double *V = cv.take<double>((int64_t)ms * ld), *HV = cv.take<double>((int64_t)ms * ld);
+  double *SV = cv.take<double>((int64_t)ms * ld);
+  double *R = cv.take<double>(ld), *T1 = cv.take<double>(ld), *T2 = cv.take<double>(ld);
+  double *mean = cv.take<double>(ld);
+  LmBufs lb{cv.take<double>((int64_t)nb * kLmMaxSub), cv.take<double>(kLmMaxSub), nb};
+  // the column means once, so that the products do not recompute them
+  sr_matrix Om = *O, Dm = *D;
+  if (!O->col_mean) {
+    rc = run_grad(O, nullptr, nullptr, nullptr, mean, nullptr, dev, di, stream);
+    if (rc) return rc;
+    Om.col_mean = mean;
+  }
+  auto row = [&](double *B, int i) { return B + (int64_t)i * ld; };
+  // S t = (t_0, (S_c) t_1..n_p)
+  auto s_product = [&](const double *t, double *st) -> int {
+    HIP_TRY(hipMemcpyAsync(st, t, 8, hipMemcpyDeviceToDevice, stream));
+    return sr_sv_product(&Om, t + 1, st + 1, 0.0, stream);
+  };
+  std::vector<double> A((size_t)ms * ms, 0.0), h(ms), y, tmp(ms);
+  int m = 0, iters = 0, restarts = 0, status = SR_NOT_CONVERGED;
+  double theta = 0.0, rnorm = INFINITY, ref_norm = 1.0;
+  // start vector: Psi, c = e_0 (S-norm 1)
+  rc = fill_zero(row(V, 0), ld * 2, stream);
+  if (rc) return rc;
+  {
+    const double one = 1.0;
+    HIP_TRY(hipMemcpyAsync(row(V, 0), &one, 8, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  bool fresh = true;                       // row(V, m) holds a new, not yet orthogonalized direction
+  while (iters < o.max_iter) {
+    double *t = row(V, m), *st = row(SV, m), *ht = row(HV, m);
+    if (fresh) {
+      rc = s_product(t, st);
+      if (rc) return rc;
+      iters++;
+      // S-orthogonalize against the basis (classical Gram-Schmidt, twice); S t follows
+      // by linearity
+      for (int pass = 0; pass < 2 && m > 0; ++pass) {
+        rc = lm_mdot(lb, SV, ld, m, t, n, h.data(), stream);
+        if (rc) return rc;
+        for (int i = 0; i < m; ++i) tmp[i] = -h[i];
+        rc = lm_lincomb(V, tmp.data(), m, nullptr, nullptr, 0, ld, 1.0, t, n, stream);
+        if (rc) return rc;
+        rc = lm_lincomb(SV, tmp.data(), m, nullptr, nullptr, 0, ld, 1.0, st, n, stream);
+        if (rc) return rc;
+      }
+      double nrm2 = 0.0;
+      rc = lm_mdot(lb, t, ld, 1, st, n, &nrm2, stream);
+      if (rc) return rc;
+      if (m == 0) ref_norm = nrm2;
+      if (!(nrm2 > 1e-28 * ref_norm)) break;  // no new direction (converged or S singular there)
+      const double inv = 1.0 / std::sqrt(nrm2);
+      rc = lm_lincomb(nullptr, nullptr, 0, nullptr, nullptr, 0, ld, inv, t, n, stream);
+      if (rc) return rc;
+      rc = lm_lincomb(nullptr, nullptr, 0, nullptr, nullptr, 0, ld, inv, st, n, stream);
+      if (rc) return rc;
+      rc = lm_hv_product(&Om, E, &Dm, t, ht, stream);
+      if (rc) return rc;
+      // the new row and column of the projected matrix A = V^T H V
+      std::vector<double> col(m + 1), rw(m + 1);
+      rc = lm_mdot(lb, V, ld, m + 1, ht, n, col.data(), stream);
+      if (rc) return rc;
+      rc = lm_mdot(lb, HV, ld, m + 1, t, n, rw.data(), stream);
+      if (rc) return rc;
+      for (int i = 0; i <= m; ++i) {
+        A[(size_t)i * ms + m] = col[i];
+        A[(size_t)m * ms + i] = rw[i];
+      }
+      m++;
+    }
+    std::vector<double> Am((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Am[(size_t)i * m + j] = A[(size_t)i * ms + j];
+    if (!lowest_eigenpair(Am, m, &theta, y)) {
+      status = SR_BREAKDOWN;                 // the projected eigenproblem's QR did not converge
+      break;
+    }
+    // Ritz residual r = H c - theta S c
+    for (int i = 0; i < m; ++i) tmp[i] = -theta * y[i];
+    rc = lm_lincomb(HV, y.data(), m, SV, tmp.data(), m, ld, 0.0, R, n, stream);
+    if (rc) return rc;
+    double rr = 0.0;
+    rc = lm_mdot(lb, R, ld, 1, R, n, &rr, stream);
+    if (rc) return rc;
+    rnorm = std::sqrt(rr);
+    if (rnorm <= o.tol * std::abs(theta)) {
+      status = SR_OK;
+      break;
+    }
+    if (m == ms) {
+      // restart from the Ritz vector: V = [c], HV = [H c], SV = [S c] (y has unit norm, so
+      // c^T S c = 1)
+      rc = lm_lincomb(V, y.data(), m, nullptr, nullptr, 0, ld, 0.0, T1, n, stream);
+      if (rc) return rc;
+      rc = lm_lincomb(HV, y.data(), m, nullptr, nullptr, 0, ld, 0.0, T2, n, stream);
+      if (rc) return rc;
+      rc = lm_lincomb(SV, y.data(), m, nullptr, nullptr, 0, ld, 0.0, R, n, stream);
+      if (rc) return rc;
+      HIP_TRY(hipMemcpyAsync(row(V, 0), T1, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(row(HV, 0), T2, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+      HIP_TRY(hipMemcpyAsync(row(SV, 0), R, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+      double a00 = 0.0;
+      rc = lm_mdot(lb, V, ld, 1, row(HV, 0), n, &a00, stream);
+      if (rc) return rc;
+      A.assign((size_t)ms * ms, 0.0);
+      A[0] = a00;
+      m = 1;
+      restarts++;
+      // the new direction: the residual of the restarted Ritz pair, H c - a00 S c
+      y.assign(1, 1.0);
+      tmp[0] = -a00;
+      rc = lm_lincomb(HV, y.data(), 1, SV, tmp.data(), 1, ld, 0.0, row(V, 1), n, stream);
+      if (rc) return rc;
+      fresh = true;
+      continue;
+    }
+    // next direction: the residual
+    HIP_TRY(hipMemcpyAsync(row(V, m), R, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    fresh = true;
+  }
+  // c = V y (the last Ritz vector)
+  if (y.empty()) {
+    y.assign(1, 1.0);
+    m = std::max(m, 1);
+  }
+  rc = lm_lincomb(V, y.data(), std::min<int>(m, (int)y.size()), nullptr, nullptr, 0, ld, 0.0, c, n, stream);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(stream));
+  info->iters = iters;
+  info->restarts = restarts;
+  info->status = status;
+  info->reserved = 0;
+  info->theta = theta;
+  info->res_norm = rnorm;
   return status;
 }
 

@@ -47,6 +47,15 @@ class SrCgInfo(ctypes.Structure):
 BATCH_MAX_RHS = 8
 
 
+class LmDavidsonOpts(ctypes.Structure):
+    _fields_ = [("tol", _c_d), ("max_iter", _c_i32), ("max_sub", _c_i32)]
+
+
+class LmDavidsonInfo(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("restarts", _c_i32), ("status", _c_i32), ("reserved", _c_i32),
+                ("theta", _c_d), ("res_norm", _c_d)]
+
+
 class SrBatchSystem(ctypes.Structure):
     _fields_ = [("O", SrMatrix), ("g", _c_p), ("x", _c_p), ("eps", _c_d * BATCH_MAX_RHS)]
 
@@ -57,6 +66,8 @@ PROTOTYPES = {
     "sr_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
                                    ctypes.POINTER(SrCgInfo), _c_p]),
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
+    "lm_davidson": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix),
+                                   ctypes.POINTER(LmDavidsonOpts), _c_p, ctypes.POINTER(LmDavidsonInfo), _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
     "sr_adjoint": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, ctypes.c_int64,
@@ -270,6 +281,25 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
            "lm_hv_product")
     return y
+
+
+def lm_davidson(M: Matrix, E: torch.Tensor, Dm: Matrix, tol: float = 1e-8, max_iter: int = 1000, max_sub: int = 40,
+                raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
+    """Lowest eigenpair of the linear method, H c = theta S c (lm_davidson).  Returns
+    (theta, c [n_p + 1] float64 with c^T S c = 1, info dict)."""
+    E = _vec(E, M.O.shape[0], "E")
+    c = torch.empty(M.n_p + 1, dtype=torch.float64, device=M.O.device)
+    opts = LmDavidsonOpts()
+    opts.tol = float(tol)
+    opts.max_iter = int(max_iter)
+    opts.max_sub = int(max_sub)
+    info = LmDavidsonInfo()
+    m, d = M.c(), Dm.c()
+    st = lib().lm_davidson(ctypes.byref(m), _ptr(E), ctypes.byref(d), ctypes.byref(opts), _ptr(c), ctypes.byref(info),
+                           _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "lm_davidson")
+    return info.theta, c, {"status": st, "iters": info.iters, "restarts": info.restarts, "res_norm": info.res_norm}
 
 
 def _rhs_block(V: torch.Tensor, n_p: int, name: str) -> torch.Tensor:

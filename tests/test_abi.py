@@ -22,7 +22,8 @@ def _declared_functions():
 
 def test_header_declares_the_entry_points():
     names = _declared_functions()
-    for n in ("sr_grad", "sr_sv_product", "sr_cg_solve", "lm_hv_product", "sr_quantize", "sr_adjoint", "sr_release",
+    for n in ("sr_grad", "sr_sv_product", "sr_cg_solve", "lm_hv_product", "lm_davidson", "sr_quantize", "sr_adjoint",
+              "sr_svk_product", "sr_cg_solve_batched", "sr_release",
               "sr_status_string", "sr_last_error", "sr_version"):
         assert n in names, n
 
@@ -41,6 +42,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 4
     assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
+    assert ctypes.sizeof(sr.LmDavidsonOpts) == 8 + 4 * 2
+    assert ctypes.sizeof(sr.LmDavidsonInfo) == 4 * 4 + 8 * 2
 
 
 def test_status_strings_and_version():
@@ -139,6 +142,17 @@ def test_invalid_scalars_rejected():
                         None) == sr.SR_ERR_INVALID
     assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p(4096), sr.SR_F64, 4, None,
                         None) == sr.SR_ERR_INVALID          # overlaps v
+    # Davidson: options and required outputs
+    dopt = sr.LmDavidsonOpts()
+    dinf = sr.LmDavidsonInfo()
+    for tol, mi, ms in ((0.0, 10, 8), (1e-8, 0, 8), (1e-8, 10, 1), (1e-8, 10, 65), (float("nan"), 10, 8)):
+        dopt.tol, dopt.max_iter, dopt.max_sub = tol, mi, ms
+        assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, ctypes.byref(dinf),
+                             None) == sr.SR_ERR_INVALID
+    dopt.tol, dopt.max_iter, dopt.max_sub = 1e-8, 10, 8
+    assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, None, None) == sr.SR_ERR_INVALID
+    assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(d), ctypes.byref(dopt), y, ctypes.byref(dinf),
+                         None) == sr.SR_ERR_INVALID      # D's shape differs
     # lm: a second code plane is rejected
     mb = _mat(dtype=sr.SR_BF16, ld=8, scale=512, lo=1024)
     assert L.lm_hv_product(ctypes.byref(mb), E, ctypes.byref(mb), v, y, None) == sr.SR_ERR_INVALID
