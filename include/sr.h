@@ -232,11 +232,14 @@ int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const doubl
  * one H product (lm_hv_product, one read of O and D) and one S product (sr_sv_product,
  * one read of O); the subspace basis is S-orthonormal (classical Gram-Schmidt, twice),
  * the projected matrix is solved on the host (Hessenberg QR), the new direction is the
- * Ritz residual H c - theta S c, and the subspace restarts from the Ritz vector when it
- * reaches opt->max_sub vectors.  The start vector is Psi itself, c = (1, 0, ..., 0).
+ * Ritz residual r = H c - theta S c, and the subspace restarts from the Ritz vector when
+ * it reaches opt->max_sub vectors.  With opt->precond = 1 the new direction is Davidson's
+ * diagonal correction (diag H - theta diag S)^{-1} r with diag H approximated by
+ * <E> diag S, i.e. r_0 and r_i / S_ii (one extra prepare pass computes diag S).  The start
+ * vector is Psi itself, c = (1, 0, ..., 0).
  * O, D, E: as lm_hv_product (same n_s, n_p, dtype; single code plane).  c: device
  * [n_p + 1] float64, receives the Ritz vector (S-normalized, c^T S c = 1).  info: host,
- * required.  opt: NULL for the defaults (tol 1e-8, max_iter 1000, max_sub 40); converged
+ * required.  opt: NULL for the defaults (tol 1e-8, max_iter 1000, max_sub 40, precond 0); converged
  * when ||H c - theta S c|| <= tol |theta|.  Needs S positive definite on the explored
  * subspace (a direction of S-norm <= 1e-28 relative ends the iteration).  Synchronizes
  * `stream`.  Returns SR_OK when converged, SR_NOT_CONVERGED otherwise (c then holds the
@@ -247,6 +250,8 @@ typedef struct lm_davidson_opts {
   double tol;                /* > 0 */
   int32_t max_iter;          /* H products, >= 1 */
   int32_t max_sub;           /* subspace size before a restart, in [2, 64] */
+  int32_t precond;           /* 1: diagonal (Davidson) correction; 0: the residual */
+  int32_t reserved;          /* 0 */
 } lm_davidson_opts;
 typedef struct lm_davidson_info {
   int32_t iters;             /* iterations (each one H and one S product) */

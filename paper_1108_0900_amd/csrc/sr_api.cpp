@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "sr_launch.hpp"
+#include "sr_lm.hpp"
 
 namespace {
 
@@ -1017,8 +1018,10 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   if (O->O_lo != nullptr || D->O_lo != nullptr)
     return fail(SR_ERR_INVALID, "lm_davidson: a second code plane is not supported");
   if (E == nullptr || c == nullptr || info == nullptr) return fail(SR_ERR_INVALID, "lm_davidson: null E, c or info");
-  lm_davidson_opts o{1e-8, 1000, 40};
+  lm_davidson_opts o{1e-8, 1000, 40, 0, 0};
   if (opt) o = *opt;
+  if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "lm_davidson: precond must be 0 or 1");
+  if (o.reserved != 0) return fail(SR_ERR_INVALID, "lm_davidson: reserved must be 0");
   if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(SR_ERR_INVALID, "lm_davidson: tol must be finite and > 0");
   if (o.max_iter < 1) return fail(SR_ERR_INVALID, "lm_davidson: max_iter must be >= 1");
   if (o.max_sub < 2 || o.max_sub > kLmMaxSub)
@@ -1031,7 +1034,7 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   const int ms = o.max_sub;
   const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n, 4096)));
   // V, HV, SV [ms][ld]; r, c-temporaries [3][ld]; column means [ld]; reduction buffers
-  const size_t bytes = ((size_t)3 * ms + 4) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 4096;
+  const size_t bytes = ((size_t)3 * ms + 5) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 4096;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base, g_lm_ws);
   if (rc) return rc;
@@ -1039,15 +1042,33 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   double *V = cv.take<double>((int64_t)ms * ld), *HV = cv.take<double>((int64_t)ms * ld);
   double *SV = cv.take<double>((int64_t)ms * ld);
   double *R = cv.take<double>(ld), *T1 = cv.take<double>(ld), *T2 = cv.take<double>(ld);
-  double *mean = cv.take<double>(ld);
+  double *mean = cv.take<double>(ld), *dvec = cv.take<double>(ld);
   LmBufs lb{cv.take<double>((int64_t)nb * kLmMaxSub), cv.take<double>(kLmMaxSub), nb};
-  // the column means once, so that the products do not recompute them
+  // the column means once, so that the products do not recompute them (and diag S for
+  // the diagonal correction: dvec = (1, diag S))
   sr_matrix Om = *O, Dm = *D;
-  if (!O->col_mean) {
-    rc = run_grad(O, nullptr, nullptr, nullptr, mean, nullptr, dev, di, stream);
+  if (!O->col_mean || o.precond) {
+    rc = run_grad(O, nullptr, nullptr, nullptr, mean, o.precond ? dvec + 1 : nullptr, dev, di, stream);
     if (rc) return rc;
-    Om.col_mean = mean;
+    if (!O->col_mean) Om.col_mean = mean;
   }
+  if (o.precond) {
+    const double one = 1.0;
+    HIP_TRY(hipMemcpyAsync(dvec, &one, 8, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  // the next direction from a residual: itself, or its diagonal correction
+  auto correction = [&](const double *r, double *t) -> int {
+    if (!o.precond) {
+      if (r != t) HIP_TRY(hipMemcpyAsync(t, r, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+      return SR_OK;
+    }
+    DivArgs a{r, dvec, t, n};
+    void *args[] = {&a};
+    const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, lm_threads())));
+    HIP_TRY(hipLaunchKernel(divide_kernel(), dim3(blocks), dim3(lm_threads()), args, 0, stream));
+    return SR_OK;
+  };
   auto row = [&](double *B, int i) { return B + (int64_t)i * ld; };
   // S t = (t_0, (S_c) t_1..n_p)
   auto s_product = [&](const double *t, double *st) -> int {
@@ -1150,11 +1171,14 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
       tmp[0] = -a00;
       rc = lm_lincomb(HV, y.data(), 1, SV, tmp.data(), 1, ld, 0.0, row(V, 1), n, stream);
       if (rc) return rc;
+      rc = correction(row(V, 1), row(V, 1));
+      if (rc) return rc;
       fresh = true;
       continue;
     }
-    // next direction: the residual
-    HIP_TRY(hipMemcpyAsync(row(V, m), R, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
+    // next direction: the residual or its correction
+    rc = correction(R, row(V, m));
+    if (rc) return rc;
     fresh = true;
   }
   // c = V y (the last Ritz vector)

@@ -135,29 +135,6 @@ struct BatchEntry {
 };
 const BatchEntry *batched_entry(int dt);   // nullptr if the type has none
 
-// Generalized Davidson of the linear method: subspace dot products and combinations.
-constexpr int kLmMaxSub = 64;        // largest subspace
-struct MdotArgs {
-  const double *X;                   // [m][ld]
-  int64_t ld, n;
-  int m, nb;                         // rows of X; workgroups of the partial pass
-  const double *w;                   // [n]
-  double *part;                      // [nb][m]
-  double *out;                       // [m]
-};
-struct LincombArgs {
-  const double *X, *Z;               // [mx][ld], [mz][ld]
-  int mx, mz;
-  int64_t ld, n;
-  double beta;
-  double *out;                       // [n]
-  double ca[kLmMaxSub], cz[kLmMaxSub];
-};
-const void *mdot_part_kernel();
-const void *mdot_final_kernel();
-const void *lincomb_kernel();
-int lm_threads();
-
 // Adjoint backward (row dots, finish, rank-2 write).
 struct RowDotsArgs {
   const unsigned char *O;

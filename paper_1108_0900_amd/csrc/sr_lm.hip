@@ -2,7 +2,7 @@
 // products H t and S t come from the fused product kernels; what remains per iteration
 // are a few dot products against the subspace bases and linear combinations of them.
 // Every reduction has a fixed order (partial sums per workgroup, then one workgroup).
-#include "sr_launch.hpp"
+#include "sr_lm.hpp"
 
 namespace sr {
 
@@ -49,6 +49,16 @@ __global__ __launch_bounds__(kLmNT) void k_lincomb(LincombArgs a) {
   }
 }
 
+// out[j] = in[j] / d[j] (the diagonal preconditioner of the Davidson correction); a
+// non-positive d[j] (a constant column) leaves the component as it is.
+__global__ __launch_bounds__(kLmNT) void k_divide(DivArgs a) {
+  for (int64_t j = (int64_t)blockIdx.x * kLmNT + threadIdx.x; j < a.n; j += (int64_t)gridDim.x * kLmNT) {
+    const double d = a.d[j];
+    a.out[j] = d > 0.0 ? a.in[j] / d : a.in[j];
+  }
+}
+
+const void *divide_kernel() { return (const void *)&k_divide; }
 const void *mdot_part_kernel() { return (const void *)&k_mdot_part; }
 const void *mdot_final_kernel() { return (const void *)&k_mdot_final; }
 const void *lincomb_kernel() { return (const void *)&k_lincomb; }

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 4
     assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8 + 8 + 8
     assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
-    assert ctypes.sizeof(sr.LmDavidsonOpts) == 8 + 4 * 2
+    assert ctypes.sizeof(sr.LmDavidsonOpts) == 8 + 4 * 4
     assert ctypes.sizeof(sr.LmDavidsonInfo) == 4 * 4 + 8 * 2
 
 
@@ -150,6 +150,11 @@ def test_invalid_scalars_rejected():
         assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, ctypes.byref(dinf),
                              None) == sr.SR_ERR_INVALID
     dopt.tol, dopt.max_iter, dopt.max_sub = 1e-8, 10, 8
+    for pc, rsv in ((2, 0), (0, 1)):
+        dopt.precond, dopt.reserved = pc, rsv
+        assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, ctypes.byref(dinf),
+                             None) == sr.SR_ERR_INVALID
+    dopt.precond, dopt.reserved = 0, 0
     assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, None, None) == sr.SR_ERR_INVALID
     assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(d), ctypes.byref(dopt), y, ctypes.byref(dinf),
                          None) == sr.SR_ERR_INVALID      # D's shape differs
