@@ -1086,10 +1086,10 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
     HIP_TRY(hipMemcpyAsync(row(V, 0), &one, 8, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
   }
-  bool fresh = true;                       // row(V, m) holds a new, not yet orthogonalized direction
   while (iters < o.max_iter) {
+    // row(V, m) holds the new direction: S-orthonormalize it, then its H and S products
     double *t = row(V, m), *st = row(SV, m), *ht = row(HV, m);
-    if (fresh) {
+    {
       rc = s_product(t, st);
       if (rc) return rc;
       iters++;
@@ -1173,13 +1173,11 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
       if (rc) return rc;
       rc = correction(row(V, 1), row(V, 1));
       if (rc) return rc;
-      fresh = true;
       continue;
     }
     // next direction: the residual or its correction
     rc = correction(R, row(V, m));
     if (rc) return rc;
-    fresh = true;
   }
   // c = V y (the last Ritz vector)
   if (y.empty()) {

@@ -55,3 +55,18 @@ def test_davidson_not_converged_reports_status():
                                     raise_on=())
     assert info["status"] == sr.SR_NOT_CONVERGED and info["iters"] == 3
     assert np.isfinite(theta) and torch.isfinite(c).all()
+
+
+@pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=["bf16", "f16"])
+def test_davidson_scaled_storage(dtype):
+    """bf16/f16 codes with column scales: the products accumulate in float32, so the Ritz
+    value matches the dense eigensolve of the dequantized matrices to 1e-5 (relative)."""
+    O, E, D = _case(3000, 200, seed=41)
+    Os, Ds = stored_dense(O, dtype), stored_dense(D, dtype)
+    M, Md = device_matrix(O, dtype), device_matrix(D, dtype)
+    theta, c, info = sr.lm_davidson(M, torch.from_numpy(E).to(DEV), Md, tol=1e-6, max_iter=2000, max_sub=40,
+                                    precond=True)
+    assert info["status"] == 0, info
+    H, S = orc.lm_matrices(Os, E, Ds)
+    ev, _ = orc.lm_lowest_eigenpair(H, S)
+    assert abs(theta - ev) <= 1e-5 * abs(ev), (theta, ev, info)
