@@ -233,10 +233,12 @@ int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const doubl
  * one read of O); the subspace basis is S-orthonormal (classical Gram-Schmidt, twice),
  * the projected matrix is solved on the host (Hessenberg QR), the new direction is the
  * Ritz residual r = H c - theta S c, and the subspace restarts from the Ritz vector when
- * it reaches opt->max_sub vectors.  With opt->precond = 1 the new direction is Davidson's
- * diagonal correction (diag H - theta diag S)^{-1} r with diag H approximated by
- * <E> diag S, i.e. r_0 and r_i / S_ii (one extra prepare pass computes diag S).  The start
- * vector is Psi itself, c = (1, 0, ..., 0).
+ * it reaches opt->max_sub vectors.  With opt->precond the new direction is Davidson's
+ * diagonal correction (diag H - theta diag S)^{-1} r: precond = 2 with the sampled
+ * diag H (H_00 = <E>, H_jj = <Oc_j E Oc_j> + <Oc_j D_j>; one extra pass over O and D and
+ * one prepare pass over O), precond = 1 with diag H approximated by <E> diag S, i.e. r_0
+ * and r_i / S_ii (one prepare pass).  Near-zero denominators are kept at 1e-8 of their
+ * terms' size.  The start vector is Psi itself, c = (1, 0, ..., 0).
  * O, D, E: as lm_hv_product (same n_s, n_p, dtype; single code plane).  c: device
  * [n_p + 1] float64, receives the Ritz vector (S-normalized, c^T S c = 1).  info: host,
  * required.  opt: NULL for the defaults (tol 1e-8, max_iter 1000, max_sub 40, precond 0); converged
@@ -250,7 +252,7 @@ typedef struct lm_davidson_opts {
   double tol;                /* > 0 */
   int32_t max_iter;          /* H products, >= 1 */
   int32_t max_sub;           /* subspace size before a restart, in [2, 64] */
-  int32_t precond;           /* 1: diagonal (Davidson) correction; 0: the residual */
+  int32_t precond;           /* 0: the residual; 1: approximate, 2: exact diagonal correction */
   int32_t reserved;          /* 0 */
 } lm_davidson_opts;
 typedef struct lm_davidson_info {

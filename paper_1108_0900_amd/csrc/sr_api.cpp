@@ -1020,7 +1020,7 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   if (E == nullptr || c == nullptr || info == nullptr) return fail(SR_ERR_INVALID, "lm_davidson: null E, c or info");
   lm_davidson_opts o{1e-8, 1000, 40, 0, 0};
   if (opt) o = *opt;
-  if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "lm_davidson: precond must be 0 or 1");
+  if (o.precond < 0 || o.precond > 2) return fail(SR_ERR_INVALID, "lm_davidson: precond must be 0, 1 or 2");
   if (o.reserved != 0) return fail(SR_ERR_INVALID, "lm_davidson: reserved must be 0");
   if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(SR_ERR_INVALID, "lm_davidson: tol must be finite and > 0");
   if (o.max_iter < 1) return fail(SR_ERR_INVALID, "lm_davidson: max_iter must be >= 1");
@@ -1034,7 +1034,9 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   const int ms = o.max_sub;
   const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n, 4096)));
   // V, HV, SV [ms][ld]; r, c-temporaries [3][ld]; column means [ld]; reduction buffers
-  const size_t bytes = ((size_t)3 * ms + 5) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 4096;
+  const int sp_h = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(O->n_s, 128)));   // diag H splits
+  const size_t bytes = ((size_t)3 * ms + 6) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 +
+                       (o.precond == 2 ? (size_t)sp_h * n_p * 8 : 0) + 4096;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base, g_lm_ws);
   if (rc) return rc;
@@ -1042,13 +1044,15 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   double *V = cv.take<double>((int64_t)ms * ld), *HV = cv.take<double>((int64_t)ms * ld);
   double *SV = cv.take<double>((int64_t)ms * ld);
   double *R = cv.take<double>(ld), *T1 = cv.take<double>(ld), *T2 = cv.take<double>(ld);
-  double *mean = cv.take<double>(ld), *dvec = cv.take<double>(ld);
+  double *mean = cv.take<double>(ld), *dvec = cv.take<double>(ld), *dhvec = cv.take<double>(ld);
+  double *hpart = o.precond == 2 ? cv.take<double>((int64_t)sp_h * n_p) : nullptr;
   LmBufs lb{cv.take<double>((int64_t)nb * kLmMaxSub), cv.take<double>(kLmMaxSub), nb};
-  // the column means once, so that the products do not recompute them (and diag S for
-  // the diagonal correction: dvec = (1, diag S))
+  // the column means once, so that the products do not recompute them; for the diagonal
+  // correction dvec = (1, diag S) and, for the exact one, dhvec = (<E>, diag H)
   sr_matrix Om = *O, Dm = *D;
   if (!O->col_mean || o.precond) {
-    rc = run_grad(O, nullptr, nullptr, nullptr, mean, o.precond ? dvec + 1 : nullptr, dev, di, stream);
+    rc = run_grad(O, o.precond == 2 ? E : nullptr, nullptr, o.precond == 2 ? dhvec : nullptr, mean,
+                  o.precond ? dvec + 1 : nullptr, dev, di, stream);
     if (rc) return rc;
     if (!O->col_mean) Om.col_mean = mean;
   }
@@ -1057,13 +1061,31 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
     HIP_TRY(hipMemcpyAsync(dvec, &one, 8, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));
   }
+  if (o.precond == 2) {
+    DiagHArgs ha{};
+    ha.o = make_operand(O);
+    ha.d = make_operand(D);
+    ha.mean = Om.col_mean;
+    ha.E = E;
+    ha.n_s = O->n_s;
+    ha.n_p = n_p;
+    ha.rs = cdiv(O->n_s, sp_h);
+    ha.SP = (int)cdiv(O->n_s, ha.rs);
+    ha.part = hpart;
+    ha.out = dhvec + 1;
+    void *hargs[] = {&ha};
+    const unsigned cb = (unsigned)cdiv(n_p, lm_threads());
+    HIP_TRY(hipLaunchKernel(diagh_part_kernel(O->dtype), dim3(cb, (unsigned)ha.SP), dim3(lm_threads()), hargs, 0,
+                            stream));
+    HIP_TRY(hipLaunchKernel(diagh_final_kernel(), dim3(cb), dim3(lm_threads()), hargs, 0, stream));
+  }
   // the next direction from a residual: itself, or its diagonal correction
-  auto correction = [&](const double *r, double *t) -> int {
+  auto correction = [&](const double *r, double *t, double th) -> int {
     if (!o.precond) {
       if (r != t) HIP_TRY(hipMemcpyAsync(t, r, (size_t)n * 8, hipMemcpyDeviceToDevice, stream));
       return SR_OK;
     }
-    DivArgs a{r, dvec, t, n};
+    DivArgs a{r, o.precond == 2 ? dhvec : nullptr, dvec, t, n, th};
     void *args[] = {&a};
     const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, lm_threads())));
     HIP_TRY(hipLaunchKernel(divide_kernel(), dim3(blocks), dim3(lm_threads()), args, 0, stream));
@@ -1171,12 +1193,12 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
       tmp[0] = -a00;
       rc = lm_lincomb(HV, y.data(), 1, SV, tmp.data(), 1, ld, 0.0, row(V, 1), n, stream);
       if (rc) return rc;
-      rc = correction(row(V, 1), row(V, 1));
+      rc = correction(row(V, 1), row(V, 1), a00);
       if (rc) return rc;
       continue;
     }
     // next direction: the residual or its correction
-    rc = correction(R, row(V, m));
+    rc = correction(R, row(V, m), theta);
     if (rc) return rc;
   }
   // c = V y (the last Ritz vector)

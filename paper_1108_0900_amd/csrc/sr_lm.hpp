@@ -23,11 +23,25 @@ struct LincombArgs {
   double ca[kLmMaxSub], cz[kLmMaxSub];
 };
 struct DivArgs {
-  const double *in, *d;              // [n]
-  double *out;                       // [n]; out[j] = in[j] / d[j] (in[j] where d[j] <= 0)
+  const double *in;                  // [n]
+  const double *dh, *ds;             // [n] diag H (or nullptr) and diag S
+  double *out;                       // [n]; out[j] = in[j] / (dh[j] - theta ds[j]), or in[j] / ds[j]
   int64_t n;
+  double theta;
 };
 const void *divide_kernel();
+// diag H of the linear method, H_jj = (1/N) sum_k Oc_kj (E_k Oc_kj + D_kj), j < n_p
+struct DiagHArgs {
+  Operand o, d;                      // O and D (single code plane each)
+  const double *mean;                // [n_p] column means of O
+  const double *E;                   // [n_s]
+  int64_t n_s, n_p, rs;              // rows per split
+  int SP;                            // splits (grid y)
+  double *part;                      // [SP][n_p]
+  double *out;                       // [n_p]
+};
+const void *diagh_part_kernel(int dt);
+const void *diagh_final_kernel();
 const void *mdot_part_kernel();
 const void *mdot_final_kernel();
 const void *lincomb_kernel();

@@ -285,8 +285,9 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
 
 
 def lm_davidson(M: Matrix, E: torch.Tensor, Dm: Matrix, tol: float = 1e-8, max_iter: int = 1000, max_sub: int = 40,
-                precond: bool = False, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
-    """Lowest eigenpair of the linear method, H c = theta S c (lm_davidson).  Returns
+                precond: int = 0, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
+    """Lowest eigenpair of the linear method, H c = theta S c (lm_davidson); precond 0: the
+    residual as new direction, 1: approximate, 2: exact diagonal (Davidson) correction.  Returns
     (theta, c [n_p + 1] float64 with c^T S c = 1, info dict)."""
     E = _vec(E, M.O.shape[0], "E")
     c = torch.empty(M.n_p + 1, dtype=torch.float64, device=M.O.device)
@@ -294,7 +295,7 @@ def lm_davidson(M: Matrix, E: torch.Tensor, Dm: Matrix, tol: float = 1e-8, max_i
     opts.tol = float(tol)
     opts.max_iter = int(max_iter)
     opts.max_sub = int(max_sub)
-    opts.precond = 1 if precond else 0
+    opts.precond = int(precond)
     info = LmDavidsonInfo()
     m, d = M.c(), Dm.c()
     st = lib().lm_davidson(ctypes.byref(m), _ptr(E), ctypes.byref(d), ctypes.byref(opts), _ptr(c), ctypes.byref(info),

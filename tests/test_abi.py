@@ -150,7 +150,7 @@ def test_invalid_scalars_rejected():
         assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, ctypes.byref(dinf),
                              None) == sr.SR_ERR_INVALID
     dopt.tol, dopt.max_iter, dopt.max_sub = 1e-8, 10, 8
-    for pc, rsv in ((2, 0), (0, 1)):
+    for pc, rsv in ((3, 0), (-1, 0), (0, 1)):
         dopt.precond, dopt.reserved = pc, rsv
         assert L.lm_davidson(ctypes.byref(m), E, ctypes.byref(m), ctypes.byref(dopt), y, ctypes.byref(dinf),
                              None) == sr.SR_ERR_INVALID

@@ -27,7 +27,7 @@ def _case(n_s, n_p, seed):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("shape", [(400, 7), (3000, 120), (5000, 600)], ids=lambda s: f"{s[0]}x{s[1]}")
 @pytest.mark.parametrize("max_sub", [40, 8])
-@pytest.mark.parametrize("precond", [False, True], ids=["residual", "diagonal"])
+@pytest.mark.parametrize("precond", [0, 1, 2], ids=["residual", "approx-diag", "exact-diag"])
 def test_davidson_matches_dense_eigensolve(shape, dtype, max_sub, precond):
     n_s, n_p = shape
     print(f"[davidson] {n_s}x{n_p} {dtype} max_sub={max_sub} precond={precond}", flush=True)
@@ -65,7 +65,7 @@ def test_davidson_scaled_storage(dtype):
     Os, Ds = stored_dense(O, dtype), stored_dense(D, dtype)
     M, Md = device_matrix(O, dtype), device_matrix(D, dtype)
     theta, c, info = sr.lm_davidson(M, torch.from_numpy(E).to(DEV), Md, tol=1e-6, max_iter=2000, max_sub=40,
-                                    precond=True)
+                                    precond=2)
     assert info["status"] == 0, info
     H, S = orc.lm_matrices(Os, E, Ds)
     ev, _ = orc.lm_lowest_eigenpair(H, S)
