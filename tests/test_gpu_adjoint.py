@@ -185,7 +185,8 @@ def test_adjoint_full_size_differentiation_case():
     M.mean = sr.sr_grad(M, None)["mean"]
     lam, info = sr.sr_cg_solve(M, w, cfg.eps_abs, rtol=1e-9, refresh_every=20)
     assert info["status"] == 0
-    assert abs(float(epst.grad) + float(lam @ x)) <= 1e-6 * abs(float(lam @ x))
+    lx = float(lam @ x.detach())
+    assert abs(float(epst.grad) + lx) <= 1e-6 * abs(lx)
     res = sr.sr_sv_product(M, lam, cfg.eps_abs) - w
     assert float(res.norm() / w.norm()) <= 1e-8
     # sampled rows, recomputed in float64 on the CPU from the stored float32 values
