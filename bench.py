@@ -381,8 +381,29 @@ def measure_batched(args):
     for i in range(8):
         (r, ms_i) = timed_events(lambda: sr.sr_cg_solve(M, G[i], eps[i], rtol=cfg.rtol, refresh_every=20))
         t_single += ms_i
+    (res_m, ms_m) = timed_events(lambda: sr.sr_cg_solve_shifts(M, G[0], eps, rtol=cfg.rtol))
     out["system0"] = {"n_s": M.O.shape[0], "n_p": M.n_p, "batched_ms": round(ms1, 2),
-                      "eight_single_solves_ms": round(t_single, 2), "speedup": round(t_single / ms1, 2)}
+                      "eight_single_solves_ms": round(t_single, 2), "speedup": round(t_single / ms1, 2),
+                      "multi_shift_ms": round(ms_m, 2), "multi_shift_status": res_m[2]}
+    # every system by multi-shift CG (one right-hand side, 8 shifts, one Krylov sequence),
+    # one call per system, single-column products with the tuned tiles of each system's type
+    worst_m = 0.0
+    t0 = time.perf_counter()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    statuses = []
+    for Ms, Gs, es in systems:
+        Xm, inf_m, st_m = sr.sr_cg_solve_shifts(Ms, Gs[0], es, rtol=cfg.rtol)
+        statuses.append(st_m)
+        worst_m = max(worst_m, max(c["rel_res_true"] for c in inf_m))
+        del Xm
+    e1.record()
+    e1.synchronize()
+    out["multi_shift_all_systems"] = {"ms": round(e0.elapsed_time(e1), 1), "calls": len(systems),
+                                      "all_ok": all(st_m == 0 for st_m in statuses),
+                                      "worst_rel_res_true": worst_m}
     # the 8-column product alone on the largest system
     big = max(range(len(systems)), key=lambda k: gb_o[k])
     Mb = systems[big][0]

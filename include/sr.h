@@ -202,6 +202,24 @@ typedef struct sr_batch_system {
 
 int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double *eps, double *Y, int32_t exact,
                    hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * sr_cg_solve_shifts: (S + eps_i I) x_i = g for up to SR_BATCH_MAX_RHS shifts eps_i and
+ * one right-hand side g, by multi-shift CG (not in the paper): Krylov spaces do not
+ * depend on the shift, so one CG sequence of the smallest shift, one fused product per
+ * iteration, serves every shift through scalar recurrences (x_i and its direction are
+ * the only per-shift vectors).  A shift stops once its recurrence residual reaches
+ * opt->rtol; afterwards every shift's true residual is computed with a float64 product,
+ * and a shift that missed rtol continues with sr_cg_solve from its x_i (warm start,
+ * refresh_every of opt, 20 if 0).  Storage SR_F64 or SR_F32, one code plane.
+ * g: device [n_p]; eps: host [k], finite, >= 0, any order; X: device [k][n_p] (row i for
+ * eps_i), must not overlap g.  info: host [k] or NULL (iters and products include the
+ * shared sequence, the residual check and any continuation).  opt->use_x0, refine,
+ * precond and res_history are not used.  Synchronizes `stream`.  Returns SR_OK if every
+ * shift converged, else the first non-OK status or an error code.
+ * ------------------------------------------------------------------------------------ */
+int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const double *eps, double *X,
+                       const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream);
 int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, const sr_cg_opts *opt,
                         sr_cg_info *info, hipStream_t stream);
 

@@ -18,6 +18,7 @@
 
 #include "sr_launch.hpp"
 #include "sr_lm.hpp"
+#include "sr_shifts.hpp"
 
 namespace {
 
@@ -370,6 +371,9 @@ int get_mean_scratch(int dev, hipStream_t s, int64_t n, double **out) {
 
 // Buffers of the Davidson solver (its products carve g_ws for themselves).
 std::map<std::pair<int, hipStream_t>, Workspace> g_lm_ws;
+// Solutions, directions and checks of the multi-shift solve (kept apart from g_ws, which
+// its launch and the residual checks carve).
+std::map<std::pair<int, hipStream_t>, Workspace> g_shift_ws;
 
 // ------------------------------------------------------------------------------------
 // Small dense eigenproblem of the Davidson subspace (host)
@@ -614,7 +618,7 @@ const char *sr_status_string(int status) {
 int sr_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = SR_OK;
-  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws, &g_lm_ws}) {
+  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws, &g_lm_ws, &g_shift_ws}) {
     for (auto &kv : *mp) {
       if (kv.second.ptr) {
         int cur = 0;
@@ -1215,6 +1219,150 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   info->reserved = 0;
   info->theta = theta;
   info->res_norm = rnorm;
+  return status;
+}
+
+int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const double *eps, double *X,
+                       const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream) {
+  int rc = check_matrix(O, "sr_cg_solve_shifts");
+  if (rc) return rc;
+  if (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32))
+    return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: storage must be SR_F64 or SR_F32, one plane");
+  if (k < 1 || k > kMaxShifts) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: k must be in [1, %d]", kMaxShifts);
+  if (g == nullptr || X == nullptr || eps == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: null g, X or eps");
+  const int64_t n_p = O->n_p;
+  if (ranges_overlap(g, n_p * 8, X, (int64_t)k * n_p * 8))
+    return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: g and X overlap");
+  for (int i = 0; i < k; ++i)
+    if (!(eps[i] >= 0.0) || !std::isfinite(eps[i]))
+      return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: eps must be finite and >= 0");
+  sr_cg_opts o{};
+  o.rtol = 1e-10;
+  if (opt) o = *opt;
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: bad rtol");
+  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: refresh_every must be >= 0");
+  int64_t max_iter = o.max_iter > 0 ? o.max_iter : n_p + 100;
+  if (max_iter > (1 << 30)) max_iter = 1 << 30;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  // shifts in increasing order: the smallest drives the Krylov sequence
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return eps[a] < eps[b]; });
+  // own buffers: sorted solutions and directions, a residual temporary, the kernel's info
+  const int64_t ld = round_up(n_p, 32);
+  const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n_p, 4096)));
+  const size_t own = ((size_t)2 * k + 2) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 1024;
+  void *obase = nullptr;
+  rc = get_workspace(dev, stream, own, &obase, g_shift_ws);
+  if (rc) return rc;
+  Carve oc(obase);
+  double *xs = oc.take<double>((int64_t)k * ld), *ps = oc.take<double>((int64_t)k * ld);
+  double *tmp = oc.take<double>(ld), *mbuf = oc.take<double>(ld);
+  double *sinfo = oc.take<double>(2 * kMaxShifts + 4);
+  LmBufs lb{oc.take<double>((int64_t)nb * kLmMaxSub), oc.take<double>(kLmMaxSub), nb};
+  sr_matrix Om = *O;
+  if (!O->col_mean) {
+    rc = run_grad(O, nullptr, nullptr, nullptr, mbuf, nullptr, dev, di, stream);
+    if (rc) return rc;
+    Om.col_mean = mbuf;
+  }
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, n_p, 1, &pl);
+  if (rc) return rc;
+  const void *fn = shift_kernel(O->dtype, pl.ke->nv, pl.ke->r, pl.ke->look, pl.ke->poll, pl.ke->nt);
+  if (fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: no multi-shift kernel for this configuration");
+  const int64_t ypd = (int64_t)pl.pg.RG * n_p;
+  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (n_p * 8 + 256) + 1024;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, bytes, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  ShiftArgs sa{};
+  CgArgs &a = sa.c;
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(&Om);
+  a.mean = Om.col_mean;
+  a.g = g;
+  a.x = nullptr;
+  a.r = cv.take<double>(n_p);
+  a.p = cv.take<double>(n_p);
+  a.q = cv.take<double>(n_p);
+  a.eps = eps[order[0]];
+  a.rtol = o.rtol;
+  a.max_iter = (int)max_iter;
+  sa.n_shift = k;
+  for (int s = 0; s < kMaxShifts; ++s) sa.dshift[s] = s < k ? eps[order[s]] - eps[order[0]] : 0.0;
+  sa.xs = xs;
+  sa.ps = ps;
+  sa.sinfo = sinfo;
+  // the kernel indexes its rows with stride n_p
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  rc = launch_coop(fn, pl.pg.G, &sa, stream, pl.ke->nt, pl.ke->ring_bytes);
+  if (rc) return rc;
+  std::vector<double> hs(2 * kMaxShifts + 4);
+  uint32_t habort = 0;
+  HIP_TRY(hipMemcpyAsync(hs.data(), sinfo, hs.size() * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (habort != 0u || hs[2 * k + 1] == 0.0)
+    return fail(SR_ERR_TIMEOUT, "sr_cg_solve_shifts: a cross-workgroup wait timed out");
+  const int kstatus = (int)hs[2 * k];
+  const int launch_products = (int)hs[2 * k + 2];
+  // each shift: its solution into X, its true residual with the float64-accumulated single
+  // product, and, where the recurrence drifted past rtol, plain CG from it (warm start)
+  double gg = 0.0;
+  rc = lm_mdot(lb, g, ld, 1, g, n_p, &gg, stream);
+  if (rc) return rc;
+  int status = kstatus < 0 ? kstatus : SR_OK;
+  for (int s = 0; s < k && status >= 0; ++s) {
+    const int i = order[s];
+    double *xi = X + (int64_t)i * n_p;
+    HIP_TRY(hipMemcpyAsync(xi, xs + (int64_t)s * n_p, (size_t)n_p * 8, hipMemcpyDeviceToDevice, stream));
+    rc = sr_sv_product(&Om, xi, tmp, eps[i], stream);
+    if (rc) return rc;
+    const double m1 = -1.0, p1 = 1.0;
+    rc = lm_lincomb(g, &p1, 1, tmp, &m1, 1, ld, 0.0, tmp, n_p, stream);
+    if (rc) return rc;
+    double rr = 0.0;
+    rc = lm_mdot(lb, tmp, ld, 1, tmp, n_p, &rr, stream);
+    if (rc) return rc;
+    double rel = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
+    sr_cg_info ci{};
+    ci.iters = (int32_t)hs[2 * s];
+    ci.products = launch_products + 1;
+    ci.rel_res_recur = hs[2 * s + 1];
+    ci.rel_res_true = rel;
+    ci.status = SR_OK;
+    if (!(rel <= o.rtol)) {
+      sr_cg_opts po = o;
+      po.use_x0 = 1;
+      po.precond = 0;
+      po.refine = 0;
+      po.res_history = nullptr;
+      if (po.refresh_every == 0) po.refresh_every = 20;
+      sr_cg_info pi{};
+      const int prc = sr_cg_solve(&Om, g, eps[i], xi, &po, &pi, stream);
+      if (prc < 0) return prc;
+      ci.iters += pi.iters;
+      ci.refreshes = pi.refreshes;
+      ci.products += pi.products;
+      ci.rel_res_recur = pi.rel_res_recur;
+      ci.rel_res_true = pi.rel_res_true;
+      ci.status = prc;
+    }
+    if (info) info[i] = ci;
+    if (status == SR_OK && ci.status != SR_OK) status = ci.status;
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (status < 0) return fail(status, "sr_cg_solve_shifts: %s", sr_status_string(status));
   return status;
 }
 

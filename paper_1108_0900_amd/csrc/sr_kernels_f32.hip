@@ -1,5 +1,6 @@
 // Product, CG and linear-method kernels for DT_F32 storage.
 #include "sr_batch.hpp"
+#include "sr_shifts.hpp"
 
 namespace sr {
 
@@ -19,6 +20,15 @@ static const KernelEntry g_entries_f32[] = {SR_SR_CONFIGS_F32(SR_REG_SR) SR_LM_C
 static const BatchEntry g_batch_f32 = {(const void *)&k_cg_batched<DT_F32, kBatchNT>,
                                            (const void *)&k_svk<DT_F32, kBatchNT>, kBatchNT};
 const BatchEntry *batched_entry_f32() { return &g_batch_f32; }
+
+// Multi-shift CG, one kernel per SR tile configuration.
+#define SR_REG_SHIFT(NV, R, L, P, NT) {NV, R, L, P, NT, (const void *)&k_cg_shifts<DT_F32, NV, R, L, P, NT>},
+static const ShiftEntry g_shift_f32[] = {SR_SR_CONFIGS_F32(SR_REG_SHIFT)};
+const void *shift_kernel_f32(int nv, int r, int look, int poll, int nt) {
+  for (const ShiftEntry &e : g_shift_f32)
+    if (e.nv == nv && e.r == r && e.look == look && e.poll == poll && e.nt == nt) return e.fn;
+  return nullptr;
+}
 
 const KernelEntry *kernel_table_f32(int *count) {
   *count = (int)(sizeof(g_entries_f32) / sizeof(g_entries_f32[0]));

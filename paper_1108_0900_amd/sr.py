@@ -67,6 +67,8 @@ PROTOTYPES = {
     "sr_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
                                    ctypes.POINTER(SrCgInfo), _c_p]),
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
+    "sr_cg_solve_shifts": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_i32, _c_p, _c_p,
+                                          ctypes.POINTER(SrCgOpts), _c_p, _c_p]),
     "lm_davidson": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix),
                                    ctypes.POINTER(LmDavidsonOpts), _c_p, ctypes.POINTER(LmDavidsonInfo), _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
@@ -282,6 +284,32 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
            "lm_hv_product")
     return y
+
+
+def sr_cg_solve_shifts(M: Matrix, g: torch.Tensor, eps, rtol: float = 1e-10, max_iter: int = 0,
+                       refresh_every: int = 0,
+                       raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT),
+                       stream=None):
+    """Multi-shift CG (sr_cg_solve_shifts): X[i] = (S + eps[i] I)^{-1} g for k <= 8 shifts.
+    Returns (X (k, n_p), list of per-shift info dicts, status)."""
+    g = _vec(g, M.n_p, "g")
+    eps = [float(e) for e in eps]
+    k = len(eps)
+    X = torch.empty(k, M.n_p, dtype=torch.float64, device=g.device)
+    arr = (_c_d * max(k, 1))(*eps)
+    opts = SrCgOpts()
+    opts.rtol = float(rtol)
+    opts.max_iter = int(max_iter)
+    opts.refresh_every = int(refresh_every)
+    infos = (SrCgInfo * max(k, 1))()
+    m = M.c()
+    st = lib().sr_cg_solve_shifts(ctypes.byref(m), _ptr(g), k, arr, _ptr(X), ctypes.byref(opts), infos,
+                                  _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "sr_cg_solve_shifts")
+    out = [{"status": c.status, "iters": c.iters, "refreshes": c.refreshes, "products": c.products,
+            "rel_res_recur": c.rel_res_recur, "rel_res_true": c.rel_res_true} for c in infos[:k]]
+    return X, out, st
 
 
 def lm_davidson(M: Matrix, E: torch.Tensor, Dm: Matrix, tol: float = 1e-8, max_iter: int = 1000, max_sub: int = 40,

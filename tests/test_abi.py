@@ -142,6 +142,17 @@ def test_invalid_scalars_rejected():
                         None) == sr.SR_ERR_INVALID
     assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p(4096), sr.SR_F64, 4, None,
                         None) == sr.SR_ERR_INVALID          # overlaps v
+    # multi-shift CG
+    eps2 = (ctypes.c_double * 9)(*([0.1] * 9))
+    for kk in (0, 9):
+        assert L.sr_cg_solve_shifts(ctypes.byref(m), v, kk, eps2, y, None, None, None) == sr.SR_ERR_INVALID
+    eps2[1] = -1.0
+    assert L.sr_cg_solve_shifts(ctypes.byref(m), v, 2, eps2, y, None, None, None) == sr.SR_ERR_INVALID
+    eps2[1] = 0.1
+    mq2 = _mat(dtype=sr.SR_BF16, ld=8, scale=512)
+    assert L.sr_cg_solve_shifts(ctypes.byref(mq2), v, 2, eps2, y, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_cg_solve_shifts(ctypes.byref(m), v, 2, eps2, ctypes.c_void_p(4096 + 8), None, None,
+                                None) == sr.SR_ERR_INVALID       # X overlaps g
     # Davidson: options and required outputs
     dopt = sr.LmDavidsonOpts()
     dinf = sr.LmDavidsonInfo()

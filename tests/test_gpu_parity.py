@@ -466,3 +466,42 @@ def test_autotuner_selects_a_built_config_and_caches(tmp_path):
         assert res["best"] in sr.tile_configs(torch.float64, 1)
     finally:
         sr.set_tile_config()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=_dname)
+@pytest.mark.parametrize("shape", [(50, 9), (1500, 1200), (3000, 5000), (513, 12001)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_cg_shifts_match_cholesky(shape, dtype):
+    """Multi-shift CG: 8 shifts 1e-4..1e-1 of mean(diag S), given in scrambled order, from
+    one Krylov sequence; each solution against the dense solve of the stored system."""
+    n_s, n_p = shape
+    print(f"[cg-shifts] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=31 + n_p)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    dS = float(st["diag"].mean())
+    rel = list(10.0 ** np.linspace(-4, -1, 8))
+    eps = [dS * rel[i] for i in (3, 0, 7, 5, 1, 6, 2, 4)]
+    X, info, status = sr.sr_cg_solve_shifts(M, st["g"], eps, rtol=1e-11)
+    assert status == 0, info
+    g_ref = orc.energy_gradient(Os, E)
+    dS_ref = orc.diag_overlap(Os).mean()
+    for i, e in enumerate(eps):
+        assert info[i]["status"] == 0 and info[i]["rel_res_true"] <= 1e-11, info[i]
+        x_ref = orc.solve_dense(Os, g_ref, e / dS * dS_ref)
+        assert rel_err(to_np(X[i]), x_ref) <= 1e-8, (i, rel_err(to_np(X[i]), x_ref), info[i])
+    # the shared sequence: no shift needs more products than the smallest one
+    assert max(c["products"] for c in info) == info[1]["products"]
+
+
+def test_cg_shifts_single_shift_and_zero_rhs():
+    O, E = rand_dense(800, 300, seed=77)
+    M = device_matrix(O, torch.float64)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    X, info, status = sr.sr_cg_solve_shifts(M, st["g"], [0.05], rtol=1e-12)
+    assert status == 0
+    assert rel_err(to_np(X[0]), orc.solve_dense(O, orc.energy_gradient(O, E), 0.05)) <= 1e-9
+    X0, info0, status0 = sr.sr_cg_solve_shifts(M, torch.zeros_like(st["g"]), [0.1, 0.2], rtol=1e-12)
+    assert status0 == 0 and torch.count_nonzero(X0) == 0
