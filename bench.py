@@ -356,6 +356,10 @@ def measure_batched(args):
         if s_i % 8 == 7:
             log(f"[bench] batched workload: {s_i + 1} systems built")
     gb_o = [M.O.numel() * 4 / 1e9 for M, _, _ in systems]
+    # batched geometry tuned on the largest system (one geometry serves the launch)
+    from paper_1108_0900_amd import tune
+    big = max(range(len(systems)), key=lambda k: gb_o[k])
+    bt = tune.autotune(systems[big][0], kind=2, reps=3)
     sr.sr_cg_solve_batched(systems[:2], rtol=cfg.rtol, refresh_every=20)      # warm
     log("[bench] batched: one launch over all systems")
     (res, ms) = timed_events(lambda: sr.sr_cg_solve_batched(systems, rtol=cfg.rtol, refresh_every=20))
@@ -369,12 +373,13 @@ def measure_batched(args):
                        "to rel. true residual %g, refresh every 20" % (len(systems), cfg.rtol),
            "O_GB": round(sum(gb_o), 1), "launch_ms": round(ms, 1), "status": status,
            "column_solves": 8 * len(systems), "products": sum(prods), "worst_rel_res_true": worst,
-           "O_stream_GBps": round(passes_gb / ms * 1e3, 1)}
+           "O_stream_GBps": round(passes_gb / ms * 1e3, 1),
+           "tuned_geometry": {"split_rows_tasks": list(bt["best"]),
+                              "ms": {str(list(k)): round(v, 3) for k, v in bt["ms"].items()}}}
     del X
     # the same 8 columns of the first system: one batched launch vs 8 single solves (the
     # single-column product's tiles tuned on this matrix first)
     M, G, eps = systems[0]
-    from paper_1108_0900_amd import tune
     tune.autotune(M, kind=0, reps=3)
     (res1, ms1) = timed_events(lambda: sr.sr_cg_solve_batched([systems[0]], rtol=cfg.rtol, refresh_every=20))
     t_single = 0.0
@@ -405,7 +410,6 @@ def measure_batched(args):
                                       "all_ok": all(st_m == 0 for st_m in statuses),
                                       "worst_rel_res_true": worst_m}
     # the 8-column product alone on the largest system
-    big = max(range(len(systems)), key=lambda k: gb_o[k])
     Mb = systems[big][0]
     V = torch.randn(8, Mb.n_p, dtype=torch.float64, device=dev)
     sr.sr_svk_product(Mb, V, [0.1] * 8)

@@ -316,6 +316,12 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
  * SR_ERR_INVALID if no kernel of that type and kind has that configuration.
  * ------------------------------------------------------------------------------------ */
 int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max);
+/* Geometry of the batched products (sr_svk_product, sr_cg_solve_batched), process-wide:
+ * split_rows = the most rows per split of the update pass (a power of two in
+ * [128, 1024]; fewer rows give more, shorter tasks and more partial traffic), tasks = the
+ * tasks per workgroup aimed at when choosing column parts and splits (1..8).  (0, 0)
+ * restores the defaults (1024, 2).  Returns SR_ERR_INVALID otherwise. */
+int sr_set_batch_config(int32_t split_rows, int32_t tasks);
 int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
                        int32_t poll_delay, int32_t threads, int32_t col_groups);
 

@@ -94,6 +94,11 @@ struct DeviceInfo {
 };
 
 std::mutex g_mu;
+// Geometry of the batched products, tunable: the most rows per update split (a power of
+// two in [128, kBatchSplitRows]) and the tasks per workgroup aimed at in each pass (1..8);
+// set by sr_set_batch_config.
+int g_batch_split_rows = kBatchSplitRows;
+int g_batch_tasks = 2;
 std::map<int, DeviceInfo> g_dev;
 
 struct Workspace {
@@ -633,6 +638,21 @@ int sr_release(void) {
   return rc;
 }
 
+int sr_set_batch_config(int32_t split_rows, int32_t tasks) {
+  if (split_rows == 0 && tasks == 0) {
+    g_batch_split_rows = kBatchSplitRows;
+    g_batch_tasks = 2;
+    return SR_OK;
+  }
+  if (split_rows < 128 || split_rows > kBatchSplitRows || (split_rows & (split_rows - 1)) != 0)
+    return fail(SR_ERR_INVALID, "sr_set_batch_config: split_rows must be a power of two in [128, %d]",
+                kBatchSplitRows);
+  if (tasks < 1 || tasks > 8) return fail(SR_ERR_INVALID, "sr_set_batch_config: tasks must be in [1, 8]");
+  g_batch_split_rows = split_rows;
+  g_batch_tasks = tasks;
+  return SR_OK;
+}
+
 int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
                        int32_t poll_delay, int32_t threads, int32_t col_groups) {
   if (nv == 0 && dtype == -1) {
@@ -773,14 +793,15 @@ BatchGeom batch_geometry(int G, int64_t n_s, int64_t n_p, int vec) {
   g.n_p = n_p;
   const int nw = kBatchNT / 64;
   const int64_t cw = 64 * (int64_t)vec, bw = (int64_t)kBatchNT * vec;
+  const int64_t target = (int64_t)g_batch_tasks * G;
   g.n_rb = cdiv(n_s, (int64_t)nw * kBatchRows);
   const int64_t max_parts = std::max<int64_t>(1, cdiv(n_p, 4 * cw));   // parts of >= 4 chunks
-  const int64_t parts = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(2 * (int64_t)G, g.n_rb)));
+  const int64_t parts = std::min<int64_t>(max_parts, std::max<int64_t>(1, cdiv(target, g.n_rb)));
   g.pw = round_up(cdiv(n_p, parts), cw);
   g.P = (int)cdiv(n_p, g.pw);
   g.C = (int)cdiv(n_p, bw);
-  const int64_t sp = std::max<int64_t>(cdiv(n_s, kBatchSplitRows),
-                                       std::min<int64_t>(cdiv(2 * (int64_t)G, g.C), cdiv(n_s, 64)));
+  const int64_t sp = std::max<int64_t>(cdiv(n_s, g_batch_split_rows),
+                                       std::min<int64_t>(cdiv(target, g.C), cdiv(n_s, 64)));
   g.rs = cdiv(n_s, sp);
   g.SP = (int)cdiv(n_s, g.rs);
   return g;

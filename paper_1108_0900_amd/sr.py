@@ -69,6 +69,7 @@ PROTOTYPES = {
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
     "sr_cg_solve_shifts": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_i32, _c_p, _c_p,
                                           ctypes.POINTER(SrCgOpts), _c_p, _c_p]),
+    "sr_set_batch_config": (ctypes.c_int, [_c_i32, _c_i32]),
     "lm_davidson": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix),
                                    ctypes.POINTER(LmDavidsonOpts), _c_p, ctypes.POINTER(LmDavidsonInfo), _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
@@ -284,6 +285,14 @@ def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: 
     _check(lib().lm_hv_product(ctypes.byref(m), _ptr(E), ctypes.byref(d), _ptr(v), _ptr(y), _stream(stream)),
            "lm_hv_product")
     return y
+
+
+BATCH_CONFIGS = [(r, t) for r in (256, 512, 1024) for t in (1, 2, 4)]
+
+
+def set_batch_config(split_rows: int = 0, tasks: int = 0):
+    """Geometry of the batched products (sr_set_batch_config); no arguments: the defaults."""
+    _check(lib().sr_set_batch_config(int(split_rows), int(tasks)), "sr_set_batch_config")
 
 
 def sr_cg_solve_shifts(M: Matrix, g: torch.Tensor, eps, rtol: float = 1e-10, max_iter: int = 0,

@@ -8,6 +8,8 @@ configuration on the caller's own matrix with HIP events and selects the fastest
 that storage type and product kind, process-wide (`sr.set_tile_config`).  Results can
 be cached in a JSON file keyed by device, storage type, shape and product kind, so a
 later process reuses them without timing.  The CG solve uses the configuration of the SR product (kind 0).
+Kind 2 tunes the batched products' geometry (`sr.BATCH_CONFIGS`: rows per update split,
+tasks per workgroup) by timing the 8-column product on the caller's matrix.
 """
 from __future__ import annotations
 
@@ -63,14 +65,15 @@ def _median_ms(fn, reps: int, warm: int = 1) -> float:
 def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None = None,
              E: torch.Tensor | None = None, D: sr.Matrix | None = None, apply: bool = True) -> dict:
     """Time every built configuration of the product of `kind` (0: (S + eps I) v,
-    1: linear-method H v, which needs E and D) on M; select the fastest if `apply`.
+    1: linear-method H v, which needs E and D, 2: the 8-column batched product, whose
+    configurations are (split_rows, tasks)) on M; select the fastest if `apply`.
 
     Returns {"best": (nv, rows, lookahead, poll_depth, threads), "ms": {config: ms},
     "cached": bool}.  A configuration whose call fails (for example, one that cannot hold
     n_p columns) is skipped.  M's column means are computed first if missing.
     """
-    if kind not in (0, 1):
-        raise ValueError("kind must be 0 (SR product) or 1 (linear-method product)")
+    if kind not in (0, 1, 2):
+        raise ValueError("kind must be 0 (SR product), 1 (linear-method product) or 2 (batched products)")
     if kind == 1 and (E is None or D is None):
         raise ValueError("the linear-method product needs E and D")
     if M.lo is not None:
@@ -81,13 +84,32 @@ def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None 
     if key in table:
         best = tuple(table[key]["best"])
         if apply:
-            sr.set_tile_config(M.O.dtype, kind, *best)
+            if kind == 2:
+                sr.set_batch_config(*best)
+            else:
+                sr.set_tile_config(M.O.dtype, kind, *best)
         return {"best": best, "ms": {tuple(json.loads(k)): v for k, v in table[key]["ms"].items()}, "cached": True}
 
     if M.mean is None:
         M.mean = sr.sr_grad(M, None)["mean"]
     gen = torch.Generator(device=M.O.device)
     gen.manual_seed(0)
+    if kind == 2:
+        V = torch.randn(8, M.n_p, generator=gen, dtype=torch.float64, device=M.O.device)
+        Y = torch.empty_like(V)
+        times = {}
+        try:
+            for cfg in sr.BATCH_CONFIGS:
+                sr.set_batch_config(*cfg)
+                times[cfg] = _median_ms(lambda: sr.sr_svk_product(M, V, [0.1] * 8, out=Y), reps)
+        finally:
+            sr.set_batch_config()
+        best = min(times, key=times.get)
+        if apply:
+            sr.set_batch_config(*best)
+        table[key] = {"best": list(best), "ms": {json.dumps(list(k)): v for k, v in times.items()}}
+        _save(cache_path, table)
+        return {"best": best, "ms": times, "cached": False}
     n = M.n_p + (1 if kind == 1 else 0)
     v = torch.randn(n, generator=gen, dtype=torch.float64, device=M.O.device)
     y = torch.empty_like(v)

@@ -142,6 +142,11 @@ def test_invalid_scalars_rejected():
                         None) == sr.SR_ERR_INVALID
     assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p(4096), sr.SR_F64, 4, None,
                         None) == sr.SR_ERR_INVALID          # overlaps v
+    # batched geometry
+    for sr_rows, tasks in ((100, 2), (2048, 2), (512, 0), (512, 9)):
+        assert L.sr_set_batch_config(sr_rows, tasks) == sr.SR_ERR_INVALID
+    assert L.sr_set_batch_config(512, 4) == sr.SR_OK
+    assert L.sr_set_batch_config(0, 0) == sr.SR_OK
     # multi-shift CG
     eps2 = (ctypes.c_double * 9)(*([0.1] * 9))
     for kk in (0, 9):

@@ -79,6 +79,41 @@ def test_multi_rhs_product_wide_matches_single_products():
     del O, A
 
 
+@pytest.mark.parametrize("cfg", sr.BATCH_CONFIGS, ids=lambda c: f"split{c[0]}-tasks{c[1]}")
+def test_multi_rhs_product_every_batch_config(cfg):
+    """Every batched geometry the autotuner chooses from gives the oracle's product."""
+    n_s, n_p = 3000, 9001
+    O, _ = rand_dense(n_s, n_p, seed=5, offset=0.3)
+    M = device_matrix(O, torch.float32)
+    Os = stored_dense(O, torch.float32)
+    V = np.random.default_rng(6).standard_normal((8, n_p))
+    eps = [0.1 * (i + 1) for i in range(8)]
+    try:
+        sr.set_batch_config(*cfg)
+        Y = to_np(sr.sr_svk_product(M, to_dev(V), eps))
+    finally:
+        sr.set_batch_config()
+    for i in range(8):
+        ref = orc.sv_product_swapped(Os, V[i], eps[i])
+        mag = _mag(Os, V[i], eps[i])
+        assert np.all(np.abs(Y[i] - ref) <= 1e-12 * mag), (cfg, i)
+
+
+def test_batched_autotuner_selects_a_config(tmp_path):
+    from paper_1108_0900_amd import tune
+    O, _ = rand_dense(4000, 20000, seed=8)
+    M = device_matrix(O, torch.float32)
+    cache = str(tmp_path / "tiles.json")
+    try:
+        res = tune.autotune(M, kind=2, reps=2, cache_path=cache)
+        assert tuple(res["best"]) in sr.BATCH_CONFIGS and not res["cached"]
+        assert len(res["ms"]) == len(sr.BATCH_CONFIGS)
+        res2 = tune.autotune(M, kind=2, cache_path=cache)
+        assert res2["cached"] and tuple(res2["best"]) == tuple(res["best"])
+    finally:
+        sr.set_batch_config()
+
+
 def _batch_case(dtype, shapes, k, seed):
     systems, refs = [], []
     for s, (n_s, n_p) in enumerate(shapes):
