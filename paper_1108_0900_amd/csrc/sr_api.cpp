@@ -568,7 +568,7 @@ int lm_mdot(const LmBufs &b, const double *X, int64_t ld, int m, const double *w
   a.part = b.part;
   a.out = b.dots;
   void *args[] = {&a};
-  HIP_TRY(hipLaunchKernel(mdot_part_kernel(), dim3(b.nb), dim3(lm_threads()), args, 0, s));
+  HIP_TRY(hipLaunchKernel(mdot_part_kernel(), dim3(b.nb, m), dim3(lm_threads()), args, 0, s));
   HIP_TRY(hipLaunchKernel(mdot_final_kernel(), dim3(1), dim3(64), args, 0, s));
   HIP_TRY(hipMemcpyAsync(out_host, b.dots, (size_t)m * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));

@@ -8,23 +8,22 @@ namespace sr {
 
 constexpr int kLmNT = 256;
 
-// part[b][i] = sum over workgroup b's slice of j of X[i][j] * w[j], i < m.
+// part[b][i] = sum over workgroup (b, i)'s slice of j of X[i][j] * w[j]: one workgroup
+// row per dot (grid nb x m), so the m reductions run side by side.
 __global__ __launch_bounds__(kLmNT) void k_mdot_part(MdotArgs a) {
   const int64_t ch = (a.n + gridDim.x - 1) / gridDim.x;
   const int64_t j0 = min(a.n, (int64_t)blockIdx.x * ch), j1 = min(a.n, j0 + ch);
+  const int i = (int)blockIdx.y;
   __shared__ double s_w[kLmNT / 64];
-  for (int i = 0; i < a.m; ++i) {
-    double acc = 0.0;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += kLmNT) acc += a.X[i * a.ld + j] * a.w[j];
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int q = 0; q < kLmNT / 64; ++q) t += s_w[q];
-      a.part[(int64_t)blockIdx.x * a.m + i] = t;
-    }
-    __syncthreads();
+  double acc = 0.0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kLmNT) acc += a.X[i * a.ld + j] * a.w[j];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kLmNT / 64; ++q) t += s_w[q];
+    a.part[(int64_t)blockIdx.x * a.m + i] = t;
   }
 }
 
