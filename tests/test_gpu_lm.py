@@ -70,3 +70,12 @@ def test_davidson_scaled_storage(dtype):
     H, S = orc.lm_matrices(Os, E, Ds)
     ev, _ = orc.lm_lowest_eigenpair(H, S)
     assert abs(theta - ev) <= 1e-5 * abs(ev), (theta, ev, info)
+
+
+def test_davidson_deterministic():
+    O, E, D = _case(3000, 250, seed=13)
+    M, Md = device_matrix(O, torch.float64), device_matrix(D, torch.float64)
+    Et = torch.from_numpy(E).to(DEV)
+    t1, c1, i1 = sr.lm_davidson(M, Et, Md, tol=1e-9, max_sub=16, precond=2)
+    t2, c2, i2 = sr.lm_davidson(M, Et, Md, tol=1e-9, max_sub=16, precond=2)
+    assert t1 == t2 and torch.equal(c1, c2) and i1 == i2

@@ -505,3 +505,14 @@ def test_cg_shifts_single_shift_and_zero_rhs():
     assert rel_err(to_np(X[0]), orc.solve_dense(O, orc.energy_gradient(O, E), 0.05)) <= 1e-9
     X0, info0, status0 = sr.sr_cg_solve_shifts(M, torch.zeros_like(st["g"]), [0.1, 0.2], rtol=1e-12)
     assert status0 == 0 and torch.count_nonzero(X0) == 0
+
+
+def test_cg_shifts_deterministic():
+    O, E = rand_dense(2000, 1500, seed=78)
+    M = device_matrix(O, torch.float32)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = [1e-3, 1e-2, 5e-2]
+    X1, i1, s1 = sr.sr_cg_solve_shifts(M, st["g"], eps, rtol=1e-9)
+    X2, i2, s2 = sr.sr_cg_solve_shifts(M, st["g"], eps, rtol=1e-9)
+    assert s1 == s2 == 0 and torch.equal(X1, X2) and i1 == i2
