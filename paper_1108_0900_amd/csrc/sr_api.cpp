@@ -197,7 +197,7 @@ TileForce g_force[4][2] = {};
 int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg) {
   int64_t C = pow2_ceil(cdiv(n_p, cols_per_wg));
   if (force_c > 0 && force_c >= C) C = force_c;
-  if (C > G) return fail(SR_ERR_INVALID, "n_p = %lld exceeds the column capacity of this build (%lld)",
+  if (C > G) return fail(SR_ERR_INVALID, "n_p = %lld exceeds the column capacity of the built tiles (%lld)",
                          (long long)n_p, (long long)G * cols_per_wg);
   pg->G = G;
   pg->C = (int)C;
