@@ -39,6 +39,7 @@ Functions and the passage each follows:
   lm_matrices, lm_hv_dense ............... Sec. II.B, Eq. linear_eigen (H and S in Omega)
   lm_lowest_eigenpair .................... Sec. II.B, Eq. linear_eigen (dense generalized solve)
   quantize_bf16/_f16/_split, dequantize_* . precision form of the stored ratios (not in the paper)
+  quantize_cols, dequantize_cols ......... remainder codes kept only for the columns that need them
   solve_adjoint_gradients ................ implicit-adjoint derivative of the solve (not in the paper)
 
 Every function is pinned by the CPU tests against something other than itself
@@ -55,7 +56,8 @@ __all__ = [
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
     "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense", "lm_hv_swapped",
     "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
-    "quantize_split", "dequantize_split", "solve_adjoint_gradients",
+    "quantize_split", "dequantize_split", "quantize_cols", "dequantize_cols", "REMAINDER_TOL",
+    "solve_adjoint_gradients",
 ]
 
 
@@ -362,6 +364,46 @@ def dequantize_split(q_hi, q_lo, s, code: str = "bf16") -> np.ndarray:
     else:
         v = (np.asarray(q_hi, dtype=np.uint16).view(np.float16).astype(np.float64)
              + np.asarray(q_lo, dtype=np.uint16).view(np.float16).astype(np.float64))
+    return v * np.asarray(s, dtype=np.float32).astype(np.float64)[None, :]
+
+
+# Default selection bound of quantize_cols: the error bound of the two-plane codes relative
+# to the column scale (bf16: the remainder is at most 2^-9 and its nearest bf16 code is
+# within 2^-18 of it; f16: remainder at most 2^-12, code within 2^-22 even in the subnormal
+# range of the remainder), with one bit of slack.
+REMAINDER_TOL = {"bf16": 2.0 ** -17, "f16": 2.0 ** -21}
+
+
+def quantize_cols(O, code: str = "bf16", tol: float | None = None):
+    """Codes with the remainder plane kept only where it is needed.
+
+    q_hi and s are those of quantize_bf16 / quantize_f16.  Column j gets a remainder code
+    (the nearest code of O_kj / s_j - q_hi_kj, as in quantize_split) iff its single-plane
+    error max_k |O_kj / s_j - q_hi_kj| (in float64) exceeds `tol` (default REMAINDER_TOL), so
+    that every stored value is within max(tol, two-plane bound) s_j of O_kj.
+    Returns (q_hi, s, lo_cols, q_lo): lo_cols the selected columns in increasing order
+    (int64), q_lo their remainder codes, shape (n_s, len(lo_cols))."""
+    O = np.asarray(O, dtype=np.float64)
+    tol = REMAINDER_TOL[code] if tol is None else float(tol)
+    q_hi, q_lo_full, s = quantize_split(O, code)
+    t = O / s.astype(np.float64)[None, :]
+    hi = _bf16_bits_to_f64(q_hi) if code == "bf16" else q_hi.view(np.float16).astype(np.float64)
+    err = np.abs(t - hi).max(axis=0) if O.shape[0] else np.zeros(O.shape[1])
+    lo_cols = np.nonzero(err > tol)[0].astype(np.int64)
+    return q_hi, s, lo_cols, np.ascontiguousarray(q_lo_full[:, lo_cols])
+
+
+def dequantize_cols(q_hi, s, lo_cols, q_lo, code: str = "bf16") -> np.ndarray:
+    """Stored values of quantize_cols: s_j (q_hi_kj + q_lo_kj) for the columns j in lo_cols
+    (the sum taken in float64), s_j q_hi_kj for the others."""
+    if code == "bf16":
+        v = _bf16_bits_to_f64(q_hi)
+        lo = _bf16_bits_to_f64(q_lo)
+    else:
+        v = np.asarray(q_hi, dtype=np.uint16).view(np.float16).astype(np.float64)
+        lo = np.asarray(q_lo, dtype=np.uint16).view(np.float16).astype(np.float64)
+    v = v.copy()
+    v[:, np.asarray(lo_cols, dtype=np.int64)] += lo
     return v * np.asarray(s, dtype=np.float32).astype(np.float64)[None, :]
 
 

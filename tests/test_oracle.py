@@ -233,8 +233,48 @@ def test_paper_system_projection_exact_enumeration():
     target = P0 - tau * (H @ P0)
     resid = target - basis @ x
     assert np.abs(basis.T @ resid).max() < 1e-12 * np.abs(target).max()
-    # the update alpha' = alpha + x_i / x_0
-    np.testing.assert_allclose(orc.sr_update(alpha, x), alpha + x[1:] / x[0], rtol=1e-15)
+
+
+def test_sr_update_linear_ansatz_reproduces_projection():
+    """For a wavefunction linear in its parameters, Psi(alpha) = psi0 + B alpha, the
+    projected vector sum_j x_j Psi^j of Eq. sr_lin_eq equals x_0 Psi(alpha') exactly,
+    with alpha' = alpha + x_i / x_0 (Sec. II.A): the update moves Psi to the projection."""
+    rng = np.random.default_rng(90)
+    M, P = 9, 4
+    A = rng.standard_normal((M, M))
+    H = 0.5 * (A + A.T)
+    psi0 = 1.0 + rng.random(M)
+    B = 0.3 * rng.standard_normal((M, P))
+    alpha = np.array([0.2, -0.1, 0.05, 0.3])
+    P0 = psi0 + B @ alpha
+    O = B / P0[:, None]
+    E = (H @ P0) / P0
+    w = P0 ** 2 / (P0 @ P0)
+    for tau in (0.01, 0.2):
+        Asys, b = orc.paper_linear_system(O, E, tau, w)
+        x = np.linalg.solve(Asys, b)
+        projected = x[0] * P0 + B @ x[1:]
+        a_new = orc.sr_update(alpha, x)
+        np.testing.assert_allclose(x[0] * (psi0 + B @ a_new), projected, rtol=1e-12, atol=1e-13)
+        # and the projection is the least-squares fit of (1 - tau H) Psi in the span
+        basis = np.concatenate([P0[:, None], B], axis=1)
+        c = np.linalg.lstsq(basis, P0 - tau * (H @ P0), rcond=None)[0]
+        np.testing.assert_allclose(projected, basis @ c, rtol=1e-10, atol=1e-12)
+
+
+def test_lm_eigenvector_is_the_ground_state_when_complete():
+    """With Omega spanning the whole space, the lowest LM eigenvector c gives the exact
+    ground state: sum_i c_i Psi_bar^i is proportional to the lowest eigenvector of H."""
+    H, psi, dpsi = _tiny_space(M=4, P=3, seed=5)
+    alpha = np.array([0.1, 0.2, -0.1])
+    O, E, D, w = _sampled_from_enumeration(H, psi, dpsi, alpha)
+    _, c = orc.lm_lowest_eigenpair(*orc.lm_matrices(O, E, D, w))
+    P0, dP = psi(alpha), dpsi(alpha)
+    bar = dP - np.outer(P0, (P0 @ dP) / (P0 @ P0))
+    phi = np.concatenate([P0[:, None], bar], axis=1) @ c
+    gs = np.linalg.eigh(H)[1][:, 0]
+    cosang = abs(phi @ gs) / np.linalg.norm(phi)
+    assert cosang == pytest.approx(1.0, abs=1e-12)
 
 
 def test_centred_system_equals_paper_system():
@@ -443,6 +483,54 @@ def test_quantize_split_two_planes():
             rem = O[k, j] / float(s[j]) - deq_hi[k, j] / float(s[j])
             assert (deq[k, j] - deq_hi[k, j]) / float(s[j]) == nearest(rem)
         assert np.all(lo[:, 2] == 0)
+
+
+def test_quantize_cols_selects_exactly_the_columns_that_need_a_remainder():
+    """Compact remainder plane on a CPS-shaped matrix with dense pairing columns: the CPS
+    columns hold one value per column (1/c), so their single-plane codes are exact up to the
+    float32 rounding of the scale (2^-24) and need no remainder; the dense columns do.  The
+    stored values then meet the two-plane error bound everywhere."""
+    d = synth.small_cps_inputs(seed=8, n_s=400, n_corr=3, n_states=8, n_dense=7)
+    O = d["O"].numpy()
+    n_sparse = 24
+    for code, nearest, bound in (("bf16", _nearest_bf16_fraction, 2.0 ** -17),
+                                 ("f16", _nearest_f16_fraction, 2.0 ** -21)):
+        q_hi, s, lo_cols, q_lo = orc.quantize_cols(O, code)
+        assert np.array_equal(lo_cols, np.arange(n_sparse, O.shape[1]))
+        assert q_lo.shape == (O.shape[0], O.shape[1] - n_sparse)
+        deq = orc.dequantize_cols(q_hi, s, lo_cols, q_lo, code)
+        assert np.all(np.abs(deq - O) <= bound * s.astype(np.float64)[None, :])
+        # every selected column's single-plane error exceeds the bound (computed entry by
+        # entry with exact rational rounding), every other column's stays within it
+        for j in range(O.shape[1]):
+            err = max(abs(O[k, j] / float(s[j]) - nearest(O[k, j] / float(s[j]))) for k in range(0, O.shape[0], 7))
+            if j < n_sparse:
+                assert err <= 2.0 ** -23, (code, j, err)
+            else:
+                assert err > bound, (code, j, err)
+        # the remainder codes are the nearest codes of the remainder
+        for (k, jj) in [(0, 0), (13, 2), (399, 6)]:
+            j = int(lo_cols[jj])
+            hi = nearest(O[k, j] / float(s[j]))
+            rem = O[k, j] / float(s[j]) - hi
+            assert (deq[k, j] / float(s[j])) - hi == nearest(rem)
+
+
+def test_quantize_cols_limits_equal_one_and_two_planes():
+    """tol < 0 keeps a remainder for every column (the two-plane values); tol = inf for none
+    (the single-plane values)."""
+    rng = np.random.default_rng(24)
+    O = rng.standard_normal((30, 9)) * np.exp(rng.standard_normal(9))
+    O[:, 4] = 0.0
+    for code in ("bf16", "f16"):
+        q_hi, s, cols, q_lo = orc.quantize_cols(O, code, tol=-1.0)
+        assert np.array_equal(cols, np.arange(9))
+        np.testing.assert_array_equal(orc.dequantize_cols(q_hi, s, cols, q_lo, code),
+                                      orc.dequantize_split(*orc.quantize_split(O, code), code))
+        q_hi, s, cols, q_lo = orc.quantize_cols(O, code, tol=np.inf)
+        assert cols.size == 0 and q_lo.shape == (30, 0)
+        one = orc.dequantize_bf16(*orc.quantize_bf16(O)) if code == "bf16" else orc.dequantize_f16(*orc.quantize_f16(O))
+        np.testing.assert_array_equal(orc.dequantize_cols(q_hi, s, cols, q_lo, code), one)
 
 
 # ------------------------------------------------------------------------------------------
