@@ -47,18 +47,20 @@ def elem_bytes(dt):
     return {torch.float64: 8, torch.float32: 4, torch.bfloat16: 2, torch.float16: 2}[dt]
 
 
-def product_bytes(n_s, n_p, dt, scaled, planes=1):
-    """Algorithmic bytes of one product: one read of each code plane of O plus the O(N_p)
-    vectors (scale, column mean, v, y)."""
-    return planes * n_s * n_p * elem_bytes(dt) + n_p * ((4 if scaled else 0) + 3 * 8)
+def product_bytes(n_s, n_p, dt, scaled):
+    """Algorithmic bytes of one product: one read of O in its storage type plus the O(N_p)
+    vectors (scale, column mean, v, y) and the N_s row weights."""
+    return n_s * n_p * elem_bytes(dt) + n_p * ((4 if scaled else 0) + 3 * 8) + n_s * 8
 
 
-def grad_bytes(n_s, n_p, dt, scaled, planes=1):
-    return planes * n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
+def grad_bytes(n_s, n_p, dt, scaled):
+    """Algorithmic bytes of the prepare pass: one read of O and E, the O(N_p) outputs."""
+    return n_s * n_p * elem_bytes(dt) + n_s * 8 + n_p * ((4 if scaled else 0) + 3 * 8)
 
 
 KERNEL_SOURCES = ("sr_device.hpp", "sr_product.hpp", "sr_kernels.hpp", "sr_launch.hpp", "sr_kernels_bf16.hip")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_bf16x2_cps500k_traffic.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_bf16_compact_cps500k_traffic.md")
+TRAFFIC_KERNEL = "void sr::k_cg<2, 2, 2, 1, 1, 512, 0>(sr::CgArgs)"
 
 
 def kernel_source_hash():
@@ -109,6 +111,46 @@ def timed_events(fn):
     return out, e0.elapsed_time(e1)
 
 
+def host_facts():
+    """The host the CPU baseline ran on: usable cores, CPU model, BLAS threads."""
+    import platform
+    facts = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count(),
+             "cpu_count": os.cpu_count(), "machine": platform.machine()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                facts["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_info
+        facts["blas"] = [{"api": i.get("internal_api"), "threads": i.get("num_threads")} for i in threadpool_info()]
+    except Exception:
+        pass
+    return facts
+
+
+def cpu_cg_timing(O_dev, E_dev, eps_rel, eps_abs, iters, gpu_products, name):
+    """The oracle's matrix-free CG (two products with the stored O per iteration, float64,
+    numpy/OpenBLAS) on the whole matrix of a workload, run for `iters` iterations; the
+    full solve is estimated as the time per product times the GPU solve's product count."""
+    import numpy as np
+    import oracle as orc
+    O = O_dev.double().cpu().numpy()
+    E = E_dev.cpu().numpy()
+    g = orc.energy_gradient(O, E)
+    eps = eps_abs if eps_abs is not None else eps_rel * float(orc.diag_overlap(O).mean())
+    t0 = time.perf_counter()
+    _, it, _ = orc.cg_solve(lambda u: orc.sv_product_swapped(O, u, eps), g, rtol=1e-300, max_iter=iters)
+    t = time.perf_counter() - t0
+    per = t / max(it, 1)
+    del O
+    return {"workload": name, "iterations_timed": it, "s_per_iteration": round(per, 4),
+            "gpu_products": gpu_products, "estimated_solve_s": round(per * gpu_products, 2),
+            "method": "oracle cg_solve with sv_product_swapped (float64, numpy/OpenBLAS)"}
+
+
 def cpu_baseline(O_dev, n_rows, eps, budget_s=15.0):
     """The oracle's matrix-free product (sv_product_swapped) on the first n_rows rows."""
     import numpy as np
@@ -132,7 +174,8 @@ def cpu_baseline(O_dev, n_rows, eps, budget_s=15.0):
     gbps = product_bytes(n_rows, n_p, __import__("torch").float64, False) / t / 1e9
     return {"value": round(gbps, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
             "sample": f"oracle sv_product_swapped (float64, numpy/OpenBLAS) on the first {n_rows} rows x {n_p} "
-                      f"columns of the same matrix, {reps} repetitions, {t * 1e3:.1f} ms each"}
+                      f"columns of the same matrix, {reps} repetitions, {t * 1e3:.1f} ms each",
+            "host": host_facts()}
 
 
 def main():
@@ -146,8 +189,10 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 comparison solve")
     ap.add_argument("--one-plane", action="store_true",
                     help="time the single-plane bf16 solve (no quantisation-remainder plane)")
-    ap.add_argument("--refine", action="store_true",
-                    help="search-direction products read the first plane only (iterative refinement)")
+    ap.add_argument("--two-planes", action="store_true",
+                    help="time the solve over a full remainder plane (default: compact remainder plane)")
+    ap.add_argument("--search-f64", action="store_true",
+                    help="bf16 search-direction products accumulate in float64 too")
     ap.add_argument("--refresh-drop", type=float, default=None)
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -181,12 +226,17 @@ def main():
         out["other_configs"], dense_case = measure_other_configs(args)
         if out["cpu_baseline"] is not None:
             out["cpu_baseline"]["dense_solve"] = cpu_baseline_dense(*dense_case)
+    if out["cpu_baseline"] is not None:
+        cg = [c for c in ((out.get("other_configs") or {}).pop("_cpu_cg", []) +
+                          [(out.get("adjoint") or {}).pop("_cpu_cg", None)]) if c]
+        out["cpu_baseline"]["cg_solves"] = cg
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline_dense(O, E, x_gpu):
+def cpu_baseline_dense(O, E, x_gpu, x_gpu_tight):
     """The oracle's dense solve (explicit S, Cholesky, float64 on the host cores) of the
-    dense 8192 x 4000 workload, and the GPU solution's error against it."""
+    dense 8192 x 4000 workload, and the GPU solutions' errors against it (CG to the
+    workload's 1e-10 and to 1e-13)."""
     import numpy as np
     import oracle as orc
     t0 = time.perf_counter()
@@ -194,7 +244,8 @@ def cpu_baseline_dense(O, E, x_gpu):
     t = time.perf_counter() - t0
     return {"workload": "dense float64 O 8192 x 4000, eps = 1e-3 mean(diag S)", "kind": "oracle",
             "method": "form S, Cholesky (numpy/OpenBLAS)", "seconds": round(t, 3),
-            "gpu_cg_err_vs_oracle": float(np.linalg.norm(x_gpu - x_ref) / np.linalg.norm(x_ref))}
+            "gpu_cg_err_vs_oracle": float(np.linalg.norm(x_gpu - x_ref) / np.linalg.norm(x_ref)),
+            "gpu_cg_rtol_1e-13_err_vs_oracle": float(np.linalg.norm(x_gpu_tight - x_ref) / np.linalg.norm(x_ref))}
 
 
 def measure_other_configs(args):
@@ -225,15 +276,18 @@ def measure_other_configs(args):
             raise RuntimeError(f"CG did not converge: {info}")
         return x, info, ms, eps
     x, info, ms, eps = solve(M, cfg.rtol)
+    xt, infot, mst, _ = solve(M, 1e-13)
     xj, infoj, msj, _ = solve(M, cfg.rtol, True)
     pb = product_bytes(n_s, n_p, torch.float64, False)
     c1 = {"workload": "dense float64 O 8192 x 4000 N(0,1) x lognormal(0, 0.5), eps = 1e-3 mean(diag S), CG to 1e-10",
           "cg_ms": round(ms, 2), "iters": info["iters"], "products": info["products"],
           "GBps": round(info["products"] * pb / ms / 1e6, 1),
+          "rtol_1e-13": {"cg_ms": round(mst, 2), "iters": infot["iters"], "products": infot["products"]},
           "jacobi": {"cg_ms": round(msj, 2), "iters": infoj["iters"], "products": infoj["products"],
                      "x_rel_diff_vs_plain": float(torch.linalg.vector_norm(xj - x) / torch.linalg.vector_norm(x))}}
     res["dense_8192x4000_f64"] = c1
-    dense_case = (O.cpu().numpy(), E.cpu().numpy(), x.cpu().numpy())
+    dense_case = (O.cpu().numpy(), E.cpu().numpy(), x.cpu().numpy(), xt.cpu().numpy())
+    res["_cpu_cg"] = [cpu_cg_timing(O, E, 1e-3, None, 20, info["products"], "dense float64 O 8192 x 4000, CG to 1e-10")]
     # the linear method on the same samples: D = 0.1 N(0,1) s_j, lowest eigenpair of
     # H c = theta S c by generalized Davidson (one H and one S product per iteration), and
     # the H product alone
@@ -275,6 +329,9 @@ def measure_other_configs(args):
         xs[name] = x
         out2[name] = {"cg_ms": round(ms, 2), "iters": info["iters"], "products": info["products"],
                       "GBps": round(info["products"] * product_bytes(n_s, n_p, dt, False) / ms / 1e6, 1)}
+        if name == "f64":
+            res["_cpu_cg"].append(cpu_cg_timing(O64, E, 1e-3, None, 2, info["products"],
+                                                "CPS-shaped float64 O 65536 x 24512, CG to 1e-8"))
         del M, Ot
     out2["f32_err_vs_f64"] = float(torch.linalg.vector_norm(xs["f32"] - xs["f64"]) /
                                    torch.linalg.vector_norm(xs["f64"]))
@@ -328,7 +385,10 @@ def measure_adjoint(args):
                       "forward_products": info_xj["products"], "adjoint_cg_products": info_lj["products"],
                       "x_rel_diff_vs_plain": float(torch.linalg.vector_norm(x_jac - x_plain) /
                                                    torch.linalg.vector_norm(x_plain))},
-           "sr_adjoint_ms": round(ts[2], 3), "sr_adjoint_GBps": round(gb / ts[2] * 1e3, 1)}
+           "sr_adjoint_ms": round(ts[2], 3), "sr_adjoint_GBps": round(gb / ts[2] * 1e3, 1),
+           "_cpu_cg": None if args.quick else cpu_cg_timing(O, E, None, cfg.eps_abs, 5, info_x["products"],
+                                                            "dense float32 O 16384 x 16384 (float64 on the host), "
+                                                            "eps = 1e-3, CG to 1e-9")}
     log(f"[bench] adjoint: {out}")
     return out
 
@@ -424,6 +484,24 @@ def measure_batched(args):
     return out
 
 
+def measure_stream_ceiling(T, reps=3):
+    """Streaming-read ceiling: sr_stream_read over the tensor T (the products' own loads),
+    every built unroll and 1, 2, 4 workgroups per CU; the fastest setting's median GB/s."""
+    import torch
+    from paper_1108_0900_amd import sr
+    nbytes = (T.numel() * T.element_size()) // 16 * 16
+    out = {}
+    for bpc in (1, 2, 4):
+        for unroll in (2, 4, 8):
+            sr.stream_read(T, bpc, unroll)
+            ts = sorted(timed_events(lambda: sr.stream_read(T, bpc, unroll))[1] for _ in range(reps))
+            out[f"{bpc}x{unroll}"] = round(nbytes / ts[len(ts) // 2] / 1e6, 1)
+    best = max(out, key=out.get)
+    return {"GBps": out[best], "frac": round(out[best] / HBM_PEAK_GBPS, 4), "bytes": nbytes,
+            "setting_blocks_per_cu_x_unroll": best, "all": out,
+            "kernel": "k_stream_read (sr_stream_read): non-temporal 16-byte loads, grid-stride"}
+
+
 def measure_single(args):
     import torch
     from paper_1108_0900_amd import sr
@@ -433,26 +511,43 @@ def measure_single(args):
     O64, E = d["O"], d["E"]
     n_s, n_p = O64.shape
     refresh = cfg.refresh_every or 20
+    del d
 
     # ---- storage forms ----
     scaled = args.config == "cps_32768x500000"
-    planes, search_planes = 1, 1
+    form = "plain"
+    n_lo = 0
     if scaled:
-        q, s, lo = sr.sr_quantize(O64, out_dtype=torch.bfloat16, with_lo=True)
-        torch.cuda.synchronize()
+        form = "one_plane" if args.one_plane else ("two_planes" if args.two_planes else "compact")
+        q, s = sr.sr_quantize(O64, out_dtype=torch.bfloat16)
         M1 = sr.as_matrix(q, scale=s)                 # first code plane only
-        M2 = sr.as_matrix(q, scale=s, lo=lo)          # both planes (quantisation remainder)
-        Mt = M1 if args.one_plane else M2
-        planes = 1 if args.one_plane else 2
-        search_planes = 1 if (args.one_plane or args.refine) else 2
+        if form == "compact":
+            cols = sr.sr_remainder_columns(O64, s, torch.bfloat16)
+            lo = sr.sr_quantize_remainder(O64, s, cols, torch.bfloat16)
+            Mt = sr.as_matrix(q, scale=s, lo=lo, lo_cols=cols)
+            n_lo = int(cols.numel())
+        elif form == "two_planes":
+            _, _, lo = sr.sr_quantize(O64, out_dtype=torch.bfloat16, with_lo=True)
+            Mt = sr.as_matrix(q, scale=s, lo=lo)
+        else:
+            Mt = M1
+        torch.cuda.synchronize()
         dt_t, dtype_name = torch.bfloat16, "bf16"
-        default_rtol = 1e-7 if args.refine else 1e-6
+        default_rtol = 1e-6
         rtol = args.rtol if args.rtol is not None else default_rtol
     else:
         Mt = sr.as_matrix(O64)
         dt_t, dtype_name = O64.dtype, {torch.float64: "f64", torch.float32: "f32"}[O64.dtype]
         rtol = args.rtol if args.rtol is not None else cfg.rtol
     M64 = sr.as_matrix(O64)
+    eb = elem_bytes(dt_t)
+
+    # bytes of one product: the algorithmic count reads one plane of O (plus the O(N_p)
+    # vectors); the streamed count adds what the storage form reads besides (the
+    # remainder plane's columns)
+    alg_pb = product_bytes(n_s, n_p, dt_t, scaled)
+    extra_search = {"compact": n_s * n_lo * eb, "two_planes": n_s * n_p * eb}.get(form, 0)
+    extra_res = {"compact": n_s * n_lo * eb, "two_planes": n_s * n_p * eb}.get(form, 0)
 
     # ---- tile autotuning (not timed): every built configuration on these matrices ----
     from paper_1108_0900_amd import tune
@@ -463,25 +558,22 @@ def measure_single(args):
         res = tune.autotune(M, kind=0, reps=3)
         tiles[name] = {"best": list(res["best"]), "ms": {str(list(k)): round(v, 3) for k, v in res["ms"].items()}}
         log(f"[bench] tuned {name}: {res['best']}  {tiles[name]['ms']}")
-    drop = args.refresh_drop if args.refresh_drop is not None else (0.1 if args.refine else 0.0)
-    m_refresh = 0 if (args.refine and args.refresh_drop is None) else refresh
+    drop = args.refresh_drop if args.refresh_drop is not None else 0.0
 
-    def step(M, tol, refine=False):
+    def step(M, tol, search_f64=False):
         st = sr.sr_grad(M, E)
         M.mean = st["mean"]
         eps = 1e-3 * float(st["diag"].mean()) if cfg.eps_abs is None else cfg.eps_abs
-        kw = dict(refine=True, refresh_drop=drop, refresh_every=m_refresh) if refine else dict(refresh_every=refresh)
+        kw = dict(refresh_every=refresh, refresh_drop=drop, search_f64=search_f64)
         (x, info), ms_cg = timed_events(lambda: sr.sr_cg_solve(M, st["g"], eps, rtol=tol, **kw))
         if info["status"] != 0:
             raise RuntimeError(f"CG did not converge: {info}")
         return x, info, ms_cg, eps
 
-    def solve_summary(info, ms, tol, planes_s, planes_r, dt):
-        it = info["iters"]
-        by = it * product_bytes(n_s, n_p, dt, dt in (torch.bfloat16, torch.float16), planes_s) + \
-            (info["products"] - it) * product_bytes(n_s, n_p, dt, dt in (torch.bfloat16, torch.float16), planes_r)
-        return {"solve_ms": round(ms, 3), "iters": it, "products": info["products"],
-                "rel_res_true": info["rel_res_true"], "rtol": tol, "GBps": round(by / ms / 1e6, 1)}
+    def solve_summary(info, ms, tol, dt):
+        pb = product_bytes(n_s, n_p, dt, dt in (torch.bfloat16, torch.float16))
+        return {"solve_ms": round(ms, 3), "iters": info["iters"], "products": info["products"],
+                "rel_res_true": info["rel_res_true"], "rtol": tol, "GBps": round(info["products"] * pb / ms / 1e6, 1)}
 
     # ---- float64 solves of the same matrix (reference solution and time-to-accuracy) ----
     f64 = None
@@ -491,8 +583,8 @@ def measure_single(args):
         step(M64, 1e-10)      # warm
         x64, info64, ms64, _ = step(M64, 1e-10)
         xr, infor, msr, _ = step(M64, rtol)
-        f64 = {"reference": solve_summary(info64, ms64, 1e-10, 1, 1, torch.float64),
-               "same_rtol": solve_summary(infor, msr, rtol, 1, 1, torch.float64)}
+        f64 = {"reference": solve_summary(info64, ms64, 1e-10, torch.float64),
+               "same_rtol": solve_summary(infor, msr, rtol, torch.float64)}
         f64["same_rtol"]["err_vs_reference"] = float(torch.linalg.vector_norm(xr - x64) /
                                                      torch.linalg.vector_norm(x64))
         del xr
@@ -500,7 +592,7 @@ def measure_single(args):
 
     # ---- single-plane bf16 solve, for its error against float64 (not timed as a step) ----
     err_one_plane = None
-    if scaled and planes == 2 and x64 is not None:
+    if scaled and form != "one_plane" and x64 is not None:
         x1, info1, _, _ = step(M1, rtol)
         err_one_plane = float(torch.linalg.vector_norm(x1 - x64) / torch.linalg.vector_norm(x64))
         log(f"[bench] one-plane bf16 solve: {info1}, err vs f64 {err_one_plane:.3e}")
@@ -509,32 +601,31 @@ def measure_single(args):
     # ---- timed steps ----
     log(f"[bench] warmup {args.warmup} step(s)")
     for _ in range(args.warmup):
-        step(Mt, rtol, args.refine)
+        step(Mt, rtol, args.search_f64)
     torch.cuda.synchronize()
     cg_ms, infos = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x, info, ms_cg, eps = step(Mt, rtol, args.refine)
+        x, info, ms_cg, eps = step(Mt, rtol, args.search_f64)
         cg_ms.append(ms_cg)
         infos.append(info)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     ms_per_step = wall_ms / args.steps
     products = sum(i["products"] for i in infos) / len(infos)
-    # search-direction products read search_planes code planes; residual products
-    # (refreshes, exit checks) read every plane.  A converged solve makes one search
-    # product per iteration.
+    # a converged solve makes one search-direction product per iteration; the others are
+    # residual products (refreshes, exit checks)
     searches = sum(i["iters"] for i in infos) / len(infos)
     residuals = products - searches
-    pb = product_bytes(n_s, n_p, dt_t, scaled, search_planes)
-    pb_res = product_bytes(n_s, n_p, dt_t, scaled, planes)
-    cg_bytes = searches * pb + residuals * pb_res
-    step_bytes = grad_bytes(n_s, n_p, dt_t, scaled, planes) + cg_bytes
+    cg_alg_bytes = products * alg_pb
+    cg_streamed_bytes = cg_alg_bytes + searches * extra_search + residuals * extra_res
+    step_bytes = grad_bytes(n_s, n_p, dt_t, scaled) + cg_alg_bytes
     value = step_bytes / (ms_per_step * 1e6)
     cg_avg = sum(cg_ms) / len(cg_ms)
-    achieved = cg_bytes / (cg_avg * 1e6)
-    log(f"[bench] {dtype_name}: {ms_per_step:.2f} ms/step, CG {cg_avg:.2f} ms, products {products}, "
-        f"{value:.0f} GB/s step, {achieved:.0f} GB/s CG")
+    achieved = cg_alg_bytes / (cg_avg * 1e6)
+    streamed = cg_streamed_bytes / (cg_avg * 1e6)
+    log(f"[bench] {dtype_name} {form}: {ms_per_step:.2f} ms/step, CG {cg_avg:.2f} ms, products {products}, "
+        f"{value:.0f} GB/s step, {achieved:.0f} GB/s CG (algorithmic), {streamed:.0f} GB/s streamed")
 
     # ---- standalone product timing ----
     def sv_time(M, reps=5):
@@ -548,6 +639,7 @@ def measure_single(args):
         ts.sort()
         return ts[len(ts) // 2]
     sv = {}
+    ceiling = None
     if args.copy_gb > 0:
         nbytes = int(args.copy_gb * 1e9) // 16 * 16
         src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -560,19 +652,21 @@ def measure_single(args):
     if args.quick:
         sv = None
     else:
-        ms_t = sv_time(M1 if scaled else Mt)
-        pb1 = product_bytes(n_s, n_p, dt_t, scaled)
-        sv[dtype_name] = {"ms": round(ms_t, 3), "GBps": round(pb1 / ms_t / 1e6, 1),
-                          "frac": round(pb1 / ms_t / 1e6 / HBM_PEAK_GBPS, 4)}
+        def rec(ms, alg, streamed_b=None):
+            r = {"ms": round(ms, 3), "GBps": round(alg / ms / 1e6, 1), "frac": round(alg / ms / 1e6 / HBM_PEAK_GBPS, 4)}
+            if streamed_b is not None:
+                r["streamed_GBps"] = round(streamed_b / ms / 1e6, 1)
+            return r
         if scaled:
-            ms_2 = sv_time(M2)
-            b2 = product_bytes(n_s, n_p, dt_t, scaled, 2)
-            sv["bf16_two_planes"] = {"ms": round(ms_2, 3), "GBps": round(b2 / ms_2 / 1e6, 1),
-                                     "frac": round(b2 / ms_2 / 1e6 / HBM_PEAK_GBPS, 4)}
-            ms_d = sv_time(M64)
+            sv["bf16_one_plane"] = rec(sv_time(M1), alg_pb)
+            if form in ("compact", "two_planes"):
+                sv[f"bf16_{form}"] = rec(sv_time(Mt), alg_pb, alg_pb + extra_res)
             b64 = product_bytes(n_s, n_p, torch.float64, False)
-            sv["f64"] = {"ms": round(ms_d, 3), "GBps": round(b64 / ms_d / 1e6, 1),
-                         "frac": round(b64 / ms_d / 1e6 / HBM_PEAK_GBPS, 4)}
+            sv["f64"] = rec(sv_time(M64), b64)
+        else:
+            sv[dtype_name] = rec(sv_time(Mt), alg_pb)
+        ceiling = measure_stream_ceiling(M1.O if scaled else Mt.O)
+        log(f"[bench] streaming ceiling: {ceiling}")
 
     err = None
     if x64 is not None:
@@ -587,11 +681,17 @@ def measure_single(args):
     # HBM traffic of the CG launch from the committed counter record (same kernel build and
     # same algorithmic bytes per launch), else null
     traffic = None
-    rec = traffic_record("void sr::k_cg<2, 2, 1, 1, 1, 512, 1>(sr::CgArgs)") if (scaled and planes == 2
-                                                                                 and not args.refine) else None
-    if rec is not None and abs(rec["algorithmic_bytes"] - cg_bytes) <= 1e-6 * cg_bytes:
-        traffic = round(rec["traffic_bytes"] / 1e9, 1)
+    rec_t = traffic_record(TRAFFIC_KERNEL) if (scaled and form == "compact") else None
+    if rec_t is not None and abs(rec_t["algorithmic_bytes"] - cg_alg_bytes) <= 1e-6 * cg_alg_bytes:
+        traffic = round(rec_t["traffic_bytes"] / 1e9, 1)
 
+    forms = {"compact": "bf16 codes + float32 column scales + a bf16 remainder plane for the %d columns whose "
+                        "one-plane error exceeds 2^-17 (the dense pairing columns); search products accumulate in "
+                        "%s, residual refreshes in float64" % (n_lo, "float64" if args.search_f64 else "float32"),
+             "two_planes": "bf16 codes + float32 column scales + a full bf16 remainder plane (4 bytes per element); "
+                           "every product accumulates in float64",
+             "one_plane": "bf16 codes + float32 column scales; search products accumulate in float32, refreshes in "
+                          "float64"}
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -603,26 +703,33 @@ def measure_single(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype_name,
+        "dtype": {"compact": "bf16 (f64 accumulation)" if args.search_f64 else "bf16 (f32 accumulation)",
+                  "one_plane": "bf16 (f32 accumulation)",
+                  "two_planes": "bf16 x2 planes (f64 accumulation)"}.get(form, dtype_name),
         "data": "synthetic",
         "config": {
-            "workload": {"cps_32768x500000": "CPS-shaped O, 32768 samples x 500000 parameters (2048 correlators x 240 states + "
-                               "8480 dense pairing columns), bf16 codes + float32 column scales; prepare pass + "
-                               "CG to rel. residual %g, float64 residual refresh every %d" % (rtol, refresh),
+            "workload": {"cps_32768x500000": "CPS-shaped O, 32768 samples x 500000 parameters (2048 correlators x 240 "
+                                             "states + 8480 dense pairing columns), %s; prepare pass + CG to rel. "
+                                             "residual %g, float64 residual refresh every %d" % (forms[form], rtol,
+                                                                                                  refresh),
                          "dense_8192x4000": "dense O 8192 x 4000 float64; prepare pass + CG to %g" % rtol,
                          "cps_65536x24512": "CPS-shaped O 65536 x 24512 float64; prepare pass + CG to %g" % rtol,
                          "dense_16384": "dense O 16384 x 16384 float32; prepare pass + CG to %g" % rtol}[args.config],
-            "n_s": n_s, "n_p": n_p, "seed": cfg.seed, "parallelism": "single GPU",
+            "n_s": n_s, "n_p": n_p, "seed": cfg.seed, "parallelism": "single GPU", "storage_form": form,
         },
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_cg (persistent CG; products read O once each)",
-                     "algorithmic_GB_per_launch": round(cg_bytes / 1e9, 1),
-                     "algorithmic_bytes_per_launch": int(round(cg_bytes)), "launch_ms": round(cg_avg, 3)},
+                     "algorithmic_bytes_per_product": int(alg_pb),
+                     "algorithmic_GB_per_launch": round(cg_alg_bytes / 1e9, 2),
+                     "algorithmic_bytes_per_launch": int(round(cg_alg_bytes)),
+                     "streamed_GB_per_launch": round(cg_streamed_bytes / 1e9, 2),
+                     "streamed_GBps": round(streamed, 1), "launch_ms": round(cg_avg, 3),
+                     "stream_ceiling": ceiling},
         "cpu_baseline": cpu,
         "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
-                  "residual_products": residuals, "planes": planes, "search_planes": search_planes,
+                  "residual_products": residuals, "storage_form": form, "remainder_columns": n_lo,
                   "rel_res_true": infos[-1]["rel_res_true"], "rtol": rtol, "eps": eps},
         "sv_product": sv,
         "tiles": tiles,
@@ -630,6 +737,8 @@ def measure_single(args):
         "err_vs_f64": err,
         "err_vs_f64_one_plane": err_one_plane,
     }
+    if f64 is not None:
+        out["speedup_vs_f64_same_rtol"] = round(f64["same_rtol"]["solve_ms"] / cg_avg, 3)
     return out
 
 

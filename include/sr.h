@@ -57,7 +57,8 @@ enum sr_dtype {
   SR_F16 = 3     /* float16 codes with float32 column scales, as SR_BF16             */
 };
 
-/* Non-owning view of a derivative-ratio matrix (Sec. II.A: "pre-computed and stored"). */
+/* Non-owning view of a derivative-ratio matrix: the per-sample ratios of Eq. sr_overlap,
+ * computed once per sample set and kept for every product (Sec. II.A, Eq. sr_multiply_2). */
 typedef struct sr_matrix {
   int64_t n_s;               /* rows = samples, >= 1                                   */
   int64_t n_p;               /* columns = parameters, >= 1                             */
@@ -65,13 +66,23 @@ typedef struct sr_matrix {
   int32_t dtype;             /* enum sr_dtype                                          */
   int32_t reserved;          /* must be 0                                              */
   const void *O;             /* [n_s][ld] device                                       */
-  const void *O_lo;          /* SR_BF16/SR_F16 only, optional: second code plane       */
-                             /* [n_s][ld] (same dtype and ld) holding the quantisation */
-                             /* remainder, so the stored value is s_j*(q_kj + lo_kj);   */
-                             /* NULL: single plane                                     */
+  const void *O_lo;          /* SR_BF16/SR_F16 only, optional: second code plane holding */
+                             /* the quantisation remainder, so the stored value is       */
+                             /* s_j*(q_kj + lo_kj).  Full plane (lo_cols NULL): [n_s][ld], */
+                             /* same dtype and ld as O.  Compact plane (lo_cols given):   */
+                             /* [n_s][ld_lo], column i holding the remainder of parameter */
+                             /* lo_cols[i]; every other parameter is stored as s_j*q_kj.  */
+                             /* NULL: single plane                                       */
   const float *col_scale;    /* [n_p] device; required for SR_BF16/SR_F16, else NULL   */
   const double *col_mean;    /* [n_p] device column means of the STORED values         */
                              /* (s_j*q_kj for scaled types); NULL: computed by the call */
+  const int32_t *lo_cols;    /* [n_lo] device, strictly increasing parameter indices in  */
+                             /* [0, n_p) (sr_remainder_columns writes such a list; other */
+                             /* lists give wrong results but no out-of-bounds access), or */
+                             /* NULL: O_lo, if given, is a full plane                    */
+  int64_t n_lo;              /* columns of the compact plane (0 with lo_cols NULL)      */
+  int64_t ld_lo;             /* row stride of the compact plane in elements, >= n_lo,   */
+                             /* ld_lo * 2 a multiple of 16 bytes                         */
 } sr_matrix;
 
 /* Conjugate-gradient options (Sec. II.A: iterate until the requested accuracy). */
@@ -87,12 +98,14 @@ typedef struct sr_cg_opts {
   double refresh_drop;       /* in [0, 1): > 0 also refreshes as soon as ||r|| has      */
                              /* fallen below refresh_drop times its value at the last   */
                              /* refresh (or start); 0: periodic refreshes only          */
-  int32_t refine;            /* with O_lo only: 1: search-direction products read the  */
-                             /* first code plane only (iterative refinement); 0: they  */
-                             /* read both planes (float32 accumulation)                */
   int32_t precond;           /* 1: Jacobi preconditioner, z = r / (diag S + eps) (one  */
                              /* extra prepare pass computes diag S); SR_F64 / SR_F32    */
                              /* storage only; 0: none                                  */
+  int32_t search_f64;        /* SR_BF16/SR_F16 with one plane or a compact plane: 1:   */
+                             /* search-direction products accumulate in float64 too     */
+                             /* (robust to tight rtol when eps is far below the spread */
+                             /* of S); 0: float32.  Ignored for other storage           */
+  int32_t reserved;          /* must be 0                                              */
 } sr_cg_opts;
 
 /* CG outcome, written to host memory. */
@@ -140,14 +153,13 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
  * Residual refreshes and the exit check use products accumulated in float64 for every
  * storage type, so for bf16/f16 storage the iteration converges to the solution of the
  * stored (dequantized) system although its search-direction products accumulate in
- * float32 (mixed-precision residual replacement).  With a second code plane (O_lo) the
- * stored system is the two-plane one and refreshes and the exit check read both planes.
- * Search-direction products read both planes too unless opt->refine is set; then they
- * read only the first (mixed-precision iterative refinement): the two operators differ,
- * so every refresh also restarts the search direction (p <- r) whatever
- * restart_on_refresh says, and a refresh_drop of about 0.1 keeps the refinement
- * convergent on ill-conditioned systems.  Refinement leaves error along directions where
- * S is nearly singular that the residual hardly sees: solve to a tighter rtol with it.
+ * float32 (mixed-precision residual replacement; opt->search_f64 makes them float64
+ * too).  With a second code plane (O_lo, full or compact) the stored system is the
+ * two-plane one and every product reads the remainder codes; a full plane's products
+ * all accumulate in float64.  Float32 search products inject rounding errors of about
+ * 1e-7 of the largest eigenvalue of S into every direction, including the null space of
+ * S where the system is only eps: with N_s < N_p and eps far below the spread of S,
+ * tolerances much below 1e-6 need search_f64.
  * This call synchronizes `stream` before returning (it reads the outcome back).
  * Returns SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN or an error code.
  * ------------------------------------------------------------------------------------ */
@@ -187,7 +199,7 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D,
  * opt->refresh_drop since the last check if refresh_drop > 0, and at max_iter).
  * sys: host [n_sys]; every O has the same dtype (SR_F64 or SR_F32).  info: host
  * [n_sys * k] (system-major) or NULL; its `refreshes` is 0 and rel_res_recur repeats
- * rel_res_true.  opt->use_x0, restart_on_refresh, refine, precond and res_history are
+ * rel_res_true.  opt->use_x0, restart_on_refresh, precond, search_f64 and res_history are
  * not used.
  * Synchronizes `stream`.  Returns SR_OK if every column converged, else
  * SR_NOT_CONVERGED / SR_BREAKDOWN (the first such status met) or an error code.
@@ -214,7 +226,7 @@ int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double 
  * refresh_every of opt, 20 if 0).  Storage SR_F64 or SR_F32, one code plane.
  * g: device [n_p]; eps: host [k], finite, >= 0, any order; X: device [k][n_p] (row i for
  * eps_i), must not overlap g.  info: host [k] or NULL (iters and products include the
- * shared sequence, the residual check and any continuation).  opt->use_x0, refine,
+ * shared sequence, the residual check and any continuation).  opt->use_x0, search_f64,
  * precond and res_history are not used.  Synchronizes `stream`.  Returns SR_OK if every
  * shift converged, else the first non-OK status or an error code.
  * ------------------------------------------------------------------------------------ */
@@ -299,6 +311,27 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
                 void *q, void *q_lo, int64_t ld_out, int32_t out_dtype, float *scale, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Compact remainder plane (the precision form, not in the paper): a second code only for
+ * the columns whose single-plane codes are not accurate enough.
+ * sr_remainder_columns: with `scale` the column scales sr_quantize wrote for `in`, selects
+ * the columns j with  max_k |O_kj / s_j - q_kj| > tol  (quotient and difference in
+ * float64, q_kj the out_dtype code of O_kj / s_j) and writes them in increasing order to
+ * lo_cols (device [n_p]); their number goes to *n_lo (host).  A tol equal to the two-plane
+ * error bound (bf16: 2^-17, f16: 2^-21) selects exactly the columns a second plane
+ * improves; the stored values then meet that bound everywhere.  Synchronizes `stream`.
+ * sr_quantize_remainder: writes the compact plane q_lo (device [n_s][ld_lo], ld_lo >= n_lo,
+ * ld_lo * 2 a multiple of 16 bytes, padding columns set to zero): q_lo_ki = the nearest code
+ * of O_kj / s_j - q_kj with j = lo_cols[i] (as the second plane of sr_quantize).
+ * Same input rules as sr_quantize.  Pass the plane with lo_cols, n_lo, ld_lo in sr_matrix.
+ * ------------------------------------------------------------------------------------ */
+int sr_remainder_columns(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
+                         int32_t out_dtype, const float *scale, double tol, int32_t *lo_cols, int64_t *n_lo,
+                         hipStream_t stream);
+int sr_quantize_remainder(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
+                          int32_t out_dtype, const float *scale, const int32_t *lo_cols, int64_t n_lo, void *q_lo,
+                          int64_t ld_lo, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Tuning hooks (not in the paper).  The fused product is built for a few tile
  * configurations: nv 16-byte vectors per thread and row, `rows` rows per tile, `lookahead`
  * tiles of loads in flight, a `poll_delay` (poll depth) of steps between issuing the
@@ -324,6 +357,15 @@ int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max);
 int sr_set_batch_config(int32_t split_rows, int32_t tasks);
 int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
                        int32_t poll_delay, int32_t threads, int32_t col_groups);
+
+/* Measurement helper (not in the paper): reads `bytes` (a multiple of 16) at p (16-byte
+ * aligned, device) with the products' non-temporal 16-byte loads, `unroll` (2, 4 or 8)
+ * loads in flight per thread, blocks_per_cu (1..8) workgroups of 512 threads per compute
+ * unit, and writes one folded word per workgroup to sink (device, [CUs * blocks_per_cu]
+ * uint32).  Its duration gives the streaming-read ceiling the products are compared
+ * with.  Asynchronous on `stream`. */
+int sr_stream_read(const void *p, int64_t bytes, int32_t blocks_per_cu, int32_t unroll, uint32_t *sink,
+                   hipStream_t stream);
 
 /* Frees every workspace the library holds (all devices, all streams).  Must not be
  * called while library work is pending on any stream. */

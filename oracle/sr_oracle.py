@@ -35,6 +35,7 @@ Functions and the passage each follows:
   sv_product_swapped ..................... Sec. II.A, Eq. sr_multiply_2 (sums interchanged)
   paper_linear_system, sr_update ......... Sec. II.A, Eq. sr_lin_eq and alpha' = alpha + x_i/x_0
   solve_dense ............................ Sec. II.A, Eq. sr_lin_eq solved by Cholesky
+  solve_dual ............................. the same solution through the N_s x N_s dual system
   cg_solve ............................... Sec. II.A, conjugate gradient (Hestenes-Stiefel)
   lm_matrices, lm_hv_dense ............... Sec. II.B, Eq. linear_eigen (H and S in Omega)
   lm_lowest_eigenpair .................... Sec. II.B, Eq. linear_eigen (dense generalized solve)
@@ -54,7 +55,7 @@ import scipy.linalg as sla
 __all__ = [
     "sample_weights", "sample_mean", "centred", "overlap_matrix", "overlap_matrix_uncentred",
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
-    "paper_linear_system", "sr_update", "solve_dense", "cg_solve", "lm_matrices", "lm_hv_dense", "lm_hv_swapped",
+    "paper_linear_system", "sr_update", "solve_dense", "solve_dual", "cg_solve", "lm_matrices", "lm_hv_dense", "lm_hv_swapped",
     "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
     "quantize_split", "dequantize_split", "quantize_cols", "dequantize_cols", "REMAINDER_TOL",
     "solve_adjoint_gradients",
@@ -194,6 +195,21 @@ def solve_dense(O, g, eps: float, w=None) -> np.ndarray:
         c = sla.cho_factor(S + eps * np.eye(n), lower=True)
         return sla.cho_solve(c, g)
     return np.linalg.pinv(S, rcond=1e-12, hermitian=True) @ g
+
+
+def solve_dual(O, g, eps: float, w=None) -> np.ndarray:
+    """x = (S + eps I)^{-1} g through the N_s-dimensional dual system, for N_s << N_p:
+    with S = Oc^T W Oc (W = diag(w)) the Woodbury identity gives
+        x = (g - Oc^T W^{1/2} (eps I + W^{1/2} Oc Oc^T W^{1/2})^{-1} W^{1/2} Oc g) / eps,
+    one N_s x N_s Cholesky solve (eps > 0).  Never forms S."""
+    assert eps > 0.0
+    Oc = centred(O, w)
+    w = sample_weights(Oc.shape[0], w)
+    g = np.asarray(g, dtype=np.float64)
+    B = np.sqrt(w)[:, None] * Oc
+    K = B @ B.T + eps * np.eye(B.shape[0])
+    c = sla.cho_factor(K, lower=True)
+    return (g - B.T @ sla.cho_solve(c, B @ g)) / eps
 
 
 def cg_solve(apply_A, b, rtol: float = 1e-10, max_iter: int | None = None,

@@ -76,7 +76,29 @@ int check_matrix(const sr_matrix *m, const char *name) {
   if (m->O_lo != nullptr && !scaled(m->dtype))
     return fail(SR_ERR_INVALID, "%s: a second code plane (O_lo) needs bf16/f16 storage", name);
   if (((uintptr_t)m->O_lo) % 16 != 0) return fail(SR_ERR_INVALID, "%s: O_lo must be 16-byte aligned", name);
+  if (m->lo_cols != nullptr) {
+    if (!scaled(m->dtype)) return fail(SR_ERR_INVALID, "%s: a compact remainder plane needs bf16/f16 storage", name);
+    if (m->n_lo < 0 || m->n_lo > m->n_p)
+      return fail(SR_ERR_INVALID, "%s: n_lo must be in [0, n_p] (got %lld)", name, (long long)m->n_lo);
+    if (m->n_lo > 0 && m->O_lo == nullptr) return fail(SR_ERR_INVALID, "%s: lo_cols given without O_lo", name);
+    if (m->n_lo > 0 && (m->ld_lo < m->n_lo || (m->ld_lo * 2) % 16 != 0))
+      return fail(SR_ERR_INVALID, "%s: ld_lo must be >= n_lo with ld_lo * 2 a multiple of 16 bytes", name);
+    if (round_up(m->n_p, 8) + m->n_lo >= ((int64_t)1 << 31) - 64)
+      return fail(SR_ERR_INVALID, "%s: n_p + n_lo out of range", name);
+  } else if (m->n_lo != 0 || m->ld_lo != 0) {
+    return fail(SR_ERR_INVALID, "%s: n_lo and ld_lo must be 0 without lo_cols", name);
+  }
   return SR_OK;
+}
+
+// A compact remainder plane with at least one column.
+bool compact(const sr_matrix *m) { return m->lo_cols != nullptr && m->n_lo > 0; }
+// A full second code plane.
+bool two_planes(const sr_matrix *m) { return m->O_lo != nullptr && m->lo_cols == nullptr; }
+// Columns a single-plane product streams: the parameters, then (compact plane) its columns
+// starting at n_p rounded up to whole 16-byte vectors.
+int64_t streamed_cols(const sr_matrix *m) {
+  return compact(m) ? round_up(m->n_p, vec_of(m->dtype)) + m->n_lo : m->n_p;
 }
 
 bool ranges_overlap(const void *a, int64_t na, const void *b, int64_t nb) {
@@ -194,22 +216,26 @@ struct TileForce {
 };
 TileForce g_force[4][2] = {};
 
-int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg) {
-  int64_t C = pow2_ceil(cdiv(n_p, cols_per_wg));
+// Column groups and slices over the n_v streamed columns (n_v < 0: n_v = n_p).
+int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg,
+             int64_t n_v = -1) {
+  if (n_v < 0) n_v = n_p;
+  int64_t C = pow2_ceil(cdiv(n_v, cols_per_wg));
   if (force_c > 0 && force_c >= C) C = force_c;
-  if (C > G) return fail(SR_ERR_INVALID, "n_p = %lld exceeds the column capacity of the built tiles (%lld)",
-                         (long long)n_p, (long long)G * cols_per_wg);
+  if (C > G) return fail(SR_ERR_INVALID, "%lld columns exceed the column capacity of the built tiles (%lld)",
+                         (long long)n_v, (long long)G * cols_per_wg);
   pg->G = G;
   pg->C = (int)C;
   pg->RG = G / (int)C;
   pg->n_s = n_s;
   pg->n_p = n_p;
-  pg->wslice = round_up(cdiv(n_p, C), vec);
+  pg->n_v = n_v;
+  pg->wslice = round_up(cdiv(n_v, C), vec);
   pg->n_tiles = (int)cdiv(n_s, r);
   return SR_OK;
 }
 
-int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
+int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan, int64_t n_v = -1) {
   int count = 0;
   const KernelEntry *tab = kernel_table(dt, &count);
   const int vec = vec_of(dt);
@@ -230,7 +256,7 @@ int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan) {
   }
   plan->ke = pick;
   const int cols = pick->nv * vec * pick->nt;
-  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg);
+  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg, n_v);
   if (rc) return rc;
   plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
   return SR_OK;
@@ -295,6 +321,18 @@ Operand make_operand(const sr_matrix *m) {
   Operand op;
   op.O = (const unsigned char *)m->O;
   op.lo = (const unsigned char *)m->O_lo;
+  op.lo_cols = nullptr;
+  op.n_lo = 0;
+  op.ldb_lo = 0;
+  op.n_q = (int64_t)1 << 62;
+  if (compact(m)) {
+    op.lo_cols = m->lo_cols;
+    op.n_lo = m->n_lo;
+    op.ldb_lo = m->ld_lo * elem_bytes(m->dtype);
+    op.n_q = round_up(m->n_p, vec_of(m->dtype));
+  } else if (m->lo_cols != nullptr) {
+    op.lo = nullptr;     // an empty compact plane: single plane
+  }
   op.ldb = m->ld * elem_bytes(m->dtype);
   op.scale = m->col_scale;
   return op;
@@ -310,8 +348,13 @@ int run_grad(const sr_matrix *m, const double *E, double *g, double *Emean, doub
   int rc = geometry(di.grid, m->n_s, m->n_p, grad_nv(dt) * vec * kNT, vec, grad_rows(dt), 0, &pl.pg);
   if (rc) return rc;
   const int64_t ypd = (int64_t)pl.pg.RG * 3 * m->n_p;
+  // a compact remainder plane: the pass over the first plane gives every column, then the
+  // remainder columns are redone from both planes (row blocks, then a fixed-order sum)
+  const bool cmp = compact(m);
+  const int64_t n_rb = cmp ? cdiv(m->n_s, kGradLoRows) : 0;
+  const size_t extra = cmp ? (size_t)(4 * n_rb * m->n_lo + 64) * 8 + 512 : 0;
   void *base = nullptr;
-  rc = get_workspace(dev, s, prod_ws_bytes(pl, ypd), &base);
+  rc = get_workspace(dev, s, prod_ws_bytes(pl, ypd) + extra, &base);
   if (rc) return rc;
   Carve cv(base);
   ProdWs w;
@@ -321,14 +364,45 @@ int run_grad(const sr_matrix *m, const double *E, double *g, double *Emean, doub
   a.pb = w.pb;
   a.sb = w.sb;
   a.op = make_operand(m);
+  if (cmp) a.op.lo = nullptr;
   a.E = E;
   a.g_out = g;
   a.mean_out = mean;
   a.diag_out = diag;
   a.Emean_out = Emean;
+  double *emean_ws = nullptr, *part = nullptr;
+  if (cmp) {
+    emean_ws = cv.take<double>(8);
+    part = cv.take<double>(4 * n_rb * m->n_lo);
+    if (a.Emean_out == nullptr) a.Emean_out = emean_ws;
+  }
   rc = zero_sync(w, s);
   if (rc) return rc;
-  return launch_coop(grad_kernel(dt), pl.pg.G, &a, s);
+  rc = launch_coop(grad_kernel(dt), pl.pg.G, &a, s);
+  if (rc || !cmp) return rc;
+  GradLoArgs b{};
+  b.Q = (const unsigned char *)m->O;
+  b.LO = (const unsigned char *)m->O_lo;
+  b.ldb = m->ld * elem_bytes(dt);
+  b.ldb_lo = m->ld_lo * elem_bytes(dt);
+  b.cols = m->lo_cols;
+  b.n_lo = m->n_lo;
+  b.n_s = m->n_s;
+  b.n_p = m->n_p;
+  b.scale = m->col_scale;
+  b.E = E;
+  b.Emean = a.Emean_out;
+  b.rows_per_block = kGradLoRows;
+  b.n_rb = (int)n_rb;
+  b.part = part;
+  b.g_out = g;
+  b.mean_out = mean;
+  b.diag_out = diag;
+  void *args[] = {&b};
+  const int nb = (int)cdiv(m->n_lo, kNT);
+  HIP_TRY(hipLaunchKernel(gradlo_part_kernel(dt), dim3(nb, (unsigned)n_rb), dim3(kNT), args, 0, s));
+  HIP_TRY(hipLaunchKernel(gradlo_finish_kernel(dt), dim3(nb), dim3(kNT), args, 0, s));
+  return SR_OK;
 }
 
 // Column means into `mean` when the matrix does not carry them.
@@ -620,6 +694,25 @@ const char *sr_status_string(int status) {
   }
 }
 
+int sr_stream_read(const void *p, int64_t bytes, int32_t blocks_per_cu, int32_t unroll, uint32_t *sink,
+                   hipStream_t stream) {
+  if (p == nullptr || sink == nullptr) return fail(SR_ERR_INVALID, "sr_stream_read: null pointer");
+  if (((uintptr_t)p) % 16 || bytes < 16 || bytes % 16)
+    return fail(SR_ERR_INVALID, "sr_stream_read: p must be 16-byte aligned and bytes a positive multiple of 16");
+  if (blocks_per_cu < 1 || blocks_per_cu > 8) return fail(SR_ERR_INVALID, "sr_stream_read: blocks_per_cu in [1, 8]");
+  const void *fn = stream_read_kernel(unroll);
+  if (fn == nullptr) return fail(SR_ERR_INVALID, "sr_stream_read: unroll must be 2, 4 or 8");
+  int dev;
+  DeviceInfo di;
+  int rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const unsigned char *src = (const unsigned char *)p;
+  int64_t n_vec = bytes / 16;
+  void *args[] = {&src, &n_vec, &sink};
+  HIP_TRY(hipLaunchKernel(fn, dim3(di.cus * blocks_per_cu), dim3(512), args, 0, stream));
+  return SR_OK;
+}
+
 int sr_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = SR_OK;
@@ -735,9 +828,9 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   rc = ensure_mean(O, mscr, &mean, dev, di, stream);
   if (rc) return rc;
   Plan pl;
-  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl);
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
   if (rc) return rc;
-  const int64_t ypd = (int64_t)pl.pg.RG * O->n_p;
+  const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
   void *base = nullptr;
   rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd), &base);
   if (rc) return rc;
@@ -755,7 +848,7 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   a.eps = eps;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  if (O->O_lo != nullptr) {
+  if (two_planes(O)) {
     if (pl.ke->sv2 == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: no two-plane kernel for this configuration");
     return launch_coop(pl.ke->sv2, pl.pg.G, &a, stream, pl.ke->nt, 0);
   }
@@ -1366,7 +1459,7 @@ int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const dou
       sr_cg_opts po = o;
       po.use_x0 = 1;
       po.precond = 0;
-      po.refine = 0;
+      po.search_f64 = 0;
       po.res_history = nullptr;
       if (po.refresh_every == 0) po.refresh_every = 20;
       sr_cg_info pi{};
@@ -1545,9 +1638,10 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     return fail(SR_ERR_INVALID, "sr_cg_solve: restart_on_refresh must be 0 or 1");
   if (!(o.refresh_drop >= 0.0 && o.refresh_drop < 1.0))
     return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_drop must be in [0, 1)");
-  if (o.refine != 0 && o.refine != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: refine must be 0 or 1");
   if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: use_x0 must be 0 or 1");
   if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: precond must be 0 or 1");
+  if (o.search_f64 != 0 && o.search_f64 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: search_f64 must be 0 or 1");
+  if (o.reserved != 0) return fail(SR_ERR_INVALID, "sr_cg_solve: reserved must be 0");
   if (o.precond && (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32)))
     return fail(SR_ERR_INVALID, "sr_cg_solve: the Jacobi preconditioner needs SR_F64 or SR_F32 storage, one plane");
   int64_t max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
@@ -1575,9 +1669,9 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     if (rc) return rc;
   }
   Plan pl;
-  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl);
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
   if (rc) return rc;
-  const int64_t ypd = (int64_t)pl.pg.RG * O->n_p;
+  const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
   const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (O->n_p * 8 + 256) + 1024;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base);
@@ -1602,17 +1696,14 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.max_iter = (int)max_iter;
   a.refresh_every = o.refresh_every;
   a.use_x0 = o.use_x0;
-  // refinement over two code planes: search directions and residuals use different
-  // operators, so a refresh must restart the direction
-  a.refine = (O->O_lo != nullptr && o.refine != 0) ? 1 : 0;
-  a.restart_on_refresh = (o.restart_on_refresh != 0 || a.refine) ? 1 : 0;
+  a.restart_on_refresh = o.restart_on_refresh;
   a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
   a.hist = o.res_history;
   a.diag = diag;
   rc = zero_sync(w, stream);
   if (rc) return rc;
-  const void *cg_fn =
-      O->O_lo == nullptr ? (o.precond ? pl.ke->cgj : pl.ke->cg) : (a.refine ? pl.ke->cgr : pl.ke->cg2);
+  const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
+  const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
   if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no two-plane CG kernel for this configuration");
   rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
   if (rc) return rc;
@@ -1681,6 +1772,93 @@ int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t
   if (rc) return rc;
   void *args[] = {&a};
   HIP_TRY(hipLaunchKernel(quantize_kernel(in_dtype, out_dtype), dim3(di.grid * 8), dim3(kNT), args, 0, stream));
+  return SR_OK;
+}
+
+static int check_quant_input(const char *where, int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
+                      int32_t out_dtype, const float *scale) {
+  if (n_s < 1 || n_p < 1) return fail(SR_ERR_INVALID, "%s: n_s and n_p must be >= 1", where);
+  if (n_s > (int64_t)1 << 40 || n_p > (int64_t)1 << 31) return fail(SR_ERR_INVALID, "%s: dimensions out of range", where);
+  if (in_dtype != SR_F64 && in_dtype != SR_F32) return fail(SR_ERR_INVALID, "%s: in_dtype must be f64 or f32", where);
+  if (out_dtype != SR_BF16 && out_dtype != SR_F16) return fail(SR_ERR_INVALID, "%s: out_dtype must be bf16 or f16", where);
+  if (in == nullptr || scale == nullptr) return fail(SR_ERR_INVALID, "%s: null pointer", where);
+  if (ld_in < n_p) return fail(SR_ERR_INVALID, "%s: ld_in < n_p", where);
+  if (((uintptr_t)in) % 16 || (ld_in * elem_bytes(in_dtype)) % 16)
+    return fail(SR_ERR_INVALID, "%s: the input must be 16-byte aligned with rows of whole 16-byte vectors", where);
+  return SR_OK;
+}
+
+int sr_remainder_columns(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, int32_t out_dtype,
+                         const float *scale, double tol, int32_t *lo_cols, int64_t *n_lo, hipStream_t stream) {
+  int rc = check_quant_input("sr_remainder_columns", n_s, n_p, in, ld_in, in_dtype, out_dtype, scale);
+  if (rc) return rc;
+  if (lo_cols == nullptr || n_lo == nullptr) return fail(SR_ERR_INVALID, "sr_remainder_columns: null output");
+  if (std::isnan(tol)) return fail(SR_ERR_INVALID, "sr_remainder_columns: tol is NaN");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  Plan pl;
+  pl.words = 0;
+  rc = geometry(di.grid, n_s, n_p, kNT * 8, 1, 1, 0, &pl.pg);
+  if (rc) return rc;
+  const int64_t ypd = (int64_t)pl.pg.RG * n_p;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd) + (size_t)n_p * 8 + 1024, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  RemArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.in = (const unsigned char *)in;
+  a.ldb_in = ld_in * elem_bytes(in_dtype);
+  a.scale = scale;
+  a.err = cv.take<double>(n_p);
+  int64_t *count = cv.take<int64_t>(1);
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  rc = launch_coop(remmax_kernel(in_dtype, out_dtype), pl.pg.G, &a, stream);
+  if (rc) return rc;
+  SelectArgs b{a.err, n_p, tol, lo_cols, count};
+  void *args[] = {&b};
+  HIP_TRY(hipLaunchKernel(select_kernel(), dim3(1), dim3(1024), args, 0, stream));
+  int64_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, count, sizeof(h), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  *n_lo = h;
+  return SR_OK;
+}
+
+int sr_quantize_remainder(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype,
+                          int32_t out_dtype, const float *scale, const int32_t *lo_cols, int64_t n_lo, void *q_lo,
+                          int64_t ld_lo, hipStream_t stream) {
+  int rc = check_quant_input("sr_quantize_remainder", n_s, n_p, in, ld_in, in_dtype, out_dtype, scale);
+  if (rc) return rc;
+  if (n_lo < 0 || n_lo > n_p) return fail(SR_ERR_INVALID, "sr_quantize_remainder: n_lo must be in [0, n_p]");
+  if (n_lo == 0) return SR_OK;
+  if (lo_cols == nullptr || q_lo == nullptr) return fail(SR_ERR_INVALID, "sr_quantize_remainder: null pointer");
+  if (ld_lo < n_lo || (ld_lo * 2) % 16 || ((uintptr_t)q_lo) % 16)
+    return fail(SR_ERR_INVALID, "sr_quantize_remainder: q_lo must be 16-byte aligned, ld_lo >= n_lo, ld_lo * 2 a "
+                                "multiple of 16 bytes");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  QuantLoArgs a{};
+  a.in = (const unsigned char *)in;
+  a.ldb_in = ld_in * elem_bytes(in_dtype);
+  a.n_s = n_s;
+  a.n_p = n_p;
+  a.n_lo = n_lo;
+  a.ld_lo = ld_lo;
+  a.scale = scale;
+  a.cols = lo_cols;
+  a.out = (unsigned char *)q_lo;
+  void *args[] = {&a};
+  HIP_TRY(hipLaunchKernel(quantize_lo_kernel(in_dtype, out_dtype), dim3(di.grid * 8), dim3(kNT), args, 0, stream));
   return SR_OK;
 }
 

@@ -258,6 +258,151 @@ __global__ __launch_bounds__(kNT) void k_quantize(QuantArgs a) {
 }
 
 // ======================================================================================
+// Compact remainder plane: column selection, codes, and the prepare pass of its columns
+// ======================================================================================
+template <int OUT_DT> __device__ __forceinline__ uint16_t rne_code(double t) {
+  return OUT_DT == DT_BF16 ? rne_bf16(t) : rne_f16(t);
+}
+template <int OUT_DT> __device__ __forceinline__ double code_to_double(uint16_t c) {
+  return OUT_DT == DT_BF16 ? (double)__uint_as_float((uint32_t)c << 16) : (double)(float)__builtin_bit_cast(_Float16, c);
+}
+template <int IN_DT> __device__ __forceinline__ double input_value(const unsigned char *rowp, int64_t col) {
+  return IN_DT == DT_F64 ? ((const double *)rowp)[col] : (double)((const float *)rowp)[col];
+}
+
+// err_j = max_k |O_kj / s_j - q_kj| (the single-plane error relative to the column scale),
+// a column reduction over row groups like k_absmax.
+template <int IN_DT, int OUT_DT>
+__global__ __launch_bounds__(kNT) void k_remmax(RemArgs a) {
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, 1);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  for (int64_t col = ctx.c0 + tid; col < ctx.c1; col += kNT) {
+    const double s = (double)a.scale[col];
+    double m = 0.0;
+    for (int64_t row = ctx.rg; row < a.pg.n_s; row += a.pg.RG) {
+      const double t = input_value<IN_DT>(a.in + row * a.ldb_in, col) / s;
+      m = fmax(m, fabs(t - code_to_double<OUT_DT>(rne_code<OUT_DT>(t))));
+    }
+    st_coh(&a.pb.ypart[(int64_t)ctx.rg * a.pg.n_p + col], m);
+  }
+  if (!grid_sync(ctx.gs)) return;
+  const int64_t ch = (a.pg.n_p + G - 1) / G;
+  const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
+  for (int64_t j = j0 + tid; j < j1; j += kNT) {
+    double m = 0.0;
+    for (int rg = 0; rg < a.pg.RG; ++rg) m = fmax(m, ld_coh(&a.pb.ypart[(int64_t)rg * a.pg.n_p + j]));
+    a.err[j] = m;
+  }
+}
+
+// Remainder codes of the selected columns: lo_ki = code(O_k,j / s_j - q_kj), j = cols[i];
+// padding columns n_lo..ld_lo-1 are written as zero.
+template <int IN_DT, int OUT_DT>
+__global__ __launch_bounds__(kNT) void k_quantize_lo(QuantLoArgs a) {
+  const int64_t nvec_row = a.ld_lo / 8;
+  const int64_t total = a.n_s * nvec_row;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = idx / nvec_row, c0 = (idx % nvec_row) * 8;
+    const unsigned char *rin = a.in + row * a.ldb_in;
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      uint32_t pair = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t c = c0 + 2 * h + e;
+        uint16_t code = 0;
+        if (c < a.n_lo) {
+          const int64_t j = lo_param(a.cols, c, a.n_p);
+          const double t = input_value<IN_DT>(rin, j) / (double)a.scale[j];
+          code = rne_code<OUT_DT>(t - code_to_double<OUT_DT>(rne_code<OUT_DT>(t)));
+        }
+        pair |= (uint32_t)code << (16 * e);
+      }
+      w[h] = pair;
+    }
+    *(u32x4 *)(a.out + row * a.ld_lo * 2 + c0 * 2) = u32x4{w[0], w[1], w[2], w[3]};
+  }
+}
+
+// Prepare pass of the remainder columns (their stored value is s_j (q_kj + lo_ki)): sums of
+// x - K, (x - K)^2, e (x - K) and e over a block of rows per thread and column, with the
+// shift K = the column's value in row 0 and e = E - <E>.
+template <int DT>
+__device__ __forceinline__ double two_plane_value(const GradLoArgs &a, int64_t k, int64_t i, int64_t j, double s) {
+  return (code_value(a.Q + k * a.ldb, j, DT) + code_value(a.LO + k * a.ldb_lo, i, DT)) * s;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_gradlo_part(GradLoArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  const int64_t rb = blockIdx.y;
+  if (i >= a.n_lo) return;
+  const int64_t j = lo_param(a.cols, i, a.n_p);
+  const double s = (double)a.scale[j];
+  const double K = two_plane_value<DT>(a, 0, i, j, s);
+  const double Em = a.E != nullptr ? *a.Emean : 0.0;
+  const int64_t k0 = rb * a.rows_per_block;
+  const int64_t k1 = min(a.n_s, k0 + a.rows_per_block);
+  double sA = 0.0, sB = 0.0, sC = 0.0, sE = 0.0;
+  int64_t k = k0;
+  for (; k + 8 <= k1; k += 8) {
+    double x[8], e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      x[u] = two_plane_value<DT>(a, k + u, i, j, s) - K;
+      e[u] = a.E != nullptr ? a.E[k + u] - Em : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sA += x[u];
+      sB = fma(x[u], x[u], sB);
+      sC = fma(e[u], x[u], sC);
+      sE += e[u];
+    }
+  }
+  for (; k < k1; ++k) {
+    const double x = two_plane_value<DT>(a, k, i, j, s) - K;
+    const double e = a.E != nullptr ? a.E[k] - Em : 0.0;
+    sA += x;
+    sB = fma(x, x, sB);
+    sC = fma(e, x, sC);
+    sE += e;
+  }
+  double *p = a.part + rb * 4 * a.n_lo;
+  p[i] = sA;
+  p[a.n_lo + i] = sB;
+  p[2 * a.n_lo + i] = sC;
+  p[3 * a.n_lo + i] = sE;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kNT) void k_gradlo_finish(GradLoArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (i >= a.n_lo) return;
+  double A = 0.0, B = 0.0, Cg = 0.0, Es = 0.0;
+  for (int rb = 0; rb < a.n_rb; ++rb) {
+    const double *p = a.part + (int64_t)rb * 4 * a.n_lo;
+    A += p[i];
+    B += p[a.n_lo + i];
+    Cg += p[2 * a.n_lo + i];
+    Es += p[3 * a.n_lo + i];
+  }
+  const int64_t j = lo_param(a.cols, i, a.n_p);
+  const double inv_n = 1.0 / (double)a.n_s;
+  const double K = two_plane_value<DT>(a, 0, i, j, (double)a.scale[j]);
+  const double dmean = A * inv_n;
+  if (a.mean_out) a.mean_out[j] = K + dmean;
+  if (a.diag_out) {
+    const double var = B * inv_n - dmean * dmean;
+    a.diag_out[j] = var > 0.0 ? var : 0.0;
+  }
+  if (a.g_out) a.g_out[j] = 2.0 * inv_n * (Cg - dmean * Es);
+}
+
+// ======================================================================================
 // (S + eps I) v
 // ======================================================================================
 template <int DT, int NV, int R, int L, int P_, int NT>
@@ -286,6 +431,9 @@ __global__ __launch_bounds__(NT) void k_sv(SvArgs a) {
     const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
     a.y[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * a.v[j];
   }
+  int64_t i0, i1;
+  lo_range(a.op, j0, j1, i0, i1);
+  finish_lo<NT>(a.pb, a.pg, a.op, i0, i1, inv_n, a.y);
 }
 
 // (S + eps I) v for two code planes (stored value s_j (q + lo)), float64 accumulation.
@@ -381,6 +529,11 @@ struct CgKernel {
       const double s = a.op.scale ? (double)a.op.scale[j] : 1.0;
       q[j] = (s * acc - a.mean[j] * S1) * inv_n + a.eps * ld_coh(&vin[j]);
     }
+    if (PLANES == 1 && a.op.lo_cols != nullptr) {
+      int64_t i0, i1;
+      lo_range(a.op, j0, j1, i0, i1);
+      finish_lo<NT>(a.pb, a.pg, a.op, i0, i1, inv_n, q);
+    }
     products++;
     return true;
   }
@@ -393,10 +546,11 @@ struct CgKernel {
 //   kCgOnePlane   one code plane: search directions in the storage type's accumulation,
 //                 residuals float64-accumulated for scaled storage
 //   kCgTwoPlanes  two code planes everywhere, float64 accumulation
-//   kCgRefine     search directions on the first plane, residuals on both (refinement)
 //   kCgJacobi     one plane, Jacobi-preconditioned: z = r / (diag S + eps), rho = r . z
 //                 (the convergence test stays on ||r|| / ||g||)
-enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgRefine = 2, kCgJacobi = 3 };
+//   kCgExact      one plane (or a compact remainder plane) of scaled storage, every product
+//                 float64-accumulated
+enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgJacobi = 3, kCgExact = 4 };
 
 template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane>
 __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
@@ -478,9 +632,8 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       // one product code for search directions and residuals: float64 accumulation
       // (measured faster here than float32 with the two planes in one kernel)
       ok = K::template apply<true, 2>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
-    } else if constexpr (CGM == kCgRefine) {
-      if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
-      else ok = K::template apply<true, 2>(a, ctx, a.x, a.q, j0, j1, products);
+    } else if constexpr (CGM == kCgExact) {
+      ok = K::template apply<true>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
     } else if constexpr (K::kExactResidual) {
       if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
       else ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);

@@ -7,7 +7,8 @@ namespace sr {
   {DT_BF16, NV, R, L, P, NT, 0, (const void *)&k_sv<DT_BF16, NV, R, L, P, NT>,                        \
    (const void *)&k_cg<DT_BF16, NV, R, L, P, NT>, nullptr,                                            \
    (const void *)&k_sv2<DT_BF16, NV, NT>, (const void *)&k_cg<DT_BF16, NV, 1, 1, 1, NT, kCgTwoPlanes>,             \
-   (const void *)&k_cg<DT_BF16, NV, R, L, P, NT, kCgRefine>, nullptr,                                  \
+   nullptr,                                                                                          \
+   (const void *)&k_cg<DT_BF16, NV, R, L, P, NT, kCgExact>,                                             \
    Product<DT_BF16, NV, R, 1, false, L, P, NT>::ring_bytes()},
 #define SR_REG_LM(NV, R, L, P, NT)                                                                   \
   {DT_BF16, NV, R, L, P, NT, 1, nullptr, nullptr, (const void *)&k_lm<DT_BF16, NV, R, L, P, NT>, nullptr, \

@@ -43,7 +43,6 @@ struct CgArgs {
   double eps, rtol;
   int max_iter, refresh_every, use_x0, restart_on_refresh;
   double refresh_drop2;       // squared relative drop that triggers a refresh; 0: off
-  int refine;                 // two planes: search products read the first plane only
   double *hist;         // [max_iter + 1] or nullptr
   double *info;         // [8]
   const double *diag;   // [n_p] diag S (Jacobi-preconditioned CG), else nullptr
@@ -167,8 +166,9 @@ struct KernelEntry {
   int kind;              // 0: SR (sv + cg), 1: LM
   const void *sv, *cg, *lm;
   const void *sv2;       // two-code-plane product (scaled storage), or nullptr
-  const void *cg2, *cgr; // CG over two code planes / refinement (scaled storage), or nullptr
+  const void *cg2;       // CG over two code planes (scaled storage), or nullptr
   const void *cgj;       // Jacobi-preconditioned CG (float64 / float32 storage), or nullptr
+  const void *cgx;       // CG with float64-accumulated search products (scaled storage), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 
@@ -179,5 +179,51 @@ int grad_rows(int dt);
 const void *absmax_kernel(int in_dt);
 const void *quantize_kernel(int in_dt, int out_dt);
 const void *fill_kernel();
+
+// Compact remainder plane: prepare pass of its columns, column selection and codes.
+struct GradLoArgs {
+  const unsigned char *Q, *LO;       // first code plane, compact remainder plane
+  int64_t ldb, ldb_lo;               // their row strides in bytes
+  const int32_t *cols;               // [n_lo] parameter of each remainder column
+  int64_t n_lo, n_s, n_p;
+  const float *scale;                // [n_p]
+  const double *E;                   // [n_s] or nullptr
+  const double *Emean;               // device scalar <E> (when E is given)
+  int64_t rows_per_block;
+  int n_rb;                          // row blocks
+  double *part;                      // [n_rb][4][n_lo]: sums of x - K, (x - K)^2, e (x - K), e
+  double *g_out, *mean_out, *diag_out;   // [n_p] (entries of the remainder columns rewritten)
+};
+constexpr int kGradLoRows = 256;     // rows per block of the remainder columns' prepare pass
+const void *gradlo_part_kernel(int dt);
+const void *gradlo_finish_kernel(int dt);
+
+struct RemArgs {
+  ProdGeom pg;
+  ProdBufs pb;                       // ypart holds [RG][n_p] partial maxima
+  SyncBufs sb;
+  const unsigned char *in;
+  int64_t ldb_in;                    // bytes
+  const float *scale;                // [n_p]
+  double *err;                       // [n_p] max_k |O_kj / s_j - q_kj|
+};
+struct SelectArgs {
+  const double *err;                 // [n_p]
+  int64_t n_p;
+  double tol;
+  int32_t *cols;                     // [n_p] selected columns, increasing
+  int64_t *count;                    // device scalar
+};
+struct QuantLoArgs {
+  const unsigned char *in;
+  int64_t ldb_in, n_s, n_p, n_lo, ld_lo;   // ld_lo in codes (multiple of 8)
+  const float *scale;
+  const int32_t *cols;
+  unsigned char *out;
+};
+const void *stream_read_kernel(int unroll);   // 512 threads per workgroup
+const void *remmax_kernel(int in_dt, int out_dt);
+const void *select_kernel();
+const void *quantize_lo_kernel(int in_dt, int out_dt);
 
 }  // namespace sr

@@ -40,10 +40,12 @@ struct ProdGeom {
   int G, C, RG;                     // grid size, column groups, row groups (G = C*RG)
   int n_tiles;                      // ceil(n_s / R)
   int64_t n_s, n_p, wslice;         // wslice: columns per column group, multiple of VEC
+  int64_t n_v;                      // streamed columns: n_p, or with a compact remainder
+                                    // plane n_q + n_lo (see Operand)
 };
 
 struct ProdBufs {
-  double *ypart;                    // [RG][n_p]   row-group partial O^T w
+  double *ypart;                    // [RG][n_v]   row-group partial O^T w
   double *spart;                    // [RG][2]     row-group scalars
   u64 *xchg;                        // [RG][kRing][C][words]
   u64 *sink;                        // [G][words]  target of the tail steps' publishes
@@ -77,8 +79,8 @@ __device__ __forceinline__ void init_ctx(WgCtx &ctx, const ProdGeom &pg, uint32_
   map_workgroup((int)blockIdx.x, pg.G, pg.C, ctx.rg, ctx.cg);
   ctx.c0 = (int64_t)ctx.cg * pg.wslice;
   ctx.c1 = ctx.c0 + pg.wslice;
-  if (ctx.c1 > pg.n_p) ctx.c1 = pg.n_p;
-  if (ctx.c0 > pg.n_p) ctx.c0 = pg.n_p;
+  if (ctx.c1 > pg.n_v) ctx.c1 = pg.n_v;
+  if (ctx.c0 > pg.n_v) ctx.c0 = pg.n_v;
   ctx.xstep = 0;
   ctx.gs.flags = flags;
   ctx.gs.abort = abort;
@@ -87,12 +89,51 @@ __device__ __forceinline__ void init_ctx(WgCtx &ctx, const ProdGeom &pg, uint32_
 }
 
 // One matrix operand of the product.
+//
+// Compact remainder plane (scaled storage, lo_cols != nullptr): only the columns
+// lo_cols[0..n_lo) (strictly increasing parameter indices) carry a second code, stored as
+// their own matrix `lo` with row stride ldb_lo.  The single-plane product streams it as n_lo
+// extra columns after the first plane: streamed column c < n_q is parameter c of the first
+// plane (n_q = n_p rounded up to whole 16-byte vectors, so no vector spans both), column
+// n_q + i is remainder column i, whose coefficient is that of parameter lo_cols[i] and whose
+// partial (O^T w) is added to that parameter's when the product is finished.
 struct Operand {
   const unsigned char *O;           // base pointer
-  const unsigned char *lo;          // second code plane (same layout) or nullptr
+  const unsigned char *lo;          // second code plane (same layout, PLANES = 2), the
+                                    // compact remainder plane (lo_cols given), or nullptr
   int64_t ldb;                      // row stride in bytes
   const float *scale;               // per-column scale (scaled storage) or nullptr
+  const int32_t *lo_cols;           // compact remainder plane: parameter of each column
+  int64_t n_lo, ldb_lo;             // its columns and row stride in bytes
+  int64_t n_q;                      // first streamed column of the compact plane; with no
+                                    // compact plane larger than any column
 };
+
+// Parameter of compact remainder column i, kept inside [0, n_p) whatever the list holds.
+__device__ __forceinline__ int64_t lo_param(const int32_t *L, int64_t i, int64_t n_p) {
+  const int64_t j = L[i];
+  return j < 0 ? 0 : (j >= n_p ? n_p - 1 : j);
+}
+
+// First index i in [0, n) with L[i] >= key (L increasing), or n; every lane of the calling
+// wave gets the result.  64-way search: a few rounds of one load per lane.
+__device__ __forceinline__ int64_t lower_bound_wave(const int32_t *L, int64_t n, int64_t key) {
+  const int lane = (int)threadIdx.x & 63;
+  int64_t lo = 0, hi = n;           // every index < lo has L < key, every index >= hi has L >= key
+  while (hi - lo > 64) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t pos = lo + (int64_t)lane * step;
+    const bool less = pos < hi && (int64_t)L[pos] < key;
+    const int c = __popcll(__ballot(less));
+    if (c == 0) return lo;
+    const int64_t nhi = lo + (int64_t)c * step;
+    lo = lo + (int64_t)(c - 1) * step + 1;
+    hi = nhi < hi ? nhi : hi;
+  }
+  const int64_t pos = lo + lane;
+  const bool less = pos < hi && (int64_t)L[pos] < key;
+  return lo + __popcll(__ballot(less));
+}
 
 // Accumulation type of a product: the storage type's own, or float64 when EXACT (used
 // for the residual products of scaled storage, so that the residual is that of the
@@ -115,6 +156,8 @@ template <int DT, int NV, int R, int NDOT, bool EXACT = false, int LOOK = 2, int
 struct Product {
   static_assert(PLANES == 1 || NDOT == 1, "two code planes only for the SR product");
   static constexpr int NOPS = NDOT + PLANES - 1;   // loaded tiles per row (operands, planes)
+  // the single-plane SR product of scaled storage can stream a compact remainder plane
+  static constexpr bool kCompact = PLANES == 1 && NDOT == 1 && Storage<DT>::BYTES == 2;
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int kLook = LOOK;
   static constexpr int kAdv = 2;              // the poll of tile t starts at step t + kAdv
@@ -140,9 +183,11 @@ struct Product {
   static constexpr int PW = NDOT * R * WPD;                  // polled words per column group
 
   // --- per-thread state (data threads) ---
-  int col0;                         // first column of vector 0; vector i starts at col0 + i*NT*VEC
+  int col0;                         // first streamed column of vector 0; vector i starts at col0 + i*NT*VEC
   int nvec;                         // owned vectors that start inside the slice (0..NV)
-  int n_p;                          // total columns (for the mask of a vector straddling n_p)
+  int n_p;                          // parameters (for the mask of a vector straddling n_p)
+  int n_q, n_qe;                    // streamed columns [n_q, n_qe) are the compact remainder
+                                    // plane's (n_q = n_qe = 2^31 - 1 without one)
   acc_t vc[NDOT][NV][VEC];          // v_j * s_j per operand (0 outside the slice)
   acc_t yacc[NV][VEC];              // partial (O^T w)_j
   u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
@@ -171,6 +216,13 @@ struct Product {
 
   __device__ __forceinline__ int64_t colv(int i) const { return (int64_t)col0 + (int64_t)i * (NT * VEC); }
 
+  // Valid elements of the 16-byte vector starting at streamed column c (0..VEC).
+  __device__ __forceinline__ int valid_of(int64_t c) const {
+    const int64_t end = c < n_q ? (int64_t)n_p : (int64_t)n_qe;
+    const int64_t nv = end - c;
+    return nv < 0 ? 0 : (nv > VEC ? VEC : (int)nv);
+  }
+
   // Load the owned coefficients; returns this workgroup's share of obar . v (operand 0).
   __device__ __forceinline__ double setup(const WgCtx &ctx, const ProdGeom &pg, const Operand *ops,
                                           const double *__restrict__ mean, const double *v) {
@@ -180,6 +232,9 @@ struct Product {
     col0 = (int)(ctx.c0 + (int64_t)tid * VEC);
     nvec = 0;
     n_p = (int)pg.n_p;
+    const bool compact = kCompact && ops[0].lo_cols != nullptr;
+    n_q = compact ? (int)ops[0].n_q : 0x7fffffff;
+    n_qe = compact ? (int)(ops[0].n_q + ops[0].n_lo) : 0x7fffffff;
     bool straddles = false;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -188,21 +243,24 @@ struct Product {
       int nvalid = 0;
       if (in) {
         nvec = i + 1;
-        const int64_t rem = pg.n_p - col;
-        nvalid = rem >= VEC ? VEC : (int)rem;
+        nvalid = valid_of(col);
         if (nvalid < VEC) straddles = true;
       }
+      const bool lo = col >= n_q;     // a vector of the compact remainder plane
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
+        // parameter of streamed column col + e
+        int64_t j = col + e;
+        if (lo && e < nvalid) j = lo_param(ops[0].lo_cols, col - n_q + e, pg.n_p);
         double vj = 0.0;
         if (e < nvalid) {
-          vj = ld_coh(&v[col + e]);
-          cpart += mean[col + e] * vj;
+          vj = ld_coh(&v[j]);
+          if (!lo) cpart += mean[j] * vj;
         }
 #pragma unroll
         for (int d = 0; d < NDOT; ++d) {
           double s = 1.0;
-          if (ops[d].scale != nullptr && e < nvalid) s = (double)ops[d].scale[col + e];
+          if (ops[d].scale != nullptr && e < nvalid) s = (double)ops[d].scale[j];
           vc[d][i][e] = (acc_t)(vj * s);
         }
         yacc[i][e] = (acc_t)0;
@@ -232,10 +290,14 @@ struct Product {
         const Operand &op = ops[PLANES == 2 ? 0 : d];
         const unsigned char *base = (PLANES == 2 && d == 1) ? op.lo : op.O;
         const unsigned char *rowp = base + row * op.ldb;
+        // the compact remainder plane's row (its vectors are selected per thread)
+        const unsigned char *rowl = kCompact ? op.lo + row * op.ldb_lo : rowp;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
           const int64_t col = i < nvec ? colv(i) : 0;
-          buf[B][d][r][i] = load_stream(rowp + col * St::BYTES);
+          // one load either way (the address is selected), so no load sits in a branch
+          const bool lo = kCompact && col >= n_q;
+          buf[B][d][r][i] = load_stream(lo ? rowl + (col - n_q) * St::BYTES : rowp + col * St::BYTES);
         }
       }
   }
@@ -247,9 +309,7 @@ struct Product {
       // of each vector is computed, not looked up, so the tile stays in registers
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        int nv = n_p - (col0 + i * (NT * VEC));
-        nv = nv < 0 ? 0 : (nv > VEC ? VEC : nv);
-        const u32x4 m = elem_mask(nv);
+        const u32x4 m = elem_mask(valid_of(colv(i)));
 #pragma unroll
         for (int d = 0; d < NOPS; ++d)
 #pragma unroll
@@ -602,10 +662,11 @@ struct Product {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       if (i >= nvec) continue;
+      const int nvalid = valid_of(colv(i));
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         const int64_t col = colv(i) + e;
-        if (col < pg.n_p) st_coh(&pb.ypart[(int64_t)ctx.rg * pg.n_p + col], (double)yacc[i][e]);
+        if (e < nvalid) st_coh(&pb.ypart[(int64_t)ctx.rg * pg.n_v + col], (double)yacc[i][e]);
       }
     }
     if (ctx.cg == 0 && threadIdx.x == 0) {
@@ -619,8 +680,35 @@ struct Product {
 // S1 = sum_rg spart[rg][0]; a fixed summation order over row groups.
 __device__ __forceinline__ double finish_column(const ProdBufs &pb, const ProdGeom &pg, int64_t j) {
   double acc = 0.0;
-  for (int rg = 0; rg < pg.RG; ++rg) acc += ld_coh(&pb.ypart[(int64_t)rg * pg.n_p + j]);
+  for (int rg = 0; rg < pg.RG; ++rg) acc += ld_coh(&pb.ypart[(int64_t)rg * pg.n_v + j]);
   return acc;
+}
+
+// Remainder columns [i0, i1) of a compact plane whose parameters lie in [j0, j1).
+__device__ __forceinline__ void lo_range(const Operand &op, int64_t j0, int64_t j1, int64_t &i0, int64_t &i1) {
+  if (op.lo_cols == nullptr) {
+    i0 = i1 = 0;
+    return;
+  }
+  i0 = lower_bound_wave(op.lo_cols, op.n_lo, j0);
+  i1 = lower_bound_wave(op.lo_cols, op.n_lo, j1);
+}
+
+// Add the compact remainder plane's share to the finished columns of this workgroup:
+// y_j += s_j (sum_rg ypart[rg][n_q + i]) / n_s for the remainder columns i in [i0, i1)
+// (parameters j = lo_cols[i] inside the workgroup's finished range).  The callers wrote
+// y_j in the same workgroup; barriers before and after order the accesses.
+template <int NT>
+__device__ __forceinline__ void finish_lo(const ProdBufs &pb, const ProdGeom &pg, const Operand &op, int64_t i0,
+                                          int64_t i1, double inv_n, double *y) {
+  if (i1 <= i0) return;
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += NT) {
+    const int64_t j = lo_param(op.lo_cols, i, pg.n_p);
+    const double acc = finish_column(pb, pg, op.n_q + i);
+    y[j] += (double)op.scale[j] * acc * inv_n;
+  }
+  __syncthreads();
 }
 
 __device__ __forceinline__ void sum_row_scalars(const ProdBufs &pb, const ProdGeom &pg, double &S1, double &S2) {

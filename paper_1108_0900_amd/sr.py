@@ -30,13 +30,14 @@ _c_i64, _c_i32, _c_p, _c_d = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ct
 
 class SrMatrix(ctypes.Structure):
     _fields_ = [("n_s", _c_i64), ("n_p", _c_i64), ("ld", _c_i64), ("dtype", _c_i32), ("reserved", _c_i32),
-                ("O", _c_p), ("O_lo", _c_p), ("col_scale", _c_p), ("col_mean", _c_p)]
+                ("O", _c_p), ("O_lo", _c_p), ("col_scale", _c_p), ("col_mean", _c_p), ("lo_cols", _c_p),
+                ("n_lo", _c_i64), ("ld_lo", _c_i64)]
 
 
 class SrCgOpts(ctypes.Structure):
     _fields_ = [("rtol", _c_d), ("max_iter", _c_i32), ("refresh_every", _c_i32), ("use_x0", _c_i32),
                 ("restart_on_refresh", _c_i32), ("res_history", _c_p), ("refresh_drop", _c_d),
-                ("refine", _c_i32), ("precond", _c_i32)]
+                ("precond", _c_i32), ("search_f64", _c_i32), ("reserved", _c_i32)]
 
 
 class SrCgInfo(ctypes.Structure):
@@ -73,7 +74,12 @@ PROTOTYPES = {
     "lm_davidson": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix),
                                    ctypes.POINTER(LmDavidsonOpts), _c_p, ctypes.POINTER(LmDavidsonInfo), _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
+    "sr_remainder_columns": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_d, _c_p,
+                                            ctypes.POINTER(_c_i64), _c_p]),
+    "sr_quantize_remainder": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p,
+                                             _c_i64, _c_p]),
     "sr_release": (ctypes.c_int, []),
+    "sr_stream_read": (ctypes.c_int, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p]),
     "sr_adjoint": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, ctypes.c_int64,
                                   _c_p, _c_p]),
     "sr_svk_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_i32, _c_p, ctypes.POINTER(_c_d), _c_p, _c_i32,
@@ -135,7 +141,8 @@ class Matrix:
     n_p: int
     scale: torch.Tensor | None = None
     mean: torch.Tensor | None = None
-    lo: torch.Tensor | None = None   # second code plane, same layout as O
+    lo: torch.Tensor | None = None   # second code plane: same layout as O, or compact (n_s, n_lo)
+    lo_cols: torch.Tensor | None = None  # int32 parameters of the compact plane's columns
 
     @property
     def dtype_code(self) -> int:
@@ -159,15 +166,48 @@ class Matrix:
         m.O_lo = None if self.lo is None else self.lo.data_ptr()
         m.col_scale = None if self.scale is None else self.scale.data_ptr()
         m.col_mean = None if self.mean is None else self.mean.data_ptr()
+        m.lo_cols = None
+        m.n_lo = 0
+        m.ld_lo = 0
+        if self.lo_cols is not None:
+            m.lo_cols = self.lo_cols.data_ptr() if self.lo_cols.numel() else None
+            m.n_lo = self.lo_cols.numel()
+            if m.n_lo:
+                m.ld_lo = self.lo.stride(0) if self.lo.shape[0] > 1 else ((m.n_lo + 7) // 8) * 8
+            else:
+                m.O_lo = None
         return m
+
+    @property
+    def n_lo(self) -> int:
+        return 0 if self.lo_cols is None else self.lo_cols.numel()
+
+
+def _padded(t: torch.Tensor, vec: int) -> torch.Tensor:
+    """t itself if its layout meets the rules of sr.h (16-byte aligned base, row stride a
+    multiple of 16 bytes, unit column stride, rows spanning the allocation), else a copy
+    with padded rows."""
+    n_s, n = t.shape
+    eb = t.element_size()
+    ld = t.stride(0) if n_s > 1 else ((n + vec - 1) // vec) * vec
+    ok = t.stride(1) == 1 and ld >= n and (ld * eb) % 16 == 0 and t.data_ptr() % 16 == 0
+    if ok:
+        need = t.storage_offset() + (n_s - 1) * ld + ((n + vec - 1) // vec) * vec
+        ok = need <= t.untyped_storage().nbytes() // eb
+    if ok:
+        return t
+    P = torch.zeros(n_s, max(vec, ((n + vec - 1) // vec) * vec), dtype=t.dtype, device=t.device)
+    P[:, :n] = t
+    return P[:, :n]
 
 
 def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Tensor | None = None,
-              lo: torch.Tensor | None = None) -> Matrix:
+              lo: torch.Tensor | None = None, lo_cols: torch.Tensor | None = None) -> Matrix:
     """Wrap a 2-D device tensor (float64/float32, or bfloat16/float16 codes with a float32
     column scale).  A copy with padded rows is made only when the layout rules of sr.h
     (16-byte aligned base, row stride a multiple of 16 bytes, unit column stride, rows
-    spanning the allocation) are not met."""
+    spanning the allocation) are not met.  `lo` is the second code plane: the full plane
+    (shape of O), or with `lo_cols` (int32, increasing) the compact plane of those columns."""
     if O.dim() != 2:
         raise ValueError("O must be 2-D")
     if O.dtype not in _TORCH_DT:
@@ -190,6 +230,16 @@ def as_matrix(O: torch.Tensor, scale: torch.Tensor | None = None, mean: torch.Te
         scale = scale.contiguous()
     if mean is not None:
         mean = mean.contiguous()
+    if lo_cols is not None:
+        lo_cols = lo_cols.to(torch.int32).contiguous()
+        if lo is None and lo_cols.numel():
+            raise ValueError("lo_cols needs the compact plane lo")
+        if lo is not None:
+            if lo.dim() != 2 or lo.shape != (n_s, lo_cols.numel()) or lo.dtype != O.dtype:
+                raise ValueError("the compact plane must be (n_s, len(lo_cols)) of O's dtype")
+            if lo_cols.numel():
+                lo = _padded(lo, vec)
+        return Matrix(O=O, n_p=n_p, scale=scale, mean=mean, lo=lo, lo_cols=lo_cols)
     if lo is not None:
         if lo.shape != O.shape or lo.dtype != O.dtype:
             raise ValueError("lo must have the shape and dtype of O")
@@ -239,8 +289,8 @@ def sr_sv_product(M: Matrix, v: torch.Tensor, eps: float = 0.0, out: torch.Tenso
 
 def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max_iter: int = 0,
                 refresh_every: int = 0, x0: torch.Tensor | None = None, history: bool = False,
-                restart_on_refresh: bool = False, refresh_drop: float = 0.0, refine: bool = False,
-                precond: bool = False, out: torch.Tensor | None = None, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP,
+                restart_on_refresh: bool = False, refresh_drop: float = 0.0,
+                precond: bool = False, search_f64: bool = False, out: torch.Tensor | None = None, raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP,
                                                            SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
     """CG solve of (S + eps I) x = g (sr_cg_solve).  Returns (x, info dict)."""
     g = _vec(g, M.n_p, "g")
@@ -255,8 +305,8 @@ def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max
     opts.use_x0 = 1 if x0 is not None else 0
     opts.restart_on_refresh = 1 if restart_on_refresh else 0
     opts.refresh_drop = float(refresh_drop)
-    opts.refine = 1 if refine else 0
     opts.precond = 1 if precond else 0
+    opts.search_f64 = 1 if search_f64 else 0
     hist = None
     if history:
         mi = max_iter if max_iter > 0 else M.n_p + 100
@@ -434,10 +484,47 @@ def sr_adjoint(M: Matrix, E: torch.Tensor, x: torch.Tensor, lam: torch.Tensor, d
     return dO, dE, p12
 
 
+REMAINDER_TOL = {torch.bfloat16: 2.0 ** -17, torch.float16: 2.0 ** -21}
+
+
+def sr_remainder_columns(O: torch.Tensor, scale: torch.Tensor, out_dtype=torch.bfloat16, tol: float | None = None,
+                         stream=None) -> torch.Tensor:
+    """Columns whose single-plane codes miss `tol` (default: the two-plane error bound),
+    as an increasing int32 tensor (sr_remainder_columns)."""
+    Min = as_matrix(O)
+    n_s, n_p = O.shape
+    cols = torch.empty(n_p, dtype=torch.int32, device=O.device)
+    n = _c_i64(0)
+    tol = REMAINDER_TOL[out_dtype] if tol is None else float(tol)
+    _check(lib().sr_remainder_columns(n_s, n_p, _ptr(Min.O), Min.ld, Min.dtype_code, _TORCH_DT[out_dtype], _ptr(scale),
+                                      tol, _ptr(cols), ctypes.byref(n), _stream(stream)), "sr_remainder_columns")
+    return cols[: n.value].clone()
+
+
+def sr_quantize_remainder(O: torch.Tensor, scale: torch.Tensor, lo_cols: torch.Tensor, out_dtype=torch.bfloat16,
+                          stream=None) -> torch.Tensor:
+    """The compact remainder plane of the columns lo_cols, (n_s, n_lo) codes viewed from an
+    (n_s, ld_lo) tensor (sr_quantize_remainder)."""
+    Min = as_matrix(O)
+    n_s, n_p = O.shape
+    n_lo = lo_cols.numel()
+    ld_lo = max(8, ((n_lo + 7) // 8) * 8)
+    q_lo = torch.empty(n_s, ld_lo, dtype=out_dtype, device=O.device)
+    _check(lib().sr_quantize_remainder(n_s, n_p, _ptr(Min.O), Min.ld, Min.dtype_code, _TORCH_DT[out_dtype],
+                                       _ptr(scale), _ptr(lo_cols.to(torch.int32).contiguous()), n_lo, _ptr(q_lo),
+                                       ld_lo, _stream(stream)), "sr_quantize_remainder")
+    return q_lo[:, :n_lo]
+
+
 def sr_quantize(O: torch.Tensor, out_dtype=torch.bfloat16, with_lo: bool = False, stream=None):
     """bf16/f16 codes with per-column float32 scales (sr_quantize).  Returns (q, scale), or
     (q, scale, lo) with the second code plane; codes are (n_s, ld) tensors viewed as
-    (n_s, n_p)."""
+    (n_s, n_p).  with_lo="compact" gives (q, scale, lo, lo_cols): the remainder plane of the
+    columns that need it only (sr_remainder_columns, sr_quantize_remainder)."""
+    if with_lo == "compact":
+        q, s = sr_quantize(O, out_dtype, False, stream)
+        cols = sr_remainder_columns(O, s, out_dtype, stream=stream)
+        return q, s, sr_quantize_remainder(O, s, cols, out_dtype, stream=stream), cols
     if O.dtype not in (torch.float64, torch.float32) or O.dim() != 2:
         raise ValueError("O must be a 2-D float64/float32 tensor")
     Min = as_matrix(O)
@@ -477,3 +564,14 @@ def set_tile_config(dtype=None, kind: int = 0, nv: int = 0, rows: int = 0, looka
 
 def release():
     return lib().sr_release()
+
+
+def stream_read(t: torch.Tensor, blocks_per_cu: int = 2, unroll: int = 4, stream=None) -> torch.Tensor:
+    """Read all of t's bytes once with the products' streaming loads (sr_stream_read);
+    returns the per-workgroup folded words (to keep the loads)."""
+    nbytes = (t.numel() * t.element_size()) // 16 * 16
+    cus = torch.cuda.get_device_properties(t.device).multi_processor_count
+    sink = torch.empty(cus * blocks_per_cu, dtype=torch.int32, device=t.device)
+    _check(lib().sr_stream_read(_ptr(t), nbytes, int(blocks_per_cu), int(unroll), _ptr(sink), _stream(stream)),
+           "sr_stream_read")
+    return sink

@@ -35,15 +35,41 @@ def test_library_exports_every_declared_symbol():
     assert set(sr.PROTOTYPES) == set(_declared_functions())
 
 
-def test_struct_layouts_match_header():
-    # sr_matrix: 3 int64 + 2 int32 + 4 pointers; sr_cg_opts: double + 4 int32 + pointer + double
-    # + int32 (padded);
-    # sr_cg_info: 4 int32 + 2 double
-    assert ctypes.sizeof(sr.SrMatrix) == 8 * 3 + 4 * 2 + 8 * 4
-    assert ctypes.sizeof(sr.SrCgOpts) == 8 + 4 * 4 + 8 + 8 + 8
-    assert ctypes.sizeof(sr.SrCgInfo) == 4 * 4 + 8 * 2
-    assert ctypes.sizeof(sr.LmDavidsonOpts) == 8 + 4 * 4
-    assert ctypes.sizeof(sr.LmDavidsonInfo) == 4 * 4 + 8 * 2
+_STRUCTS = {"sr_matrix": "SrMatrix", "sr_cg_opts": "SrCgOpts", "sr_cg_info": "SrCgInfo",
+            "lm_davidson_opts": "LmDavidsonOpts", "lm_davidson_info": "LmDavidsonInfo",
+            "sr_batch_system": "SrBatchSystem"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the binding equals what a C compiler makes of
+    include/sr.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sr.h"', 'int main(void) {']
+    for cname, pyname in _STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in getattr(sr, pyname)._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        cname, field, value = line.split()
+        st = getattr(sr, _STRUCTS[cname])
+        if field == "size":
+            assert ctypes.sizeof(st) == int(value), (cname, ctypes.sizeof(st), value)
+        else:
+            assert getattr(st, field).offset == int(value), (cname, field, getattr(st, field).offset, value)
+        seen += 1
+    assert seen == sum(len(getattr(sr, p)._fields_) + 1 for p in _STRUCTS.values())
 
 
 def test_status_strings_and_version():
@@ -114,9 +140,12 @@ def test_invalid_scalars_rejected():
         opts.refresh_drop = drop
         assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
     opts.refresh_drop = 0.0
-    opts.refine = 2
+    opts.search_f64 = 2
     assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
-    opts.refine = 0
+    opts.search_f64 = 0
+    opts.reserved = 1
+    assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
+    opts.reserved = 0
     opts.precond = 2
     assert L.sr_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(opts), None, None) == sr.SR_ERR_INVALID
     opts.precond = 1          # Jacobi needs float64 / float32 storage, one plane

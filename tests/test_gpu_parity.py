@@ -331,7 +331,8 @@ def test_two_plane_product_and_grad_match_oracle(shape, dtype):
 
 @pytest.mark.parametrize("dtype", [torch.bfloat16, torch.float16], ids=_dname)
 def test_cg_two_planes_reaches_float64_accuracy(dtype):
-    """Refinement: float32 single-plane search directions, float64 two-plane residuals."""
+    """Full second plane: every product reads both planes and accumulates in float64; the
+    solution is that of the two-plane stored system and within 1e-4 of float64 storage."""
     n_s, n_p = 2000, 1500
     O, E = rand_dense(n_s, n_p, seed=31)
     Os = orc.dequantize_split(*orc.quantize_split(O, _split(dtype)), _split(dtype))
@@ -349,7 +350,7 @@ def test_cg_two_planes_reaches_float64_accuracy(dtype):
 
 def test_cg_two_planes_ill_conditioned_cps_with_refresh_drop():
     """CPS-shaped system with N_p > N_s: the one-plane solution is far from the float64 one;
-    refinement with drop-triggered, restarting refreshes recovers it."""
+    the full second plane with drop-triggered refreshes (no periodic ones) recovers it."""
     d = synth.small_cps_inputs(seed=21, n_s=2048, n_corr=16, n_states=240, n_dense=530)
     O, E = d["O"].numpy(), d["E"].numpy()
     M = _two_plane_matrix(O, torch.bfloat16)

@@ -305,6 +305,12 @@ def test_solve_dense_library_and_woodbury():
     n = O.shape[0]
     dual = (g - Oc.T @ np.linalg.solve(n * eps * np.eye(n) + Oc @ Oc.T, Oc @ g)) / eps
     np.testing.assert_allclose(x, dual, rtol=1e-9, atol=1e-12)
+    # the oracle's dual solve (uniform and non-uniform weights) equals the Cholesky solve
+    np.testing.assert_allclose(orc.solve_dual(O, g, eps), x, rtol=1e-9, atol=1e-12)
+    wts = np.random.default_rng(4).random(25)
+    wts /= wts.sum()
+    np.testing.assert_allclose(orc.solve_dual(O, g, eps, wts), orc.solve_dense(O, g, eps, wts), rtol=1e-9,
+                               atol=1e-12)
 
 
 def test_solve_sherman_morrison_two_samples():
