@@ -552,10 +552,12 @@ def measure_single(args):
     # ---- tile autotuning (not timed): every built configuration on these matrices ----
     from paper_1108_0900_amd import tune
     tiles = {}
-    for name, M in (("f64", M64), (dtype_name, M1 if scaled else Mt)):
+    for name, M in (("f64", M64), (dtype_name, Mt)):
         if name in tiles or args.quick:
             continue
-        res = tune.autotune(M, kind=0, reps=3)
+        # scaled storage: timed on a short CG solve (its search steps and residual products
+        # are separate kernels); float64: on the product
+        res = tune.autotune(M, kind=0, reps=3, cg_iters=4 if M is Mt and scaled and form != "two_planes" else 0)
         tiles[name] = {"best": list(res["best"]), "ms": {str(list(k)): round(v, 3) for k, v in res["ms"].items()}}
         log(f"[bench] tuned {name}: {res['best']}  {tiles[name]['ms']}")
     drop = args.refresh_drop if args.refresh_drop is not None else 0.0

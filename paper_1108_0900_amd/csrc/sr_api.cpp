@@ -1672,7 +1672,7 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
   if (rc) return rc;
   const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
-  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (O->n_p * 8 + 256) + 1024;
+  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (O->n_p * 8 + 256) + 2048;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base);
   if (rc) return rc;
@@ -1690,7 +1690,7 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.r = cv.take<double>(O->n_p);
   a.p = cv.take<double>(O->n_p);
   a.q = cv.take<double>(O->n_p);
-  a.info = cv.take<double>(8);
+  a.info = cv.take<double>(kInfoWords);
   a.eps = eps;
   a.rtol = o.rtol;
   a.max_iter = (int)max_iter;
@@ -1703,15 +1703,48 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   rc = zero_sync(w, stream);
   if (rc) return rc;
   const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
-  const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
-  if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no two-plane CG kernel for this configuration");
-  rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
-  if (rc) return rc;
-  double hinfo[8];
+  // scaled storage with float32 search products and float64 residual products: the two
+  // product codes run in separate kernels that alternate (search phase, residual phase),
+  // batches of pairs between host checks of the state
+  const bool split = scaled(O->dtype) && !two_planes(O) && !exact_search;
+  double hinfo[kInfoWords];
   uint32_t habort = 0;
-  HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
+  if (split) {
+    if (pl.ke->cgs == nullptr || pl.ke->cgr == nullptr)
+      return fail(SR_ERR_INVALID, "sr_cg_solve: no split CG kernels for this configuration");
+    rc = fill_zero(a.info, 2 * kInfoWords, stream);      // state: initial mode, counters 0
+    if (rc) return rc;
+    // a round: search steps up to the next periodic refresh, then the residual phase;
+    // launches in a state that is not theirs return at once
+    const int steps = (o.refresh_every > 0 ? o.refresh_every : 16) + 1;
+    int64_t pairs = 0;
+    for (int batch = 1;; batch = batch < 16 ? 2 * batch : 16) {
+      for (int k = 0; k < batch; ++k) {
+        for (int sidx = 0; sidx < steps; ++sidx) {
+          rc = launch_coop(pl.ke->cgs, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+          if (rc) return rc;
+        }
+        rc = launch_coop(pl.ke->cgr, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+        if (rc) return rc;
+      }
+      pairs += (int64_t)batch * steps;
+      HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      if (habort != 0u || hinfo[kInfoOk] == 0.0 || (int)hinfo[kInfoMode] == kCgModeDone) break;
+      // every pair makes at least one product until the solve is done; past max_iter the
+      // state machine ends it, so this bound is never reached by a working kernel
+      if (pairs > max_iter + 64) return fail(SR_ERR_HIP, "sr_cg_solve: split solve did not finish");
+    }
+  } else {
+    const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
+    if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no CG kernel of this kind for this configuration");
+    rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
   int status = (int)hinfo[2];
   if (habort != 0u || hinfo[6] == 0.0) status = fail(SR_ERR_TIMEOUT, "sr_cg_solve: a cross-workgroup wait timed out");
   else if (status == SR_ERR_NONFINITE) fail(SR_ERR_NONFINITE, "sr_cg_solve: non-finite scalar in CG");

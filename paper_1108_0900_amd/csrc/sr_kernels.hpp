@@ -509,13 +509,14 @@ __global__ __launch_bounds__(NT) void k_lm(LmArgs a) {
 template <int DT, int NV, int R, int L, int P_, int NT>
 struct CgKernel {
   // q[j] = ((S + eps I) vin)_j for this workgroup's vector chunk [j0, j1).  EXACT selects
-  // float64 accumulation (residual products of scaled storage).
-  template <bool EXACT, int PLANES = 1>
+  // float64 accumulation (residual products of scaled storage).  SMALL: one-row tiles, one
+  // tile of lookahead and the shortest poll depth (same column geometry, fewer registers),
+  // used where a kernel holds two product codes or reads two planes; a kernel with a
+  // single product code keeps the tuned tile.
+  template <bool EXACT, int PLANES = 1, bool SMALL = (EXACT || PLANES == 2)>
   __device__ __forceinline__ static bool apply(const CgArgs &a, WgCtx &ctx, const double *vin, double *q,
                                                int64_t j0, int64_t j1, int &products) {
-    // the float64-accumulated and the two-plane products use one-row tiles, one tile of
-    // lookahead and the shortest poll depth (same column geometry, fewer registers)
-    constexpr bool kSmall = EXACT || PLANES == 2;
+    constexpr bool kSmall = SMALL;
     Product<DT, NV, (kSmall ? 1 : R), 1, EXACT, (kSmall ? 1 : L), (kSmall ? 1 : P_), NT, PLANES> P;
     const double cshare = P.setup(ctx, a.pg, &a.op, a.mean, vin);
     if (!P.accumulate(a.pg, a.pb, ctx, &a.op, cshare, nullptr, 0.0)) return false;
@@ -552,7 +553,7 @@ struct CgKernel {
 //                 float64-accumulated
 enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgJacobi = 3, kCgExact = 4 };
 
-template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane>
+template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane, int PH = kPhAll>
 __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   // Conjugate gradient (Hestenes-Stiefel) as a state machine with one product per pass
   // through the loop, so the product code is instantiated once per accumulation type.
@@ -562,11 +563,21 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   //   MODE_CONFIRM  q = A x when the recurrence residual meets rtol; accept or replace r
   //   MODE_FINAL    q = A x to report the true residual of an unconverged exit
   //   MODE_X0       q = A x0 for a warm start
+  //   MODE_INIT     (split solves) x = 0, r = p = g, first decision
   typedef CgKernel<DT, NV, R, L, P_, NT> K;
-  enum { MODE_P, MODE_REFRESH, MODE_CONFIRM, MODE_FINAL, MODE_X0, MODE_DONE };
+  enum { MODE_P = kCgModeP, MODE_REFRESH = kCgModeRefresh, MODE_CONFIRM = kCgModeConfirm, MODE_FINAL = kCgModeFinal,
+         MODE_X0 = kCgModeX0, MODE_DONE = kCgModeDone, MODE_INIT = kCgModeInit };
   constexpr bool kJac = CGM == kCgJacobi;
+  static_assert(PH == kPhAll || (CGM == kCgOnePlane && K::kExactResidual), "split solves: one plane, scaled storage");
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  if constexpr (PH != kPhAll) {
+    // resume: the barrier epochs and exchange steps continue from the previous launch
+    // (every workgroup passed the same barriers and products there)
+    if (ld_coh32(a.sb.abort) != 0u) return;
+    ctx.gs.epoch = ld_coh32(&a.sb.flags[blockIdx.x]);
+    ctx.xstep = (uint32_t)ld_coh(&a.info[kInfoXstep]);
+  }
   const int G = (int)gridDim.x, tid = (int)threadIdx.x;
   const int64_t n = a.pg.n_p;
   const int64_t ch = (n + G - 1) / G;
@@ -578,6 +589,20 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   double rz = 0.0;       // r . z with z = r / (diag S + eps) (Jacobi; rho = r . r stays the test)
   bool ok = true, restart = false;
   int mode;
+  if constexpr (PH != kPhAll) {
+    it = (int)ld_coh(&a.info[kInfoIters]);
+    refreshes = (int)ld_coh(&a.info[kInfoRefreshes]);
+    status = (int)ld_coh(&a.info[kInfoStatus]);
+    products = (int)ld_coh(&a.info[kInfoProducts]);
+    rel_true = ld_coh(&a.info[kInfoRelTrue]);
+    mode = (int)ld_coh(&a.info[kInfoMode]);
+    rho = ld_coh(&a.info[kInfoRho]);
+    gg = ld_coh(&a.info[kInfoGg]);
+    rho_ref = ld_coh(&a.info[kInfoRhoRef]);
+    rz = ld_coh(&a.info[kInfoRz]);
+    if (mode == MODE_DONE || mode == MODE_P || mode == MODE_INIT)
+      return;     // nothing for the residual phase (uniform: every workgroup read the same state)
+  }
 
   // choose the next product from the recurrence residual
   auto decide = [&]() -> int {
@@ -599,9 +624,9 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
     return grid_sync(ctx.gs);
   };
 
-  if (a.use_x0) {
+  if (PH == kPhAll && a.use_x0) {
     mode = MODE_X0;
-  } else {
+  } else if (PH == kPhAll) {
     double prr = 0.0, pgg = 0.0, prz = 0.0;
     for (int64_t j = j0 + tid; j < j1; j += NT) {
       st_coh(&a.x[j], 0.0);
@@ -628,11 +653,16 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
 
   while (ok && mode != MODE_DONE) {
     const bool on_p = (mode == MODE_P);
-    if constexpr (CGM == kCgTwoPlanes) {
+    if (PH == kPhResidual && on_p) break;      // hand over to the search phase
+    if constexpr (PH == kPhResidual) {
+      ok = K::template apply<true>(a, ctx, a.x, a.q, j0, j1, products);
+    } else if constexpr (CGM == kCgTwoPlanes) {
       // one product code for search directions and residuals: float64 accumulation
       // (measured faster here than float32 with the two planes in one kernel)
       ok = K::template apply<true, 2>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
     } else if constexpr (CGM == kCgExact) {
+      // one product code, float64 accumulation (one-row tiles: the tuned float32 tile held
+      // in float64 spills inside the streaming loop)
       ok = K::template apply<true>(a, ctx, on_p ? a.p : a.x, a.q, j0, j1, products);
     } else if constexpr (K::kExactResidual) {
       if (on_p) ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, products);
@@ -645,7 +675,11 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       double ppq = 0.0, pq;
       for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * a.q[j];
       if (!(ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy))) break;
-      if (!isfinite(pq)) { status = -4; break; }
+      if (!isfinite(pq)) {
+        status = -4;
+        mode = MODE_DONE;
+        break;
+      }
       if (!(pq > 0.0)) { status = 2; mode = MODE_FINAL; continue; }
       const double alpha = (kJac ? rz : rho) / pq;
       double prr = 0.0, prz = 0.0;
@@ -745,14 +779,145 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
     }
   }
   if (blockIdx.x == 0 && tid == 0) {
-    a.info[0] = (double)it;
-    a.info[1] = (double)refreshes;
-    a.info[2] = (double)status;
-    a.info[3] = (double)products;
-    a.info[4] = sqrt(rho / gg);
-    a.info[5] = rel_true;
-    a.info[6] = ok ? 1.0 : 0.0;
+    a.info[kInfoIters] = (double)it;
+    a.info[kInfoRefreshes] = (double)refreshes;
+    a.info[kInfoStatus] = (double)status;
+    a.info[kInfoProducts] = (double)products;
+    a.info[kInfoRelRecur] = sqrt(rho / gg);
+    a.info[kInfoRelTrue] = rel_true;
+    a.info[kInfoOk] = ok ? 1.0 : 0.0;
+    a.info[kInfoMode] = (double)(ok ? mode : MODE_DONE);
+    a.info[kInfoRho] = rho;
+    a.info[kInfoGg] = gg;
+    a.info[kInfoRhoRef] = rho_ref;
+    a.info[kInfoRz] = rz;
+    a.info[kInfoXstep] = (double)ctx.xstep;
   }
+}
+
+// One search-direction iteration of a split CG solve (scaled storage, float32 products):
+// q = (S + eps I) p, alpha, x += alpha p, r -= alpha q, rho, beta, p = r + beta p and the
+// next decision, with the state read from CgArgs::info after the product and written back
+// at the end, so nothing but the product is live during its streaming loop.  A launch in
+// the initial state sets up x = 0, r = p = g (or hands a warm start to the residual
+// phase); a launch in any state but the search one returns at once.
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
+  typedef CgKernel<DT, NV, R, L, P_, NT> K;
+  WgCtx ctx;
+  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  if (ld_coh32(a.sb.abort) != 0u) return;
+  const int mode0 = (int)ld_coh(&a.info[kInfoMode]);
+  if (mode0 != kCgModeP && mode0 != kCgModeInit) return;
+  ctx.gs.epoch = ld_coh32(&a.sb.flags[blockIdx.x]);
+  ctx.xstep = (uint32_t)ld_coh(&a.info[kInfoXstep]);
+  const int G = (int)gridDim.x, tid = (int)threadIdx.x;
+  const int64_t n = a.pg.n_p;
+  const int64_t ch = (n + G - 1) / G;
+  const int64_t j0 = min(n, (int64_t)blockIdx.x * ch), j1 = min(n, j0 + ch);
+  int nred = 0;
+  double dummy;
+  auto save = [&](int mode, bool ok, int it, int products, int status, double rho, double gg, double rho_ref) {
+    if (blockIdx.x == 0 && tid == 0) {
+      a.info[kInfoIters] = (double)it;
+      a.info[kInfoStatus] = (double)status;
+      a.info[kInfoProducts] = (double)products;
+      a.info[kInfoRelRecur] = sqrt(rho / gg);
+      a.info[kInfoOk] = ok ? 1.0 : 0.0;
+      a.info[kInfoMode] = (double)(ok ? mode : kCgModeDone);
+      a.info[kInfoRho] = rho;
+      a.info[kInfoGg] = gg;
+      a.info[kInfoRhoRef] = rho_ref;
+      a.info[kInfoXstep] = (double)ctx.xstep;
+    }
+  };
+  auto decide = [&](int it, double rho, double gg, int &status) -> int {
+    const double rel = sqrt(rho / gg);
+    if (a.hist != nullptr && blockIdx.x == 0 && tid == 0 && it <= a.max_iter) a.hist[it] = rel;
+    if (!isfinite(rho)) { status = -4; return kCgModeDone; }
+    if (rel <= a.rtol) return kCgModeConfirm;
+    if (it >= a.max_iter) { status = 1; return kCgModeFinal; }
+    return kCgModeP;
+  };
+
+  if (mode0 == kCgModeInit) {
+    if (a.use_x0) {                 // the warm start's product runs in the residual phase
+      save(kCgModeX0, true, 0, 0, 0, 0.0, 1.0, 0.0);
+      if (blockIdx.x == 0 && tid == 0) a.info[kInfoRelTrue] = -1.0;
+      return;
+    }
+    double prr = 0.0;
+    for (int64_t j = j0 + tid; j < j1; j += NT) {
+      st_coh(&a.x[j], 0.0);
+      const double gj = a.g[j];
+      a.r[j] = gj;
+      st_coh(&a.p[j], gj);
+      prr += gj * gj;
+    }
+    double rho, gg;
+    const bool ok = grid_allreduce2(prr, prr, a.sb.red, nred, ctx.gs, rho, gg);
+    int status = 0, mode;
+    if (blockIdx.x == 0 && tid == 0) a.info[kInfoRelTrue] = -1.0;
+    if (gg == 0.0) {
+      gg = 1.0;
+      mode = kCgModeDone;
+      if (blockIdx.x == 0 && tid == 0) a.info[kInfoRelTrue] = 0.0;
+    } else {
+      mode = decide(0, rho, gg, status);
+    }
+    save(mode, ok, 0, 0, status, rho, gg, rho);
+    return;
+  }
+
+  int dummy_products = 0;
+  bool ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, dummy_products);
+  // the state, read after the product
+  int it = (int)ld_coh(&a.info[kInfoIters]);
+  int products = (int)ld_coh(&a.info[kInfoProducts]) + 1;
+  int status = (int)ld_coh(&a.info[kInfoStatus]);
+  double rho = ld_coh(&a.info[kInfoRho]);
+  const double gg = ld_coh(&a.info[kInfoGg]);
+  const double rho_ref = ld_coh(&a.info[kInfoRhoRef]);
+  int mode = kCgModeP;
+  if (!ok) {
+    save(kCgModeDone, false, it, products, status, rho, gg, rho_ref);
+    return;
+  }
+  double ppq = 0.0, pq;
+  for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * a.q[j];
+  ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy);
+  if (ok && !isfinite(pq)) {
+    status = -4;
+    mode = kCgModeDone;
+  } else if (ok && !(pq > 0.0)) {
+    status = 2;
+    mode = kCgModeFinal;
+  } else if (ok) {
+    const double alpha = rho / pq;
+    double prr = 0.0;
+    for (int64_t j = j0 + tid; j < j1; j += NT) {
+      st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
+      const double rj = a.r[j] - alpha * a.q[j];
+      a.r[j] = rj;
+      prr += rj * rj;
+    }
+    it++;
+    if (a.refresh_every > 0 && it % a.refresh_every == 0) {
+      mode = kCgModeRefresh;        // x is visible to the next launch
+    } else {
+      double rho_new;
+      ok = grid_allreduce2(prr, 0.0, a.sb.red, nred, ctx.gs, rho_new, dummy);
+      if (ok && rho_new <= a.refresh_drop2 * rho_ref && sqrt(rho_new / gg) > a.rtol) {
+        mode = kCgModeRefresh;
+      } else if (ok) {
+        const double beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t j = j0 + tid; j < j1; j += NT) st_coh(&a.p[j], a.r[j] + beta * ld_coh(&a.p[j]));
+        mode = decide(it, rho, gg, status);
+      }
+    }
+  }
+  save(mode, ok, it, products, status, rho, gg, rho_ref);
 }
 
 }  // namespace sr

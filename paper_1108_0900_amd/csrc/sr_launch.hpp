@@ -44,9 +44,21 @@ struct CgArgs {
   int max_iter, refresh_every, use_x0, restart_on_refresh;
   double refresh_drop2;       // squared relative drop that triggers a refresh; 0: off
   double *hist;         // [max_iter + 1] or nullptr
-  double *info;         // [8]
+  double *info;         // [16]: outcome, then the state between the launches of a split solve
   const double *diag;   // [n_p] diag S (Jacobi-preconditioned CG), else nullptr
 };
+
+// A CG solve split over launches (scaled storage with float32 search products and float64
+// residual products, so that each kernel holds a single product code; two in one kernel
+// cost register spills in the streaming loop): k_cg_step runs one search-direction
+// iteration per launch, k_cg<..., kPhResidual> runs the residual products (refresh, exit
+// check, warm start) and returns at the next search step; kPhAll runs a whole solve in one
+// launch.  Between launches the state lives in CgArgs::info.
+enum { kPhAll = 0, kPhResidual = 2 };
+// Layout of CgArgs::info: outcome (read by the host) then the state of a split solve.
+enum { kInfoIters = 0, kInfoRefreshes, kInfoStatus, kInfoProducts, kInfoRelRecur, kInfoRelTrue, kInfoOk,
+       kInfoMode, kInfoRho, kInfoGg, kInfoRhoRef, kInfoRz, kInfoXstep, kInfoWords = 16 };
+enum { kCgModeInit = 0, kCgModeP, kCgModeRefresh, kCgModeConfirm, kCgModeFinal, kCgModeX0, kCgModeDone };
 
 struct GradArgs {
   ProdGeom pg;          // wslice / C / RG for the column reduction (R unused)
@@ -169,6 +181,7 @@ struct KernelEntry {
   const void *cg2;       // CG over two code planes (scaled storage), or nullptr
   const void *cgj;       // Jacobi-preconditioned CG (float64 / float32 storage), or nullptr
   const void *cgx;       // CG with float64-accumulated search products (scaled storage), or nullptr
+  const void *cgs, *cgr; // split CG (scaled storage, one plane): search step and residual phase, or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 

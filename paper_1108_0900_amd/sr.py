@@ -6,6 +6,7 @@ library is not built, `lib()` raises instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -94,6 +95,22 @@ PROTOTYPES = {
 }
 
 _lib = None
+
+
+def _release_at_exit():
+    """Free the library's device workspaces before the interpreter (and with it the HIP
+    runtime) shuts down, after the work queued on the device has finished."""
+    if _lib is None:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+        _lib.sr_release()
+    except Exception:
+        pass
+
+
+atexit.register(_release_at_exit)
 
 
 def lib():

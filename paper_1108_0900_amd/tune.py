@@ -7,7 +7,10 @@ dots per row, the rows per row group, and the bytes per element.  `autotune` tim
 configuration on the caller's own matrix with HIP events and selects the fastest for
 that storage type and product kind, process-wide (`sr.set_tile_config`).  Results can
 be cached in a JSON file keyed by device, storage type, shape and product kind, so a
-later process reuses them without timing.  The CG solve uses the configuration of the SR product (kind 0).
+later process reuses them without timing.  The CG solve uses the configuration of the SR product (kind 0);
+with `cg_iters` > 0 the configurations are timed on a CG solve of that many iterations
+(what the solve runs: for scaled storage its search steps and residual products are
+separate kernels, which need not rank like the standalone product).
 Kind 2 tunes the batched products' geometry (`sr.BATCH_CONFIGS`: rows per update split,
 tasks per workgroup) by timing the 8-column product on the caller's matrix.
 """
@@ -23,9 +26,10 @@ from . import sr
 CACHE_ENV = "SR_TUNE_CACHE"
 
 
-def _key(M: sr.Matrix, kind: int) -> str:
+def _key(M: sr.Matrix, kind: int, cg_iters: int = 0) -> str:
     dev = torch.cuda.get_device_name(M.O.device)
-    return f"{dev}|{str(M.O.dtype).split('.')[-1]}|{M.O.shape[0]}|{M.n_p}|kind{kind}"
+    extra = f"|cg{cg_iters}|lo{M.n_lo}" if cg_iters else ""
+    return f"{dev}|{str(M.O.dtype).split('.')[-1]}|{M.O.shape[0]}|{M.n_p}|kind{kind}{extra}"
 
 
 def _load(path):
@@ -63,10 +67,13 @@ def _median_ms(fn, reps: int, warm: int = 1) -> float:
 
 
 def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None = None,
-             E: torch.Tensor | None = None, D: sr.Matrix | None = None, apply: bool = True) -> dict:
+             E: torch.Tensor | None = None, D: sr.Matrix | None = None, apply: bool = True,
+             cg_iters: int = 0) -> dict:
     """Time every built configuration of the product of `kind` (0: (S + eps I) v,
     1: linear-method H v, which needs E and D, 2: the 8-column batched product, whose
     configurations are (split_rows, tasks)) on M; select the fastest if `apply`.
+    kind 0 with cg_iters > 0 times a CG solve of cg_iters iterations instead (M may carry a
+    compact remainder plane then).
 
     Returns {"best": (nv, rows, lookahead, poll_depth, threads), "ms": {config: ms},
     "cached": bool}.  A configuration whose call fails (for example, one that cannot hold
@@ -76,11 +83,11 @@ def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None 
         raise ValueError("kind must be 0 (SR product), 1 (linear-method product) or 2 (batched products)")
     if kind == 1 and (E is None or D is None):
         raise ValueError("the linear-method product needs E and D")
-    if M.lo is not None:
-        raise ValueError("tune the first code plane alone (two-plane products use a fixed tile)")
+    if M.lo is not None and not (kind == 0 and cg_iters > 0 and M.lo_cols is not None):
+        raise ValueError("tune the first code plane alone (full two-plane products use a fixed tile)")
     cache_path = cache_path or os.environ.get(CACHE_ENV)
     table = _load(cache_path)
-    key = _key(M, kind)
+    key = _key(M, kind, cg_iters if kind == 0 else 0)
     if key in table:
         best = tuple(table[key]["best"])
         if apply:
@@ -113,7 +120,15 @@ def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None 
     n = M.n_p + (1 if kind == 1 else 0)
     v = torch.randn(n, generator=gen, dtype=torch.float64, device=M.O.device)
     y = torch.empty_like(v)
-    if kind == 0:
+    if kind == 0 and cg_iters > 0:
+        g = torch.randn(M.n_p, generator=gen, dtype=torch.float64, device=M.O.device)
+        x = torch.empty_like(g)
+
+        def call():
+            sr.sr_cg_solve(M, g, 0.1, rtol=1e-300, max_iter=cg_iters, refresh_every=0, out=x,
+                           raise_on=(sr.SR_ERR_INVALID, sr.SR_ERR_NOMEM, sr.SR_ERR_HIP, sr.SR_ERR_NODEVICE,
+                                     sr.SR_ERR_TIMEOUT))
+    elif kind == 0:
         def call():
             sr.sr_sv_product(M, v, 0.1, out=y)
     else:

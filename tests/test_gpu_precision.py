@@ -249,3 +249,28 @@ def test_cg_one_plane_float64_refresh_reaches_rtol(dtype):
     kappa = (lam[-1] + eps_ref) / (lam[0] + eps_ref)
     x_ref = orc.solve_dense(Os, g_ref, eps_ref)
     assert rel_err(to_np(x), x_ref) <= 2 * kappa * rtol, (rel_err(to_np(x), x_ref), kappa)
+
+
+def test_autotune_on_cg_with_compact_plane(tmp_path):
+    """Tiles of scaled storage timed on a short CG solve over the compact plane: a built
+    configuration is selected and cached, and the solve with it matches the oracle."""
+    from paper_1108_0900_amd import tune
+    O, E = _cps_permuted(600, 12, 240, 300, seed=51)
+    M, _, _ = _compact_matrix(O, torch.bfloat16)
+    cache = str(tmp_path / "tune.json")
+    try:
+        res = tune.autotune(M, kind=0, reps=2, cache_path=cache, cg_iters=3)
+        assert res["best"] in sr.tile_configs(torch.bfloat16, 0) and not res["cached"]
+        again = tune.autotune(M, kind=0, cache_path=cache, cg_iters=3)
+        assert again["cached"] and again["best"] == res["best"]
+        Os = orc.dequantize_cols(*orc.quantize_cols(O, "bf16"), "bf16")
+        st = sr.sr_grad(M, to_dev(E))
+        M.mean = st["mean"]
+        eps = 1e-2 * float(st["diag"].mean())
+        x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=1e-8, refresh_every=20)
+        assert info["status"] == 0, info
+        g_ref = orc.energy_gradient(Os, E)
+        r = g_ref - orc.sv_product_swapped(Os, to_np(x), 1e-2 * orc.diag_overlap(Os).mean())
+        assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(g_ref)
+    finally:
+        sr.set_tile_config()
