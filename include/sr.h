@@ -144,6 +144,18 @@ int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean,
 int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * sr_sv_product_noalloc: sr_sv_product for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and result; it calls no hipMalloc, hipFree or allocating routine.  Its scratch
+ * (barrier flags, partial-dot exchange, row-group partials) is a 36 MiB array the library
+ * holds on each device for the life of the process; a product that would need more returns
+ * SR_ERR_INVALID (no built tile plans more than 33 MiB).  O->col_mean is required (the call
+ * runs no prepare pass).  Calls that overlap in time on one device share that array and
+ * race: serialize them (one stream, or events).
+ * ------------------------------------------------------------------------------------ */
+int sr_sv_product_noalloc(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * sr_cg_solve: conjugate gradient on (S + eps I) x = g with S applied only through the
  * product above (Sec. II.A), all iterations in one persistent launch.
  * g: [n_p] float64 right-hand side.  x: [n_p] float64 solution (starting guess on

@@ -668,6 +668,32 @@ int lm_lincomb(const double *X, const double *ca, int mx, const double *Z, const
   return SR_OK;
 }
 
+// Scratch of sr_sv_product_noalloc: barrier flags, exchange ring, row-group partials.  The
+// largest product any built tile plans needs G * (widest column slice) float64 partials,
+// 256 * 16384 * 8 bytes = 32 MiB, plus under 0.5 MiB of synchronisation data.  Each device
+// holds its own copy for the life of the process.  In host code the name is not a device
+// address; scratch_address gives the device's.
+constexpr size_t kNoAllocScratchBytes = (size_t)36 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::map<int, void *> g_scratch_ptr;
+
+// Device address of `scratch` on device `dev` (the current device), looked up once.
+int scratch_address(int dev, void **out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+      (void)hipGetLastError();
+      return fail(SR_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    }
+    it = g_scratch_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return SR_OK;
+}
+
 }  // namespace
 
 // ======================================================================================
@@ -809,12 +835,43 @@ int sr_grad(const sr_matrix *O, const double *E, double *g, double *E_mean, doub
   return run_grad(O, E, g, E_mean, col_mean_out, diagS_out, dev, di, stream);
 }
 
-int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream) {
-  int rc = check_matrix(O, "sr_sv_product");
+static int check_sv_args(const sr_matrix *O, const double *v, double *y, double eps, const char *name) {
+  int rc = check_matrix(O, name);
   if (rc) return rc;
-  if (v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: null v or y");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_sv_product: eps must be finite and >= 0");
-  if (ranges_overlap(v, O->n_p * 8, y, O->n_p * 8)) return fail(SR_ERR_INVALID, "sr_sv_product: v and y overlap");
+  if (v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "%s: null v or y", name);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
+  if (ranges_overlap(v, O->n_p * 8, y, O->n_p * 8)) return fail(SR_ERR_INVALID, "%s: v and y overlap", name);
+  return SR_OK;
+}
+
+// The product's launch over a caller-provided workspace of prod_ws_bytes(pl, RG * n_v).
+static int launch_sv(const sr_matrix *O, const double *v, double *y, double eps, const double *mean, const Plan &pl,
+                     void *base, hipStream_t stream) {
+  const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  SvArgs a{};
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(O);
+  a.mean = mean;
+  a.v = v;
+  a.y = y;
+  a.eps = eps;
+  int rc = zero_sync(w, stream);
+  if (rc) return rc;
+  if (two_planes(O)) {
+    if (pl.ke->sv2 == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: no two-plane kernel for this configuration");
+    return launch_coop(pl.ke->sv2, pl.pg.G, &a, stream, pl.ke->nt, 0);
+  }
+  return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+}
+
+int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream) {
+  int rc = check_sv_args(O, v, y, eps, "sr_sv_product");
+  if (rc) return rc;
   int dev;
   DeviceInfo di;
   rc = device_check(&dev, &di);
@@ -830,29 +887,32 @@ int sr_sv_product(const sr_matrix *O, const double *v, double *y, double eps, hi
   Plan pl;
   rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
   if (rc) return rc;
-  const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
   void *base = nullptr;
-  rc = get_workspace(dev, stream, prod_ws_bytes(pl, ypd), &base);
+  rc = get_workspace(dev, stream, prod_ws_bytes(pl, (int64_t)pl.pg.RG * pl.pg.n_v), &base);
   if (rc) return rc;
-  Carve cv(base);
-  ProdWs w;
-  carve_prod(cv, pl, ypd, &w);
-  SvArgs a{};
-  a.pg = pl.pg;
-  a.pb = w.pb;
-  a.sb = w.sb;
-  a.op = make_operand(O);
-  a.mean = mean;
-  a.v = v;
-  a.y = y;
-  a.eps = eps;
-  rc = zero_sync(w, stream);
+  return launch_sv(O, v, y, eps, mean, pl, base, stream);
+}
+
+int sr_sv_product_noalloc(const sr_matrix *O, const double *v, double *y, double eps, hipStream_t stream) {
+  int rc = check_sv_args(O, v, y, eps, "sr_sv_product_noalloc");
   if (rc) return rc;
-  if (two_planes(O)) {
-    if (pl.ke->sv2 == nullptr) return fail(SR_ERR_INVALID, "sr_sv_product: no two-plane kernel for this configuration");
-    return launch_coop(pl.ke->sv2, pl.pg.G, &a, stream, pl.ke->nt, 0);
-  }
-  return launch_coop(pl.ke->sv, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+  if (O->col_mean == nullptr)
+    return fail(SR_ERR_INVALID, "sr_sv_product_noalloc: col_mean is required (no pass computes it here)");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
+  if (rc) return rc;
+  const size_t need = prod_ws_bytes(pl, (int64_t)pl.pg.RG * pl.pg.n_v);
+  if (need > kNoAllocScratchBytes)
+    return fail(SR_ERR_INVALID, "sr_sv_product_noalloc: this product needs %zu bytes of scratch, more than the %zu "
+                                "the library holds", need, kNoAllocScratchBytes);
+  void *base = nullptr;
+  rc = scratch_address(dev, &base);
+  if (rc) return rc;
+  return launch_sv(O, v, y, eps, O->col_mean, pl, base, stream);
 }
 
 // ------------------------------------------------------------------------------------

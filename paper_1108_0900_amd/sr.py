@@ -66,6 +66,7 @@ class SrBatchSystem(ctypes.Structure):
 PROTOTYPES = {
     "sr_grad": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "sr_sv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_d, _c_p]),
+    "sr_sv_product_noalloc": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_d, _c_p]),
     "sr_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
                                    ctypes.POINTER(SrCgInfo), _c_p]),
     "lm_hv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p]),
@@ -302,6 +303,18 @@ def sr_sv_product(M: Matrix, v: torch.Tensor, eps: float = 0.0, out: torch.Tenso
     m = M.c()
     _check(lib().sr_sv_product(ctypes.byref(m), _ptr(v), _ptr(y), float(eps), _stream(stream)), "sr_sv_product")
     return y
+
+
+def sr_sv_product_noalloc(M: Matrix, v: torch.Tensor, eps: float, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """y = (S + eps I) v with the library's fixed scratch, no allocation
+    (sr_sv_product_noalloc); M.mean and `out` are required."""
+    v = _vec(v, M.n_p, "v")
+    if M.mean is None:
+        raise ValueError("sr_sv_product_noalloc needs the column means (M.mean)")
+    m = M.c()
+    _check(lib().sr_sv_product_noalloc(ctypes.byref(m), _ptr(v), _ptr(out), float(eps), _stream(stream)),
+           "sr_sv_product_noalloc")
+    return out
 
 
 def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max_iter: int = 0,
