@@ -179,6 +179,18 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x,
                 const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * sr_cg_solve_async: sr_cg_solve without waiting for the solve: the outcome goes to device
+ * memory, info_dev [16] float64: iters, refreshes, status (an sr_status value), products,
+ * rel_res_recur, rel_res_true, then words the kernel uses for itself.  The whole solve is
+ * one persistent launch (for bf16/f16 storage with float32 search products that kernel
+ * holds both product codes and runs slower than the split solve sr_cg_solve uses).  Only a
+ * workspace that has to grow synchronizes `stream` (sr_workspace_reserve avoids it).
+ * Returns SR_OK once the work is queued, or an error detected before any launch.
+ * ------------------------------------------------------------------------------------ */
+int sr_cg_solve_async(const sr_matrix *O, const double *g, double eps, double *x,
+                      const sr_cg_opts *opt, double *info_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * lm_hv_product: the linear method's Hamiltonian product in the basis
  * {Psi, Psi^i - obar_i Psi} (Sec. II.B, Eq. linear_eigen), estimated from local energies
  * E and their parameter derivatives D (D_kj = d E_L / d alpha_j on sample k):
@@ -254,17 +266,20 @@ int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, co
  * sr_cg_solve).  One read of O gives p1 = Oc x and p2 = Oc lambda; then
  *   dE_k      = (2/n_s) p2_k                                              [n_s]
  *   dO_kj     = (1/n_s) [ (2 (E_k - E_mean) - p1_k) lambda_j - p2_k x_j ]   [n_s][ld_dO]
- * (dL/dg = lambda and dL/deps = -lambda . x need no kernel).  The derivative is taken
+ *   deps      = -lambda . x                                               (device scalar)
+ * (dL/dg = lambda needs no kernel).  The derivative is taken
  * with respect to the stored values of O (s_j q_kj for scaled storage), the column means
  * depending on O included.
  * O: single code plane (O_lo = NULL); col_mean may be NULL (computed).  E, x, lam:
- * device float64 [n_s], [n_p], [n_p].  dE: device [n_s] float64 or NULL.  dO: device,
+ * device float64 [n_s], [n_p], [n_p].  dE: device [n_s] float64 or NULL.  deps: device
+ * float64 scalar or NULL (with dE, dO and p12 all NULL only deps is computed, without a
+ * pass over O).  dO: device,
  * dO_dtype SR_F64 or SR_F32, row stride ld_dO >= n_p elements with 16-byte aligned rows,
  * or NULL (columns >= n_p are not written).  p12: device [2 n_s] float64 (p1 then p2) or
  * NULL.  Outputs must not overlap the inputs.  Asynchronous on `stream`.
  * ------------------------------------------------------------------------------------ */
 int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const double *lam, double *dE,
-               void *dO, int32_t dO_dtype, int64_t ld_dO, double *p12, hipStream_t stream);
+               void *dO, int32_t dO_dtype, int64_t ld_dO, double *p12, double *deps, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
  * lm_davidson: lowest eigenpair of the linear method's generalized eigenproblem
@@ -369,6 +384,23 @@ int sr_tile_configs(int32_t dtype, int32_t kind, int32_t *out, int32_t max);
 int sr_set_batch_config(int32_t split_rows, int32_t tasks);
 int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, int32_t lookahead,
                        int32_t poll_delay, int32_t threads, int32_t col_groups);
+
+/* ------------------------------------------------------------------------------------
+ * Workspace (the library's own memory for partials, exchange words and CG vectors; one per
+ * device and stream, grown on demand by reallocation, which synchronizes the stream).
+ * sr_workspace_bytes: bytes that workspace must hold for `call` (enum sr_call) on the
+ * matrix O on the current device (tile choices in effect included; a call with
+ * O->col_mean NULL also runs the prepare pass, counted here, and keeps the n_p column
+ * means in a separate small buffer of n_p * 8 bytes).  Negative: an sr_status error.
+ * sr_workspace_reserve: grows the (current device, stream) workspace to at least `bytes`
+ * now, so that later calls within that size allocate nothing there.
+ * sr_workspace_held: bytes the (current device, stream) workspace holds (0 if none).
+ * ------------------------------------------------------------------------------------ */
+enum sr_call { SR_CALL_GRAD = 0, SR_CALL_SV_PRODUCT = 1, SR_CALL_CG_SOLVE = 2, SR_CALL_LM_HV_PRODUCT = 3,
+               SR_CALL_ADJOINT = 4 };
+int64_t sr_workspace_bytes(const sr_matrix *O, int32_t call);
+int sr_workspace_reserve(int64_t bytes, hipStream_t stream);
+int64_t sr_workspace_held(hipStream_t stream);
 
 /* Measurement helper (not in the paper): reads `bytes` (a multiple of 16) at p (16-byte
  * aligned, device) with the products' non-temporal 16-byte loads, `unroll` (2, 4 or 8)

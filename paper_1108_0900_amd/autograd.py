@@ -49,14 +49,16 @@ class SRSolve(torch.autograd.Function):
                                    refresh_every=ctx.refresh_every, precond=ctx.precond)
         if info["status"] != sr.SR_OK:
             raise RuntimeError(f"SRSolve backward: CG did not converge: {info}")
-        need_O, need_E, need_eps = ctx.needs_input_grad[0], ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        need_O, need_E = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        need_eps = ctx.needs_input_grad[2] and ctx.eps_is_tensor
         dO = dE = deps = None
-        if need_O or need_E:
-            dO, dE, _ = sr.sr_adjoint(M, E.detach(), x, lam, dO_dtype=O.dtype if need_O else None, want_dE=need_E)
+        if need_O or need_E or need_eps:
+            dO, dE, _, deps = sr.sr_adjoint(M, E.detach(), x, lam, dO_dtype=O.dtype if need_O else None,
+                                            want_dE=need_E, want_deps=True)
             if dO is not None and dO.stride(0) != dO.shape[1]:
                 dO = dO.contiguous()
-        if need_eps and ctx.eps_is_tensor:
-            deps = -(lam @ x).to(torch.float64).reshape(())
+            if not need_eps:
+                deps = None
         return dO, dE, deps, None, None, None
 
 

@@ -104,10 +104,25 @@ __global__ __launch_bounds__(kAdjNT) void k_rowdots2(RowDotsArgs a) {
 }
 
 // One workgroup: <E>, then per row p1, p2 (fixed order over column groups), dE and the
-// coefficients of the rank-2 update: coef[k] = (2 e_k - p1_k)/N, coef[n_s + k] = -p2_k/N.
+// coefficients of the rank-2 update: coef[k] = (2 e_k - p1_k)/N, coef[n_s + k] = -p2_k/N;
+// and dL/deps = -lambda . x when asked (n_s = 0: that alone).
 __global__ __launch_bounds__(1024) void k_adjoint_finish(AdjFinishArgs a) {
   __shared__ double s_w[16];
   const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (a.deps != nullptr) {
+    double d = 0.0;
+    for (int64_t j = tid; j < a.n_p; j += 1024) d += a.lam[j] * a.x[j];
+    d = wave_sum(d);
+    if (lane == 0) s_w[wave] = d;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int w = 0; w < 16; ++w) t += s_w[w];
+      *a.deps = -t;
+    }
+    __syncthreads();
+  }
+  if (a.n_s == 0) return;
   double se = 0.0;
   for (int64_t k = tid; k < a.n_s; k += 1024) se += a.E[k];
   se = wave_sum(se);

@@ -668,6 +668,17 @@ int lm_lincomb(const double *X, const double *ca, int mx, const double *Z, const
   return SR_OK;
 }
 
+// Column layout of the adjoint's row-dot pass: NV 16-byte vectors per thread (more for wide
+// matrices), column groups of NV * VEC * threads columns.
+int adjoint_nv(const sr_matrix *O) {
+  const int64_t vec = vec_of(O->dtype), nt = adjoint_threads();
+  return O->n_p >= 4 * vec * nt * 8 ? 4 : (O->n_p >= 2 * vec * nt * 8 ? 2 : 1);
+}
+int64_t adjoint_column_groups(const sr_matrix *O) {
+  const int64_t cols = (int64_t)adjoint_nv(O) * vec_of(O->dtype) * adjoint_threads();
+  return std::min<int64_t>(cdiv(O->n_p, cols), 1 << 20);
+}
+
 // Scratch of sr_sv_product_noalloc: barrier flags, exchange ring, row-group partials.  The
 // largest product any built tile plans needs G * (widest column slice) float64 partials,
 // 256 * 16384 * 8 bytes = 32 MiB, plus under 0.5 MiB of synchronisation data.  Each device
@@ -718,6 +729,70 @@ const char *sr_status_string(int status) {
     case SR_ERR_TIMEOUT: return "SR_ERR_TIMEOUT: cross-workgroup wait exceeded its bound";
     default: return "unknown status";
   }
+}
+
+int64_t sr_workspace_bytes(const sr_matrix *O, int32_t call) {
+  int rc = check_matrix(O, "sr_workspace_bytes");
+  if (rc) return rc;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const int dt = O->dtype, vec = vec_of(dt);
+  // the prepare pass (also run by the products and the solve when col_mean is NULL)
+  Plan gp;
+  gp.words = 0;
+  rc = geometry(di.grid, O->n_s, O->n_p, grad_nv(dt) * vec * kNT, vec, grad_rows(dt), 0, &gp.pg);
+  if (rc) return rc;
+  size_t grad = prod_ws_bytes(gp, (int64_t)gp.pg.RG * 3 * O->n_p);
+  if (compact(O)) grad += (size_t)(4 * cdiv(O->n_s, kGradLoRows) * O->n_lo + 64) * 8 + 512;
+  const size_t pre = O->col_mean ? 0 : grad;
+  switch (call) {
+    case SR_CALL_GRAD: return (int64_t)grad;
+    case SR_CALL_SV_PRODUCT:
+    case SR_CALL_CG_SOLVE: {
+      Plan pl;
+      rc = make_plan(dt, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
+      if (rc) return rc;
+      size_t b = prod_ws_bytes(pl, (int64_t)pl.pg.RG * pl.pg.n_v);
+      if (call == SR_CALL_CG_SOLVE) b += (size_t)3 * (O->n_p * 8 + 256) + 2048;
+      return (int64_t)std::max(b, pre);
+    }
+    case SR_CALL_LM_HV_PRODUCT: {
+      if (O->O_lo != nullptr) return fail(SR_ERR_INVALID, "sr_workspace_bytes: lm_hv_product takes one code plane");
+      Plan pl;
+      rc = make_plan(dt, di.grid, O->n_s, O->n_p, 2, &pl);
+      if (rc) return rc;
+      return (int64_t)std::max(prod_ws_bytes(pl, (int64_t)pl.pg.RG * O->n_p), pre);
+    }
+    case SR_CALL_ADJOINT: {
+      if (O->O_lo != nullptr) return fail(SR_ERR_INVALID, "sr_workspace_bytes: sr_adjoint takes one code plane");
+      const int64_t C = adjoint_column_groups(O);
+      return (int64_t)std::max((size_t)C * O->n_s * 16 + (size_t)O->n_s * 16 + 1024, pre);
+    }
+    default: return fail(SR_ERR_INVALID, "sr_workspace_bytes: unknown call %d", call);
+  }
+}
+
+int sr_workspace_reserve(int64_t bytes, hipStream_t stream) {
+  if (bytes < 0) return fail(SR_ERR_INVALID, "sr_workspace_reserve: bytes must be >= 0");
+  int dev;
+  DeviceInfo di;
+  int rc = device_check(&dev, &di);
+  if (rc) return rc;
+  void *base = nullptr;
+  return bytes == 0 ? SR_OK : get_workspace(dev, stream, (size_t)bytes, &base);
+}
+
+int64_t sr_workspace_held(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SR_ERR_NODEVICE, "no HIP device available");
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(std::make_pair(dev, stream));
+  return it == g_ws.end() ? 0 : (int64_t)it->second.bytes;
 }
 
 int sr_stream_read(const void *p, int64_t bytes, int32_t blocks_per_cu, int32_t unroll, uint32_t *sink,
@@ -1541,9 +1616,28 @@ int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const dou
 }
 
 int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const double *lam, double *dE, void *dO,
-               int32_t dO_dtype, int64_t ld_dO, double *p12, hipStream_t stream) {
+               int32_t dO_dtype, int64_t ld_dO, double *p12, double *deps, hipStream_t stream) {
   int rc = check_matrix(O, "sr_adjoint");
   if (rc) return rc;
+  if (deps != nullptr && (ranges_overlap(deps, 8, x, O->n_p * 8) || ranges_overlap(deps, 8, lam, O->n_p * 8)))
+    return fail(SR_ERR_INVALID, "sr_adjoint: deps overlaps x or lam");
+  if (dO == nullptr && dE == nullptr && p12 == nullptr) {
+    // dL/deps alone: no pass over O
+    if (x == nullptr || lam == nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: null x or lam");
+    if (deps == nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: no output requested");
+    int dev;
+    DeviceInfo di;
+    rc = device_check(&dev, &di);
+    if (rc) return rc;
+    AdjFinishArgs fa{};
+    fa.x = x;
+    fa.lam = lam;
+    fa.n_p = O->n_p;
+    fa.deps = deps;
+    void *args[] = {&fa};
+    HIP_TRY(hipLaunchKernel(adjoint_finish_kernel(), dim3(1), dim3(1024), args, 0, stream));
+    return SR_OK;
+  }
   if (O->O_lo != nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: a second code plane is not supported");
   if (E == nullptr || x == nullptr || lam == nullptr) return fail(SR_ERR_INVALID, "sr_adjoint: null E, x or lam");
   const int64_t n_s = O->n_s, n_p = O->n_p;
@@ -1576,9 +1670,8 @@ int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const doubl
   if (rc) return rc;
   // row dots: column groups of NV 16-byte vectors per thread, about 2048 workgroups
   const int vec = vec_of(O->dtype), nt = adjoint_threads(), rr = adjoint_rows_per_block();
-  const int nv = n_p >= (int64_t)4 * vec * nt * 8 ? 4 : (n_p >= (int64_t)2 * vec * nt * 8 ? 2 : 1);
-  const int64_t cols = (int64_t)nv * vec * nt;
-  const int C = (int)std::min<int64_t>(cdiv(n_p, cols), 1 << 20);
+  const int nv = adjoint_nv(O);
+  const int C = (int)adjoint_column_groups(O);
   const int RG = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_s, rr), std::max<int64_t>(1, 2048 / C)));
   void *base = nullptr;
   rc = get_workspace(dev, stream, (size_t)C * n_s * 16 + (size_t)n_s * 16 + 1024, &base);
@@ -1610,6 +1703,10 @@ int sr_adjoint(const sr_matrix *O, const double *E, const double *x, const doubl
   fa.coef = cv.take<double>(2 * n_s);
   fa.dE = dE;
   fa.p12 = p12;
+  fa.x = x;
+  fa.lam = lam;
+  fa.n_p = n_p;
+  fa.deps = deps;
   {
     void *args[] = {&fa};
     HIP_TRY(hipLaunchKernel(adjoint_finish_kernel(), dim3(1), dim3(1024), args, 0, stream));
@@ -1682,29 +1779,32 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const
   return launch_coop(pl.ke->lm, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
-int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt, sr_cg_info *info,
-                hipStream_t stream) {
-  int rc = check_matrix(O, "sr_cg_solve");
+// Checks, prepare pass (Jacobi), plan and workspace of a CG solve; fills `a` (its info
+// array in the workspace) and zeroes the synchronisation words.
+static int cg_setup(const char *name, const sr_matrix *O, const double *g, double eps, double *x,
+                    const sr_cg_opts *opt, hipStream_t stream, CgArgs &a, Plan &pl, ProdWs &w, sr_cg_opts &o,
+                    int64_t &max_iter) {
+  int rc = check_matrix(O, name);
   if (rc) return rc;
-  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: null g or x");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_cg_solve: eps must be finite and >= 0");
-  if (ranges_overlap(g, O->n_p * 8, x, O->n_p * 8)) return fail(SR_ERR_INVALID, "sr_cg_solve: g and x overlap");
-  sr_cg_opts o{};
+  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "%s: null g or x", name);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
+  if (ranges_overlap(g, O->n_p * 8, x, O->n_p * 8)) return fail(SR_ERR_INVALID, "%s: g and x overlap", name);
+  o = sr_cg_opts{};
   o.rtol = 1e-10;
   if (opt) o = *opt;
-  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "sr_cg_solve: rtol must be finite and > 0");
-  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_every must be >= 0");
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "%s: rtol must be finite and > 0", name);
+  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "%s: refresh_every must be >= 0", name);
   if (o.restart_on_refresh != 0 && o.restart_on_refresh != 1)
-    return fail(SR_ERR_INVALID, "sr_cg_solve: restart_on_refresh must be 0 or 1");
+    return fail(SR_ERR_INVALID, "%s: restart_on_refresh must be 0 or 1", name);
   if (!(o.refresh_drop >= 0.0 && o.refresh_drop < 1.0))
-    return fail(SR_ERR_INVALID, "sr_cg_solve: refresh_drop must be in [0, 1)");
-  if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: use_x0 must be 0 or 1");
-  if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: precond must be 0 or 1");
-  if (o.search_f64 != 0 && o.search_f64 != 1) return fail(SR_ERR_INVALID, "sr_cg_solve: search_f64 must be 0 or 1");
-  if (o.reserved != 0) return fail(SR_ERR_INVALID, "sr_cg_solve: reserved must be 0");
+    return fail(SR_ERR_INVALID, "%s: refresh_drop must be in [0, 1)", name);
+  if (o.use_x0 != 0 && o.use_x0 != 1) return fail(SR_ERR_INVALID, "%s: use_x0 must be 0 or 1", name);
+  if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "%s: precond must be 0 or 1", name);
+  if (o.search_f64 != 0 && o.search_f64 != 1) return fail(SR_ERR_INVALID, "%s: search_f64 must be 0 or 1", name);
+  if (o.reserved != 0) return fail(SR_ERR_INVALID, "%s: reserved must be 0", name);
   if (o.precond && (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32)))
-    return fail(SR_ERR_INVALID, "sr_cg_solve: the Jacobi preconditioner needs SR_F64 or SR_F32 storage, one plane");
-  int64_t max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
+    return fail(SR_ERR_INVALID, "%s: the Jacobi preconditioner needs SR_F64 or SR_F32 storage, one plane", name);
+  max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
   if (max_iter > (1 << 30)) max_iter = 1 << 30;
   int dev;
   DeviceInfo di;
@@ -1728,7 +1828,6 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     rc = ensure_mean(O, mscr, &mean, dev, di, stream);
     if (rc) return rc;
   }
-  Plan pl;
   rc = make_plan(O->dtype, di.grid, O->n_s, O->n_p, 1, &pl, streamed_cols(O));
   if (rc) return rc;
   const int64_t ypd = (int64_t)pl.pg.RG * pl.pg.n_v;
@@ -1737,9 +1836,8 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   rc = get_workspace(dev, stream, bytes, &base);
   if (rc) return rc;
   Carve cv(base);
-  ProdWs w;
   carve_prod(cv, pl, ypd, &w);
-  CgArgs a{};
+  a = CgArgs{};
   a.pg = pl.pg;
   a.pb = w.pb;
   a.sb = w.sb;
@@ -1760,7 +1858,17 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
   a.hist = o.res_history;
   a.diag = diag;
-  rc = zero_sync(w, stream);
+  return zero_sync(w, stream);
+}
+
+int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt, sr_cg_info *info,
+                hipStream_t stream) {
+  CgArgs a;
+  Plan pl;
+  ProdWs w;
+  sr_cg_opts o;
+  int64_t max_iter = 0;
+  int rc = cg_setup("sr_cg_solve", O, g, eps, x, opt, stream, a, pl, w, o, max_iter);
   if (rc) return rc;
   const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
   // scaled storage with float32 search products and float64 residual products: the two
@@ -1819,6 +1927,26 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     info->rel_res_true = hinfo[5];
   }
   return status;
+}
+
+int sr_cg_solve_async(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt,
+                      double *info_dev, hipStream_t stream) {
+  if (info_dev == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_async: null info_dev");
+  if (O != nullptr && (ranges_overlap(info_dev, kInfoWords * 8, x, O->n_p * 8) ||
+                       ranges_overlap(info_dev, kInfoWords * 8, g, O->n_p * 8)))
+    return fail(SR_ERR_INVALID, "sr_cg_solve_async: info_dev overlaps g or x");
+  CgArgs a;
+  Plan pl;
+  ProdWs w;
+  sr_cg_opts o;
+  int64_t max_iter = 0;
+  int rc = cg_setup("sr_cg_solve_async", O, g, eps, x, opt, stream, a, pl, w, o, max_iter);
+  if (rc) return rc;
+  a.info = info_dev;
+  const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
+  const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
+  if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_async: no CG kernel of this kind for this configuration");
+  return launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
 }
 
 int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, void *q, void *q_lo,

@@ -781,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   if (blockIdx.x == 0 && tid == 0) {
     a.info[kInfoIters] = (double)it;
     a.info[kInfoRefreshes] = (double)refreshes;
-    a.info[kInfoStatus] = (double)status;
+    a.info[kInfoStatus] = (double)(ok ? status : -6);   // SR_ERR_TIMEOUT when a wait gave up
     a.info[kInfoProducts] = (double)products;
     a.info[kInfoRelRecur] = sqrt(rho / gg);
     a.info[kInfoRelTrue] = rel_true;
@@ -820,7 +820,7 @@ __global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
   auto save = [&](int mode, bool ok, int it, int products, int status, double rho, double gg, double rho_ref) {
     if (blockIdx.x == 0 && tid == 0) {
       a.info[kInfoIters] = (double)it;
-      a.info[kInfoStatus] = (double)status;
+      a.info[kInfoStatus] = (double)(ok ? status : -6);   // SR_ERR_TIMEOUT when a wait gave up
       a.info[kInfoProducts] = (double)products;
       a.info[kInfoRelRecur] = sqrt(rho / gg);
       a.info[kInfoOk] = ok ? 1.0 : 0.0;

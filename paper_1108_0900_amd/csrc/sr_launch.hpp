@@ -161,6 +161,9 @@ struct AdjFinishArgs {
   int64_t n_s;
   int C;
   double *coef, *dE, *p12;
+  const double *x, *lam;             // [n_p]
+  int64_t n_p;
+  double *deps;                      // device scalar -lambda . x, or nullptr
 };
 struct Rank2Args {
   const double *coef, *lam, *x;

@@ -81,9 +81,14 @@ PROTOTYPES = {
     "sr_quantize_remainder": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p,
                                              _c_i64, _c_p]),
     "sr_release": (ctypes.c_int, []),
+    "sr_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(SrMatrix), _c_i32]),
+    "sr_workspace_reserve": (ctypes.c_int, [_c_i64, _c_p]),
+    "sr_workspace_held": (ctypes.c_int64, [_c_p]),
+    "sr_cg_solve_async": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts), _c_p,
+                                         _c_p]),
     "sr_stream_read": (ctypes.c_int, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p]),
     "sr_adjoint": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_i32, ctypes.c_int64,
-                                  _c_p, _c_p]),
+                                  _c_p, _c_p, _c_p]),
     "sr_svk_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_i32, _c_p, ctypes.POINTER(_c_d), _c_p, _c_i32,
                                       _c_p]),
     "sr_cg_solve_batched": (ctypes.c_int, [_c_i32, ctypes.POINTER(SrBatchSystem), _c_i32, ctypes.POINTER(SrCgOpts),
@@ -355,6 +360,56 @@ def sr_cg_solve(M: Matrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max
     return x, d
 
 
+def _cg_opts(rtol, max_iter, refresh_every, use_x0, restart_on_refresh, refresh_drop, precond, search_f64):
+    opts = SrCgOpts()
+    opts.rtol = float(rtol)
+    opts.max_iter = int(max_iter)
+    opts.refresh_every = int(refresh_every)
+    opts.use_x0 = 1 if use_x0 else 0
+    opts.restart_on_refresh = 1 if restart_on_refresh else 0
+    opts.refresh_drop = float(refresh_drop)
+    opts.precond = 1 if precond else 0
+    opts.search_f64 = 1 if search_f64 else 0
+    return opts
+
+
+def sr_cg_solve_async(M: Matrix, g: torch.Tensor, eps: float, x: torch.Tensor, info: torch.Tensor,
+                      rtol: float = 1e-10, max_iter: int = 0, refresh_every: int = 0, use_x0: bool = False,
+                      restart_on_refresh: bool = False, refresh_drop: float = 0.0, precond: bool = False,
+                      search_f64: bool = False, stream=None):
+    """CG solve queued on the stream without waiting (sr_cg_solve_async): x (in/out) and
+    info, a float64 device tensor of 16 (iters, refreshes, status, products, rel_res_recur,
+    rel_res_true, ...), are written when the solve runs."""
+    g = _vec(g, M.n_p, "g")
+    if info.dtype != torch.float64 or info.numel() < 16 or not info.is_contiguous():
+        raise ValueError("info must be a contiguous float64 tensor of at least 16 entries")
+    opts = _cg_opts(rtol, max_iter, refresh_every, use_x0, restart_on_refresh, refresh_drop, precond, search_f64)
+    m = M.c()
+    _check(lib().sr_cg_solve_async(ctypes.byref(m), _ptr(g), float(eps), _ptr(x), ctypes.byref(opts), _ptr(info),
+                                   _stream(stream)), "sr_cg_solve_async")
+    return x
+
+
+CALLS = {"grad": 0, "sv_product": 1, "cg_solve": 2, "lm_hv_product": 3, "adjoint": 4}
+
+
+def workspace_bytes(M: Matrix, call: str) -> int:
+    """Bytes of the library workspace the call needs on M (sr_workspace_bytes)."""
+    m = M.c()
+    b = lib().sr_workspace_bytes(ctypes.byref(m), CALLS[call])
+    if b < 0:
+        raise SrError(int(b), "sr_workspace_bytes")
+    return int(b)
+
+
+def workspace_reserve(nbytes: int, stream=None):
+    _check(lib().sr_workspace_reserve(int(nbytes), _stream(stream)), "sr_workspace_reserve")
+
+
+def workspace_held(stream=None) -> int:
+    return int(lib().sr_workspace_held(_stream(stream)))
+
+
 def lm_hv_product(M: Matrix, E: torch.Tensor, Dm: Matrix, v: torch.Tensor, out: torch.Tensor | None = None,
                   stream=None) -> torch.Tensor:
     """y = H v of the linear method, length n_p + 1 (lm_hv_product)."""
@@ -490,10 +545,11 @@ def sr_cg_solve_batched(systems, rtol: float = 1e-10, max_iter: int = 0, refresh
 
 
 def sr_adjoint(M: Matrix, E: torch.Tensor, x: torch.Tensor, lam: torch.Tensor, dO_dtype=torch.float32,
-               want_dE: bool = True, want_p12: bool = False, stream=None):
-    """Gradients through the SR solve (sr_adjoint): returns (dO, dE, p12); dO is an
-    (n_s, n_p) tensor of dO_dtype (None if dO_dtype is None), dE [n_s] float64 or None,
-    p12 [2, n_s] float64 (p1 = Oc x, p2 = Oc lambda) or None."""
+               want_dE: bool = True, want_p12: bool = False, want_deps: bool = False, stream=None):
+    """Gradients through the SR solve (sr_adjoint): returns (dO, dE, p12), or
+    (dO, dE, p12, deps) with want_deps; dO is an (n_s, n_p) tensor of dO_dtype (None if
+    dO_dtype is None), dE [n_s] float64 or None, p12 [2, n_s] float64 (p1 = Oc x,
+    p2 = Oc lambda) or None, deps a 0-d float64 tensor -lambda . x."""
     n_s = M.O.shape[0]
     E = _vec(E, n_s, "E")
     x = _vec(x, M.n_p, "x")
@@ -508,9 +564,12 @@ def sr_adjoint(M: Matrix, E: torch.Tensor, x: torch.Tensor, lam: torch.Tensor, d
         dO = dO_arg[:, :M.n_p]
     dE = torch.empty(n_s, dtype=torch.float64, device=E.device) if want_dE else None
     p12 = torch.empty(2, n_s, dtype=torch.float64, device=E.device) if want_p12 else None
+    deps = torch.empty((), dtype=torch.float64, device=E.device) if want_deps else None
     m = M.c()
     _check(lib().sr_adjoint(ctypes.byref(m), _ptr(E), _ptr(x), _ptr(lam), _ptr(dE), _ptr(dO_arg), code, ld,
-                            _ptr(p12), _stream(stream)), "sr_adjoint")
+                            _ptr(p12), _ptr(deps), _stream(stream)), "sr_adjoint")
+    if want_deps:
+        return dO, dE, p12, deps
     return dO, dE, p12
 
 

@@ -80,10 +80,12 @@ def test_status_strings_and_version():
     assert L.sr_status_string(12345) == b"unknown status"
 
 
-def _mat(n_s=4, n_p=3, ld=4, dtype=sr.SR_F64, O=256, scale=None, mean=None, reserved=0, lo=None):
+def _mat(n_s=4, n_p=3, ld=4, dtype=sr.SR_F64, O=256, scale=None, mean=None, reserved=0, lo=None, lo_cols=None,
+         n_lo=0, ld_lo=0):
     m = sr.SrMatrix()
     m.n_s, m.n_p, m.ld, m.dtype, m.reserved = n_s, n_p, ld, dtype, reserved
     m.O, m.O_lo, m.col_scale, m.col_mean = O, lo, scale, mean
+    m.lo_cols, m.n_lo, m.ld_lo = lo_cols, n_lo, ld_lo
     return m
 
 
@@ -98,6 +100,12 @@ BAD = [
     ("f64 with scale", dict(scale=512)),
     ("bad dtype", dict(dtype=7)),
     ("reserved", dict(reserved=1)),
+    ("lo_cols on f64", dict(lo_cols=1024, n_lo=1, ld_lo=8, lo=2048)),
+    ("lo_cols without O_lo", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo_cols=1024, n_lo=1, ld_lo=8)),
+    ("n_lo > n_p", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo_cols=1024, n_lo=4, ld_lo=8, lo=2048)),
+    ("ld_lo < n_lo", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo_cols=1024, n_lo=2, ld_lo=1, lo=2048)),
+    ("ld_lo bytes", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo_cols=1024, n_lo=2, ld_lo=4, lo=2048)),
+    ("n_lo without lo_cols", dict(n_lo=1)),
     ("lo plane on f64", dict(lo=1024)),
     ("misaligned lo plane", dict(dtype=sr.SR_BF16, ld=8, scale=512, lo=1032)),
 ]
@@ -163,14 +171,15 @@ def test_invalid_scalars_rejected():
     assert L.sr_quantize(4, 3, v, 2, sr.SR_F64, y, None, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
     assert L.sr_quantize(4, 3, v, 4, sr.SR_F64, y, y, 8, sr.SR_BF16, ctypes.c_void_p(1 << 16), None) == sr.SR_ERR_INVALID
     # adjoint
-    assert L.sr_adjoint(ctypes.byref(m), None, v, v, None, None, 0, 0, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), None, v, v, None, None, 0, 0, None, None, None) == sr.SR_ERR_INVALID
     dO = ctypes.c_void_p(1 << 24)
-    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_BF16, 4, None, None) == sr.SR_ERR_INVALID
-    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_F64, 2, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_BF16, 4, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, dO, sr.SR_F64, 2, None, None, None) == sr.SR_ERR_INVALID
     assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p((1 << 24) + 8), sr.SR_F64, 4, None,
-                        None) == sr.SR_ERR_INVALID
+                        None, None) == sr.SR_ERR_INVALID
     assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, ctypes.c_void_p(4096), sr.SR_F64, 4, None,
-                        None) == sr.SR_ERR_INVALID          # overlaps v
+                        None, None) == sr.SR_ERR_INVALID          # overlaps v
+    assert L.sr_adjoint(ctypes.byref(m), E, v, v, None, None, 0, 0, None, None, None) == sr.SR_ERR_INVALID  # nothing
     # batched geometry
     for sr_rows, tasks in ((100, 2), (2048, 2), (512, 0), (512, 9)):
         assert L.sr_set_batch_config(sr_rows, tasks) == sr.SR_ERR_INVALID
@@ -206,7 +215,7 @@ def test_invalid_scalars_rejected():
     # lm: a second code plane is rejected
     mb = _mat(dtype=sr.SR_BF16, ld=8, scale=512, lo=1024)
     assert L.lm_hv_product(ctypes.byref(mb), E, ctypes.byref(mb), v, y, None) == sr.SR_ERR_INVALID
-    assert L.sr_adjoint(ctypes.byref(mb), E, v, v, None, None, 0, 0, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_adjoint(ctypes.byref(mb), E, v, v, None, None, 0, 0, None, None, None) == sr.SR_ERR_INVALID
 
 
 def test_no_device_reported_without_gpu():
@@ -243,3 +252,32 @@ def test_tile_config_hooks():
         sr.set_tile_config(torch.float64, 0, *cfg, col_groups=3)
     with pytest.raises(sr.SrError):
         sr.set_tile_config(torch.float64, 2, *cfg)
+
+
+def test_boundary_helpers_reject_bad_arguments():
+    L = sr.lib()
+    m = _mat()
+    v = ctypes.c_void_p(4096)
+    y = ctypes.c_void_p(1 << 20)
+    info = ctypes.c_void_p(1 << 21)
+    assert L.sr_workspace_bytes(ctypes.byref(_mat(O=None)), 1) == sr.SR_ERR_INVALID
+    assert L.sr_workspace_reserve(-1, None) == sr.SR_ERR_INVALID
+    assert L.sr_cg_solve_async(ctypes.byref(m), v, 0.1, y, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_cg_solve_async(ctypes.byref(m), v, 0.1, y, None, v, None) == sr.SR_ERR_INVALID   # info overlaps g
+    assert L.sr_cg_solve_async(ctypes.byref(m), v, -1.0, y, None, info, None) == sr.SR_ERR_INVALID
+    assert L.sr_sv_product_noalloc(ctypes.byref(m), v, y, 0.1, None) == sr.SR_ERR_INVALID      # no col_mean
+    assert L.sr_stream_read(ctypes.c_void_p(4097), 16, 1, 4, y, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_read(v, 16, 1, 3, y, None) == sr.SR_ERR_INVALID
+    assert L.sr_remainder_columns(4, 3, v, 4, sr.SR_F64, sr.SR_F32, y, 1e-5, y, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_quantize_remainder(4, 3, v, 4, sr.SR_F64, sr.SR_BF16, y, y, 5, y, 8, None) == sr.SR_ERR_INVALID
+
+
+def test_boundary_helpers_report_no_device():
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU may be present")
+    L = sr.lib()
+    m = _mat()
+    assert L.sr_workspace_bytes(ctypes.byref(m), 1) == sr.SR_ERR_NODEVICE
+    assert L.sr_workspace_reserve(1024, None) == sr.SR_ERR_NODEVICE
+    assert L.sr_cg_solve_async(ctypes.byref(m), ctypes.c_void_p(4096), 0.1, ctypes.c_void_p(1 << 20), None,
+                               ctypes.c_void_p(1 << 21), None) == sr.SR_ERR_NODEVICE
