@@ -172,6 +172,9 @@ int sr_sv_product_noalloc(const sr_matrix *O, const double *v, double *y, double
  * 1e-7 of the largest eigenvalue of S into every direction, including the null space of
  * S where the system is only eps: with N_s < N_p and eps far below the spread of S,
  * tolerances much below 1e-6 need search_f64.
+ * Below the accuracy float64 arithmetic can attain (about kappa * 1e-16) the iteration
+ * drifts; a refresh or exit check whose true residual exceeds 1000 times the best one seen
+ * ends the solve with SR_NOT_CONVERGED (x is that iterate) instead of letting it grow.
  * This call synchronizes `stream` before returning (it reads the outcome back).
  * Returns SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN or an error code.
  * ------------------------------------------------------------------------------------ */

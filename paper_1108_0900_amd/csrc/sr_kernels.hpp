@@ -587,6 +587,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   double rel_true = -1.0, rho = 0.0, gg = 1.0, dummy = 0.0;
   double rho_ref = 0.0;  // rho at the start or the last refresh (drop-triggered refreshes)
   double rz = 0.0;       // r . z with z = r / (diag S + eps) (Jacobi; rho = r . r stays the test)
+  double rel_best = 0.0; // smallest true relative residual seen at a refresh or exit check
   bool ok = true, restart = false;
   int mode;
   if constexpr (PH != kPhAll) {
@@ -600,6 +601,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
     gg = ld_coh(&a.info[kInfoGg]);
     rho_ref = ld_coh(&a.info[kInfoRhoRef]);
     rz = ld_coh(&a.info[kInfoRz]);
+    rel_best = ld_coh(&a.info[kInfoRelBest]);
     if (mode == MODE_DONE || mode == MODE_P || mode == MODE_INIT)
       return;     // nothing for the residual phase (uniform: every workgroup read the same state)
   }
@@ -721,6 +723,18 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       refreshes++;
       if (!(ok = grid_allreduce2(prr, kJac ? prz : 0.0, a.sb.red, nred, ctx.gs, rho_new, kJac ? rz_new : dummy)))
         break;
+      {
+        // below the accuracy float64 can attain the iteration drifts: a true residual far
+        // above the best one seen ends the solve (not converged) before it grows further
+        const double tr_rel = sqrt(rho_new / gg);
+        if (rel_best > 0.0 && tr_rel > kCgDivergence * rel_best) {
+          status = 1;
+          rel_true = tr_rel;
+          mode = MODE_DONE;
+          continue;
+        }
+        rel_best = (rel_best > 0.0 && rel_best < tr_rel) ? rel_best : tr_rel;
+      }
       const double beta = a.restart_on_refresh ? 0.0 : (kJac ? rz_new / rz : rho_new / rho);
       rho = rho_new;
       if constexpr (kJac) rz = rz_new;
@@ -763,7 +777,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
       rel_true = sqrt(tr / gg);
       if (mode == MODE_FINAL || rel_true <= a.rtol) {
         mode = MODE_DONE;
-      } else if (it >= a.max_iter) {
+      } else if (it >= a.max_iter || (rel_best > 0.0 && rel_true > kCgDivergence * rel_best)) {
         status = 1;
         mode = MODE_DONE;
       } else {
@@ -771,6 +785,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
         rho = tr;
         rho_ref = tr;
         if constexpr (kJac) rz = trz;
+        rel_best = (rel_best > 0.0 && rel_best < rel_true) ? rel_best : rel_true;
         refreshes++;
         rel_true = -1.0;
         if (a.restart_on_refresh && !(ok = update_p(0.0))) break;
@@ -792,6 +807,7 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
     a.info[kInfoRhoRef] = rho_ref;
     a.info[kInfoRz] = rz;
     a.info[kInfoXstep] = (double)ctx.xstep;
+    a.info[kInfoRelBest] = rel_best;
   }
 }
 

@@ -57,7 +57,10 @@ struct CgArgs {
 enum { kPhAll = 0, kPhResidual = 2 };
 // Layout of CgArgs::info: outcome (read by the host) then the state of a split solve.
 enum { kInfoIters = 0, kInfoRefreshes, kInfoStatus, kInfoProducts, kInfoRelRecur, kInfoRelTrue, kInfoOk,
-       kInfoMode, kInfoRho, kInfoGg, kInfoRhoRef, kInfoRz, kInfoXstep, kInfoWords = 16 };
+       kInfoMode, kInfoRho, kInfoGg, kInfoRhoRef, kInfoRz, kInfoXstep, kInfoRelBest, kInfoWords = 16 };
+// A refresh or exit check whose true residual exceeds this multiple of the best one seen
+// ends the solve as not converged (the iteration is past the attainable accuracy).
+constexpr double kCgDivergence = 1e3;
 enum { kCgModeInit = 0, kCgModeP, kCgModeRefresh, kCgModeConfirm, kCgModeFinal, kCgModeX0, kCgModeDone };
 
 struct GradArgs {

@@ -7,7 +7,9 @@
   oracle's own g and eps;
 * dense 16384 x 16384 (the differentiation workload), float64 storage: central finite
   differences (h = 1e-3) of L = w . x on 32 entries of O and 16 of E against the
-  implicit-adjoint backward.
+  implicit-adjoint backward, with float64 CG to rtol 1e-12 (kappa is about 2.5e4 here, so
+  float64 CG cannot attain the workload's 1e-13: the true residual stalls near
+  kappa * 1e-16).
 
 Inputs are the seeded generators of synth at the workload's seed, made on the device and
 copied to the host for the oracle; nothing the oracle uses comes from the GPU path.
@@ -78,7 +80,7 @@ def test_cps_65536x24512_true_residual_by_oracle(dtype):
 def test_differentiation_16384_finite_differences():
     """dL/dO and dL/dE of L = w . x, x = (S + eps I)^{-1} g, on the 16384 x 16384 workload
     (float64 storage of its values, eps = 1e-3) against central differences h = 1e-3 of
-    float64 solves to rtol 1e-13 (32 entries of O, 16 of E)."""
+    float64 solves to rtol 1e-12 (32 entries of O, 16 of E)."""
     cfg = synth.CONFIGS["dense_16384"]
     d = synth.dense_inputs(cfg.n_s, cfg.n_p, cfg.seed, device=DEV, dtype=torch.float32)
     O = d["O"].double()
@@ -88,7 +90,7 @@ def test_differentiation_16384_finite_differences():
     gen = torch.Generator(device=DEV)
     gen.manual_seed(55)
     w = torch.randn(n_p, generator=gen, dtype=torch.float64, device=DEV)
-    rtol = 1e-13
+    rtol = 1e-12
     Ot = O.clone().requires_grad_(True)
     Et = E.clone().requires_grad_(True)
     x = sr_solve(Ot, Et, cfg.eps_abs, rtol, 20, True)
