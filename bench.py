@@ -60,7 +60,7 @@ def grad_bytes(n_s, n_p, dt, scaled):
 
 KERNEL_SOURCES = ("sr_device.hpp", "sr_product.hpp", "sr_kernels.hpp", "sr_launch.hpp", "sr_kernels_bf16.hip")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_bf16_compact_cps500k_traffic.md")
-TRAFFIC_KERNEL = "void sr::k_cg<2, 2, 2, 1, 1, 512, 0>(sr::CgArgs)"
+TRAFFIC_KERNEL = "void sr::k_cg_step<2, 2, 2, 1, 1, 512>(sr::CgArgs)"
 
 
 def kernel_source_hash():
@@ -606,6 +606,7 @@ def measure_single(args):
         step(Mt, rtol, args.search_f64)
     torch.cuda.synchronize()
     cg_ms, infos = [], []
+    sr.timing(True)           # HIP events around the CG launches, on their stream
     t0 = time.perf_counter()
     for _ in range(args.steps):
         x, info, ms_cg, eps = step(Mt, rtol, args.search_f64)
@@ -613,6 +614,10 @@ def measure_single(args):
         infos.append(info)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
+    launch_cls = "search_step" if (scaled and form in ("compact", "one_plane") and not args.search_f64) \
+        else "solve_launch"
+    t_ms, t_n = sr.timing_read(launch_cls)
+    sr.timing(False)
     ms_per_step = wall_ms / args.steps
     products = sum(i["products"] for i in infos) / len(infos)
     # a converged solve makes one search-direction product per iteration; the others are
@@ -624,8 +629,20 @@ def measure_single(args):
     step_bytes = grad_bytes(n_s, n_p, dt_t, scaled) + cg_alg_bytes
     value = step_bytes / (ms_per_step * 1e6)
     cg_avg = sum(cg_ms) / len(cg_ms)
-    achieved = cg_alg_bytes / (cg_avg * 1e6)
-    streamed = cg_streamed_bytes / (cg_avg * 1e6)
+    # the dominant kernel: one search step per launch (a product and the CG updates) for
+    # the split solves of scaled storage, the whole solve's launch otherwise
+    if launch_cls == "search_step":
+        launch_ms = t_ms / max(t_n, 1)
+        launch_alg = alg_pb
+        launch_streamed = alg_pb + extra_search
+        kernel_name = "k_cg_step (one search iteration of the split CG: fused product + CG updates)"
+    else:
+        launch_ms = t_ms / max(t_n, 1)
+        launch_alg = cg_alg_bytes
+        launch_streamed = cg_streamed_bytes
+        kernel_name = "k_cg (persistent CG; products read O once each)"
+    achieved = launch_alg / (launch_ms * 1e6)
+    streamed = launch_streamed / (launch_ms * 1e6)
     log(f"[bench] {dtype_name} {form}: {ms_per_step:.2f} ms/step, CG {cg_avg:.2f} ms, products {products}, "
         f"{value:.0f} GB/s step, {achieved:.0f} GB/s CG (algorithmic), {streamed:.0f} GB/s streamed")
 
@@ -684,7 +701,7 @@ def measure_single(args):
     # same algorithmic bytes per launch), else null
     traffic = None
     rec_t = traffic_record(TRAFFIC_KERNEL) if (scaled and form == "compact") else None
-    if rec_t is not None and abs(rec_t["algorithmic_bytes"] - cg_alg_bytes) <= 1e-6 * cg_alg_bytes:
+    if rec_t is not None and abs(rec_t["algorithmic_bytes"] - alg_pb) <= 1e-6 * alg_pb:
         traffic = round(rec_t["traffic_bytes"] / 1e9, 1)
 
     forms = {"compact": "bf16 codes + float32 column scales + a bf16 remainder plane for the %d columns whose "
@@ -722,13 +739,17 @@ def measure_single(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "k_cg (persistent CG; products read O once each)",
+                     "kernel": kernel_name,
                      "algorithmic_bytes_per_product": int(alg_pb),
-                     "algorithmic_GB_per_launch": round(cg_alg_bytes / 1e9, 2),
-                     "algorithmic_bytes_per_launch": int(round(cg_alg_bytes)),
-                     "streamed_GB_per_launch": round(cg_streamed_bytes / 1e9, 2),
-                     "streamed_GBps": round(streamed, 1), "launch_ms": round(cg_avg, 3),
-                     "stream_ceiling": ceiling},
+                     "algorithmic_bytes_per_launch": int(round(launch_alg)),
+                     "streamed_bytes_per_launch": int(round(launch_streamed)),
+                     "streamed_GBps": round(streamed, 1), "launch_ms": round(launch_ms, 4),
+                     "launches_timed": t_n,
+                     "solve": {"cg_ms": round(cg_avg, 3), "algorithmic_GB": round(cg_alg_bytes / 1e9, 2),
+                               "GBps": round(cg_alg_bytes / (cg_avg * 1e6), 1),
+                               "frac": round(cg_alg_bytes / (cg_avg * 1e6) / HBM_PEAK_GBPS, 4)},
+                     "stream_ceiling": ceiling,
+                     "frac_of_stream_ceiling": round(achieved / ceiling["GBps"], 4) if ceiling else None},
         "cpu_baseline": cpu,
         "solve": {"cg_ms": round(cg_avg, 3), "iters": infos[-1]["iters"], "products": products,
                   "residual_products": residuals, "storage_form": form, "remainder_columns": n_lo,

@@ -405,6 +405,17 @@ int64_t sr_workspace_bytes(const sr_matrix *O, int32_t call);
 int sr_workspace_reserve(int64_t bytes, hipStream_t stream);
 int64_t sr_workspace_held(hipStream_t stream);
 
+/* Kernel timing (measurement, not in the paper).  sr_timing(1) clears the totals and has
+ * the CG solves record HIP events, on their stream, around their launches; sr_timing(0)
+ * stops it.  sr_timing_read gives the total milliseconds and the number of launches of a
+ * class: 0 the search steps of a split solve (bf16/f16 storage, float32 search products)
+ * that ran a product, 1 its residual phases that ran one, 2 single-launch solves (other
+ * storage).  Split solves time their launches only where they check the state after every
+ * launch (products of at least 2^30 streamed bytes).  Timing adds a synchronization per
+ * timed launch. */
+int sr_timing(int32_t enable);
+int sr_timing_read(int32_t cls, double *ms, int64_t *count);
+
 /* Measurement helper (not in the paper): reads `bytes` (a multiple of 16) at p (16-byte
  * aligned, device) with the products' non-temporal 16-byte loads, `unroll` (2, 4 or 8)
  * loads in flight per thread, blocks_per_cu (1..8) workgroups of 512 threads per compute

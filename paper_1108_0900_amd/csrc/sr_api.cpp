@@ -668,6 +668,59 @@ int lm_lincomb(const double *X, const double *ca, int mx, const double *Z, const
   return SR_OK;
 }
 
+// Products of at least this many streamed bytes run their split solve with a state check
+// after every launch.
+constexpr int64_t kStepSyncBytes = (int64_t)1 << 30;
+
+// Kernel timing (sr_timing): HIP events around the launches of the CG solves, on their
+// stream; accumulated per class while enabled.
+enum { kTimeSearchStep = 0, kTimeResidualPhase = 1, kTimeSolveLaunch = 2, kTimeClasses = 3 };
+struct TimingTotals {
+  bool on = false;
+  double ms[kTimeClasses] = {0.0, 0.0, 0.0};
+  int64_t count[kTimeClasses] = {0, 0, 0};
+};
+TimingTotals g_timing;
+
+// Events around one launch when timing is enabled; record() (after the stream has passed
+// the end event) adds the elapsed time to a class.
+struct TimedLaunch {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t s;
+  explicit TimedLaunch(hipStream_t s_) : s(s_) {
+    bool on;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      on = g_timing.on;
+    }
+    if (on && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      (void)hipEventRecord(e0, s);
+    } else {
+      (void)hipGetLastError();
+      release();
+    }
+  }
+  void stop() {
+    if (e1) (void)hipEventRecord(e1, s);
+  }
+  void record(int cls) {
+    if (!e0 || !e1) return;
+    float ms = 0.0f;
+    if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_timing.ms[cls] += ms;
+      g_timing.count[cls] += 1;
+    }
+    (void)hipGetLastError();
+  }
+  void release() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    e0 = e1 = nullptr;
+  }
+  ~TimedLaunch() { release(); }
+};
+
 // Column layout of the adjoint's row-dot pass: NV 16-byte vectors per thread (more for wide
 // matrices), column groups of NV * VEC * threads columns.
 int adjoint_nv(const sr_matrix *O) {
@@ -782,6 +835,23 @@ int sr_workspace_reserve(int64_t bytes, hipStream_t stream) {
   if (rc) return rc;
   void *base = nullptr;
   return bytes == 0 ? SR_OK : get_workspace(dev, stream, (size_t)bytes, &base);
+}
+
+int sr_timing(int32_t enable) {
+  if (enable != 0 && enable != 1) return fail(SR_ERR_INVALID, "sr_timing: enable must be 0 or 1");
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timing = TimingTotals{};
+  g_timing.on = enable != 0;
+  return SR_OK;
+}
+
+int sr_timing_read(int32_t cls, double *ms, int64_t *count) {
+  if (cls < 0 || cls >= kTimeClasses || ms == nullptr || count == nullptr)
+    return fail(SR_ERR_INVALID, "sr_timing_read: bad argument");
+  std::lock_guard<std::mutex> lk(g_mu);
+  *ms = g_timing.ms[cls];
+  *count = g_timing.count[cls];
+  return SR_OK;
 }
 
 int64_t sr_workspace_held(hipStream_t stream) {
@@ -1875,13 +1945,39 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   // product codes run in separate kernels that alternate (search phase, residual phase),
   // batches of pairs between host checks of the state
   const bool split = scaled(O->dtype) && !two_planes(O) && !exact_search;
-  double hinfo[kInfoWords];
+  double hinfo[kInfoWords] = {};
   uint32_t habort = 0;
   if (split) {
-    if (pl.ke->cgs == nullptr || pl.ke->cgr == nullptr)
+    if (pl.ke->cgs == nullptr || pl.ke->cgr == nullptr || pl.ke->cgi == nullptr)
       return fail(SR_ERR_INVALID, "sr_cg_solve: no split CG kernels for this configuration");
     rc = fill_zero(a.info, 2 * kInfoWords, stream);      // state: initial mode, counters 0
     if (rc) return rc;
+    rc = launch_coop(pl.ke->cgi, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+    if (rc) return rc;
+    const int64_t product_bytes = O->n_s * streamed_cols(O) * elem_bytes(O->dtype);
+    if (product_bytes >= kStepSyncBytes) {
+      // long products: the host reads the state after every launch, so it launches exactly
+      // the phase the state asks for (no launch returns idle); a synchronisation costs tens
+      // of microseconds against a product of a fifth of a millisecond or more
+      int64_t launches = 0, products = 0;
+      HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      for (;;) {
+        if (habort != 0u || hinfo[kInfoOk] == 0.0 || (int)hinfo[kInfoMode] == kCgModeDone) break;
+        const bool search = (int)hinfo[kInfoMode] == kCgModeP;
+        TimedLaunch tl(stream);
+        rc = launch_coop(search ? pl.ke->cgs : pl.ke->cgr, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+        if (rc) return rc;
+        tl.stop();
+        HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        const int64_t now = (int64_t)hinfo[kInfoProducts];
+        if (now > products) tl.record(search ? kTimeSearchStep : kTimeResidualPhase);
+        products = now;
+        if (++launches > 4 * max_iter + 64) return fail(SR_ERR_HIP, "sr_cg_solve: split solve did not finish");
+      }
+    } else {
     // a round: search steps up to the next periodic refresh, then the residual phase;
     // launches in a state that is not theirs return at once
     const int steps = (o.refresh_every > 0 ? o.refresh_every : 16) + 1;
@@ -1904,14 +2000,18 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
       // state machine ends it, so this bound is never reached by a working kernel
       if (pairs > max_iter + 64) return fail(SR_ERR_HIP, "sr_cg_solve: split solve did not finish");
     }
+    }
   } else {
     const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
     if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no CG kernel of this kind for this configuration");
+    TimedLaunch tl(stream);
     rc = launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
     if (rc) return rc;
+    tl.stop();
     HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    tl.record(kTimeSolveLaunch);
   }
   int status = (int)hinfo[2];
   if (habort != 0u || hinfo[6] == 0.0) status = fail(SR_ERR_TIMEOUT, "sr_cg_solve: a cross-workgroup wait timed out");

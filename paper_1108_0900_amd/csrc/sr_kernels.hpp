@@ -814,17 +814,17 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
 // One search-direction iteration of a split CG solve (scaled storage, float32 products):
 // q = (S + eps I) p, alpha, x += alpha p, r -= alpha q, rho, beta, p = r + beta p and the
 // next decision, with the state read from CgArgs::info after the product and written back
-// at the end, so nothing but the product is live during its streaming loop.  A launch in
-// the initial state sets up x = 0, r = p = g (or hands a warm start to the residual
-// phase); a launch in any state but the search one returns at once.
-template <int DT, int NV, int R, int L, int P_, int NT>
-__global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
+// at the end, so nothing but the product is live during its streaming loop.  INIT: the
+// solve's first launch instead, x = 0, r = p = g and the first decision (or the hand-over
+// of a warm start to the residual phase).  A launch in any other state returns at once.
+template <int DT, int NV, int R, int L, int P_, int NT, bool INIT>
+__device__ __forceinline__ void cg_step_body(CgArgs &a) {
   typedef CgKernel<DT, NV, R, L, P_, NT> K;
   WgCtx ctx;
   init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
   if (ld_coh32(a.sb.abort) != 0u) return;
   const int mode0 = (int)ld_coh(&a.info[kInfoMode]);
-  if (mode0 != kCgModeP && mode0 != kCgModeInit) return;
+  if (mode0 != (INIT ? kCgModeInit : kCgModeP)) return;
   ctx.gs.epoch = ld_coh32(&a.sb.flags[blockIdx.x]);
   ctx.xstep = (uint32_t)ld_coh(&a.info[kInfoXstep]);
   const int G = (int)gridDim.x, tid = (int)threadIdx.x;
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
     return kCgModeP;
   };
 
-  if (mode0 == kCgModeInit) {
+  if constexpr (INIT) {
     if (a.use_x0) {                 // the warm start's product runs in the residual phase
       save(kCgModeX0, true, 0, 0, 0, 0.0, 1.0, 0.0);
       if (blockIdx.x == 0 && tid == 0) a.info[kInfoRelTrue] = -1.0;
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
     }
     save(mode, ok, 0, 0, status, rho, gg, rho);
     return;
-  }
+  } else {
 
   int dummy_products = 0;
   bool ok = K::template apply<false>(a, ctx, a.p, a.q, j0, j1, dummy_products);
@@ -934,6 +934,16 @@ __global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
     }
   }
   save(mode, ok, it, products, status, rho, gg, rho_ref);
+  }
+}
+
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
+  cg_step_body<DT, NV, R, L, P_, NT, false>(a);
+}
+template <int DT, int NV, int R, int L, int P_, int NT>
+__global__ __launch_bounds__(NT) void k_cg_init(CgArgs a) {
+  cg_step_body<DT, NV, R, L, P_, NT, true>(a);
 }
 
 }  // namespace sr

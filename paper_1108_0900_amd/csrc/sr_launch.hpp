@@ -188,6 +188,7 @@ struct KernelEntry {
   const void *cgj;       // Jacobi-preconditioned CG (float64 / float32 storage), or nullptr
   const void *cgx;       // CG with float64-accumulated search products (scaled storage), or nullptr
   const void *cgs, *cgr; // split CG (scaled storage, one plane): search step and residual phase, or nullptr
+  const void *cgi;       // split CG: its first launch (initial state), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 

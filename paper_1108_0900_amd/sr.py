@@ -84,6 +84,8 @@ PROTOTYPES = {
     "sr_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(SrMatrix), _c_i32]),
     "sr_workspace_reserve": (ctypes.c_int, [_c_i64, _c_p]),
     "sr_workspace_held": (ctypes.c_int64, [_c_p]),
+    "sr_timing": (ctypes.c_int, [_c_i32]),
+    "sr_timing_read": (ctypes.c_int, [_c_i32, ctypes.POINTER(_c_d), ctypes.POINTER(_c_i64)]),
     "sr_cg_solve_async": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts), _c_p,
                                          _c_p]),
     "sr_stream_read": (ctypes.c_int, [_c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p]),
@@ -404,6 +406,21 @@ def workspace_bytes(M: Matrix, call: str) -> int:
 
 def workspace_reserve(nbytes: int, stream=None):
     _check(lib().sr_workspace_reserve(int(nbytes), _stream(stream)), "sr_workspace_reserve")
+
+
+TIMING_CLASSES = {"search_step": 0, "residual_phase": 1, "solve_launch": 2}
+
+
+def timing(enable: bool = True):
+    """Start (clear) or stop the library's HIP-event timing of CG launches (sr_timing)."""
+    _check(lib().sr_timing(1 if enable else 0), "sr_timing")
+
+
+def timing_read(cls: str) -> tuple:
+    """(total ms, launches) recorded for a class of CG launches (sr_timing_read)."""
+    ms, n = _c_d(0.0), _c_i64(0)
+    _check(lib().sr_timing_read(TIMING_CLASSES[cls], ctypes.byref(ms), ctypes.byref(n)), "sr_timing_read")
+    return ms.value, n.value
 
 
 def workspace_held(stream=None) -> int:
