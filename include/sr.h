@@ -389,6 +389,60 @@ int sr_set_tile_config(int32_t dtype, int32_t kind, int32_t nv, int32_t rows, in
                        int32_t poll_delay, int32_t threads, int32_t col_groups);
 
 /* ------------------------------------------------------------------------------------
+ * Index-coded correlator-product-state (CPS) storage (Sec. II.C, Eq. ansatz; parameter
+ * layout of Sec. III.A).  A sample occupies exactly one state of each correlator, so the
+ * derivative ratio of correlator p's parameter for state s is val[p*n_states + s] (the
+ * inverse of that correlator entry) when the sample is in state s, and 0 otherwise: one
+ * nonzero per correlator per row, its value fixed by the column.  The storage keeps
+ *   idx    one byte per correlator per sample, correlator-major: idx[p*ld_idx + k] is the
+ *          state of correlator p in sample k (a state >= n_states selects no column);
+ *   val    the value of each correlator column;
+ *   dense  the remaining parameters (the pairing block) as an ordinary matrix,
+ * with the parameters ordered [correlator 0's n_states columns | correlator 1 | ... |
+ * dense columns], n_p = n_corr * n_states + dense.n_p.  Every entry point below computes
+ * exactly what the sr_* entry point of the same name computes on the expanded n_s x n_p
+ * matrix.  At 32768 samples, 2048 correlators of 240 states and 8480 dense columns a
+ * product reads 67 MB of states and the dense block (556 MB in bf16) instead of a
+ * 32768 x 500000 matrix.
+ * ------------------------------------------------------------------------------------ */
+typedef struct sr_cps_matrix {
+  int64_t n_s;               /* samples, >= 1                                          */
+  int64_t n_corr;            /* correlators, >= 0                                      */
+  int32_t n_states;          /* states (columns) per correlator, 1..256                */
+  int32_t reserved;          /* must be 0                                              */
+  const uint8_t *idx;        /* [n_corr][ld_idx] device, 16-byte aligned               */
+  int64_t ld_idx;            /* >= n_s, a multiple of 16                               */
+  const double *val;         /* [n_corr * n_states] device                             */
+  sr_matrix dense;           /* dense block, n_s rows and dense.n_p >= 0 columns (0: no */
+                             /* block; dense.O may then be NULL); SR_F64, SR_F32 or     */
+                             /* SR_BF16 with one plane (no O_lo, no lo_cols); at most  */
+                             /* 32768 (bf16; 16384 with search_f64), 16384 (f32, f64)   */
+                             /* columns; dense.col_mean is ignored                      */
+  const double *col_mean;    /* [n_p] device column means (only the dense entries are  */
+                             /* read), or NULL: computed by the call                    */
+} sr_cps_matrix;
+
+/* sr_grad of the expanded matrix.  The correlator columns' statistics come from per-state
+ * counts and per-state energy sums (int64 fixed point: the same bits on every run):
+ * mean = val f, diag S = val^2 f (1 - f), g = (2/n_s) val (B_s - f B) with e = E - E_mean,
+ * B_s the sum of e over the samples in the state, B over all samples and f the fraction of
+ * samples in the state. */
+int sr_cps_grad(const sr_cps_matrix *M, const double *E, double *g, double *E_mean, double *col_mean_out,
+                double *diagS_out, hipStream_t stream);
+/* sr_sv_product of the expanded matrix, one cooperative launch: the row values
+ * w_k = (sum of the u = val*v entries of the sample's states) + dense_k . v - obar . v,
+ * then per correlator the sums of w_k - mean(w) over the samples in each state (int64
+ * fixed point, so the result is the same bit for bit on every run), and the dense block's
+ * O^T w.  The dense block is read once; idx is read twice.  bf16 dense blocks accumulate
+ * in float32, the rest in float64. */
+int sr_cps_sv_product(const sr_cps_matrix *M, const double *v, double *y, double eps, hipStream_t stream);
+/* sr_cg_solve of the expanded matrix (same options, outcome and status codes; precond
+ * must be 0; search_f64 applies to a bf16 dense block; residual refreshes accumulate in
+ * float64). */
+int sr_cps_cg_solve(const sr_cps_matrix *M, const double *g, double eps, double *x, const sr_cg_opts *opt,
+                    sr_cg_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Workspace (the library's own memory for partials, exchange words and CG vectors; one per
  * device and stream, grown on demand by reallocation, which synchronizes the stream).
  * sr_workspace_bytes: bytes that workspace must hold for `call` (enum sr_call) on the
@@ -408,9 +462,9 @@ int64_t sr_workspace_held(hipStream_t stream);
 /* Kernel timing (measurement, not in the paper).  sr_timing(1) clears the totals and has
  * the CG solves record HIP events, on their stream, around their launches; sr_timing(0)
  * stops it.  sr_timing_read gives the total milliseconds and the number of launches of a
- * class: 0 the search steps of a split solve (bf16/f16 storage, float32 search products)
- * that ran a product, 1 its residual phases that ran one, 2 single-launch solves (other
- * storage).  Split solves time their launches only where they check the state after every
+ * class: 0 the search steps of a split solve (one stored plane, no preconditioner, the
+ * storage type's own accumulation) that ran a product, 1 its residual phases that ran one,
+ * 2 single-launch solves (two planes, Jacobi, float64 search products).  Split solves time their launches only where they check the state after every
  * launch (products of at least 2^30 streamed bytes).  Timing adds a synchronization per
  * timed launch. */
 int sr_timing(int32_t enable);

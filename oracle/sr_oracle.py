@@ -42,6 +42,8 @@ Functions and the passage each follows:
   quantize_bf16/_f16/_split, dequantize_* . precision form of the stored ratios (not in the paper)
   quantize_cols, dequantize_cols ......... remainder codes kept only for the columns that need them
   solve_adjoint_gradients ................ implicit-adjoint derivative of the solve (not in the paper)
+  cps_expand ............................. Sec. II.C, Eq. ansatz: the derivative ratios of an
+                                           index-coded correlator-product state, written out
 
 Every function is pinned by the CPU tests against something other than itself
 (library routines, closed forms, invariants, exact enumeration of a tiny Hilbert
@@ -57,7 +59,7 @@ __all__ = [
     "energy_gradient", "energy_mean", "diag_overlap", "sv_product_dense", "sv_product_swapped",
     "paper_linear_system", "sr_update", "solve_dense", "solve_dual", "cg_solve", "lm_matrices", "lm_hv_dense", "lm_hv_swapped",
     "lm_lowest_eigenpair", "quantize_bf16", "dequantize_bf16", "quantize_f16", "dequantize_f16",
-    "quantize_split", "dequantize_split", "quantize_cols", "dequantize_cols", "REMAINDER_TOL",
+    "quantize_split", "dequantize_split", "quantize_cols", "dequantize_cols", "REMAINDER_TOL", "cps_expand",
     "solve_adjoint_gradients",
 ]
 
@@ -474,3 +476,28 @@ def solve_adjoint_gradients(O, E, eps: float, dL_dx):
     dO = (np.outer(2.0 * ec - p1, lam) - np.outer(p2, x)) / n_s
     dE = 2.0 * p2 / n_s
     return {"x": x, "lam": lam, "dO": dO, "dE": dE, "dg": lam, "deps": -float(lam @ x)}
+
+
+def cps_expand(idx, val, n_states: int, dense=None) -> np.ndarray:
+    """The N_s x N_p derivative-ratio matrix of a correlator-product state stored by index
+    (Sec. II.C, Eq. ansatz).  A sample occupies one state of each correlator, so the ratio
+    of correlator p's parameter for state s is val[p * n_states + s] when the sample is in
+    state s and 0 otherwise.
+
+    idx: (n_corr, N_s) integer states, correlator-major (a state >= n_states selects no
+    column); val: (n_corr * n_states,) column values; dense: (N_s, n_d) the remaining
+    parameters or None.  Columns: [correlator 0's states | correlator 1 | ... | dense].
+    """
+    idx = np.asarray(idx).astype(np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    n_corr, n_s = idx.shape
+    n_sp = n_corr * n_states
+    n_d = 0 if dense is None else np.asarray(dense).shape[1]
+    O = np.zeros((n_s, n_sp + n_d))
+    for p in range(n_corr):
+        rows = np.nonzero(idx[p] < n_states)[0]        # samples whose state of p is a column
+        cols = p * n_states + idx[p, rows]
+        O[rows, cols] = val[cols]
+    if n_d:
+        O[:, n_sp:] = np.asarray(dense, dtype=np.float64)
+    return O

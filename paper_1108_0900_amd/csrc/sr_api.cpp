@@ -1851,14 +1851,8 @@ int lm_hv_product(const sr_matrix *O, const double *E, const sr_matrix *D, const
 
 // Checks, prepare pass (Jacobi), plan and workspace of a CG solve; fills `a` (its info
 // array in the workspace) and zeroes the synchronisation words.
-static int cg_setup(const char *name, const sr_matrix *O, const double *g, double eps, double *x,
-                    const sr_cg_opts *opt, hipStream_t stream, CgArgs &a, Plan &pl, ProdWs &w, sr_cg_opts &o,
-                    int64_t &max_iter) {
-  int rc = check_matrix(O, name);
-  if (rc) return rc;
-  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "%s: null g or x", name);
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
-  if (ranges_overlap(g, O->n_p * 8, x, O->n_p * 8)) return fail(SR_ERR_INVALID, "%s: g and x overlap", name);
+// Options of a CG solve over n_p parameters, with the defaults of a null opt, checked.
+static int check_cg_opts(const char *name, const sr_cg_opts *opt, sr_cg_opts &o) {
   o = sr_cg_opts{};
   o.rtol = 1e-10;
   if (opt) o = *opt;
@@ -1872,6 +1866,19 @@ static int cg_setup(const char *name, const sr_matrix *O, const double *g, doubl
   if (o.precond != 0 && o.precond != 1) return fail(SR_ERR_INVALID, "%s: precond must be 0 or 1", name);
   if (o.search_f64 != 0 && o.search_f64 != 1) return fail(SR_ERR_INVALID, "%s: search_f64 must be 0 or 1", name);
   if (o.reserved != 0) return fail(SR_ERR_INVALID, "%s: reserved must be 0", name);
+  return SR_OK;
+}
+
+static int cg_setup(const char *name, const sr_matrix *O, const double *g, double eps, double *x,
+                    const sr_cg_opts *opt, hipStream_t stream, CgArgs &a, Plan &pl, ProdWs &w, sr_cg_opts &o,
+                    int64_t &max_iter) {
+  int rc = check_matrix(O, name);
+  if (rc) return rc;
+  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "%s: null g or x", name);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
+  if (ranges_overlap(g, O->n_p * 8, x, O->n_p * 8)) return fail(SR_ERR_INVALID, "%s: g and x overlap", name);
+  rc = check_cg_opts(name, opt, o);
+  if (rc) return rc;
   if (o.precond && (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32)))
     return fail(SR_ERR_INVALID, "%s: the Jacobi preconditioner needs SR_F64 or SR_F32 storage, one plane", name);
   max_iter = o.max_iter > 0 ? o.max_iter : O->n_p + 100;
@@ -1931,6 +1938,102 @@ static int cg_setup(const char *name, const sr_matrix *O, const double *g, doubl
   return zero_sync(w, stream);
 }
 
+// Kernels of a split CG solve (first launch, search step, residual phase) and their launch
+// shape.
+struct SplitKernels {
+  const void *init, *step, *resid;
+  int G, nt, shmem;
+};
+
+// Runs a split solve to its end: the first launch, then search steps and residual phases.
+// Long products (>= kStepSyncBytes streamed) and solves whose rounds stopped advancing
+// (below: fewer products than half a round's launches, as when every search step ends in
+// an exit check near the attainable accuracy): the host reads the state after every
+// launch and launches exactly the phase it asks for (a synchronisation costs tens of
+// microseconds against a product of a fifth of a millisecond or more).  Otherwise rounds
+// of search steps up to the next periodic refresh and one residual phase are queued
+// without waiting; launches in a state that is not theirs return at once, and the host
+// reads the state after each batch of rounds.  Leaves the final state in hinfo / habort.
+// Every round and every per-launch step advances the solve by at least one product until
+// it is done, and a solve makes at most 2 max_iter + 64 products, which bounds the loops.
+static int run_split_cg(const SplitKernels &k, CgArgs &a, const uint32_t *abort_dev, int64_t product_bytes,
+                        int refresh_every, int64_t max_iter, hipStream_t stream, double *hinfo, uint32_t *habort) {
+  int rc = fill_zero(a.info, 2 * kInfoWords, stream);      // state: initial mode, counters 0
+  if (rc) return rc;
+  rc = launch_coop(k.init, k.G, &a, stream, k.nt, k.shmem);
+  if (rc) return rc;
+  *habort = 0;
+  auto read_state = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(hinfo, a.info, kInfoWords * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(habort, abort_dev, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return SR_OK;
+  };
+  auto done = [&]() { return *habort != 0u || hinfo[kInfoOk] == 0.0 || (int)hinfo[kInfoMode] == kCgModeDone; };
+  const int64_t max_products = 2 * max_iter + 64;
+  const int steps = (refresh_every > 0 ? refresh_every : 16) + 1;
+  bool per_launch = product_bytes >= kStepSyncBytes;
+  int64_t rounds = 0, launches = 0;
+  if (!per_launch) {
+    for (int batch = 1;; batch = batch < 16 ? 2 * batch : 16) {
+      const int64_t before = (int64_t)hinfo[kInfoProducts];
+      for (int b = 0; b < batch; ++b) {
+        for (int sidx = 0; sidx < steps; ++sidx) {
+          rc = launch_coop(k.step, k.G, &a, stream, k.nt, k.shmem);
+          if (rc) return rc;
+        }
+        rc = launch_coop(k.resid, k.G, &a, stream, k.nt, k.shmem);
+        if (rc) return rc;
+      }
+      rounds += batch;
+      rc = read_state();
+      if (rc) return rc;
+      if (done()) return SR_OK;
+      if (rounds > max_products) return fail(SR_ERR_HIP, "split CG solve did not finish");
+      if (2 * ((int64_t)hinfo[kInfoProducts] - before) < (int64_t)batch * steps) {
+        per_launch = true;
+        break;
+      }
+    }
+  } else {
+    rc = read_state();
+    if (rc) return rc;
+  }
+  int64_t products = (int64_t)hinfo[kInfoProducts];
+  while (!done()) {
+    const bool search = (int)hinfo[kInfoMode] == kCgModeP;
+    TimedLaunch tl(stream);
+    rc = launch_coop(search ? k.step : k.resid, k.G, &a, stream, k.nt, k.shmem);
+    if (rc) return rc;
+    tl.stop();
+    rc = read_state();
+    if (rc) return rc;
+    const int64_t now = (int64_t)hinfo[kInfoProducts];
+    if (now > products) tl.record(search ? kTimeSearchStep : kTimeResidualPhase);
+    products = now;
+    if (++launches > max_products) return fail(SR_ERR_HIP, "split CG solve did not finish");
+  }
+  return SR_OK;
+}
+
+// Status and host outcome of a finished solve from its final state.
+static int cg_outcome(const char *name, const double *hinfo, uint32_t habort, sr_cg_info *info) {
+  int status = (int)hinfo[kInfoStatus];
+  if (habort != 0u || hinfo[kInfoOk] == 0.0) status = fail(SR_ERR_TIMEOUT, "%s: a cross-workgroup wait timed out", name);
+  else if (status == SR_ERR_NONFINITE) fail(SR_ERR_NONFINITE, "%s: non-finite scalar in CG", name);
+  else if (status == SR_BREAKDOWN) fail(SR_BREAKDOWN, "%s: p.(S+eps I)p <= 0", name);
+  else if (status == SR_NOT_CONVERGED) fail(SR_NOT_CONVERGED, "%s: max_iter reached", name);
+  if (info) {
+    info->iters = (int32_t)hinfo[kInfoIters];
+    info->refreshes = (int32_t)hinfo[kInfoRefreshes];
+    info->status = status;
+    info->products = (int32_t)hinfo[kInfoProducts];
+    info->rel_res_recur = hinfo[kInfoRelRecur];
+    info->rel_res_true = hinfo[kInfoRelTrue];
+  }
+  return status;
+}
+
 int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt, sr_cg_info *info,
                 hipStream_t stream) {
   CgArgs a;
@@ -1941,66 +2044,19 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   int rc = cg_setup("sr_cg_solve", O, g, eps, x, opt, stream, a, pl, w, o, max_iter);
   if (rc) return rc;
   const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
-  // scaled storage with float32 search products and float64 residual products: the two
-  // product codes run in separate kernels that alternate (search phase, residual phase),
-  // batches of pairs between host checks of the state
-  const bool split = scaled(O->dtype) && !two_planes(O) && !exact_search;
+  // one stored plane without a preconditioner: one kernel per search iteration (only the
+  // product is live during its streaming loop, which keeps the registers free of spills)
+  // and a resumable residual phase (for scaled storage the float64 residual products)
+  const bool split = !two_planes(O) && !exact_search && !o.precond;
   double hinfo[kInfoWords] = {};
   uint32_t habort = 0;
   if (split) {
     if (pl.ke->cgs == nullptr || pl.ke->cgr == nullptr || pl.ke->cgi == nullptr)
       return fail(SR_ERR_INVALID, "sr_cg_solve: no split CG kernels for this configuration");
-    rc = fill_zero(a.info, 2 * kInfoWords, stream);      // state: initial mode, counters 0
-    if (rc) return rc;
-    rc = launch_coop(pl.ke->cgi, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
-    if (rc) return rc;
+    const SplitKernels k{pl.ke->cgi, pl.ke->cgs, pl.ke->cgr, pl.pg.G, pl.ke->nt, pl.ke->ring_bytes};
     const int64_t product_bytes = O->n_s * streamed_cols(O) * elem_bytes(O->dtype);
-    if (product_bytes >= kStepSyncBytes) {
-      // long products: the host reads the state after every launch, so it launches exactly
-      // the phase the state asks for (no launch returns idle); a synchronisation costs tens
-      // of microseconds against a product of a fifth of a millisecond or more
-      int64_t launches = 0, products = 0;
-      HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
-      for (;;) {
-        if (habort != 0u || hinfo[kInfoOk] == 0.0 || (int)hinfo[kInfoMode] == kCgModeDone) break;
-        const bool search = (int)hinfo[kInfoMode] == kCgModeP;
-        TimedLaunch tl(stream);
-        rc = launch_coop(search ? pl.ke->cgs : pl.ke->cgr, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
-        if (rc) return rc;
-        tl.stop();
-        HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        const int64_t now = (int64_t)hinfo[kInfoProducts];
-        if (now > products) tl.record(search ? kTimeSearchStep : kTimeResidualPhase);
-        products = now;
-        if (++launches > 4 * max_iter + 64) return fail(SR_ERR_HIP, "sr_cg_solve: split solve did not finish");
-      }
-    } else {
-    // a round: search steps up to the next periodic refresh, then the residual phase;
-    // launches in a state that is not theirs return at once
-    const int steps = (o.refresh_every > 0 ? o.refresh_every : 16) + 1;
-    int64_t pairs = 0;
-    for (int batch = 1;; batch = batch < 16 ? 2 * batch : 16) {
-      for (int k = 0; k < batch; ++k) {
-        for (int sidx = 0; sidx < steps; ++sidx) {
-          rc = launch_coop(pl.ke->cgs, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
-          if (rc) return rc;
-        }
-        rc = launch_coop(pl.ke->cgr, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
-        if (rc) return rc;
-      }
-      pairs += (int64_t)batch * steps;
-      HIP_TRY(hipMemcpyAsync(hinfo, a.info, sizeof(hinfo), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
-      if (habort != 0u || hinfo[kInfoOk] == 0.0 || (int)hinfo[kInfoMode] == kCgModeDone) break;
-      // every pair makes at least one product until the solve is done; past max_iter the
-      // state machine ends it, so this bound is never reached by a working kernel
-      if (pairs > max_iter + 64) return fail(SR_ERR_HIP, "sr_cg_solve: split solve did not finish");
-    }
-    }
+    rc = run_split_cg(k, a, w.sb.abort, product_bytes, o.refresh_every, max_iter, stream, hinfo, &habort);
+    if (rc) return rc;
   } else {
     const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
     if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve: no CG kernel of this kind for this configuration");
@@ -2013,20 +2069,7 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
     HIP_TRY(hipStreamSynchronize(stream));
     tl.record(kTimeSolveLaunch);
   }
-  int status = (int)hinfo[2];
-  if (habort != 0u || hinfo[6] == 0.0) status = fail(SR_ERR_TIMEOUT, "sr_cg_solve: a cross-workgroup wait timed out");
-  else if (status == SR_ERR_NONFINITE) fail(SR_ERR_NONFINITE, "sr_cg_solve: non-finite scalar in CG");
-  else if (status == SR_BREAKDOWN) fail(SR_BREAKDOWN, "sr_cg_solve: p.(S+eps I)p <= 0");
-  else if (status == SR_NOT_CONVERGED) fail(SR_NOT_CONVERGED, "sr_cg_solve: max_iter reached");
-  if (info) {
-    info->iters = (int32_t)hinfo[0];
-    info->refreshes = (int32_t)hinfo[1];
-    info->status = status;
-    info->products = (int32_t)hinfo[3];
-    info->rel_res_recur = hinfo[4];
-    info->rel_res_true = hinfo[5];
-  }
-  return status;
+  return cg_outcome("sr_cg_solve", hinfo, habort, info);
 }
 
 int sr_cg_solve_async(const sr_matrix *O, const double *g, double eps, double *x, const sr_cg_opts *opt,
@@ -2047,6 +2090,251 @@ int sr_cg_solve_async(const sr_matrix *O, const double *g, double eps, double *x
   const void *cg_fn = two_planes(O) ? pl.ke->cg2 : (o.precond ? pl.ke->cgj : (exact_search ? pl.ke->cgx : pl.ke->cg));
   if (cg_fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_async: no CG kernel of this kind for this configuration");
   return launch_coop(cg_fn, pl.pg.G, &a, stream, pl.ke->nt, pl.ke->ring_bytes);
+}
+
+// ------------------------------------------------------------------------------------
+// Index-coded CPS storage
+// ------------------------------------------------------------------------------------
+static int64_t cps_n_p(const sr_cps_matrix *M) { return M->n_corr * (int64_t)M->n_states + M->dense.n_p; }
+
+static int check_cps(const sr_cps_matrix *M, const char *name) {
+  if (M == nullptr) return fail(SR_ERR_INVALID, "%s: null matrix", name);
+  if (M->reserved != 0) return fail(SR_ERR_INVALID, "%s: reserved must be 0", name);
+  if (M->n_s < 1) return fail(SR_ERR_INVALID, "%s: n_s must be >= 1", name);
+  if (M->n_corr < 0 || M->dense.n_p < 0) return fail(SR_ERR_INVALID, "%s: n_corr and dense.n_p must be >= 0", name);
+  if (M->n_states < 1 || M->n_states > 256) return fail(SR_ERR_INVALID, "%s: n_states must be in [1, 256]", name);
+  if (cps_n_p(M) < 1) return fail(SR_ERR_INVALID, "%s: no parameters", name);
+  if (M->n_corr > ((int64_t)1 << 31) / M->n_states) return fail(SR_ERR_INVALID, "%s: too many correlator columns", name);
+  if (M->n_corr > 0) {
+    if (M->idx == nullptr || M->val == nullptr) return fail(SR_ERR_INVALID, "%s: null idx or val", name);
+    if (M->ld_idx < M->n_s || M->ld_idx % 16 != 0 || ((uintptr_t)M->idx) % 16)
+      return fail(SR_ERR_INVALID, "%s: idx must be 16-byte aligned with ld_idx >= n_s a multiple of 16", name);
+  }
+  if (M->dense.n_p > 0) {
+    const sr_matrix &d = M->dense;
+    if (d.n_s != M->n_s) return fail(SR_ERR_INVALID, "%s: dense.n_s must equal n_s", name);
+    if (d.dtype != SR_F64 && d.dtype != SR_F32 && d.dtype != SR_BF16)
+      return fail(SR_ERR_INVALID, "%s: the dense block must be SR_F64, SR_F32 or SR_BF16", name);
+    if (d.O_lo != nullptr || d.lo_cols != nullptr || d.n_lo != 0)
+      return fail(SR_ERR_INVALID, "%s: the dense block must have one plane", name);
+    int rc = check_matrix(&d, name);
+    if (rc) return rc;
+  }
+  return SR_OK;
+}
+
+// The dense block as its own matrix (no means: the caller's col_mean covers all columns).
+static sr_matrix cps_dense(const sr_cps_matrix *M) {
+  sr_matrix d = M->dense;
+  d.col_mean = nullptr;
+  return d;
+}
+
+// Kernels for the dense block's width (the narrowest register tile that holds a row).
+static int cps_pick(const sr_cps_matrix *M, bool exact_search, const char *name, const CpsEntry **out) {
+  const int dt = M->dense.n_p > 0 ? M->dense.dtype : SR_F64;
+  int count = 0;
+  const CpsEntry *tab = cps_table(dt, &count);
+  const int64_t nvec = cdiv(M->dense.n_p, vec_of(dt));
+  const int64_t need = std::max<int64_t>(1, cdiv(nvec, 512));
+  const CpsEntry *pick = nullptr;
+  for (int i = 0; i < count; ++i) {
+    if (tab[i].nvt < need || (exact_search && tab[i].stepx == nullptr)) continue;
+    if (pick == nullptr || tab[i].nvt < pick->nvt) pick = &tab[i];
+  }
+  if (pick == nullptr)
+    return fail(SR_ERR_INVALID, "%s: a dense block of %lld columns is wider than the register tiles hold", name,
+                (long long)M->dense.n_p);
+  *out = pick;
+  return SR_OK;
+}
+
+// Column means of the dense block into scratch[n_sp..n_p) when the matrix has none.
+static int cps_mean(const sr_cps_matrix *M, int dev, const DeviceInfo &di, hipStream_t s, const double **mean) {
+  if (M->col_mean != nullptr || M->dense.n_p == 0) {
+    *mean = M->col_mean;
+    return SR_OK;
+  }
+  double *scr = nullptr;
+  int rc = get_mean_scratch(dev, s, cps_n_p(M), &scr);
+  if (rc) return rc;
+  const sr_matrix d = cps_dense(M);
+  rc = run_grad(&d, nullptr, nullptr, nullptr, scr + M->n_corr * (int64_t)M->n_states, nullptr, dev, di, s);
+  if (rc) return rc;
+  *mean = scr;
+  return SR_OK;
+}
+
+// Workspace and argument block of a CPS product or solve (cg: also the CG vectors).
+static int cps_args(const sr_cps_matrix *M, const double *mean, double eps, bool cg, int dev, const DeviceInfo &di,
+                    hipStream_t s, CgArgs &a) {
+  const int G = di.grid;
+  const int64_t n_p = cps_n_p(M), n_sp = M->n_corr * (int64_t)M->n_states, n_d = M->dense.n_p;
+  const int64_t n_dp = n_d > 0 ? round_up(n_d, vec_of(M->dense.dtype)) : 0;
+  size_t bytes = 0;
+  auto add = [&](size_t n) { bytes = (size_t)round_up((int64_t)bytes, 256) + n; };
+  add((size_t)G * 4);
+  add(64 * 4);
+  add((size_t)8 * G * 8);
+  add((size_t)8 * G * 8);
+  add((size_t)M->n_s * 8);
+  add((size_t)std::max<int64_t>(n_sp, 1) * 8);
+  add((size_t)G * std::max<int64_t>(n_dp, 1) * 8);
+  if (cg) {
+    add((size_t)3 * n_p * 8);
+    add(2 * kInfoWords * 8);
+  }
+  void *base = nullptr;
+  int rc = get_workspace(dev, s, bytes + 512, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  a = CgArgs{};
+  a.sb.flags = cv.take<uint32_t>(G);
+  a.sb.abort = cv.take<uint32_t>(64);
+  a.sb.red = cv.take<double>(8 * G);
+  CpsOp &c = a.cps;
+  c.red = cv.take<double>(8 * G);
+  c.w = cv.take<double>(M->n_s);
+  c.u = cv.take<double>(std::max<int64_t>(n_sp, 1));
+  c.part = cv.take<double>((int64_t)G * std::max<int64_t>(n_dp, 1));
+  c.n_dp = n_dp;
+  c.idx = (const unsigned char *)M->idx;
+  c.ld_idx = M->ld_idx;
+  c.val = M->val;
+  c.n_corr = M->n_corr;
+  c.n_states = M->n_states;
+  c.tiles = (int32_t)cdiv(M->n_s, kCpsTileRows);
+  c.n_sp = n_sp;
+  c.n_d = n_d;
+  c.dO = (const unsigned char *)M->dense.O;
+  c.dscale = n_d > 0 ? M->dense.col_scale : nullptr;
+  c.ldb_d = n_d > 0 ? M->dense.ld * elem_bytes(M->dense.dtype) : 0;
+  a.pg.G = G;
+  a.pg.C = 1;
+  a.pg.RG = G;
+  a.pg.n_s = M->n_s;
+  a.pg.n_p = n_p;
+  a.pg.n_v = n_p;
+  a.pg.wslice = n_p;
+  a.pg.n_tiles = c.tiles;
+  a.mean = mean;
+  a.eps = eps;
+  if (cg) {
+    a.r = cv.take<double>(n_p);
+    a.p = cv.take<double>(n_p);
+    a.q = cv.take<double>(n_p);
+    a.info = cv.take<double>(2 * kInfoWords);
+  }
+  return fill_zero(a.sb.flags, (int64_t)((char *)(a.sb.abort + 64) - (char *)a.sb.flags) / 4, s);
+}
+
+int sr_cps_grad(const sr_cps_matrix *M, const double *E, double *g, double *E_mean, double *col_mean_out,
+                double *diagS_out, hipStream_t stream) {
+  int rc = check_cps(M, "sr_cps_grad");
+  if (rc) return rc;
+  if (g != nullptr && E == nullptr) return fail(SR_ERR_INVALID, "sr_cps_grad: g needs E");
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const int64_t n_sp = M->n_corr * (int64_t)M->n_states;
+  if (M->dense.n_p > 0) {
+    const sr_matrix d = cps_dense(M);
+    rc = run_grad(&d, E, g ? g + n_sp : nullptr, E_mean, col_mean_out ? col_mean_out + n_sp : nullptr,
+                  diagS_out ? diagS_out + n_sp : nullptr, dev, di, stream);
+    if (rc) return rc;
+  }
+  if (M->n_corr > 0 || (E_mean != nullptr && M->dense.n_p == 0)) {
+    CpsStatsArgs a{};
+    a.idx = (const unsigned char *)M->idx;
+    a.ld_idx = M->ld_idx;
+    a.n_corr = M->n_corr;
+    a.n_s = M->n_s;
+    a.val = M->val;
+    a.E = E;
+    a.mean = col_mean_out;
+    a.diag = diagS_out;
+    a.g = g;
+    a.Emean = M->dense.n_p == 0 ? E_mean : nullptr;
+    a.n_states = M->n_states;
+    void *args[] = {&a};
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(M->n_corr, 4 * (int64_t)di.cus));
+    HIP_TRY(hipLaunchKernel(cps_stats_kernel(), dim3(blocks), dim3(512), args, 0, stream));
+  }
+  return SR_OK;
+}
+
+int sr_cps_sv_product(const sr_cps_matrix *M, const double *v, double *y, double eps, hipStream_t stream) {
+  int rc = check_cps(M, "sr_cps_sv_product");
+  if (rc) return rc;
+  const int64_t n_p = cps_n_p(M);
+  if (v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "sr_cps_sv_product: null v or y");
+  if (ranges_overlap(v, n_p * 8, y, n_p * 8)) return fail(SR_ERR_INVALID, "sr_cps_sv_product: v and y overlap");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_cps_sv_product: eps must be finite and >= 0");
+  const CpsEntry *ent = nullptr;
+  rc = cps_pick(M, false, "sr_cps_sv_product", &ent);
+  if (rc) return rc;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  rc = cps_mean(M, dev, di, stream, &mean);
+  if (rc) return rc;
+  CgArgs a;
+  rc = cps_args(M, mean, eps, false, dev, di, stream, a);
+  if (rc) return rc;
+  a.p = const_cast<double *>(v);
+  a.q = y;
+  return launch_coop(ent->sv, di.grid, &a, stream, 512, 0);
+}
+
+int sr_cps_cg_solve(const sr_cps_matrix *M, const double *g, double eps, double *x, const sr_cg_opts *opt,
+                    sr_cg_info *info, hipStream_t stream) {
+  const char *name = "sr_cps_cg_solve";
+  int rc = check_cps(M, name);
+  if (rc) return rc;
+  const int64_t n_p = cps_n_p(M);
+  if (g == nullptr || x == nullptr) return fail(SR_ERR_INVALID, "%s: null g or x", name);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
+  if (ranges_overlap(g, n_p * 8, x, n_p * 8)) return fail(SR_ERR_INVALID, "%s: g and x overlap", name);
+  sr_cg_opts o;
+  rc = check_cg_opts(name, opt, o);
+  if (rc) return rc;
+  if (o.precond) return fail(SR_ERR_INVALID, "%s: the Jacobi preconditioner is not available for CPS storage", name);
+  const bool exact_search = o.search_f64 != 0 && M->dense.n_p > 0 && M->dense.dtype == SR_BF16;
+  const CpsEntry *ent = nullptr;
+  rc = cps_pick(M, exact_search, name, &ent);
+  if (rc) return rc;
+  int64_t max_iter = o.max_iter > 0 ? o.max_iter : n_p + 100;
+  if (max_iter > (1 << 30)) max_iter = 1 << 30;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = nullptr;
+  rc = cps_mean(M, dev, di, stream, &mean);
+  if (rc) return rc;
+  CgArgs a;
+  rc = cps_args(M, mean, eps, true, dev, di, stream, a);
+  if (rc) return rc;
+  a.g = g;
+  a.x = x;
+  a.rtol = o.rtol;
+  a.max_iter = (int)max_iter;
+  a.refresh_every = o.refresh_every;
+  a.use_x0 = o.use_x0;
+  a.restart_on_refresh = o.restart_on_refresh;
+  a.refresh_drop2 = o.refresh_drop * o.refresh_drop;
+  a.hist = o.res_history;
+  double hinfo[kInfoWords] = {};
+  uint32_t habort = 0;
+  const SplitKernels k{ent->init, exact_search ? ent->stepx : ent->step, ent->resid, di.grid, 512, 0};
+  const int64_t bytes = M->n_corr * M->ld_idx +
+                        (M->dense.n_p > 0 ? M->n_s * M->dense.n_p * elem_bytes(M->dense.dtype) : 0);
+  rc = run_split_cg(k, a, a.sb.abort, bytes, o.refresh_every, max_iter, stream, hinfo, &habort);
+  if (rc) return rc;
+  return cg_outcome(name, hinfo, habort, info);
 }
 
 int sr_quantize(int64_t n_s, int64_t n_p, const void *in, int64_t ld_in, int32_t in_dtype, void *q, void *q_lo,

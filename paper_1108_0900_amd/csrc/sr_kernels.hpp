@@ -508,6 +508,10 @@ __global__ __launch_bounds__(NT) void k_lm(LmArgs a) {
 // ======================================================================================
 template <int DT, int NV, int R, int L, int P_, int NT>
 struct CgKernel {
+  // per-workgroup context of the product (column slice, barrier state)
+  __device__ __forceinline__ static void init(WgCtx &ctx, const CgArgs &a) {
+    init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  }
   // q[j] = ((S + eps I) vin)_j for this workgroup's vector chunk [j0, j1).  EXACT selects
   // float64 accumulation (residual products of scaled storage).  SMALL: one-row tiles, one
   // tile of lookahead and the shortest poll depth (same column geometry, fewer registers),
@@ -553,8 +557,8 @@ struct CgKernel {
 //                 float64-accumulated
 enum { kCgOnePlane = 0, kCgTwoPlanes = 1, kCgJacobi = 3, kCgExact = 4 };
 
-template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane, int PH = kPhAll>
-__global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
+template <class K, int NT, int CGM, int PH>
+__device__ __forceinline__ void cg_body(CgArgs &a) {
   // Conjugate gradient (Hestenes-Stiefel) as a state machine with one product per pass
   // through the loop, so the product code is instantiated once per accumulation type.
   //   MODE_P        q = A p, then alpha, x += alpha p, r -= alpha q
@@ -564,13 +568,12 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   //   MODE_FINAL    q = A x to report the true residual of an unconverged exit
   //   MODE_X0       q = A x0 for a warm start
   //   MODE_INIT     (split solves) x = 0, r = p = g, first decision
-  typedef CgKernel<DT, NV, R, L, P_, NT> K;
   enum { MODE_P = kCgModeP, MODE_REFRESH = kCgModeRefresh, MODE_CONFIRM = kCgModeConfirm, MODE_FINAL = kCgModeFinal,
          MODE_X0 = kCgModeX0, MODE_DONE = kCgModeDone, MODE_INIT = kCgModeInit };
   constexpr bool kJac = CGM == kCgJacobi;
-  static_assert(PH == kPhAll || (CGM == kCgOnePlane && K::kExactResidual), "split solves: one plane, scaled storage");
+  static_assert(PH == kPhAll || CGM == kCgOnePlane, "split solves: one plane");
   WgCtx ctx;
-  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  K::init(ctx, a);
   if constexpr (PH != kPhAll) {
     // resume: the barrier epochs and exchange steps continue from the previous launch
     // (every workgroup passed the same barriers and products there)
@@ -811,17 +814,17 @@ __global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
   }
 }
 
-// One search-direction iteration of a split CG solve (scaled storage, float32 products):
+// One search-direction iteration of a split CG solve (one stored plane, the storage type's
+// own accumulation: float32 for bf16/f16 codes, float64 for float64/float32 storage):
 // q = (S + eps I) p, alpha, x += alpha p, r -= alpha q, rho, beta, p = r + beta p and the
 // next decision, with the state read from CgArgs::info after the product and written back
 // at the end, so nothing but the product is live during its streaming loop.  INIT: the
 // solve's first launch instead, x = 0, r = p = g and the first decision (or the hand-over
 // of a warm start to the residual phase).  A launch in any other state returns at once.
-template <int DT, int NV, int R, int L, int P_, int NT, bool INIT>
+template <class K, int NT, bool INIT>
 __device__ __forceinline__ void cg_step_body(CgArgs &a) {
-  typedef CgKernel<DT, NV, R, L, P_, NT> K;
   WgCtx ctx;
-  init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
+  K::init(ctx, a);
   if (ld_coh32(a.sb.abort) != 0u) return;
   const int mode0 = (int)ld_coh(&a.info[kInfoMode]);
   if (mode0 != (INIT ? kCgModeInit : kCgModeP)) return;
@@ -937,13 +940,17 @@ __device__ __forceinline__ void cg_step_body(CgArgs &a) {
   }
 }
 
+template <int DT, int NV, int R, int L, int P_, int NT, int CGM = kCgOnePlane, int PH = kPhAll>
+__global__ __launch_bounds__(NT) void k_cg(CgArgs a) {
+  cg_body<CgKernel<DT, NV, R, L, P_, NT>, NT, CGM, PH>(a);
+}
 template <int DT, int NV, int R, int L, int P_, int NT>
 __global__ __launch_bounds__(NT) void k_cg_step(CgArgs a) {
-  cg_step_body<DT, NV, R, L, P_, NT, false>(a);
+  cg_step_body<CgKernel<DT, NV, R, L, P_, NT>, NT, false>(a);
 }
 template <int DT, int NV, int R, int L, int P_, int NT>
 __global__ __launch_bounds__(NT) void k_cg_init(CgArgs a) {
-  cg_step_body<DT, NV, R, L, P_, NT, true>(a);
+  cg_step_body<CgKernel<DT, NV, R, L, P_, NT>, NT, true>(a);
 }
 
 }  // namespace sr

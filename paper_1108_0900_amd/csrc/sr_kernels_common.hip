@@ -33,6 +33,82 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs a) {
   if (tid == 0) *a.count = base;
 }
 
+// Column statistics of the correlator columns of index-coded CPS storage (one state per
+// correlator per sample, Sec. II.C): with f_j the fraction of samples in state s of
+// correlator p (j = p * n_states + s) and value val_j,
+//   mean_j = val_j f_j,  diag S_j = val_j^2 f_j (1 - f_j),
+//   g_j = (2/n_s) val_j (B_j - f_j B),  B_j = sum_{k in state} e_k,  B = sum_k e_k,
+// with e_k = E_k - <E> (the centred form: B vanishes in exact arithmetic, and subtracting
+// f_j B cancels its rounding, so a column every sample occupies gets exactly 0).  One
+// workgroup per correlator (round robin); B_j and B are int64 fixed point (integer sums do
+// not depend on their order, so every run gives the same bits).  Every workgroup computes
+// <E>, sum |e| and B itself, in the same order.
+__global__ __launch_bounds__(512) void k_cps_stats(CpsStatsArgs a) {
+  constexpr int NT = 512;
+  __shared__ unsigned int s_cnt[256];
+  __shared__ long long s_e[256];
+  const int tid = (int)threadIdx.x;
+  const int64_t n_s = a.n_s;
+  const int ns = a.n_states;
+  const double inv_n = 1.0 / (double)n_s;
+  __shared__ long long s_ball[NT / 64];
+  double Ebar = 0.0, sigma = 1.0, Ball = 0.0;
+  if (a.E != nullptr) {
+    double se = 0.0;
+    for (int64_t k = tid; k < n_s; k += NT) se += a.E[k];
+    Ebar = block_sum(se) * inv_n;
+    double sa = 0.0;
+    for (int64_t k = tid; k < n_s; k += NT) sa += fabs(a.E[k] - Ebar);
+    const double A = block_sum(sa);
+    if (A > 0.0 && isfinite(A)) {
+      int e;
+      (void)frexp(A, &e);
+      sigma = ldexp(1.0, 62 - e);
+    }
+    long long bt = 0;
+    for (int64_t k = tid; k < n_s; k += NT) bt += __double2ll_rn((a.E[k] - Ebar) * sigma);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) bt += __shfl_xor(bt, off, 64);
+    if ((tid & 63) == 0) s_ball[tid >> 6] = bt;
+    __syncthreads();
+    long long tot = 0;
+    for (int w = 0; w < NT / 64; ++w) tot += s_ball[w];
+    Ball = (double)tot;
+    if (blockIdx.x == 0 && tid == 0 && a.Emean != nullptr) *a.Emean = Ebar;
+  }
+  for (int64_t p = blockIdx.x; p < a.n_corr; p += gridDim.x) {
+    for (int i = tid; i < 256; i += NT) {
+      s_cnt[i] = 0u;
+      s_e[i] = 0ll;
+    }
+    __syncthreads();
+    const unsigned char *row = a.idx + p * a.ld_idx;
+    for (int64_t k4 = (int64_t)tid * 4; k4 < n_s; k4 += (int64_t)NT * 4) {
+      const uint32_t word = *(const uint32_t *)(row + k4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = k4 + r;
+        const unsigned s = (word >> (8 * r)) & 0xFFu;
+        if (k < n_s && s < (unsigned)ns) {
+          atomicAdd(&s_cnt[s], 1u);
+          if (a.E != nullptr)
+            atomicAdd((unsigned long long *)&s_e[s], (unsigned long long)__double2ll_rn((a.E[k] - Ebar) * sigma));
+        }
+      }
+    }
+    __syncthreads();
+    for (int s = tid; s < ns; s += NT) {
+      const int64_t j = p * ns + s;
+      const double f = (double)s_cnt[s] * inv_n, v = a.val[j];
+      if (a.mean) a.mean[j] = v * f;
+      if (a.diag) a.diag[j] = v * v * f * (1.0 - f);
+      if (a.g && a.E) a.g[j] = 2.0 * inv_n * v * (((double)s_e[s] - f * Ball) / sigma);
+    }
+    __syncthreads();
+  }
+}
+const void *cps_stats_kernel() { return (const void *)&k_cps_stats; }
+
 // Streaming-read ceiling: every thread reads U 16-byte vectors per pass with the
 // products' non-temporal loads, grid-stride over `bytes`, and folds them into one word so
 // the loads are kept; the workgroup's words go to sink[blockIdx.x].
@@ -94,6 +170,18 @@ const BatchEntry *batched_entry(int dt) {
     case DT_F64: return batched_entry_f64();
     case DT_F32: return batched_entry_f32();
     default: return nullptr;
+  }
+}
+
+const CpsEntry *cps_table_f64(int *count);
+const CpsEntry *cps_table_f32(int *count);
+const CpsEntry *cps_table_bf16(int *count);
+const CpsEntry *cps_table(int dt, int *count) {
+  switch (dt) {
+    case DT_F64: return cps_table_f64(count);
+    case DT_F32: return cps_table_f32(count);
+    case DT_BF16: return cps_table_bf16(count);
+    default: *count = 0; return nullptr;
   }
 }
 

@@ -7,8 +7,10 @@ namespace sr {
 #define SR_REG_SR(NV, R, L, P, NT)                                                                   \
   {DT_F32, NV, R, L, P, NT, 0, (const void *)&k_sv<DT_F32, NV, R, L, P, NT>,                        \
    (const void *)&k_cg<DT_F32, NV, R, L, P, NT>, nullptr,                                            \
-   nullptr, nullptr, (const void *)&k_cg<DT_F32, NV, R, L, P, NT, kCgJacobi>,                 \
-   nullptr, nullptr, nullptr, nullptr, Product<DT_F32, NV, R, 1, false, L, P, NT>::ring_bytes()},
+   nullptr, nullptr, (const void *)&k_cg<DT_F32, NV, R, L, P, NT, kCgJacobi>, nullptr,               \
+   (const void *)&k_cg_step<DT_F32, NV, R, L, P, NT>,                                                 \
+   (const void *)&k_cg<DT_F32, NV, R, L, P, NT, kCgOnePlane, kPhResidual>,                            \
+   (const void *)&k_cg_init<DT_F32, NV, R, L, P, NT>, Product<DT_F32, NV, R, 1, false, L, P, NT>::ring_bytes()},
 #define SR_REG_LM(NV, R, L, P, NT)                                                                   \
   {DT_F32, NV, R, L, P, NT, 1, nullptr, nullptr, (const void *)&k_lm<DT_F32, NV, R, L, P, NT>, nullptr, \
    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, Product<DT_F32, NV, R, 2, false, L, P, NT>::ring_bytes()},

@@ -32,6 +32,27 @@ struct LmArgs {
   double *y;            // [n_p + 1]
 };
 
+// Index-coded correlator-product-state storage (one state per correlator per sample plus
+// a dense block): the operand of the CPS product and of the CG solves over it.
+struct CpsOp {
+  const unsigned char *idx;   // [n_corr][ld_idx] state of correlator p in sample k at p*ld_idx + k
+  int64_t ld_idx;             // bytes, multiple of 16
+  const double *val;          // [n_sp] value of each correlator column
+  int64_t n_corr;
+  int32_t n_states;           // columns per correlator (states >= n_states select no column)
+  int32_t tiles;              // row tiles of kCpsTileRows rows
+  int64_t n_sp, n_d;          // correlator columns (n_corr * n_states) and dense columns
+  const unsigned char *dO;    // dense block [n_s][ld_d] (nullptr when n_d == 0)
+  const float *dscale;        // [n_d] column scales (bf16 / f16 dense block) or nullptr
+  int64_t ldb_d;              // row stride of the dense block in bytes, multiple of 16
+  double *w;                  // [n_s] w_k of the current product
+  void *u;                    // [n_sp] val_j v_j of the current product (accumulation type)
+  void *part;                 // [G][n_dp] dense partial sums (accumulation type)
+  int64_t n_dp;               // row stride of part (n_d rounded up to the vector width)
+  double *red;                // [4][2][G] grid reductions of the product
+};
+constexpr int kCpsTileRows = 128;   // rows per tile of the row pass (2 waves of 64 rows)
+
 struct CgArgs {
   ProdGeom pg;
   ProdBufs pb;
@@ -46,14 +67,16 @@ struct CgArgs {
   double *hist;         // [max_iter + 1] or nullptr
   double *info;         // [16]: outcome, then the state between the launches of a split solve
   const double *diag;   // [n_p] diag S (Jacobi-preconditioned CG), else nullptr
+  CpsOp cps;            // index-coded storage (CPS products only)
 };
 
-// A CG solve split over launches (scaled storage with float32 search products and float64
-// residual products, so that each kernel holds a single product code; two in one kernel
-// cost register spills in the streaming loop): k_cg_step runs one search-direction
-// iteration per launch, k_cg<..., kPhResidual> runs the residual products (refresh, exit
-// check, warm start) and returns at the next search step; kPhAll runs a whole solve in one
-// launch.  Between launches the state lives in CgArgs::info.
+// A CG solve split over launches (one stored plane, no preconditioner), so that no kernel
+// holds more than one product code and the state machine around it (two product codes, or
+// the whole state machine, in one kernel cost register spills in the streaming loop):
+// k_cg_init starts the solve, k_cg_step runs one search-direction iteration per launch,
+// k_cg<..., kPhResidual> runs the residual products (refresh, exit check, warm start;
+// float64 accumulation for scaled storage) and returns at the next search step; kPhAll
+// runs a whole solve in one launch.  Between launches the state lives in CgArgs::info.
 enum { kPhAll = 0, kPhResidual = 2 };
 // Layout of CgArgs::info: outcome (read by the host) then the state of a split solve.
 enum { kInfoIters = 0, kInfoRefreshes, kInfoStatus, kInfoProducts, kInfoRelRecur, kInfoRelTrue, kInfoOk,
@@ -187,12 +210,32 @@ struct KernelEntry {
   const void *cg2;       // CG over two code planes (scaled storage), or nullptr
   const void *cgj;       // Jacobi-preconditioned CG (float64 / float32 storage), or nullptr
   const void *cgx;       // CG with float64-accumulated search products (scaled storage), or nullptr
-  const void *cgs, *cgr; // split CG (scaled storage, one plane): search step and residual phase, or nullptr
+  const void *cgs, *cgr; // split CG (one plane): search step and residual phase, or nullptr
   const void *cgi;       // split CG: its first launch (initial state), or nullptr
   int ring_bytes;        // dynamic LDS of the launch
 };
 
 const KernelEntry *kernel_table(int dt, int *count);
+
+// Index-coded CPS storage: kernels per dense storage type and register tile (nvt 16-byte
+// vectors of a dense row per thread, 512 threads).
+struct CpsEntry {
+  int dt, nvt;
+  const void *sv, *init, *step, *stepx, *resid;   // stepx: float64 search products, or nullptr
+};
+const CpsEntry *cps_table(int dt, int *count);
+
+// Column statistics of the correlator columns of CPS storage.
+struct CpsStatsArgs {
+  const unsigned char *idx;   // [n_corr][ld_idx]
+  int64_t ld_idx, n_corr, n_s;
+  const double *val;          // [n_corr * n_states]
+  const double *E;            // [n_s] or nullptr
+  double *mean, *diag, *g;    // [n_corr * n_states], each may be nullptr (g needs E)
+  double *Emean;              // device scalar or nullptr
+  int32_t n_states, pad;
+};
+const void *cps_stats_kernel();
 const void *grad_kernel(int dt);
 int grad_nv(int dt);
 int grad_rows(int dt);

@@ -35,6 +35,11 @@ class SrMatrix(ctypes.Structure):
                 ("n_lo", _c_i64), ("ld_lo", _c_i64)]
 
 
+class SrCpsMatrix(ctypes.Structure):
+    _fields_ = [("n_s", _c_i64), ("n_corr", _c_i64), ("n_states", _c_i32), ("reserved", _c_i32),
+                ("idx", _c_p), ("ld_idx", _c_i64), ("val", _c_p), ("dense", SrMatrix), ("col_mean", _c_p)]
+
+
 class SrCgOpts(ctypes.Structure):
     _fields_ = [("rtol", _c_d), ("max_iter", _c_i32), ("refresh_every", _c_i32), ("use_x0", _c_i32),
                 ("restart_on_refresh", _c_i32), ("res_history", _c_p), ("refresh_drop", _c_d),
@@ -80,6 +85,10 @@ PROTOTYPES = {
                                             ctypes.POINTER(_c_i64), _c_p]),
     "sr_quantize_remainder": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_i32, _c_p, _c_p, _c_i64, _c_p,
                                              _c_i64, _c_p]),
+    "sr_cps_grad": (ctypes.c_int, [ctypes.POINTER(SrCpsMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
+    "sr_cps_sv_product": (ctypes.c_int, [ctypes.POINTER(SrCpsMatrix), _c_p, _c_p, _c_d, _c_p]),
+    "sr_cps_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrCpsMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
+                                       ctypes.POINTER(SrCgInfo), _c_p]),
     "sr_release": (ctypes.c_int, []),
     "sr_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(SrMatrix), _c_i32]),
     "sr_workspace_reserve": (ctypes.c_int, [_c_i64, _c_p]),
@@ -390,6 +399,139 @@ def sr_cg_solve_async(M: Matrix, g: torch.Tensor, eps: float, x: torch.Tensor, i
     _check(lib().sr_cg_solve_async(ctypes.byref(m), _ptr(g), float(eps), _ptr(x), ctypes.byref(opts), _ptr(info),
                                    _stream(stream)), "sr_cg_solve_async")
     return x
+
+
+# ----------------------------------------------------------------------------------------
+# Index-coded CPS storage
+# ----------------------------------------------------------------------------------------
+@dataclass
+class CpsMatrix:
+    """Index-coded correlator-product-state storage as the library sees it (keeps the
+    tensors alive): idx (n_corr, ld_idx) uint8 states, correlator-major; val (n_corr *
+    n_states) float64 column values; dense the remaining parameters (a Matrix or None);
+    mean the column means of all n_p parameters (or None)."""
+    idx: torch.Tensor
+    n_s: int
+    n_states: int
+    val: torch.Tensor
+    dense: Matrix | None = None
+    mean: torch.Tensor | None = None
+
+    @property
+    def n_corr(self) -> int:
+        return self.idx.shape[0]
+
+    @property
+    def n_sp(self) -> int:
+        return self.n_corr * self.n_states
+
+    @property
+    def n_d(self) -> int:
+        return 0 if self.dense is None else self.dense.n_p
+
+    @property
+    def n_p(self) -> int:
+        return self.n_sp + self.n_d
+
+    def c(self) -> SrCpsMatrix:
+        m = SrCpsMatrix()
+        m.n_s = self.n_s
+        m.n_corr = self.n_corr
+        m.n_states = self.n_states
+        m.reserved = 0
+        m.idx = self.idx.data_ptr() if self.n_corr else None
+        m.ld_idx = self.idx.stride(0) if self.n_corr > 1 else ((self.n_s + 15) // 16) * 16
+        m.val = self.val.data_ptr() if self.n_corr else None
+        if self.dense is not None:
+            m.dense = self.dense.c()
+        else:
+            m.dense = SrMatrix()
+            m.dense.n_s = self.n_s
+            m.dense.dtype = SR_F64
+        m.col_mean = None if self.mean is None else self.mean.data_ptr()
+        return m
+
+
+def cps_matrix(idx: torch.Tensor, val: torch.Tensor, n_states: int, dense: torch.Tensor | Matrix | None = None,
+               dense_scale: torch.Tensor | None = None, mean: torch.Tensor | None = None) -> CpsMatrix:
+    """Wrap index-coded CPS storage: idx (n_corr, n_s) uint8 states (correlator-major),
+    val (n_corr * n_states) float64 column values, dense (n_s, n_d) the remaining
+    parameters (float64, float32, or bfloat16 codes with dense_scale) or a Matrix.  A copy
+    of idx with padded rows is made only when its layout breaks the rules of sr.h."""
+    if idx.dtype != torch.uint8 or idx.dim() != 2:
+        raise ValueError("idx must be a 2-D uint8 tensor (n_corr, n_s)")
+    n_corr, n_s = idx.shape
+    if dense is not None and not isinstance(dense, Matrix):
+        if dense.shape[0] != n_s:
+            raise ValueError("dense must have n_s rows")
+        dense = as_matrix(dense, scale=dense_scale)
+    if n_corr:
+        ld = idx.stride(0) if n_corr > 1 else ((n_s + 15) // 16) * 16
+        ok = idx.stride(1) == 1 and ld >= n_s and ld % 16 == 0 and idx.data_ptr() % 16 == 0
+        if ok:
+            ok = idx.storage_offset() + (n_corr - 1) * ld + ((n_s + 15) // 16) * 16 <= idx.untyped_storage().nbytes()
+        if not ok:
+            P = torch.zeros(n_corr, ((n_s + 15) // 16) * 16, dtype=torch.uint8, device=idx.device)
+            P[:, :n_s] = idx
+            idx = P[:, :n_s]
+    val = val.to(torch.float64).contiguous()
+    if val.numel() != n_corr * n_states:
+        raise ValueError("val must hold n_corr * n_states values")
+    return CpsMatrix(idx=idx, n_s=n_s, n_states=int(n_states), val=val, dense=dense,
+                     mean=None if mean is None else mean.contiguous())
+
+
+def sr_cps_grad(M: CpsMatrix, E: torch.Tensor | None, stream=None) -> dict:
+    """Column means, diag S, g and <E> of CPS storage (sr_cps_grad)."""
+    dev = M.val.device if M.n_corr else M.dense.O.device
+    out = {"mean": torch.empty(M.n_p, dtype=torch.float64, device=dev),
+           "diag": torch.empty(M.n_p, dtype=torch.float64, device=dev)}
+    if E is not None:
+        E = _vec(E, M.n_s, "E")
+        out["g"] = torch.empty(M.n_p, dtype=torch.float64, device=dev)
+        out["E_mean"] = torch.empty(1, dtype=torch.float64, device=dev)
+    m = M.c()
+    st = lib().sr_cps_grad(ctypes.byref(m), _ptr(E), _ptr(out.get("g")), _ptr(out.get("E_mean")), _ptr(out["mean"]),
+                           _ptr(out["diag"]), _stream(stream))
+    _check(st, "sr_cps_grad")
+    return out
+
+
+def sr_cps_sv_product(M: CpsMatrix, v: torch.Tensor, eps: float = 0.0, out: torch.Tensor | None = None,
+                      stream=None) -> torch.Tensor:
+    """y = (S + eps I) v with CPS storage (sr_cps_sv_product)."""
+    v = _vec(v, M.n_p, "v")
+    y = torch.empty_like(v) if out is None else out
+    m = M.c()
+    _check(lib().sr_cps_sv_product(ctypes.byref(m), _ptr(v), _ptr(y), float(eps), _stream(stream)),
+           "sr_cps_sv_product")
+    return y
+
+
+def sr_cps_cg_solve(M: CpsMatrix, g: torch.Tensor, eps: float, rtol: float = 1e-10, max_iter: int = 0,
+                    refresh_every: int = 0, x0: torch.Tensor | None = None, restart_on_refresh: bool = False,
+                    refresh_drop: float = 0.0, search_f64: bool = False, history: bool = False,
+                    raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT), stream=None):
+    """CG solve of (S + eps I) x = g with CPS storage (sr_cps_cg_solve).  Returns (x, info)."""
+    g = _vec(g, M.n_p, "g")
+    x = _vec(x0, M.n_p, "x0").clone() if x0 is not None else torch.empty_like(g)
+    opts = _cg_opts(rtol, max_iter, refresh_every, x0 is not None, restart_on_refresh, refresh_drop, False, search_f64)
+    hist = None
+    if history:
+        mi = max_iter if max_iter > 0 else M.n_p + 100
+        hist = torch.full((mi + 1,), float("nan"), dtype=torch.float64, device=g.device)
+        opts.res_history = hist.data_ptr()
+    info = SrCgInfo()
+    m = M.c()
+    st = lib().sr_cps_cg_solve(ctypes.byref(m), _ptr(g), float(eps), _ptr(x), ctypes.byref(opts), ctypes.byref(info),
+                               _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "sr_cps_cg_solve")
+    d = {"status": st, "iters": info.iters, "refreshes": info.refreshes, "products": info.products,
+         "rel_res_recur": info.rel_res_recur, "rel_res_true": info.rel_res_true}
+    if hist is not None:
+        d["history"] = hist
+    return x, d
 
 
 CALLS = {"grad": 0, "sv_product": 1, "cg_solve": 2, "lm_hv_product": 3, "adjoint": 4}

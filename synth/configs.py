@@ -149,3 +149,50 @@ def relative_shifts(n_shift: int = 8) -> list:
     if n_shift == 1:
         return [1e-4]
     return [10.0 ** (-4.0 + 3.0 * i / (n_shift - 1)) for i in range(n_shift)]
+
+
+def cps_index_inputs(n_s: int, n_corr: int, n_states: int, n_dense: int, seed: int, device="cpu",
+                     dense_dtype=torch.float64, dense_var: float = 0.2, row_chunk: int = 4096):
+    """The matrix of cps_inputs (same seed, the same random draws in the same order) in
+    index-coded form, without building the n_s x n_p matrix:
+
+      idx   (n_corr, ld) uint8, correlator-major, ld = n_s rounded up to 16 (the padding
+            holds 0xFF, a state that selects no column); idx[p, k] = s_kp
+      val   (n_corr * n_states,) float64, 1/c_{p,s}
+      dense (n_s, n_dense) in dense_dtype (None when n_dense = 0)
+      E     (n_s,) float64 by the same recipe, O_k . u summed over the sample's states
+            and the dense block in float64 (equal to cps_inputs' E up to rounding order)
+
+    Returns dict(idx, val, dense, E, c, n_states).  Requires n_states <= 256.
+    """
+    if n_states > 256:
+        raise ValueError("index-coded storage holds at most 256 states per correlator")
+    gen = _gen(seed, device)
+    n_sparse = n_corr * n_states
+    n_p = n_sparse + n_dense
+    c = 0.5 + torch.rand(n_corr, n_states, generator=gen, device=device, dtype=torch.float64)
+    val = (1.0 / c).reshape(-1)
+    ld = ((n_s + 15) // 16) * 16
+    idx = torch.full((n_corr, ld), 255, dtype=torch.uint8, device=device)
+    dense = torch.empty(n_s, n_dense, dtype=dense_dtype, device=device) if n_dense else None
+    states = []
+    for r0 in range(0, n_s, row_chunk):
+        r1 = min(n_s, r0 + row_chunk)
+        st = torch.randint(0, n_states, (r1 - r0, n_corr), generator=gen, device=device)
+        idx[:, r0:r1] = st.t().to(torch.uint8)
+        states.append((r0, r1, st))
+        if n_dense:
+            d = torch.randn(r1 - r0, n_dense, generator=gen, device=device, dtype=torch.float64)
+            dense[r0:r1] = (d * math.sqrt(dense_var)).to(dense_dtype)
+            del d
+    u = torch.randn(n_p, generator=gen, device=device, dtype=torch.float64) * math.sqrt(1.0 / n_p)
+    noise = torch.randn(n_s, generator=gen, device=device, dtype=torch.float64)
+    vu = val * u[:n_sparse]
+    pcols = (torch.arange(n_corr, device=device, dtype=torch.int64) * n_states)[None, :]
+    ou = torch.empty(n_s, dtype=torch.float64, device=device)
+    for r0, r1, st in states:
+        ou[r0:r1] = vu[pcols + st].sum(dim=1)
+        if n_dense:
+            ou[r0:r1] += dense[r0:r1].to(torch.float64) @ u[n_sparse:]
+    E = -20.0 + 0.3 * ou + noise
+    return {"idx": idx[:, :n_s], "val": val, "dense": dense, "E": E, "c": c, "n_states": n_states}

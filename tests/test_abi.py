@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 _STRUCTS = {"sr_matrix": "SrMatrix", "sr_cg_opts": "SrCgOpts", "sr_cg_info": "SrCgInfo",
             "lm_davidson_opts": "LmDavidsonOpts", "lm_davidson_info": "LmDavidsonInfo",
-            "sr_batch_system": "SrBatchSystem"}
+            "sr_batch_system": "SrBatchSystem", "sr_cps_matrix": "SrCpsMatrix"}
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -281,3 +281,59 @@ def test_boundary_helpers_report_no_device():
     assert L.sr_workspace_reserve(1024, None) == sr.SR_ERR_NODEVICE
     assert L.sr_cg_solve_async(ctypes.byref(m), ctypes.c_void_p(4096), 0.1, ctypes.c_void_p(1 << 20), None,
                                ctypes.c_void_p(1 << 21), None) == sr.SR_ERR_NODEVICE
+
+
+def _cps(**kw):
+    """A valid CPS matrix over fake device addresses (never dereferenced: every case here
+    is rejected, or reports no device, before any HIP call)."""
+    m = sr.SrCpsMatrix()
+    m.n_s, m.n_corr, m.n_states, m.reserved = 100, 4, 8, 0
+    m.idx, m.ld_idx, m.val = 1 << 16, 112, 1 << 18
+    m.dense = _mat(n_s=100)
+    m.col_mean = None
+    for k, v in kw.items():
+        if k.startswith("dense_"):
+            setattr(m.dense, k[6:], v)
+        else:
+            setattr(m, k, v)
+    return m
+
+
+@pytest.mark.parametrize("kw", [dict(n_s=0), dict(n_corr=-1), dict(n_states=0), dict(n_states=257), dict(reserved=1),
+                                dict(idx=None), dict(val=None), dict(ld_idx=99), dict(ld_idx=104),
+                                dict(idx=(1 << 16) + 8), dict(dense_n_s=99), dict(dense_dtype=sr.SR_F16),
+                                dict(dense_O_lo=1 << 22), dict(n_corr=0, dense_n_p=0)],
+                         ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items()))
+def test_cps_invalid_matrix_rejected(kw):
+    L = sr.lib()
+    m = _cps(**kw)
+    v, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
+    assert L.sr_cps_sv_product(ctypes.byref(m), v, y, 0.1, None) == sr.SR_ERR_INVALID
+    assert L.sr_cps_grad(ctypes.byref(m), v, y, None, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_cps_cg_solve(ctypes.byref(m), v, 0.1, y, None, None, None) == sr.SR_ERR_INVALID
+
+
+def test_cps_invalid_scalars_and_options_rejected():
+    L = sr.lib()
+    m = _cps()
+    v, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
+    assert L.sr_cps_sv_product(ctypes.byref(m), v, y, -1.0, None) == sr.SR_ERR_INVALID
+    assert L.sr_cps_sv_product(ctypes.byref(m), v, v, 0.1, None) == sr.SR_ERR_INVALID        # v and y overlap
+    assert L.sr_cps_grad(ctypes.byref(m), None, y, None, None, None, None) == sr.SR_ERR_INVALID   # g needs E
+    o = sr.SrCgOpts()
+    o.rtol, o.precond = 1e-8, 1
+    assert L.sr_cps_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(o), None, None) == sr.SR_ERR_INVALID
+    o.precond, o.rtol = 0, 0.0
+    assert L.sr_cps_cg_solve(ctypes.byref(m), v, 0.1, y, ctypes.byref(o), None, None) == sr.SR_ERR_INVALID
+    wide = _cps(dense_n_p=40000, dense_ld=40000)     # wider than the float64 register tiles
+    assert L.sr_cps_sv_product(ctypes.byref(wide), v, y, 0.1, None) == sr.SR_ERR_INVALID
+
+
+def test_cps_reports_no_device():
+    if os.path.exists("/dev/kfd"):
+        pytest.skip("a GPU may be present")
+    L = sr.lib()
+    m = _cps()
+    v, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
+    assert L.sr_cps_sv_product(ctypes.byref(m), v, y, 0.1, None) == sr.SR_ERR_NODEVICE
+    assert L.sr_cps_grad(ctypes.byref(m), v, y, None, None, None, None) == sr.SR_ERR_NODEVICE

@@ -1,0 +1,230 @@
+"""Index-coded CPS storage (sr_cps_*) against the oracle on the expanded matrix.
+
+The inputs are the seeded index-form generator (synth.cps_index_inputs); the oracle
+expands them with cps_expand (pinned on the CPU against the generator's own scattered
+matrix) and applies its plain definitions.  The dense block goes to the device as float64,
+float32 or bf16 codes from the library's quantizer; the oracle uses the values each form
+stores (stored_dense: its own bf16 quantizer, bit-exact with the library's).
+
+Tolerances (element-wise, against the magnitude reference of gpu_util):
+  * float64 / float32 dense block: float64 arithmetic, 1e-12.  The correlator sums are
+    int64 fixed point scaled by the absolute sum A of the row values; each term's rounding
+    is at most A 2^-63, so a column's error stays below n_s 2^-62 of its magnitude
+    (< 1e-14 here).
+  * bf16 dense block: float32 accumulation of the dense block, 2e-5 (as for dense storage).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+import synth
+from paper_1108_0900_amd import sr
+from tests.gpu_util import DEV, TOL_PRODUCT, magnitude_ref, rel_err, stored_dense, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32, torch.bfloat16]
+DT_IDS = ["f64", "f32", "bf16"]
+
+# (n_s, n_corr, n_states, n_dense, seed): ragged rows (not a multiple of the 128-row tile or
+# of 4), odd state counts, the full uint8 range, no dense block, no correlators, one state
+# per correlator, and dense widths across the register-tile buckets of every storage type
+SHAPES = [
+    (1000, 6, 16, 70, 1),
+    (301, 5, 7, 11, 2),
+    (129, 3, 256, 0, 3),
+    (257, 0, 1, 37, 4),
+    (64, 9, 1, 5, 5),
+    (1531, 300, 20, 8481, 6),
+]
+SHAPE_IDS = ["basic", "ragged", "states256_nodense", "dense_only", "one_state", "wide_dense"]
+
+
+def make(n_s, n_corr, n_states, n_dense, seed, dtype, bad_states=0):
+    """Device CPS matrix and the expanded float64 matrix of the values it stores."""
+    ix = synth.cps_index_inputs(n_s, n_corr, n_states, n_dense, seed, device=DEV)
+    idx, val, dense = ix["idx"], ix["val"], ix["dense"]
+    if bad_states and n_corr and n_states < 256:
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        p = torch.randint(0, n_corr, (bad_states,), generator=g)
+        k = torch.randint(0, n_s, (bad_states,), generator=g)
+        idx[p.to(DEV), k.to(DEV)] = 255
+    dvals = None
+    Md = None
+    if n_dense:
+        dh = dense.cpu().numpy()
+        dvals = stored_dense(dh, dtype)
+        if dtype == torch.bfloat16:
+            q, s = sr.sr_quantize(dense, out_dtype=torch.bfloat16)
+            Md = sr.as_matrix(q, scale=s)
+        else:
+            Md = sr.as_matrix(dense.to(dtype))
+    M = sr.cps_matrix(idx, val, n_states, Md)
+    O = orc.cps_expand(idx.cpu().numpy(), val.cpu().numpy(), n_states, dvals)
+    return M, O, ix
+
+
+def _vec(n, seed):
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DT_IDS)
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_cps_product_matches_oracle(shape, dtype):
+    M, O, _ = make(*shape, dtype)
+    v = _vec(O.shape[1], 10)
+    eps = 0.37
+    ref = orc.sv_product_swapped(O, v, eps)
+    y = to_np(sr.sr_cps_sv_product(M, to_dev(v), eps))
+    mag = magnitude_ref(O, v, eps, dtype)
+    err = np.abs(y - ref) / mag
+    print(f"[cps-product {shape} {dtype}] worst error / magnitude {err.max():.2e}", flush=True)
+    assert err.max() <= TOL_PRODUCT[dtype], err.max()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DT_IDS)
+def test_cps_product_ignores_states_outside_the_correlator(dtype):
+    M, O, _ = make(700, 7, 12, 20, 7, dtype, bad_states=40)
+    v = _vec(O.shape[1], 11)
+    ref = orc.sv_product_swapped(O, v, 0.1)
+    y = to_np(sr.sr_cps_sv_product(M, to_dev(v), 0.1))
+    assert (np.abs(y - ref) / magnitude_ref(O, v, 0.1, dtype)).max() <= TOL_PRODUCT[dtype]
+
+
+def test_cps_product_is_the_same_bit_for_bit_on_every_run():
+    M, O, _ = make(3000, 40, 30, 100, 8, torch.float64)
+    v = to_dev(_vec(O.shape[1], 12))
+    y1 = sr.sr_cps_sv_product(M, v, 0.2)
+    y2 = sr.sr_cps_sv_product(M, v, 0.2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+def test_cps_product_with_given_means_equals_computed_means():
+    M, O, _ = make(500, 4, 9, 13, 9, torch.float64)
+    v = to_dev(_vec(O.shape[1], 13))
+    y1 = sr.sr_cps_sv_product(M, v, 0.2)
+    M.mean = to_dev(orc.sample_mean(O))
+    y2 = sr.sr_cps_sv_product(M, v, 0.2)
+    assert rel_err(to_np(y1), to_np(y2)) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=DT_IDS)
+@pytest.mark.parametrize("shape", SHAPES[:5], ids=SHAPE_IDS[:5])
+def test_cps_grad_matches_oracle(shape, dtype):
+    M, O, ix = make(*shape, dtype)
+    E = ix["E"]
+    st = sr.sr_cps_grad(M, E)
+    Eh = E.cpu().numpy()
+    g_ref = orc.energy_gradient(O, Eh)
+    # magnitude of each g_j's terms; constant columns (one state) have none, and there the
+    # oracle's centred sum is rounding noise near 1e-30 while the library gives exactly 0
+    scale = np.abs(orc.centred(O)).T @ np.abs(Eh - Eh.mean()) * 2 / O.shape[0]
+    scale = scale + 1e-6 * scale.max() + 1e-300
+    assert (np.abs(to_np(st["g"]) - g_ref) / scale).max() <= 1e-12
+    const = np.ptp(O, axis=0) == 0
+    assert np.all(to_np(st["g"])[const] == 0.0)
+    np.testing.assert_allclose(to_np(st["mean"]), orc.sample_mean(O), rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(to_np(st["diag"]), orc.diag_overlap(O), rtol=1e-10, atol=1e-13)
+    assert abs(float(st["E_mean"]) - Eh.mean()) <= 1e-13 * abs(Eh.mean())
+
+
+@pytest.mark.parametrize("search_f64", [False, True], ids=["f32_search", "f64_search"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=DT_IDS)
+def test_cps_cg_matches_cholesky(dtype, search_f64):
+    if search_f64 and dtype != torch.bfloat16:
+        pytest.skip("search_f64 applies to a bf16 dense block")
+    M, O, ix = make(1200, 6, 16, 70, 14, dtype)
+    st = sr.sr_cps_grad(M, ix["E"])
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    rtol = 1e-12 if dtype != torch.bfloat16 else 1e-9
+    x, info = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=rtol, refresh_every=20, search_f64=search_f64)
+    assert info["status"] == sr.SR_OK, info
+    g_ref = orc.energy_gradient(O, ix["E"].cpu().numpy())
+    x_ref = orc.solve_dense(O, g_ref, eps)
+    lam = np.linalg.eigvalsh(orc.overlap_matrix(O))
+    kappa = (lam.max() + eps) / (max(lam.min(), 0.0) + eps)
+    err = rel_err(to_np(x), x_ref)
+    print(f"[cps-cg {dtype} search_f64={search_f64}] {info} kappa {kappa:.1e} error {err:.2e}", flush=True)
+    assert err <= 10 * kappa * rtol, (err, kappa)
+
+
+def test_cps_cg_equals_dense_storage_solve():
+    """The same system through index-coded storage and through the expanded matrix in dense
+    storage (float64 both): the two solutions agree to the solves' accuracy."""
+    M, O, ix = make(2000, 12, 24, 40, 15, torch.float64)
+    st = sr.sr_cps_grad(M, ix["E"])
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x1, i1 = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=1e-12, refresh_every=20)
+    Md = sr.as_matrix(to_dev(O))
+    sd = sr.sr_grad(Md, ix["E"])
+    Md.mean = sd["mean"]
+    x2, i2 = sr.sr_cg_solve(Md, sd["g"], eps, rtol=1e-12, refresh_every=20)
+    assert i1["status"] == 0 and i2["status"] == 0, (i1, i2)
+    assert rel_err(to_np(sd["g"]), to_np(st["g"])) <= 1e-12
+    assert rel_err(to_np(x1), to_np(x2)) <= 1e-8
+
+
+def test_cps_cg_warm_start_and_unconverged_status():
+    M, O, ix = make(900, 5, 10, 30, 16, torch.float64)
+    st = sr.sr_cps_grad(M, ix["E"])
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    x, info = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=1e-12, refresh_every=20)
+    assert info["status"] == 0
+    x2, info2 = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=1e-12, refresh_every=20, x0=x)
+    assert info2["status"] == 0 and info2["iters"] <= 2, info2
+    _, info3 = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=1e-14, max_iter=3)
+    assert info3["status"] == sr.SR_NOT_CONVERGED and info3["iters"] == 3, info3
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [torch.float64, torch.bfloat16], ids=["f64", "bf16"])
+def test_cps_product_full_width_500k_columns(dtype):
+    """2048 samples at the full column geometry of the 500,000-parameter workload (2048
+    correlators x 240 states + 8480 dense columns) against the oracle."""
+    M, O, _ = make(2048, 2048, 240, 8480, 3, dtype)
+    v = _vec(O.shape[1], 17)
+    ref = orc.sv_product_swapped(O, v, 0.05)
+    y = to_np(sr.sr_cps_sv_product(M, to_dev(v), 0.05))
+    err = (np.abs(y - ref) / magnitude_ref(O, v, 0.05, dtype)).max()
+    print(f"[cps-product 2048 x 500000 {dtype}] worst error / magnitude {err:.2e}", flush=True)
+    assert err <= TOL_PRODUCT[dtype], err
+
+
+@pytest.mark.slow
+def test_cps_full_size_equals_dense_storage():
+    """The 32768 x 500000 workload in index-coded form (float64 dense block) against the same
+    matrix in dense float64 storage (131 GB, built by the generator's scatter from the same
+    seed): products agree element-wise, and a CPS solve to rtol 1e-8 has true residual
+    below 2e-8 under the dense-storage product."""
+    cfg = synth.CONFIGS["cps_32768x500000"]
+    ix = synth.cps_index_inputs(cfg.n_s, cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.seed, device=DEV)
+    M = sr.cps_matrix(ix["idx"], ix["val"], cfg.n_states, ix["dense"])
+    st = sr.sr_cps_grad(M, ix["E"])
+    M.mean = st["mean"]
+    eps = cfg.eps_rel * float(st["diag"].mean())
+    x, info = sr.sr_cps_cg_solve(M, st["g"], eps, rtol=1e-8, refresh_every=20)
+    print(f"[cps-full] {info}", flush=True)
+    assert info["status"] == 0, info
+    v = torch.from_numpy(_vec(cfg.n_p, 18)).to(DEV)
+    y_cps = sr.sr_cps_sv_product(M, v, eps)
+    d = synth.cps_inputs(cfg.n_s, cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.seed, device=DEV)
+    Md = sr.as_matrix(d["O"])
+    del d
+    sd = sr.sr_grad(Md, ix["E"])
+    Md.mean = sd["mean"]
+    assert rel_err(to_np(sd["g"]), to_np(st["g"])) <= 1e-12
+    # the index form's means are exact counts; the dense form's shifted column sums over
+    # 32768 rows lose a few digits on indicator columns whose shift is a nonzero value
+    assert rel_err(to_np(sd["mean"]), to_np(st["mean"])) <= 1e-10
+    y_d = sr.sr_sv_product(Md, v, eps)
+    err = float((y_cps - y_d).abs().max() / y_d.abs().max())
+    r = st["g"] - sr.sr_sv_product(Md, x, eps)
+    rel = float(r.norm() / st["g"].norm())
+    print(f"[cps-full] product max difference / max {err:.2e}; true residual {rel:.2e}", flush=True)
+    assert err <= 1e-12
+    assert rel <= 2e-8

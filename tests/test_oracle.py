@@ -111,6 +111,69 @@ def test_cps_gauge_null_vectors():
         np.testing.assert_allclose(orc.sv_product_dense(O, u, 0.5), 0.5 * u, rtol=0, atol=1e-12)
 
 
+def test_cps_expand_reproduces_the_scattered_matrix():
+    """The index-coded form of the CPS generator expands to exactly the matrix the generator
+    builds by scattering 1/c into the dense O (same seed), and its energies agree to
+    rounding."""
+    args = dict(n_s=301, n_corr=5, n_states=7, n_dense=11, seed=3)
+    ref = synth.cps_inputs(args["n_s"], args["n_corr"], args["n_states"], args["n_dense"], args["seed"])
+    ix = synth.cps_index_inputs(args["n_s"], args["n_corr"], args["n_states"], args["n_dense"], args["seed"])
+    O = orc.cps_expand(ix["idx"].numpy(), ix["val"].numpy(), 7, ix["dense"].numpy())
+    np.testing.assert_array_equal(O, ref["O"].numpy())
+    np.testing.assert_allclose(ix["E"].numpy(), ref["E"].numpy(), rtol=1e-14, atol=0)
+    np.testing.assert_array_equal(ix["idx"].numpy().T, ref["state"].numpy())
+
+
+def test_cps_expand_structure_and_ignored_states():
+    """One nonzero per correlator per sample, equal to the column's value; a state outside
+    the correlator's columns leaves its block empty; the dense block follows unchanged."""
+    rng = np.random.default_rng(4)
+    n_corr, n_s, ns = 3, 40, 5
+    idx = rng.integers(0, ns, size=(n_corr, n_s))
+    idx[1, 7] = 200                                   # no column
+    val = 1.0 + rng.random(n_corr * ns)
+    dense = rng.standard_normal((n_s, 4))
+    O = orc.cps_expand(idx, val, ns, dense)
+    assert O.shape == (n_s, n_corr * ns + 4)
+    for p in range(n_corr):
+        blk = O[:, p * ns:(p + 1) * ns]
+        for k in range(n_s):
+            nz = np.nonzero(blk[k])[0]
+            if idx[p, k] < ns:
+                assert list(nz) == [idx[p, k]] and blk[k, idx[p, k]] == val[p * ns + idx[p, k]]
+            else:
+                assert len(nz) == 0
+    np.testing.assert_array_equal(O[:, n_corr * ns:], dense)
+
+
+def test_cps_column_statistics_closed_form():
+    """A correlator column is val times an indicator, so its mean is val f and its variance
+    the Bernoulli variance val^2 f (1 - f), f the fraction of samples in the state (checks
+    the oracle's centred statistics on the expanded matrix)."""
+    ix = synth.cps_index_inputs(500, 4, 6, 3, 9)
+    idx, val = ix["idx"].numpy(), ix["val"].numpy()
+    O = orc.cps_expand(idx, val, 6, ix["dense"].numpy())
+    f = np.array([[np.mean(idx[p] == s) for s in range(6)] for p in range(4)]).reshape(-1)
+    np.testing.assert_allclose(orc.sample_mean(O)[:24], val * f, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(orc.diag_overlap(O)[:24], val ** 2 * f * (1 - f), rtol=1e-12, atol=1e-15)
+    E = ix["E"].numpy()
+    ec = E - E.mean()
+    gs = np.array([2.0 / 500 * val[p * 6 + s] * ec[idx[p] == s].sum() for p in range(4) for s in range(6)])
+    np.testing.assert_allclose(orc.energy_gradient(O, E)[:24], gs, rtol=1e-10, atol=1e-12)
+
+
+def test_cps_expand_gauge_null_vectors():
+    """Each correlator's vector c_{p,.} (the inverse values) is a null vector of S of the
+    expanded matrix: every sample holds exactly one state of every correlator."""
+    ix = synth.cps_index_inputs(400, 3, 9, 4, 21)
+    O = orc.cps_expand(ix["idx"].numpy(), ix["val"].numpy(), 9, ix["dense"].numpy())
+    c = ix["c"].numpy()
+    for p in range(3):
+        u = np.zeros(O.shape[1])
+        u[p * 9:(p + 1) * 9] = c[p]
+        np.testing.assert_allclose(orc.sv_product_swapped(O, u, 0.0), 0.0, atol=1e-13)
+
+
 # ------------------------------------------------------------------------------------------
 # Exact quantum mechanics in a tiny Hilbert space
 # ------------------------------------------------------------------------------------------
