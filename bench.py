@@ -201,6 +201,7 @@ def main():
                          "products or CPU baseline")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation-form measurement")
+    ap.add_argument("--no-cps", action="store_true", help="skip the index-coded CPS storage measurement")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the dense 8192 x 4000 and CPS 65536 x 24512 solves")
     ap.add_argument("--batched-systems", type=int, default=64,
@@ -502,6 +503,55 @@ def measure_stream_ceiling(T, reps=3):
             "kernel": "k_stream_read (sr_stream_read): non-temporal 16-byte loads, grid-stride"}
 
 
+def cps_product_bytes(n_s, n_corr, n_states, n_d, dense_dt):
+    """Algorithmic bytes of one product with index-coded CPS storage: one read of the state
+    bytes and of the dense block, the O(N_p) vectors (v, y, column means of the dense
+    block, the value table) and the N_s row values."""
+    n_p = n_corr * n_states + n_d
+    return n_s * n_corr + n_s * n_d * elem_bytes(dense_dt) + n_p * 3 * 8 + n_s * 8
+
+
+def measure_cps(cfg, x64, rtol, refresh, dev):
+    """The same workload in index-coded CPS storage (one state byte per correlator per
+    sample, the pairing block dense): product time and GB/s against the algorithmic bytes
+    of that form, CG solve time, and the error against the float64 dense-storage solution,
+    for the pairing block in bf16 (float32 accumulation), float32 and float64."""
+    import torch
+    import synth
+    from paper_1108_0900_amd import sr
+    ix = synth.cps_index_inputs(cfg.n_s, cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.seed, device=dev)
+    out = {"state_bytes": int(cfg.n_s * cfg.n_corr), "forms": {}}
+    v = torch.randn(cfg.n_p, dtype=torch.float64, device=dev)
+    for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32), ("f64", torch.float64)):
+        if dt == torch.bfloat16:
+            q, s = sr.sr_quantize(ix["dense"], out_dtype=torch.bfloat16)
+            Md = sr.as_matrix(q, scale=s)
+        else:
+            Md = sr.as_matrix(ix["dense"].to(dt))
+        M = sr.cps_matrix(ix["idx"], ix["val"], cfg.n_states, Md)
+        st = sr.sr_cps_grad(M, ix["E"])
+        M.mean = st["mean"]
+        eps = cfg.eps_rel * float(st["diag"].mean())
+        alg = cps_product_bytes(cfg.n_s, cfg.n_corr, cfg.n_states, cfg.n_dense, dt)
+        y = torch.empty_like(v)
+        sr.sr_cps_sv_product(M, v, eps, out=y)
+        ts = sorted(timed_events(lambda: sr.sr_cps_sv_product(M, v, eps, out=y))[1] for _ in range(7))
+        pm = ts[len(ts) // 2]
+        sr.sr_cps_cg_solve(M, st["g"], eps, rtol=rtol, refresh_every=refresh)       # warm
+        (x, info), ms = timed_events(lambda: sr.sr_cps_cg_solve(M, st["g"], eps, rtol=rtol, refresh_every=refresh))
+        rec = {"product_ms": round(pm, 4), "product_GBps": round(alg / pm / 1e6, 1),
+               "product_frac": round(alg / pm / 1e6 / HBM_PEAK_GBPS, 4), "algorithmic_bytes_per_product": int(alg),
+               "cg_ms": round(ms, 3), "iters": info["iters"], "products": info["products"],
+               "per_product_ms": round(ms / max(info["products"], 1), 4),
+               "rel_res_true": info["rel_res_true"], "rtol": rtol, "status": info["status"]}
+        if x64 is not None:
+            rec["err_vs_f64"] = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+        out["forms"][name] = rec
+        log(f"[bench] cps index form, {name} pairing block: {rec}")
+        del M, Md, x
+    return out
+
+
 def measure_single(args):
     import torch
     from paper_1108_0900_amd import sr
@@ -614,7 +664,7 @@ def measure_single(args):
         infos.append(info)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
-    launch_cls = "search_step" if (scaled and form in ("compact", "one_plane") and not args.search_f64) \
+    launch_cls = "search_step" if (form in ("compact", "one_plane", "plain") and not args.search_f64) \
         else "solve_launch"
     t_ms, t_n = sr.timing_read(launch_cls)
     sr.timing(False)
@@ -631,7 +681,14 @@ def measure_single(args):
     cg_avg = sum(cg_ms) / len(cg_ms)
     # the dominant kernel: one search step per launch (a product and the CG updates) for
     # the split solves of scaled storage, the whole solve's launch otherwise
-    if launch_cls == "search_step":
+    if launch_cls == "search_step" and t_n == 0:
+        # products below the per-launch state-check size run in queued rounds, untimed per
+        # launch: the solve's average per product stands in
+        launch_ms = cg_avg / max(products, 1)
+        launch_alg = alg_pb
+        launch_streamed = alg_pb + extra_search
+        kernel_name = "k_cg_step (split CG; solve time per product)"
+    elif launch_cls == "search_step":
         launch_ms = t_ms / max(t_n, 1)
         launch_alg = alg_pb
         launch_streamed = alg_pb + extra_search
@@ -697,6 +754,10 @@ def measure_single(args):
         log("[bench] cpu baseline")
         cpu = cpu_baseline(O64, min(args.cpu_rows, n_s), eps, args.cpu_budget)
 
+    cps = None
+    if scaled and not args.quick and not args.no_cps:
+        cps = measure_cps(cfg, x64, rtol, refresh, dev)
+
     # HBM traffic of the CG launch from the committed counter record (same kernel build and
     # same algorithmic bytes per launch), else null
     traffic = None
@@ -759,6 +820,7 @@ def measure_single(args):
         "f64_solve": f64,
         "err_vs_f64": err,
         "err_vs_f64_one_plane": err_one_plane,
+        "cps_index": cps,
     }
     if f64 is not None:
         out["speedup_vs_f64_same_rtol"] = round(f64["same_rtol"]["solve_ms"] / cg_avg, 3)

@@ -443,6 +443,41 @@ int sr_cps_cg_solve(const sr_cps_matrix *M, const double *g, double eps, double 
                     sr_cg_info *info, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
+ * Products during sampling (Sec. I: each sampled configuration contributes an outer
+ * product, so S can be applied while the samples are generated, without keeping O).
+ * The caller owns the accumulators (device memory) and feeds batches of sample rows as its
+ * sampler produces them; only one batch need exist at a time.  After the batches of n
+ * samples in total, with obar = s1 / n:
+ *   Y_i = A_i / n - obar (s1 . z_i) / n + eps z_i = ((S + eps I) z_i)   (centred S of all n),
+ *   g = 2 (se / n - <E> obar),  col_mean = obar,  E_mean = <E>.
+ * The sums are uncentred (the means are not known before the last sample), so when a
+ * column's mean is large against its spread the subtraction loses the corresponding
+ * digits; each batch's own contributions are computed by the fused kernels of sr_grad /
+ * sr_sv_product (dense rows) or sr_cps_grad / sr_cps_sv_product (index-coded rows), one
+ * read of the batch for its statistics and one per vector.
+ * ------------------------------------------------------------------------------------ */
+typedef struct sr_stream_acc {
+  int64_t n_p;               /* parameters, >= 1                                       */
+  int32_t m;                 /* vectors z_i, 1..8                                      */
+  int32_t reserved;          /* must be 0                                              */
+  double *A;                 /* [m][n_p] device: sum over samples of O_k (O_k . z_i)   */
+  double *s1;                /* [n_p] device: sum of O_k                               */
+  double *se;                /* [n_p] device: sum of E_k O_k, or NULL (no energies)    */
+  double *scal;              /* [4] device: samples, sum of E_k, two reserved words    */
+} sr_stream_acc;
+/* Zero the accumulators. */
+int sr_stream_begin(const sr_stream_acc *acc, hipStream_t stream);
+/* Add one batch: exactly one of O (dense rows, one plane) and C (index-coded rows) is
+ * non-NULL, with n_p columns; E: [batch samples] energies or NULL; Z: [m][n_p] the vectors
+ * (the same for every batch of one product). */
+int sr_stream_accumulate(const sr_stream_acc *acc, const sr_matrix *O, const sr_cps_matrix *C, const double *E,
+                         const double *Z, hipStream_t stream);
+/* Y: [m][n_p] (S + eps I) z_i; g, col_mean: [n_p] and E_mean: scalar, each may be NULL (g
+ * needs se). */
+int sr_stream_finish(const sr_stream_acc *acc, const double *Z, double eps, double *Y, double *g, double *col_mean,
+                     double *E_mean, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
  * Workspace (the library's own memory for partials, exchange words and CG vectors; one per
  * device and stream, grown on demand by reallocation, which synchronizes the stream).
  * sr_workspace_bytes: bytes that workspace must hold for `call` (enum sr_call) on the

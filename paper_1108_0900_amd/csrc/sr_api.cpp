@@ -424,6 +424,8 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_mean_ws;
 // Buffers of the batched calls (kept apart from g_ws, which the prepare passes they
 // launch first carve for themselves).
 std::map<std::pair<int, hipStream_t>, Workspace> g_batch_ws;
+// Scratch of the streamed (during-sampling) products: batch statistics, one product.
+std::map<std::pair<int, hipStream_t>, Workspace> g_stream_ws;
 
 int get_mean_scratch(int dev, hipStream_t s, int64_t n, double **out) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -887,7 +889,7 @@ int sr_stream_read(const void *p, int64_t bytes, int32_t blocks_per_cu, int32_t 
 int sr_release(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   int rc = SR_OK;
-  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws, &g_lm_ws, &g_shift_ws}) {
+  for (auto *mp : {&g_ws, &g_mean_ws, &g_batch_ws, &g_lm_ws, &g_shift_ws, &g_stream_ws}) {
     for (auto &kv : *mp) {
       if (kv.second.ptr) {
         int cur = 0;
@@ -2264,6 +2266,31 @@ int sr_cps_grad(const sr_cps_matrix *M, const double *E, double *g, double *E_me
   return SR_OK;
 }
 
+// y = (S + eps I) v over CPS storage; raw: the uncentred O^T (O v) / n_s (zero_mean, the
+// dense block's means taken as 0).
+static int cps_product(const char *name, const sr_cps_matrix *M, const double *v, double *y, double eps,
+                       const double *zero_mean, hipStream_t stream) {
+  const CpsEntry *ent = nullptr;
+  int rc = cps_pick(M, false, name, &ent);
+  if (rc) return rc;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const double *mean = zero_mean;
+  if (mean == nullptr) {
+    rc = cps_mean(M, dev, di, stream, &mean);
+    if (rc) return rc;
+  }
+  CgArgs a;
+  rc = cps_args(M, mean, eps, false, dev, di, stream, a);
+  if (rc) return rc;
+  a.cps.raw = zero_mean != nullptr ? 1 : 0;
+  a.p = const_cast<double *>(v);
+  a.q = y;
+  return launch_coop(ent->sv, di.grid, &a, stream, 512, 0);
+}
+
 int sr_cps_sv_product(const sr_cps_matrix *M, const double *v, double *y, double eps, hipStream_t stream) {
   int rc = check_cps(M, "sr_cps_sv_product");
   if (rc) return rc;
@@ -2271,22 +2298,148 @@ int sr_cps_sv_product(const sr_cps_matrix *M, const double *v, double *y, double
   if (v == nullptr || y == nullptr) return fail(SR_ERR_INVALID, "sr_cps_sv_product: null v or y");
   if (ranges_overlap(v, n_p * 8, y, n_p * 8)) return fail(SR_ERR_INVALID, "sr_cps_sv_product: v and y overlap");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "sr_cps_sv_product: eps must be finite and >= 0");
-  const CpsEntry *ent = nullptr;
-  rc = cps_pick(M, false, "sr_cps_sv_product", &ent);
+  return cps_product("sr_cps_sv_product", M, v, y, eps, nullptr, stream);
+}
+
+// ------------------------------------------------------------------------------------
+// Products during sampling
+// ------------------------------------------------------------------------------------
+constexpr int kStreamMaxVectors = 8;
+
+static int check_stream_acc(const sr_stream_acc *acc, const char *name) {
+  if (acc == nullptr) return fail(SR_ERR_INVALID, "%s: null accumulator", name);
+  if (acc->reserved != 0) return fail(SR_ERR_INVALID, "%s: reserved must be 0", name);
+  if (acc->n_p < 1) return fail(SR_ERR_INVALID, "%s: n_p must be >= 1", name);
+  if (acc->m < 1 || acc->m > kStreamMaxVectors) return fail(SR_ERR_INVALID, "%s: m must be in [1, %d]", name, kStreamMaxVectors);
+  if (acc->A == nullptr || acc->s1 == nullptr || acc->scal == nullptr)
+    return fail(SR_ERR_INVALID, "%s: null A, s1 or scal", name);
+  return SR_OK;
+}
+
+static int stream_launch(int which, const StreamArgs &a, int blocks, hipStream_t s) {
+  StreamArgs b = a;
+  void *args[] = {&b};
+  HIP_TRY(hipLaunchKernel(stream_kernel(which), dim3(blocks), dim3(which == 2 ? 512 : 256), args, 0, s));
+  return SR_OK;
+}
+
+int sr_stream_begin(const sr_stream_acc *acc, hipStream_t stream) {
+  int rc = check_stream_acc(acc, "sr_stream_begin");
   if (rc) return rc;
   int dev;
   DeviceInfo di;
   rc = device_check(&dev, &di);
   if (rc) return rc;
-  const double *mean = nullptr;
-  rc = cps_mean(M, dev, di, stream, &mean);
+  const int64_t n = acc->n_p;
+  if ((rc = fill_zero(acc->A, 2 * n * acc->m, stream))) return rc;
+  if ((rc = fill_zero(acc->s1, 2 * n, stream))) return rc;
+  if (acc->se && (rc = fill_zero(acc->se, 2 * n, stream))) return rc;
+  return fill_zero(acc->scal, 2 * 4, stream);
+}
+
+int sr_stream_accumulate(const sr_stream_acc *acc, const sr_matrix *O, const sr_cps_matrix *C, const double *E,
+                         const double *Z, hipStream_t stream) {
+  const char *name = "sr_stream_accumulate";
+  int rc = check_stream_acc(acc, name);
   if (rc) return rc;
-  CgArgs a;
-  rc = cps_args(M, mean, eps, false, dev, di, stream, a);
+  if ((O == nullptr) == (C == nullptr)) return fail(SR_ERR_INVALID, "%s: give exactly one of O and C", name);
+  if (Z == nullptr) return fail(SR_ERR_INVALID, "%s: null Z", name);
+  int64_t n_s, n_p;
+  if (O) {
+    if ((rc = check_matrix(O, name))) return rc;
+    if (O->O_lo != nullptr || O->lo_cols != nullptr) return fail(SR_ERR_INVALID, "%s: one-plane batches only", name);
+    n_s = O->n_s;
+    n_p = O->n_p;
+  } else {
+    if ((rc = check_cps(C, name))) return rc;
+    n_s = C->n_s;
+    n_p = cps_n_p(C);
+  }
+  if (n_p != acc->n_p) return fail(SR_ERR_INVALID, "%s: the batch has %lld parameters, the accumulator %lld", name,
+                                   (long long)n_p, (long long)acc->n_p);
+  if (E != nullptr && acc->se == nullptr) return fail(SR_ERR_INVALID, "%s: energies need acc->se", name);
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
   if (rc) return rc;
-  a.p = const_cast<double *>(v);
-  a.q = y;
-  return launch_coop(ent->sv, di.grid, &a, stream, 512, 0);
+  // scratch: batch means, batch gradient, one raw product, zero means, <E>_b
+  double *scr = nullptr;
+  rc = get_workspace(dev, stream, (size_t)(4 * round_up(n_p, 32) + 64) * 8, (void **)&scr, g_stream_ws);
+  if (rc) return rc;
+  const int64_t np32 = round_up(n_p, 32);
+  double *mean_b = scr, *g_b = scr + np32, *y_b = scr + 2 * np32, *zeros = scr + 3 * np32, *Eb = scr + 4 * np32;
+  if ((rc = fill_zero(zeros, 2 * n_p, stream))) return rc;
+  if (O) {
+    rc = run_grad(O, E, E ? g_b : nullptr, E ? Eb : nullptr, mean_b, nullptr, dev, di, stream);
+  } else {
+    rc = sr_cps_grad(C, E, E ? g_b : nullptr, E ? Eb : nullptr, mean_b, nullptr, stream);
+  }
+  if (rc) return rc;
+  StreamArgs a{};
+  a.n_p = n_p;
+  a.m = acc->m;
+  a.B = (double)n_s;
+  a.A = acc->A;
+  a.s1 = acc->s1;
+  a.se = acc->se;
+  a.scal = acc->scal;
+  a.mean_b = mean_b;
+  a.g_b = E ? g_b : nullptr;
+  a.Emean_b = E ? Eb : nullptr;
+  a.y_b = y_b;
+  const int blocks = (int)std::min<int64_t>(4 * (int64_t)di.cus, std::max<int64_t>(1, cdiv(n_p, 256)));
+  if ((rc = stream_launch(0, a, blocks, stream))) return rc;
+  for (int i = 0; i < acc->m; ++i) {
+    const double *zi = Z + (int64_t)i * n_p;
+    if (O) {
+      sr_matrix Oz = *O;
+      Oz.col_mean = zeros;            // uncentred: O^T (O z) / n_s
+      rc = sr_sv_product(&Oz, zi, y_b, 0.0, stream);
+    } else {
+      rc = cps_product(name, C, zi, y_b, 0.0, zeros, stream);
+    }
+    if (rc) return rc;
+    a.i = i;
+    if ((rc = stream_launch(1, a, blocks, stream))) return rc;
+  }
+  return SR_OK;
+}
+
+int sr_stream_finish(const sr_stream_acc *acc, const double *Z, double eps, double *Y, double *g, double *col_mean,
+                     double *E_mean, hipStream_t stream) {
+  const char *name = "sr_stream_finish";
+  int rc = check_stream_acc(acc, name);
+  if (rc) return rc;
+  if (Z == nullptr || Y == nullptr) return fail(SR_ERR_INVALID, "%s: null Z or Y", name);
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
+  if (g != nullptr && acc->se == nullptr) return fail(SR_ERR_INVALID, "%s: g needs acc->se", name);
+  const int64_t n_p = acc->n_p;
+  if (ranges_overlap(Y, n_p * acc->m * 8, Z, n_p * acc->m * 8) || ranges_overlap(Y, n_p * acc->m * 8, acc->A, n_p * acc->m * 8))
+    return fail(SR_ERR_INVALID, "%s: Y overlaps Z or A", name);
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  double *scr = nullptr;
+  rc = get_workspace(dev, stream, (size_t)(4 * round_up(n_p, 32) + 64) * 8, (void **)&scr, g_stream_ws);
+  if (rc) return rc;
+  StreamArgs a{};
+  a.n_p = n_p;
+  a.m = acc->m;
+  a.A = acc->A;
+  a.s1 = acc->s1;
+  a.se = acc->se;
+  a.scal = acc->scal;
+  a.Z = Z;
+  a.eps = eps;
+  a.Y = Y;
+  a.g = g;
+  a.col_mean = col_mean;
+  a.E_mean = E_mean;
+  a.dots = scr + 4 * round_up(n_p, 32) + 16;
+  if ((rc = stream_launch(2, a, acc->m, stream))) return rc;
+  const int blocks = (int)std::min<int64_t>(4 * (int64_t)di.cus, std::max<int64_t>(1, cdiv(n_p, 256)));
+  return stream_launch(3, a, blocks, stream);
 }
 
 int sr_cps_cg_solve(const sr_cps_matrix *M, const double *g, double eps, double *x, const sr_cg_opts *opt,

@@ -227,9 +227,10 @@ struct CpsKernel {
 
       // ---- 2. correlator histograms and dense finish ----
       const double inv_n = 1.0 / (double)n_s;
-      const double wbar = Sw * inv_n;
-      // sum |w_k - wbar| <= sum |w_k| + n_s |wbar|
-      const double sigma = fixed_scale(Sa + fabs(Sw));
+      // the uncentred product (raw) sums w_k itself; otherwise w_k - wbar, whose absolute
+      // sum is at most sum |w_k| + n_s |wbar|
+      const double wbar = c.raw ? 0.0 : Sw * inv_n;
+      const double sigma = fixed_scale(c.raw ? Sa : Sa + fabs(Sw));
       const double inv_sigma = 1.0 / sigma;
       __shared__ long long s_bin[kPass][256];
       for (int64_t p0 = b; p0 < c.n_corr; p0 += (int64_t)G * kPass) {

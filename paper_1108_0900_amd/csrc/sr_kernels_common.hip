@@ -109,6 +109,59 @@ __global__ __launch_bounds__(512) void k_cps_stats(CpsStatsArgs a) {
 }
 const void *cps_stats_kernel() { return (const void *)&k_cps_stats; }
 
+// Products during sampling (Sec. I: each sampled configuration adds an outer product).
+// Accumulators over the batches seen so far, with n the samples, obar = s1 / n:
+//   A_i = sum_k O_k (O_k . z_i),  s1 = sum_k O_k,  se = sum_k E_k O_k,  scal = (n, sum_k E_k)
+// A batch of B samples with column means mean_b, <E>_b and gradient g_b adds
+//   s1 += B mean_b,  se += B (g_b / 2 + <E>_b mean_b),  A_i += B y_b (y_b = O_b^T (O_b z_i) / B).
+__global__ void k_stream_stats(StreamArgs a) {
+  const double Eb = a.Emean_b ? *a.Emean_b : 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n_p; j += (int64_t)gridDim.x * blockDim.x) {
+    a.s1[j] += a.B * a.mean_b[j];
+    if (a.se && a.g_b) a.se[j] += a.B * (0.5 * a.g_b[j] + Eb * a.mean_b[j]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.scal[0] += a.B;
+    if (a.Emean_b) a.scal[1] += a.B * Eb;
+  }
+}
+__global__ void k_stream_addy(StreamArgs a) {
+  double *Ai = a.A + (int64_t)a.i * a.n_p;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n_p; j += (int64_t)gridDim.x * blockDim.x)
+    Ai[j] += a.B * a.y_b[j];
+}
+// dots[i] = s1 . z_i, one workgroup per vector (fixed order)
+__global__ __launch_bounds__(512) void k_stream_dots(StreamArgs a) {
+  const double *z = a.Z + (int64_t)blockIdx.x * a.n_p;
+  double acc = 0.0;
+  for (int64_t j = threadIdx.x; j < a.n_p; j += 512) acc += a.s1[j] * z[j];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) a.dots[blockIdx.x] = acc;
+}
+// Y_i = A_i / n - obar (s1 . z_i) / n + eps z_i  (the centred product: sum_k (O_k - obar)(O_k . z_i) / n),
+// g = 2 (se / n - <E> obar), col_mean = obar, E_mean = <E>
+__global__ void k_stream_finish(StreamArgs a) {
+  const double n = a.scal[0], inv_n = 1.0 / n, Ebar = a.scal[1] * inv_n;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n_p; j += (int64_t)gridDim.x * blockDim.x) {
+    const double ob = a.s1[j] * inv_n;
+    for (int i = 0; i < a.m; ++i) {
+      const int64_t ij = (int64_t)i * a.n_p + j;
+      a.Y[ij] = a.A[ij] * inv_n - ob * (a.dots[i] * inv_n) + a.eps * a.Z[ij];
+    }
+    if (a.col_mean) a.col_mean[j] = ob;
+    if (a.g && a.se) a.g[j] = 2.0 * (a.se[j] * inv_n - Ebar * ob);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.E_mean) *a.E_mean = Ebar;
+}
+const void *stream_kernel(int which) {
+  switch (which) {
+    case 0: return (const void *)&k_stream_stats;
+    case 1: return (const void *)&k_stream_addy;
+    case 2: return (const void *)&k_stream_dots;
+    default: return (const void *)&k_stream_finish;
+  }
+}
+
 // Streaming-read ceiling: every thread reads U 16-byte vectors per pass with the
 // products' non-temporal loads, grid-stride over `bytes`, and folds them into one word so
 // the loads are kept; the workgroup's words go to sink[blockIdx.x].

@@ -41,6 +41,8 @@ struct CpsOp {
   int64_t n_corr;
   int32_t n_states;           // columns per correlator (states >= n_states select no column)
   int32_t tiles;              // row tiles of kCpsTileRows rows
+  int32_t raw;                // 1: uncentred product O^T (O v) / n_s (with zero dense means)
+  int32_t pad;
   int64_t n_sp, n_d;          // correlator columns (n_corr * n_states) and dense columns
   const unsigned char *dO;    // dense block [n_s][ld_d] (nullptr when n_d == 0)
   const float *dscale;        // [n_d] column scales (bf16 / f16 dense block) or nullptr
@@ -236,6 +238,20 @@ struct CpsStatsArgs {
   int32_t n_states, pad;
 };
 const void *cps_stats_kernel();
+
+// Products during sampling: accumulators of streamed sample batches and their finish.
+struct StreamArgs {
+  int64_t n_p;
+  int32_t m, i;               // vectors; the vector of a product batch (k_stream_addy)
+  double B;                   // samples in the batch
+  double *A, *s1, *se, *scal; // accumulators: [m][n_p], [n_p], [n_p] or nullptr, [4]
+  const double *mean_b, *g_b, *Emean_b, *y_b;   // batch statistics and raw product
+  const double *Z;            // [m][n_p] vectors
+  double eps;
+  double *Y, *g, *col_mean, *E_mean;            // finish outputs (any but Y may be nullptr)
+  double *dots;               // [m] s1 . z_i
+};
+const void *stream_kernel(int which);   // 0 stats, 1 addy, 2 dots, 3 finish
 const void *grad_kernel(int dt);
 int grad_nv(int dt);
 int grad_rows(int dt);

@@ -40,6 +40,11 @@ class SrCpsMatrix(ctypes.Structure):
                 ("idx", _c_p), ("ld_idx", _c_i64), ("val", _c_p), ("dense", SrMatrix), ("col_mean", _c_p)]
 
 
+class SrStreamAcc(ctypes.Structure):
+    _fields_ = [("n_p", _c_i64), ("m", _c_i32), ("reserved", _c_i32), ("A", _c_p), ("s1", _c_p), ("se", _c_p),
+                ("scal", _c_p)]
+
+
 class SrCgOpts(ctypes.Structure):
     _fields_ = [("rtol", _c_d), ("max_iter", _c_i32), ("refresh_every", _c_i32), ("use_x0", _c_i32),
                 ("restart_on_refresh", _c_i32), ("res_history", _c_p), ("refresh_drop", _c_d),
@@ -89,6 +94,10 @@ PROTOTYPES = {
     "sr_cps_sv_product": (ctypes.c_int, [ctypes.POINTER(SrCpsMatrix), _c_p, _c_p, _c_d, _c_p]),
     "sr_cps_cg_solve": (ctypes.c_int, [ctypes.POINTER(SrCpsMatrix), _c_p, _c_d, _c_p, ctypes.POINTER(SrCgOpts),
                                        ctypes.POINTER(SrCgInfo), _c_p]),
+    "sr_stream_begin": (ctypes.c_int, [ctypes.POINTER(SrStreamAcc), _c_p]),
+    "sr_stream_accumulate": (ctypes.c_int, [ctypes.POINTER(SrStreamAcc), ctypes.POINTER(SrMatrix),
+                                            ctypes.POINTER(SrCpsMatrix), _c_p, _c_p, _c_p]),
+    "sr_stream_finish": (ctypes.c_int, [ctypes.POINTER(SrStreamAcc), _c_p, _c_d, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "sr_release": (ctypes.c_int, []),
     "sr_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(SrMatrix), _c_i32]),
     "sr_workspace_reserve": (ctypes.c_int, [_c_i64, _c_p]),
@@ -532,6 +541,74 @@ def sr_cps_cg_solve(M: CpsMatrix, g: torch.Tensor, eps: float, rtol: float = 1e-
     if hist is not None:
         d["history"] = hist
     return x, d
+
+
+# ----------------------------------------------------------------------------------------
+# Products during sampling
+# ----------------------------------------------------------------------------------------
+@dataclass
+class StreamAcc:
+    """Accumulators of products during sampling (device tensors kept alive here)."""
+    A: torch.Tensor          # (m, n_p)
+    s1: torch.Tensor         # (n_p,)
+    se: torch.Tensor | None  # (n_p,) or None
+    scal: torch.Tensor       # (4,)
+
+    @property
+    def n_p(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    def c(self) -> SrStreamAcc:
+        a = SrStreamAcc()
+        a.n_p, a.m, a.reserved = self.n_p, self.m, 0
+        a.A, a.s1, a.scal = self.A.data_ptr(), self.s1.data_ptr(), self.scal.data_ptr()
+        a.se = None if self.se is None else self.se.data_ptr()
+        return a
+
+
+def sr_stream_begin(n_p: int, m: int, energies: bool = True, device="cuda", stream=None) -> StreamAcc:
+    """New zeroed accumulators for m vectors over n_p parameters (sr_stream_begin)."""
+    f64 = dict(dtype=torch.float64, device=device)
+    acc = StreamAcc(A=torch.empty(m, n_p, **f64), s1=torch.empty(n_p, **f64),
+                    se=torch.empty(n_p, **f64) if energies else None, scal=torch.empty(4, **f64))
+    c = acc.c()
+    _check(lib().sr_stream_begin(ctypes.byref(c), _stream(stream)), "sr_stream_begin")
+    return acc
+
+
+def sr_stream_accumulate(acc: StreamAcc, batch, E: torch.Tensor | None, Z: torch.Tensor, stream=None):
+    """Add one batch of sample rows (a Matrix of dense rows or a CpsMatrix) with its
+    energies for the vectors Z (m, n_p) (sr_stream_accumulate)."""
+    if Z.dtype != torch.float64 or Z.shape != (acc.m, acc.n_p) or not Z.is_contiguous():
+        raise ValueError("Z must be a contiguous float64 (m, n_p) tensor")
+    c = acc.c()
+    if isinstance(batch, CpsMatrix):
+        om, cm, n_s = None, ctypes.byref(batch.c()), batch.n_s
+    else:
+        om, cm, n_s = ctypes.byref(batch.c()), None, batch.O.shape[0]
+    if E is not None:
+        E = _vec(E, n_s, "E")
+    _check(lib().sr_stream_accumulate(ctypes.byref(c), om, cm, _ptr(E), _ptr(Z), _stream(stream)),
+           "sr_stream_accumulate")
+
+
+def sr_stream_finish(acc: StreamAcc, Z: torch.Tensor, eps: float, stream=None) -> dict:
+    """(S + eps I) z_i for every vector, g, the column means and <E> of all samples fed
+    (sr_stream_finish)."""
+    f64 = dict(dtype=torch.float64, device=acc.A.device)
+    out = {"Y": torch.empty(acc.m, acc.n_p, **f64), "mean": torch.empty(acc.n_p, **f64)}
+    if acc.se is not None:
+        out["g"] = torch.empty(acc.n_p, **f64)
+        out["E_mean"] = torch.empty(1, **f64)
+    c = acc.c()
+    _check(lib().sr_stream_finish(ctypes.byref(c), _ptr(Z.contiguous()), float(eps), _ptr(out["Y"]),
+                                  _ptr(out.get("g")), _ptr(out["mean"]), _ptr(out.get("E_mean")), _stream(stream)),
+           "sr_stream_finish")
+    return out
 
 
 CALLS = {"grad": 0, "sv_product": 1, "cg_solve": 2, "lm_hv_product": 3, "adjoint": 4}

@@ -196,3 +196,42 @@ def cps_index_inputs(n_s: int, n_corr: int, n_states: int, n_dense: int, seed: i
             ou[r0:r1] += dense[r0:r1].to(torch.float64) @ u[n_sparse:]
     E = -20.0 + 0.3 * ou + noise
     return {"idx": idx[:, :n_s], "val": val, "dense": dense, "E": E, "c": c, "n_states": n_states}
+
+
+def cps_stream_layout(n_corr: int, n_states: int, n_dense: int, seed: int, device="cpu") -> dict:
+    """The fixed part of a streamed CPS sample set: the correlator values val = 1/c (c ~
+    U[0.5, 1.5] once per column) and the energy recipe's u ~ N(0, 1/N_p)."""
+    gen = _gen(seed, device)
+    n_p = n_corr * n_states + n_dense
+    c = 0.5 + torch.rand(n_corr, n_states, generator=gen, device=device, dtype=torch.float64)
+    u = torch.randn(n_p, generator=gen, device=device, dtype=torch.float64) * math.sqrt(1.0 / n_p)
+    return {"n_corr": n_corr, "n_states": n_states, "n_dense": n_dense, "seed": seed, "c": c,
+            "val": (1.0 / c).reshape(-1), "u": u}
+
+
+def cps_stream_batch(layout: dict, batch: int, n_rows: int, device="cpu", dense_dtype=torch.float64,
+                     dense_var: float = 0.2) -> dict:
+    """Batch `batch` of a streamed CPS sample set (a stand-in for the rows a sampler produces
+    one configuration at a time): n_rows samples, each in a uniform state of every correlator
+    plus N(0, dense_var) pairing derivatives, and E by the recipe of this module.  The batch is
+    a function of (layout seed, batch) alone, so it can be produced again instead of stored.
+    Returns dict(idx (n_corr, n_rows) uint8 correlator-major, dense (n_rows, n_dense), E)."""
+    n_corr, ns, nd = layout["n_corr"], layout["n_states"], layout["n_dense"]
+    gen = _gen(layout["seed"] * 1000003 + 7919 * (batch + 1), device)
+    ld = ((n_rows + 15) // 16) * 16
+    idx = torch.full((n_corr, ld), 255, dtype=torch.uint8, device=device)
+    st = torch.randint(0, ns, (n_rows, n_corr), generator=gen, device=device)
+    idx[:, :n_rows] = st.t().to(torch.uint8)
+    dense = None
+    u = layout["u"]
+    n_sparse = n_corr * ns
+    ou = torch.zeros(n_rows, dtype=torch.float64, device=device)
+    if n_corr:
+        pcols = (torch.arange(n_corr, device=device, dtype=torch.int64) * ns)[None, :]
+        ou += (layout["val"] * u[:n_sparse])[pcols + st].sum(dim=1)
+    if nd:
+        d = torch.randn(n_rows, nd, generator=gen, device=device, dtype=torch.float64) * math.sqrt(dense_var)
+        dense = d.to(dense_dtype)
+        ou += dense.to(torch.float64) @ u[n_sparse:]
+    E = -20.0 + 0.3 * ou + torch.randn(n_rows, generator=gen, device=device, dtype=torch.float64)
+    return {"idx": idx[:, :n_rows], "dense": dense, "E": E}

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 _STRUCTS = {"sr_matrix": "SrMatrix", "sr_cg_opts": "SrCgOpts", "sr_cg_info": "SrCgInfo",
             "lm_davidson_opts": "LmDavidsonOpts", "lm_davidson_info": "LmDavidsonInfo",
-            "sr_batch_system": "SrBatchSystem", "sr_cps_matrix": "SrCpsMatrix"}
+            "sr_batch_system": "SrBatchSystem", "sr_cps_matrix": "SrCpsMatrix", "sr_stream_acc": "SrStreamAcc"}
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -337,3 +337,39 @@ def test_cps_reports_no_device():
     v, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
     assert L.sr_cps_sv_product(ctypes.byref(m), v, y, 0.1, None) == sr.SR_ERR_NODEVICE
     assert L.sr_cps_grad(ctypes.byref(m), v, y, None, None, None, None) == sr.SR_ERR_NODEVICE
+
+
+def _acc(**kw):
+    a = sr.SrStreamAcc()
+    a.n_p, a.m, a.reserved = 3, 2, 0
+    a.A, a.s1, a.se, a.scal = 1 << 20, 1 << 21, 1 << 22, 1 << 23
+    for k, v in kw.items():
+        setattr(a, k, v)
+    return a
+
+
+@pytest.mark.parametrize("kw", [dict(n_p=0), dict(m=0), dict(m=9), dict(reserved=1), dict(A=None), dict(s1=None),
+                                dict(scal=None)], ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items()))
+def test_stream_invalid_accumulator_rejected(kw):
+    L = sr.lib()
+    a = _acc(**kw)
+    z, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
+    m = _mat()
+    assert L.sr_stream_begin(ctypes.byref(a), None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_accumulate(ctypes.byref(a), ctypes.byref(m), None, None, z, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_finish(ctypes.byref(a), z, 0.1, y, None, None, None, None) == sr.SR_ERR_INVALID
+
+
+def test_stream_invalid_batches_rejected():
+    L = sr.lib()
+    a = _acc()
+    z, y = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 26)
+    m, c = _mat(), _cps()
+    assert L.sr_stream_accumulate(ctypes.byref(a), None, None, None, z, None) == sr.SR_ERR_INVALID        # neither
+    assert L.sr_stream_accumulate(ctypes.byref(a), ctypes.byref(m), ctypes.byref(c), None, z, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_accumulate(ctypes.byref(_acc(n_p=4)), ctypes.byref(m), None, None, z, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_accumulate(ctypes.byref(a), ctypes.byref(m), None, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_accumulate(ctypes.byref(_acc(se=None)), ctypes.byref(m), None, z, z, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_finish(ctypes.byref(a), z, -1.0, y, None, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_finish(ctypes.byref(_acc(se=None)), z, 0.1, y, y, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_stream_finish(ctypes.byref(a), z, 0.1, z, None, None, None, None) == sr.SR_ERR_INVALID   # Y overlaps Z
