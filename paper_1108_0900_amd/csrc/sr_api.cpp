@@ -2179,8 +2179,15 @@ static int cps_args(const sr_cps_matrix *M, const double *mean, double eps, bool
   add(64 * 4);
   add((size_t)8 * G * 8);
   add((size_t)8 * G * 8);
+  // correlator groups: the largest group whose float64 table fits the LDS table, then
+  // (group, row range) items that cover the grid at least once
+  const int64_t cpg_max = std::max<int64_t>(1, kCpsTableBytes / (8 * (int64_t)M->n_states));
+  const int64_t n_grp = std::max<int64_t>(1, cdiv(M->n_corr, cpg_max));
+  const int64_t cpg = M->n_corr > 0 ? cdiv(M->n_corr, n_grp) : 0;
+  const int64_t ranges = std::max<int64_t>(1, G / n_grp);
+  const int64_t rpr = round_up(cdiv(M->n_s, ranges), kCpsTileRows);
   add((size_t)M->n_s * 8);
-  add((size_t)std::max<int64_t>(n_sp, 1) * 8);
+  add((size_t)n_grp * M->n_s * 8);
   add((size_t)G * std::max<int64_t>(n_dp, 1) * 8);
   if (cg) {
     add((size_t)3 * n_p * 8);
@@ -2197,7 +2204,11 @@ static int cps_args(const sr_cps_matrix *M, const double *mean, double eps, bool
   CpsOp &c = a.cps;
   c.red = cv.take<double>(8 * G);
   c.w = cv.take<double>(M->n_s);
-  c.u = cv.take<double>(std::max<int64_t>(n_sp, 1));
+  c.part_sp = cv.take<double>(n_grp * M->n_s);
+  c.n_grp = (int32_t)n_grp;
+  c.cpg = (int32_t)cpg;
+  c.n_items = (int32_t)(n_grp * ranges);
+  c.rpr = (int32_t)rpr;
   c.part = cv.take<double>((int64_t)G * std::max<int64_t>(n_dp, 1));
   c.n_dp = n_dp;
   c.idx = (const unsigned char *)M->idx;

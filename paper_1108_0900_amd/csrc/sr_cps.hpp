@@ -10,11 +10,12 @@
 //
 // The product y = (S + eps I) v (Sec. II.A, Eq. sr_multiply_2) runs in one cooperative
 // launch with three grid barriers:
-//   0. u_j = val_j v_j for this workgroup's share of the correlator columns, and its share
-//      of c = obar_D . v_D over the dense columns (reduced at the barrier);
-//   1. row pass over row tiles of 128 rows: w_k = sum_p u[p, s_kp] + D_k . (s v)_D - c
-//      (gathers from the u table, the dense rows read once into registers), then the
-//      dense partial sums P_d += D_kd w_k from the same registers;
+//   A. partial row sums over groups of correlators: a workgroup stages its group's table
+//      u_j = val_j v_j in LDS and gathers u[p, s_kp] for a range of rows; its share of
+//      c = obar_D . v_D over the dense columns is reduced at the barrier;
+//   1. row pass over row tiles of 128 rows: w_k = (sum of the groups' partials) +
+//      D_k . (s v)_D - c (the dense rows read once into registers), then the dense
+//      partial sums P_d += D_kd w_k from the same registers;
 //   2. per correlator, the histogram T_{p,s} = sum_{k: s_kp = s} (w_k - wbar) in int64
 //      fixed point (integer sums do not depend on their order, so the product is the
 //      same bit for bit on every run), y = val T / n_s + eps v; the dense columns sum the
@@ -22,9 +23,10 @@
 // Centring: sum_k (O_kj - obar_j) w_k = sum_k O_kj (w_k - wbar) for any w, so the
 // correlator columns need no column means; the dense columns keep the folded form.
 //
-// Data one workgroup writes and others read inside the launch (u, w, P, y) is written
-// through (device-scope stores) and read with plain loads after an agent-scope acquire
-// fence that follows the barrier, so the gathers from u hit the XCD's L2.
+// Data one workgroup writes and others read inside the launch (the partial row sums, w,
+// P, y, and the vectors the CG updates) is written and read with device-scope accesses
+// (an agent-scope acquire fence, which invalidates the XCD's L2, measured about 20 us on
+// every workgroup: far more than these few values cost to read through).
 #pragma once
 #include <type_traits>
 
@@ -34,8 +36,8 @@ namespace sr {
 
 __device__ __forceinline__ void st_acc(double *p, double v) { st_coh(p, v); }
 __device__ __forceinline__ void st_acc(float *p, float v) { st_coh32((uint32_t *)p, __float_as_uint(v)); }
-// Make the other workgroups' written-through data visible to plain loads of this one.
-__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ double ld_acc(const double *p) { return ld_coh(p); }
+__device__ __forceinline__ float ld_acc(const float *p) { return __uint_as_float(ld_coh32((const uint32_t *)p)); }
 
 // Fixed-point scale of a histogram of values whose absolute sum is at most A: every bin
 // sum, and every partial sum on the way, stays below 2^62 in magnitude.
@@ -50,13 +52,19 @@ __device__ __forceinline__ double fixed_scale(double A) {
 // (n_d <= NVT * NT * VEC).  X: float64 accumulation for every product (search_f64).
 template <int DDT, int NVT, bool X, int NT = 512>
 struct CpsKernel {
-  static_assert(NT == 512, "the row pass maps 8 waves to 2 row halves x 4 correlator parts");
+  static_assert(NT == 512, "the row pass maps 64 lanes x 2 rows to a 128-row tile and 8 waves to correlator parts");
   static constexpr int VEC = Storage<DDT>::VEC;
-  static constexpr int RB = NVT >= 16 ? 1 : (16 / NVT > 8 ? 8 : 16 / NVT);  // rows per batch
+  // rows per batch (RB rows x NVT vectors in registers); a second buffer to load the next
+  // batch while this one is reduced measured no faster (the row pass is bound by the
+  // decode and FMA work of the dot and the update, about 4.3 TB/s here, not by latency)
+  static constexpr int RB = NVT >= 12 ? 1 : (NVT >= 8 ? 2 : (NVT >= 3 ? 4 : 8));
   static constexpr int NWAVE = NT / 64;
-  static constexpr int kParts = NWAVE / 2;      // waves along the correlators in the row pass
+  static constexpr int kSlices = NT / kCpsTileRows;   // thread slices summing the group partials
   static constexpr int kPass = 8;               // correlators per histogram pass
   static constexpr bool kExactResidual = (DDT == DT_BF16 || DDT == DT_F16);
+
+  // q was written by other workgroups in this launch
+  __device__ __forceinline__ static double ldq(const double *p) { return ld_coh(p); }
 
   __device__ __forceinline__ static void init(WgCtx &ctx, const CgArgs &a) {
     ctx.rg = (int)blockIdx.x;
@@ -82,23 +90,73 @@ struct CpsKernel {
     const int G = (int)gridDim.x, b = (int)blockIdx.x, tid = (int)threadIdx.x;
     const int64_t n_s = a.pg.n_s, n_sp = c.n_sp, n_d = c.n_d;
     const int ns = c.n_states;
-    acc_t *u = (acc_t *)c.u;
-    acc_t *part = (acc_t *)c.part;
+      acc_t *part = (acc_t *)c.part;
     int nred = 0;
     double dummy;
 
-    // ---- 0. u table and the dense centring share ----
+    // ---- A. correlator partial row sums ----
+    // Work item (group g, row range rr): correlators [g cpg, (g+1) cpg) and rows
+    // [rr rpr, (rr+1) rpr).  The group's table u = val * v goes to LDS; lanes take pairs of
+    // rows (one 2-byte state load per correlator), waves share the group's correlators, and
+    // the waves' sums of each row are combined in a fixed order into part_sp[g][k].
     {
-      const int64_t cs = (n_sp + G - 1) / G;
-      const int64_t s0 = min(n_sp, (int64_t)b * cs), s1 = min(n_sp, s0 + cs);
-      for (int64_t j = s0 + tid; j < s1; j += NT) st_acc(&u[j], (acc_t)(c.val[j] * ld_coh(&vin[j])));
+      __shared__ acc_t s_u[kCpsTableBytes / sizeof(acc_t)];
+      const int wave = tid >> 6, lane = tid & 63;
+      acc_t *part_sp = (acc_t *)c.part_sp;
+      for (int it = b; it < c.n_items; it += G) {
+        const int g = it % c.n_grp, rr = it / c.n_grp;
+        const int64_t p0 = min(c.n_corr, (int64_t)g * c.cpg), p1 = min(c.n_corr, p0 + c.cpg);
+        const int np_ = (int)(p1 - p0);
+        __syncthreads();                 // s_u of the previous item is no longer read
+        for (int e = tid; e < np_ * ns; e += NT) {
+          const int64_t j = p0 * ns + e;
+          s_u[e] = (acc_t)(c.val[j] * ld_coh(&vin[j]));
+        }
+        __syncthreads();
+        // each wave takes whole blocks of 128 rows (a pair per lane, one 2-byte state load per
+        // correlator) through all the group's correlators, so no two waves share a row and
+        // no barrier is needed (16 rows per lane with 16-byte loads measured slower)
+        const int64_t r0 = min(n_s, (int64_t)rr * c.rpr), r1 = min(n_s, r0 + c.rpr);
+        for (int64_t kb = r0 + (int64_t)wave * kCpsTileRows; kb < r1; kb += (int64_t)NWAVE * kCpsTileRows) {
+          const int64_t kp = kb + 2 * lane;
+          acc_t s0 = (acc_t)0, s1 = (acc_t)0;
+          if (kp < r1) {
+            const unsigned char *ip = c.idx + p0 * c.ld_idx + kp;
+            const int64_t sti = c.ld_idx;
+            int i = 0;
+            for (; i + 7 < np_; i += 8) {
+              uint32_t pr[8];
+#pragma unroll
+              for (int d = 0; d < 8; ++d) pr[d] = *(const uint16_t *)(ip + d * sti);
+#pragma unroll
+              for (int d = 0; d < 8; ++d) {
+                const unsigned sa = pr[d] & 0xFFu, sb = pr[d] >> 8;
+                const acc_t *ut = s_u + (i + d) * ns;
+                if (sa < (unsigned)ns) s0 += ut[sa];
+                if (sb < (unsigned)ns) s1 += ut[sb];
+              }
+              ip += 8 * sti;
+            }
+            for (; i < np_; ++i) {
+              const unsigned pr = *(const uint16_t *)ip;
+              const unsigned sa = pr & 0xFFu, sb = pr >> 8;
+              const acc_t *ut = s_u + i * ns;
+              if (sa < (unsigned)ns) s0 += ut[sa];
+              if (sb < (unsigned)ns) s1 += ut[sb];
+              ip += sti;
+            }
+            st_acc(&part_sp[(int64_t)g * n_s + kp], s0);
+            if (kp + 1 < r1) st_acc(&part_sp[(int64_t)g * n_s + kp + 1], s1);
+          }
+        }
+      }
+      // the dense block's centring share c = obar_D . v_D, reduced at the barrier
       const int64_t cd = (n_d + G - 1) / G;
       const int64_t d0 = min(n_d, (int64_t)b * cd), d1 = min(n_d, d0 + cd);
       double pc = 0.0;
       for (int64_t d = d0 + tid; d < d1; d += NT) pc += a.mean[n_sp + d] * ld_coh(&vin[n_sp + d]);
       double cD;
       if (!grid_allreduce2(pc, 0.0, c.red, nred, ctx.gs, cD, dummy)) return false;
-      acquire_agent();
 
       // ---- 1. row pass ----
       const int64_t nvec = (n_d + VEC - 1) / VEC;
@@ -110,105 +168,94 @@ struct CpsKernel {
         for (int e = 0; e < VEC; ++e) {
           const int64_t col = vi * VEC + e;
           double sv = 0.0;
-          if (vi < nvec && col < n_d) sv = (c.dscale ? (double)c.dscale[col] : 1.0) * vin[n_sp + col];
+          if (vi < nvec && col < n_d) sv = (c.dscale ? (double)c.dscale[col] : 1.0) * ld_coh(&vin[n_sp + col]);
           vs[m][e] = (acc_t)sv;
           P[m][e] = (acc_t)0;
         }
       }
-      __shared__ acc_t s_sp[kParts][kCpsTileRows];
+      __shared__ acc_t s_sp[kSlices][kCpsTileRows];
       __shared__ double s_red[2][NWAVE][RB];
-      const int wave = tid >> 6, lane = tid & 63;
       double wsum = 0.0, wabs = 0.0;
       int par = 0;
-      for (int t = b; t < c.tiles; t += G) {
-        const int64_t k0 = (int64_t)t * kCpsTileRows;
-        // 1a. correlator part of w for the tile's rows: lanes are rows, waves split the
-        //     correlators (the 64 lanes of one gather stay inside one correlator's table)
-        {
-          const int half = wave & 1, part_i = wave >> 1;
-          const int64_t k = k0 + half * 64 + lane;
-          acc_t ss = (acc_t)0;
-          if (k < n_s) {
-            // correlators part_i, part_i + kParts, ...: the state byte and the table row
-            // advance by fixed strides
-            const int64_t sti = (int64_t)kParts * c.ld_idx, stu = (int64_t)kParts * ns;
-            const unsigned char *ip = c.idx + (int64_t)part_i * c.ld_idx + k;
-            const acc_t *up = u + (int64_t)part_i * ns;
-            int64_t i = part_i;
-            for (; i + 3 * kParts < c.n_corr; i += 4 * kParts) {
-              const unsigned s0_ = ip[0], s1_ = ip[sti], s2_ = ip[2 * sti], s3_ = ip[3 * sti];
-              if (s0_ < (unsigned)ns) ss += up[s0_];
-              if (s1_ < (unsigned)ns) ss += up[stu + s1_];
-              if (s2_ < (unsigned)ns) ss += up[2 * stu + s2_];
-              if (s3_ < (unsigned)ns) ss += up[3 * stu + s3_];
-              ip += 4 * sti;
-              up += 4 * stu;
-            }
-            for (; i < c.n_corr; i += kParts) {
-              const unsigned s_ = ip[0];
-              if (s_ < (unsigned)ns) ss += up[s_];
-              ip += sti;
-              up += stu;
-            }
+      // one batch of RB dense rows into registers (rows past n_s and vectors past the row
+      // load nothing)
+      auto load_batch = [&](u32x4 (&D)[RB][NVT], int64_t k0b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int64_t k = k0b + r;
+          const unsigned char *rowp = c.dO + k * c.ldb_d;
+#pragma unroll
+          for (int m = 0; m < NVT; ++m) {
+            const int64_t vi = tid + (int64_t)m * NT;
+            if (k < n_s && vi < nvec) D[r][m] = load_stream(rowp + vi * 16);
+            else D[r][m] = u32x4{0u, 0u, 0u, 0u};
           }
-          s_sp[part_i][half * 64 + lane] = ss;
+        }
+      };
+      // row dots of a batch, their workgroup sums, w_k, then P += D w from the same registers
+      auto process = [&](u32x4 (&D)[RB][NVT], int64_t k0, int rb) __attribute__((always_inline)) {
+        acc_t pd[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          acc_t acc = (acc_t)0;
+#pragma unroll
+          for (int m = 0; m < NVT; ++m)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) acc += (acc_t)Storage<DDT>::get(D[r][m], e) * vs[m][e];
+          pd[r] = wave_sum(acc);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r) s_red[par][wave][r] = (double)pd[r];
         }
         __syncthreads();
-        // 1b. dense part in batches of RB rows, then P += D w from the same registers
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int64_t k = k0 + rb + r;
+          double wr = 0.0;
+          if (k < n_s) {
+            for (int wv = 0; wv < NWAVE; ++wv) wr += s_red[par][wv][r];
+            for (int pi = 0; pi < kSlices; ++pi) wr += (double)s_sp[pi][rb + r];
+            wr -= cD;
+          }
+          if (tid == r && k < n_s) st_coh(&c.w[k], wr);
+          if (tid == 0) {
+            wsum += wr;
+            wabs += fabs(wr);
+          }
+          const acc_t wa = (acc_t)wr;
+#pragma unroll
+          for (int m = 0; m < NVT; ++m) {
+            // decode again from the packed vector (keeping the decoded values of the
+            // whole batch live between the dot and this update costs registers)
+            asm volatile("" : "+v"(D[r][m]));
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) P[m][e] += (acc_t)Storage<DDT>::get(D[r][m], e) * wa;
+          }
+        }
+        par ^= 1;   // the next batch writes the other half of s_red; a barrier separates
+                    // this batch's reads from the writes two batches on
+      };
+      for (int t = b; t < c.tiles; t += G) {
+        const int64_t k0 = (int64_t)t * kCpsTileRows;
+        // 1a. correlator part of w for the tile's rows: the groups' partial sums, each of the
+        //     kSlices slices of threads summing a fixed subset of the groups
+        {
+          const int row = tid & (kCpsTileRows - 1), sl = tid / kCpsTileRows;
+          const int64_t k = k0 + row;
+          acc_t t = (acc_t)0;
+          if (k < n_s) {
+            const acc_t *part_sp = (const acc_t *)c.part_sp;
+            for (int g = sl; g < c.n_grp; g += kSlices) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
+          }
+          s_sp[sl][row] = t;
+        }
+        __syncthreads();
+        // 1b. dense part in batches of RB rows
         for (int rb = 0; rb < kCpsTileRows; rb += RB) {
           u32x4 D[RB][NVT];
-          acc_t pd[RB];
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            const int64_t k = k0 + rb + r;
-            const unsigned char *rowp = c.dO + k * c.ldb_d;
-#pragma unroll
-            for (int m = 0; m < NVT; ++m) {
-              const int64_t vi = tid + (int64_t)m * NT;
-              if (k < n_s && vi < nvec) D[r][m] = load_stream(rowp + vi * 16);
-              else D[r][m] = u32x4{0u, 0u, 0u, 0u};
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            acc_t acc = (acc_t)0;
-#pragma unroll
-            for (int m = 0; m < NVT; ++m)
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) acc += (acc_t)Storage<DDT>::get(D[r][m], e) * vs[m][e];
-            pd[r] = wave_sum(acc);
-          }
-          if (lane == 0) {
-#pragma unroll
-            for (int r = 0; r < RB; ++r) s_red[par][wave][r] = (double)pd[r];
-          }
-          __syncthreads();
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            const int64_t k = k0 + rb + r;
-            double wr = 0.0;
-            if (k < n_s) {
-              for (int wv = 0; wv < NWAVE; ++wv) wr += s_red[par][wv][r];
-              for (int pi = 0; pi < kParts; ++pi) wr += (double)s_sp[pi][rb + r];
-              wr -= cD;
-            }
-            if (tid == r && k < n_s) st_coh(&c.w[k], wr);
-            if (tid == 0) {
-              wsum += wr;
-              wabs += fabs(wr);
-            }
-            const acc_t wa = (acc_t)wr;
-#pragma unroll
-            for (int m = 0; m < NVT; ++m) {
-              // decode again from the packed vector (keeping the decoded values of the
-              // whole batch live between the dot and this update costs registers)
-              asm volatile("" : "+v"(D[r][m]));
-#pragma unroll
-              for (int e = 0; e < VEC; ++e) P[m][e] += (acc_t)Storage<DDT>::get(D[r][m], e) * wa;
-            }
-          }
-          par ^= 1;   // the next batch writes the other half of s_red; a barrier separates
-                      // this batch's reads from the writes two batches on
+          load_batch(D, k0 + rb);
+          process(D, k0, rb);
         }
         __syncthreads();   // s_sp is rewritten by the next tile
       }
@@ -223,7 +270,6 @@ struct CpsKernel {
       }
       double Sw, Sa;
       if (!grid_allreduce2(tid == 0 ? wsum : 0.0, tid == 0 ? wabs : 0.0, c.red, nred, ctx.gs, Sw, Sa)) return false;
-      acquire_agent();
 
       // ---- 2. correlator histograms and dense finish ----
       const double inv_n = 1.0 / (double)n_s;
@@ -242,7 +288,7 @@ struct CpsKernel {
         for (int64_t k4 = (int64_t)tid * 4; k4 < n_s; k4 += (int64_t)NT * 4) {
           long long qv[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) qv[e] = (k4 + e < n_s) ? __double2ll_rn((c.w[k4 + e] - wbar) * sigma) : 0ll;
+          for (int e = 0; e < 4; ++e) qv[e] = (k4 + e < n_s) ? __double2ll_rn((ld_coh(&c.w[k4 + e]) - wbar) * sigma) : 0ll;
           for (int e = 0; e < np; ++e) {
             const uint32_t word = *(const uint32_t *)(c.idx + (p0 + (int64_t)e * G) * c.ld_idx + k4);
 #pragma unroll
@@ -258,7 +304,7 @@ struct CpsKernel {
           for (int s_ = tid; s_ < ns; s_ += NT) {
             const int64_t j = p * ns + s_;
             const double T = (double)s_bin[e][s_] * inv_sigma;
-            st_coh(&q[j], c.val[j] * T * inv_n + a.eps * vin[j]);
+            st_coh(&q[j], c.val[j] * T * inv_n + a.eps * ld_coh(&vin[j]));
           }
         }
         __syncthreads();
@@ -273,7 +319,7 @@ struct CpsKernel {
           double acc = 0.0;
           if (d < d1) {
             const int g0 = wave * gpw, g1 = min(G, g0 + gpw);
-            for (int g = g0; g < g1; ++g) acc += (double)part[(int64_t)g * c.n_dp + d];
+            for (int g = g0; g < g1; ++g) acc += (double)ld_acc(&part[(int64_t)g * c.n_dp + d]);
           }
           s_col[wave][lane] = acc;
           __syncthreads();
@@ -282,14 +328,13 @@ struct CpsKernel {
             for (int wv = 0; wv < NWAVE; ++wv) tot += s_col[wv][lane];
             const double sc = c.dscale ? (double)c.dscale[d] : 1.0;
             const int64_t j = n_sp + d;
-            st_coh(&q[j], (sc * tot - a.mean[j] * Sw) * inv_n + a.eps * vin[j]);
+            st_coh(&q[j], (sc * tot - a.mean[j] * Sw) * inv_n + a.eps * ld_coh(&vin[j]));
           }
           __syncthreads();
         }
       }
     }
     if (!grid_sync(ctx.gs)) return false;
-    acquire_agent();
     products++;
     return true;
   }

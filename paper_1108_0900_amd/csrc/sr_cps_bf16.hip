@@ -10,7 +10,7 @@ namespace sr {
    (const void *)&k_cps_cg_step<DT_BF16, NVT, false>, STEPX(NVT), \
    (const void *)&k_cps_cg_resid<DT_BF16, NVT>},
 
-static const CpsEntry g_cps_bf16[] = {SR_REG_CPS(2) SR_REG_CPS(4) SR_REG_CPS(8)};
+static const CpsEntry g_cps_bf16[] = {SR_REG_CPS(2) SR_REG_CPS(3) SR_REG_CPS(4) SR_REG_CPS(8)};
 
 const CpsEntry *cps_table_bf16(int *count) {
   *count = (int)(sizeof(g_cps_bf16) / sizeof(g_cps_bf16[0]));

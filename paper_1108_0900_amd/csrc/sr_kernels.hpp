@@ -508,6 +508,8 @@ __global__ __launch_bounds__(NT) void k_lm(LmArgs a) {
 // ======================================================================================
 template <int DT, int NV, int R, int L, int P_, int NT>
 struct CgKernel {
+  // q[j] of this workgroup's chunk was written by this workgroup
+  __device__ __forceinline__ static double ldq(const double *p) { return *p; }
   // per-workgroup context of the product (column slice, barrier state)
   __device__ __forceinline__ static void init(WgCtx &ctx, const CgArgs &a) {
     init_ctx(ctx, a.pg, a.sb.flags, a.sb.abort, Storage<DT>::VEC);
@@ -678,7 +680,7 @@ __device__ __forceinline__ void cg_body(CgArgs &a) {
     if (!ok) break;
     if (mode == MODE_P) {
       double ppq = 0.0, pq;
-      for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * a.q[j];
+      for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * K::ldq(&a.q[j]);
       if (!(ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy))) break;
       if (!isfinite(pq)) {
         status = -4;
@@ -690,7 +692,7 @@ __device__ __forceinline__ void cg_body(CgArgs &a) {
       double prr = 0.0, prz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
         st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
-        const double rj = a.r[j] - alpha * a.q[j];
+        const double rj = a.r[j] - alpha * K::ldq(&a.q[j]);
         a.r[j] = rj;
         prr += rj * rj;
         if constexpr (kJac) prz += rj * zof(j, rj);
@@ -718,7 +720,7 @@ __device__ __forceinline__ void cg_body(CgArgs &a) {
     } else if (mode == MODE_REFRESH) {
       double prr = 0.0, prz = 0.0, rho_new, rz_new = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
-        const double rj = a.g[j] - a.q[j];
+        const double rj = a.g[j] - K::ldq(&a.q[j]);
         a.r[j] = rj;
         prr += rj * rj;
         if constexpr (kJac) prz += rj * zof(j, rj);
@@ -747,7 +749,7 @@ __device__ __forceinline__ void cg_body(CgArgs &a) {
     } else if (mode == MODE_X0) {
       double prr = 0.0, pgg = 0.0, prz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
-        const double gj = a.g[j], rj = gj - a.q[j], zj = zof(j, rj);
+        const double gj = a.g[j], rj = gj - K::ldq(&a.q[j]), zj = zof(j, rj);
         a.r[j] = rj;
         st_coh(&a.p[j], zj);
         prr += rj * rj;
@@ -771,7 +773,7 @@ __device__ __forceinline__ void cg_body(CgArgs &a) {
     } else {   // MODE_CONFIRM or MODE_FINAL: true residual g - A x
       double prr = 0.0, prz = 0.0, tr, trz = 0.0;
       for (int64_t j = j0 + tid; j < j1; j += NT) {
-        const double t = a.g[j] - a.q[j];
+        const double t = a.g[j] - K::ldq(&a.q[j]);
         if (mode == MODE_CONFIRM) a.r[j] = t;
         prr += t * t;
         if constexpr (kJac) prz += t * zof(j, t);
@@ -903,7 +905,7 @@ __device__ __forceinline__ void cg_step_body(CgArgs &a) {
     return;
   }
   double ppq = 0.0, pq;
-  for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * a.q[j];
+  for (int64_t j = j0 + tid; j < j1; j += NT) ppq += ld_coh(&a.p[j]) * K::ldq(&a.q[j]);
   ok = grid_allreduce2(ppq, 0.0, a.sb.red, nred, ctx.gs, pq, dummy);
   if (ok && !isfinite(pq)) {
     status = -4;
@@ -916,7 +918,7 @@ __device__ __forceinline__ void cg_step_body(CgArgs &a) {
     double prr = 0.0;
     for (int64_t j = j0 + tid; j < j1; j += NT) {
       st_coh(&a.x[j], ld_coh(&a.x[j]) + alpha * ld_coh(&a.p[j]));
-      const double rj = a.r[j] - alpha * a.q[j];
+      const double rj = a.r[j] - alpha * K::ldq(&a.q[j]);
       a.r[j] = rj;
       prr += rj * rj;
     }

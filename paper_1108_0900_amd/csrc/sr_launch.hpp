@@ -48,12 +48,16 @@ struct CpsOp {
   const float *dscale;        // [n_d] column scales (bf16 / f16 dense block) or nullptr
   int64_t ldb_d;              // row stride of the dense block in bytes, multiple of 16
   double *w;                  // [n_s] w_k of the current product
-  void *u;                    // [n_sp] val_j v_j of the current product (accumulation type)
+  void *part_sp;              // [n_grp][n_s] partial row sums of the correlator groups (accumulation type)
+  int32_t n_grp, cpg;         // correlator groups, correlators per group (LDS table of cpg * n_states)
+  int32_t n_items;            // (group, row range) work items of the partial sums
+  int32_t rpr;                // rows per range (a multiple of kCpsTileRows)
   void *part;                 // [G][n_dp] dense partial sums (accumulation type)
   int64_t n_dp;               // row stride of part (n_d rounded up to the vector width)
   double *red;                // [4][2][G] grid reductions of the product
 };
-constexpr int kCpsTileRows = 128;   // rows per tile of the row pass (2 waves of 64 rows)
+constexpr int kCpsTileRows = 128;   // rows per tile of the row pass (64 lanes x 2 rows)
+constexpr int kCpsTableBytes = 65536;   // LDS table of one correlator group (float64 entries: 8192)
 
 struct CgArgs {
   ProdGeom pg;
