@@ -204,6 +204,8 @@ def main():
     ap.add_argument("--no-cps", action="store_true", help="skip the index-coded CPS storage measurement")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the dense 8192 x 4000 and CPS 65536 x 24512 solves")
+    ap.add_argument("--batched-two-pass", action="store_true",
+                    help="also time the two-pass 8-column batched solve (distinct right-hand sides)")
     ap.add_argument("--batched-systems", type=int, default=64,
                     help="systems of the batched workload timed in one launch (its first n)")
     ap.add_argument("--copy-gb", type=float, default=0.0,
@@ -395,9 +397,11 @@ def measure_adjoint(args):
 
 
 def measure_batched(args):
-    """The batched form: many independent systems, 8 shifts each, one persistent launch
-    (float32 O, two-pass products shared by the 8 columns).  Also times the same work for
-    one system as 8 separate single-column solves, and the 8-column product alone."""
+    """The batched form: many independent systems (float32 O), 8 shifts each of one
+    right-hand side, solved by multi-shift CG system after system in one persistent launch
+    (one single-vector product per iteration per system, O read once per product).  Beside
+    it: the same systems one multi-shift call each, the 8-column product, and (option) the
+    two-pass 8-column batched solve meant for distinct right-hand sides."""
     import torch
     import synth
     from paper_1108_0900_amd import sr
@@ -412,65 +416,51 @@ def measure_batched(args):
         st = sr.sr_grad(M, d["E"])
         M.mean = st["mean"]
         dS = float(st["diag"].mean())
-        systems.append((M, st["g"].unsqueeze(0).repeat(8, 1).contiguous(), [dS * r for r in shifts]))
+        systems.append((M, st["g"], [dS * r for r in shifts]))
         del d
         if s_i % 8 == 7:
             log(f"[bench] batched workload: {s_i + 1} systems built")
     gb_o = [M.O.numel() * 4 / 1e9 for M, _, _ in systems]
-    # batched geometry tuned on the largest system (one geometry serves the launch)
-    from paper_1108_0900_amd import tune
-    big = max(range(len(systems)), key=lambda k: gb_o[k])
-    bt = tune.autotune(systems[big][0], kind=2, reps=3)
-    sr.sr_cg_solve_batched(systems[:2], rtol=cfg.rtol, refresh_every=20)      # warm
-    log("[bench] batched: one launch over all systems")
-    (res, ms) = timed_events(lambda: sr.sr_cg_solve_batched(systems, rtol=cfg.rtol, refresh_every=20))
+    workload = ("%d independent systems, N_p in [1000, 60000], N_s in [4096, 32768], dense float32 O N(0,1) x "
+                "lognormal(0, 0.5) column scales, 8 shifts 1e-4..1e-1 of mean(diag S) of one right-hand side (the "
+                "SR gradient) each, CG to rel. true residual %g" % (len(systems), cfg.rtol))
+    sr.sr_cg_solve_shifts_batched(systems[:2], rtol=cfg.rtol)      # warm
+    log("[bench] batched: multi-shift CG of every system in one launch")
+    sr.timing(True)
+    (res, ms) = timed_events(lambda: sr.sr_cg_solve_shifts_batched(systems, rtol=cfg.rtol))
+    launch_ms, launches = sr.timing_read("solve_launch")
+    sr.timing(False)
     X, info, status = res
-    prods = [i[0]["products"] for i in info]
-    worst = max(c["rel_res_true"] for i in info for c in i)
-    # every product streams O twice (row dots, then the update pass)
-    passes_gb = sum(2 * p * g for p, g in zip(prods, gb_o))
-    out = {"workload": "%d independent systems, N_p in [1000, 60000], N_s in [4096, 32768], dense float32 O "
-                       "N(0,1) x lognormal(0, 0.5) column scales, 8 shifts 1e-4..1e-1 of mean(diag S) each, CG "
-                       "to rel. true residual %g, refresh every 20" % (len(systems), cfg.rtol),
-           "O_GB": round(sum(gb_o), 1), "launch_ms": round(ms, 1), "status": status,
-           "column_solves": 8 * len(systems), "products": sum(prods), "worst_rel_res_true": worst,
-           "O_stream_GBps": round(passes_gb / ms * 1e3, 1),
-           "tuned_geometry": {"split_rows_tasks": list(bt["best"]),
-                              "ms": {str(list(k)): round(v, 3) for k, v in bt["ms"].items()}}}
+    # products of the launch: the shared sequence and the residual check of each shift
+    prods = [min(c["products"] for c in sys_i) for sys_i in info]
+    continued = sum(1 for sys_i in info for c in sys_i if c["products"] > min(x["products"] for x in sys_i))
+    worst = max(c["rel_res_true"] for sys_i in info for c in sys_i)
+    o_gb = sum(p * g for p, g in zip(prods, gb_o))
+    out = {"workload": workload, "O_GB": round(sum(gb_o), 1), "method": "multi-shift CG, one persistent launch",
+           "ms": round(ms, 1), "launch_ms": round(launch_ms, 1), "launches": launches, "status": status,
+           "column_solves": 8 * len(systems), "products": sum(prods), "continued_shifts": continued,
+           "worst_rel_res_true": worst, "O_read_GB": round(o_gb, 1),
+           "O_GBps": round(o_gb / launch_ms * 1e3, 1), "frac": round(o_gb / launch_ms * 1e3 / HBM_PEAK_GBPS, 4)}
     del X
-    # the same 8 columns of the first system: one batched launch vs 8 single solves (the
-    # single-column product's tiles tuned on this matrix first)
-    M, G, eps = systems[0]
-    tune.autotune(M, kind=0, reps=3)
-    (res1, ms1) = timed_events(lambda: sr.sr_cg_solve_batched([systems[0]], rtol=cfg.rtol, refresh_every=20))
-    t_single = 0.0
-    for i in range(8):
-        (r, ms_i) = timed_events(lambda: sr.sr_cg_solve(M, G[i], eps[i], rtol=cfg.rtol, refresh_every=20))
-        t_single += ms_i
-    (res_m, ms_m) = timed_events(lambda: sr.sr_cg_solve_shifts(M, G[0], eps, rtol=cfg.rtol))
-    out["system0"] = {"n_s": M.O.shape[0], "n_p": M.n_p, "batched_ms": round(ms1, 2),
-                      "eight_single_solves_ms": round(t_single, 2), "speedup": round(t_single / ms1, 2),
-                      "multi_shift_ms": round(ms_m, 2), "multi_shift_status": res_m[2]}
-    # every system by multi-shift CG (one right-hand side, 8 shifts, one Krylov sequence),
-    # one call per system, single-column products with the tuned tiles of each system's type
+    # the same systems, one multi-shift call each
     worst_m = 0.0
-    t0 = time.perf_counter()
+    statuses = []
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    statuses = []
-    for Ms, Gs, es in systems:
-        Xm, inf_m, st_m = sr.sr_cg_solve_shifts(Ms, Gs[0], es, rtol=cfg.rtol)
+    for Ms, gs, es in systems:
+        Xm, inf_m, st_m = sr.sr_cg_solve_shifts(Ms, gs, es, rtol=cfg.rtol)
         statuses.append(st_m)
         worst_m = max(worst_m, max(c["rel_res_true"] for c in inf_m))
         del Xm
     e1.record()
     e1.synchronize()
-    out["multi_shift_all_systems"] = {"ms": round(e0.elapsed_time(e1), 1), "calls": len(systems),
-                                      "all_ok": all(st_m == 0 for st_m in statuses),
-                                      "worst_rel_res_true": worst_m}
-    # the 8-column product alone on the largest system
+    out["multi_shift_one_call_per_system"] = {"ms": round(e0.elapsed_time(e1), 1), "calls": len(systems),
+                                              "all_ok": all(st_m == 0 for st_m in statuses),
+                                              "worst_rel_res_true": worst_m}
+    # the 8-column product alone on the largest system (distinct right-hand sides)
+    big = max(range(len(systems)), key=lambda k: gb_o[k])
     Mb = systems[big][0]
     V = torch.randn(8, Mb.n_p, dtype=torch.float64, device=dev)
     sr.sr_svk_product(Mb, V, [0.1] * 8)
@@ -481,6 +471,11 @@ def measure_batched(args):
                           "ms_1_column": round(ts1[2], 3),
                           "O_stream_GBps": round(2 * gb_o[big] / ms_k * 1e3, 1),
                           "columns_per_O_read_equivalent": round(8 * ts1[2] / ms_k, 2)}
+    if args.batched_two_pass:
+        # eight distinct right-hand sides per system: two-pass 8-column products in one launch
+        sys8 = [(M, g.unsqueeze(0).repeat(8, 1).contiguous(), es) for M, g, es in systems]
+        (res8, ms8) = timed_events(lambda: sr.sr_cg_solve_batched(sys8, rtol=cfg.rtol, refresh_every=20))
+        out["two_pass_8_columns"] = {"ms": round(ms8, 1), "status": res8[2]}
     log(f"[bench] batched: {out}")
     return out
 

@@ -259,6 +259,24 @@ int sr_svk_product(const sr_matrix *O, int32_t k, const double *V, const double 
  * ------------------------------------------------------------------------------------ */
 int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const double *eps, double *X,
                        const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * sr_cg_solve_shifts_batched: n_sys independent systems, each with one right-hand side g
+ * and k shifts, all by multi-shift CG in one persistent launch, system after system (one
+ * fused single-vector product per iteration per system; each system's true residuals
+ * checked with one float64 product per shift inside the launch).  Per system as
+ * sr_cg_solve_shifts (a shift that missed rtol continues with sr_cg_solve afterwards).
+ * sys: host [n_sys]; every O has the same dtype (SR_F64 or SR_F32, one plane).  info:
+ * host [n_sys * k] (system-major) or NULL.  Synchronizes `stream`.
+ * ------------------------------------------------------------------------------------ */
+typedef struct sr_shift_system {
+  sr_matrix O;               /* the system's matrix; col_mean may be NULL (computed)    */
+  const double *g;           /* device [n_p] right-hand side                            */
+  double *X;                 /* device [k][n_p] solutions, row i for eps[i]             */
+  double eps[SR_BATCH_MAX_RHS]; /* shifts, finite and >= 0, any order                   */
+} sr_shift_system;
+int sr_cg_solve_shifts_batched(int32_t n_sys, const sr_shift_system *sys, int32_t k, const sr_cg_opts *opt,
+                               sr_cg_info *info, hipStream_t stream);
 int sr_cg_solve_batched(int32_t n_sys, const sr_batch_system *sys, int32_t k, const sr_cg_opts *opt,
                         sr_cg_info *info, hipStream_t stream);
 

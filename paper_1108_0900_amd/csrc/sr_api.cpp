@@ -1543,122 +1543,51 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   return status;
 }
 
-int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const double *eps, double *X,
-                       const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream) {
-  int rc = check_matrix(O, "sr_cg_solve_shifts");
+// Checks of one multi-shift system; its shifts sorted by eps into order.
+static int check_shift_system(const char *name, const sr_matrix *O, const double *g, int32_t k, const double *eps,
+                              const double *X, std::vector<int> &order) {
+  int rc = check_matrix(O, name);
   if (rc) return rc;
   if (O->O_lo != nullptr || (O->dtype != SR_F64 && O->dtype != SR_F32))
-    return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: storage must be SR_F64 or SR_F32, one plane");
-  if (k < 1 || k > kMaxShifts) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: k must be in [1, %d]", kMaxShifts);
-  if (g == nullptr || X == nullptr || eps == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: null g, X or eps");
-  const int64_t n_p = O->n_p;
-  if (ranges_overlap(g, n_p * 8, X, (int64_t)k * n_p * 8))
-    return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: g and X overlap");
+    return fail(SR_ERR_INVALID, "%s: storage must be SR_F64 or SR_F32, one plane", name);
+  if (k < 1 || k > kMaxShifts) return fail(SR_ERR_INVALID, "%s: k must be in [1, %d]", name, kMaxShifts);
+  if (g == nullptr || X == nullptr || eps == nullptr) return fail(SR_ERR_INVALID, "%s: null g, X or eps", name);
+  if (ranges_overlap(g, O->n_p * 8, X, (int64_t)k * O->n_p * 8)) return fail(SR_ERR_INVALID, "%s: g and X overlap", name);
   for (int i = 0; i < k; ++i)
-    if (!(eps[i] >= 0.0) || !std::isfinite(eps[i]))
-      return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: eps must be finite and >= 0");
-  sr_cg_opts o{};
-  o.rtol = 1e-10;
-  if (opt) o = *opt;
-  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: bad rtol");
-  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: refresh_every must be >= 0");
-  int64_t max_iter = o.max_iter > 0 ? o.max_iter : n_p + 100;
-  if (max_iter > (1 << 30)) max_iter = 1 << 30;
-  int dev;
-  DeviceInfo di;
-  rc = device_check(&dev, &di);
-  if (rc) return rc;
+    if (!(eps[i] >= 0.0) || !std::isfinite(eps[i])) return fail(SR_ERR_INVALID, "%s: eps must be finite and >= 0", name);
   // shifts in increasing order: the smallest drives the Krylov sequence
-  std::vector<int> order(k);
+  order.resize(k);
   for (int i = 0; i < k; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return eps[a] < eps[b]; });
-  // own buffers: sorted solutions and directions, a residual temporary, the kernel's info
-  const int64_t ld = round_up(n_p, 32);
-  const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n_p, 4096)));
-  const size_t own = ((size_t)2 * k + 2) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 + 1024;
-  void *obase = nullptr;
-  rc = get_workspace(dev, stream, own, &obase, g_shift_ws);
-  if (rc) return rc;
-  Carve oc(obase);
-  double *xs = oc.take<double>((int64_t)k * ld), *ps = oc.take<double>((int64_t)k * ld);
-  double *tmp = oc.take<double>(ld), *mbuf = oc.take<double>(ld);
-  double *sinfo = oc.take<double>(2 * kMaxShifts + 4);
-  LmBufs lb{oc.take<double>((int64_t)nb * kLmMaxSub), oc.take<double>(kLmMaxSub), nb};
-  sr_matrix Om = *O;
-  if (!O->col_mean) {
-    rc = run_grad(O, nullptr, nullptr, nullptr, mbuf, nullptr, dev, di, stream);
-    if (rc) return rc;
-    Om.col_mean = mbuf;
-  }
-  Plan pl;
-  rc = make_plan(O->dtype, di.grid, O->n_s, n_p, 1, &pl);
-  if (rc) return rc;
-  const void *fn = shift_kernel(O->dtype, pl.ke->nv, pl.ke->r, pl.ke->look, pl.ke->poll, pl.ke->nt);
-  if (fn == nullptr) return fail(SR_ERR_INVALID, "sr_cg_solve_shifts: no multi-shift kernel for this configuration");
-  const int64_t ypd = (int64_t)pl.pg.RG * n_p;
-  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (n_p * 8 + 256) + 1024;
-  void *base = nullptr;
-  rc = get_workspace(dev, stream, bytes, &base);
-  if (rc) return rc;
-  Carve cv(base);
-  ProdWs w;
-  carve_prod(cv, pl, ypd, &w);
-  ShiftArgs sa{};
-  CgArgs &a = sa.c;
-  a.pg = pl.pg;
-  a.pb = w.pb;
-  a.sb = w.sb;
-  a.op = make_operand(&Om);
-  a.mean = Om.col_mean;
-  a.g = g;
-  a.x = nullptr;
-  a.r = cv.take<double>(n_p);
-  a.p = cv.take<double>(n_p);
-  a.q = cv.take<double>(n_p);
-  a.eps = eps[order[0]];
-  a.rtol = o.rtol;
-  a.max_iter = (int)max_iter;
-  sa.n_shift = k;
-  for (int s = 0; s < kMaxShifts; ++s) sa.dshift[s] = s < k ? eps[order[s]] - eps[order[0]] : 0.0;
-  sa.xs = xs;
-  sa.ps = ps;
-  sa.sinfo = sinfo;
-  // the kernel indexes its rows with stride n_p
-  rc = zero_sync(w, stream);
-  if (rc) return rc;
-  rc = launch_coop(fn, pl.pg.G, &sa, stream, pl.ke->nt, pl.ke->ring_bytes);
-  if (rc) return rc;
-  std::vector<double> hs(2 * kMaxShifts + 4);
-  uint32_t habort = 0;
-  HIP_TRY(hipMemcpyAsync(hs.data(), sinfo, hs.size() * 8, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  if (habort != 0u || hs[2 * k + 1] == 0.0)
-    return fail(SR_ERR_TIMEOUT, "sr_cg_solve_shifts: a cross-workgroup wait timed out");
+  return SR_OK;
+}
+
+static int check_shift_opts(const char *name, const sr_cg_opts *opt, sr_cg_opts &o) {
+  o = sr_cg_opts{};
+  o.rtol = 1e-10;
+  if (opt) o = *opt;
+  if (!(o.rtol > 0.0) || !std::isfinite(o.rtol)) return fail(SR_ERR_INVALID, "%s: bad rtol", name);
+  if (o.refresh_every < 0) return fail(SR_ERR_INVALID, "%s: refresh_every must be >= 0", name);
+  return SR_OK;
+}
+
+// Outcome of the shifts of one system from its kernel info (hs: 2 k per-shift words, status,
+// ok, products, then k true residuals); a shift that missed rtol continues with sr_cg_solve
+// from its x (warm start).  Returns the first non-OK status or an error code.
+static int finish_shifts(const char *name, const sr_matrix *Om, const double *g, int32_t k, const double *eps,
+                         double *X, const std::vector<int> &order, const double *hs, const sr_cg_opts &o,
+                         sr_cg_info *info, hipStream_t stream) {
+  if (hs[2 * k + 1] == 0.0) return fail(SR_ERR_TIMEOUT, "%s: a cross-workgroup wait timed out", name);
   const int kstatus = (int)hs[2 * k];
   const int launch_products = (int)hs[2 * k + 2];
-  // each shift: its solution into X, its true residual with the float64-accumulated single
-  // product, and, where the recurrence drifted past rtol, plain CG from it (warm start)
-  double gg = 0.0;
-  rc = lm_mdot(lb, g, ld, 1, g, n_p, &gg, stream);
-  if (rc) return rc;
   int status = kstatus < 0 ? kstatus : SR_OK;
   for (int s = 0; s < k && status >= 0; ++s) {
     const int i = order[s];
-    double *xi = X + (int64_t)i * n_p;
-    HIP_TRY(hipMemcpyAsync(xi, xs + (int64_t)s * n_p, (size_t)n_p * 8, hipMemcpyDeviceToDevice, stream));
-    rc = sr_sv_product(&Om, xi, tmp, eps[i], stream);
-    if (rc) return rc;
-    const double m1 = -1.0, p1 = 1.0;
-    rc = lm_lincomb(g, &p1, 1, tmp, &m1, 1, ld, 0.0, tmp, n_p, stream);
-    if (rc) return rc;
-    double rr = 0.0;
-    rc = lm_mdot(lb, tmp, ld, 1, tmp, n_p, &rr, stream);
-    if (rc) return rc;
-    double rel = gg > 0.0 ? std::sqrt(rr / gg) : 0.0;
+    double *xi = X + (int64_t)i * Om->n_p;
+    const double rel = hs[2 * k + 3 + s];
     sr_cg_info ci{};
     ci.iters = (int32_t)hs[2 * s];
-    ci.products = launch_products + 1;
+    ci.products = launch_products;
     ci.rel_res_recur = hs[2 * s + 1];
     ci.rel_res_true = rel;
     ci.status = SR_OK;
@@ -1670,7 +1599,7 @@ int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const dou
       po.res_history = nullptr;
       if (po.refresh_every == 0) po.refresh_every = 20;
       sr_cg_info pi{};
-      const int prc = sr_cg_solve(&Om, g, eps[i], xi, &po, &pi, stream);
+      const int prc = sr_cg_solve(Om, g, eps[i], xi, &po, &pi, stream);
       if (prc < 0) return prc;
       ci.iters += pi.iters;
       ci.refreshes = pi.refreshes;
@@ -1682,8 +1611,216 @@ int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const dou
     if (info) info[i] = ci;
     if (status == SR_OK && ci.status != SR_OK) status = ci.status;
   }
+  return status;
+}
+
+constexpr int kShiftInfoWords = 3 * kMaxShifts + 4;
+
+// Argument block of one multi-shift system over the shared product buffers.
+static void shift_args(ShiftArgs &sa, const Plan &pl, const ProdWs &w, const sr_matrix &Om, const double *g,
+                       int32_t k, const double *eps, double *X, const std::vector<int> &order, double *r,
+                       double *p, double *q, double *ps, double *sinfo, const sr_cg_opts &o, int64_t max_iter) {
+  sa = ShiftArgs{};
+  CgArgs &a = sa.c;
+  a.pg = pl.pg;
+  a.pb = w.pb;
+  a.sb = w.sb;
+  a.op = make_operand(&Om);
+  a.mean = Om.col_mean;
+  a.g = g;
+  a.x = nullptr;
+  a.r = r;
+  a.p = p;
+  a.q = q;
+  a.eps = eps[order[0]];
+  a.rtol = o.rtol;
+  a.max_iter = (int)max_iter;
+  sa.n_shift = k;
+  sa.check = 1;
+  for (int s = 0; s < kMaxShifts; ++s) {
+    sa.dshift[s] = s < k ? eps[order[s]] - eps[order[0]] : 0.0;
+    sa.xrow[s] = s < k ? X + (int64_t)order[s] * Om.n_p : nullptr;
+  }
+  sa.ps = ps;
+  sa.sinfo = sinfo;
+}
+
+int sr_cg_solve_shifts(const sr_matrix *O, const double *g, int32_t k, const double *eps, double *X,
+                       const sr_cg_opts *opt, sr_cg_info *info, hipStream_t stream) {
+  const char *name = "sr_cg_solve_shifts";
+  std::vector<int> order;
+  int rc = check_shift_system(name, O, g, k, eps, X, order);
+  if (rc) return rc;
+  sr_cg_opts o;
+  rc = check_shift_opts(name, opt, o);
+  if (rc) return rc;
+  const int64_t n_p = O->n_p;
+  int64_t max_iter = o.max_iter > 0 ? o.max_iter : n_p + 100;
+  if (max_iter > (1 << 30)) max_iter = 1 << 30;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  // own buffers: the directions of the shifts, the means, the kernel's info
+  const int64_t ld = round_up(n_p, 32);
+  const size_t own = ((size_t)k + 1) * ld * 8 + (size_t)kShiftInfoWords * 8 + 1024;
+  void *obase = nullptr;
+  rc = get_workspace(dev, stream, own, &obase, g_shift_ws);
+  if (rc) return rc;
+  Carve oc(obase);
+  double *ps = oc.take<double>((int64_t)k * ld), *mbuf = oc.take<double>(ld);
+  double *sinfo = oc.take<double>(kShiftInfoWords);
+  sr_matrix Om = *O;
+  if (!O->col_mean) {
+    rc = run_grad(O, nullptr, nullptr, nullptr, mbuf, nullptr, dev, di, stream);
+    if (rc) return rc;
+    Om.col_mean = mbuf;
+  }
+  Plan pl;
+  rc = make_plan(O->dtype, di.grid, O->n_s, n_p, 1, &pl);
+  if (rc) return rc;
+  const void *fn = shift_kernel(O->dtype, pl.ke->nv, pl.ke->r, pl.ke->look, pl.ke->poll, pl.ke->nt);
+  if (fn == nullptr) return fail(SR_ERR_INVALID, "%s: no multi-shift kernel for this configuration", name);
+  const int64_t ypd = (int64_t)pl.pg.RG * n_p;
+  const size_t bytes = prod_ws_bytes(pl, ypd) + (size_t)3 * (n_p * 8 + 256) + 1024;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, bytes, &base);
+  if (rc) return rc;
+  Carve cv(base);
+  ProdWs w;
+  carve_prod(cv, pl, ypd, &w);
+  double *r = cv.take<double>(n_p), *p = cv.take<double>(n_p), *q = cv.take<double>(n_p);
+  ShiftArgs sa;
+  shift_args(sa, pl, w, Om, g, k, eps, X, order, r, p, q, ps, sinfo, o, max_iter);
+  rc = zero_sync(w, stream);
+  if (rc) return rc;
+  rc = launch_coop(fn, pl.pg.G, &sa, stream, pl.ke->nt, pl.ke->ring_bytes);
+  if (rc) return rc;
+  std::vector<double> hs(kShiftInfoWords);
+  uint32_t habort = 0;
+  HIP_TRY(hipMemcpyAsync(hs.data(), sinfo, hs.size() * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&habort, w.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  if (status < 0) return fail(status, "sr_cg_solve_shifts: %s", sr_status_string(status));
+  if (habort != 0u) return fail(SR_ERR_TIMEOUT, "%s: a cross-workgroup wait timed out", name);
+  const int status = finish_shifts(name, &Om, g, k, eps, X, order, hs.data(), o, info, stream);
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (status < 0) return fail(status, "%s: %s", name, sr_status_string(status));
+  return status;
+}
+
+int sr_cg_solve_shifts_batched(int32_t n_sys, const sr_shift_system *sys, int32_t k, const sr_cg_opts *opt,
+                               sr_cg_info *info, hipStream_t stream) {
+  const char *name = "sr_cg_solve_shifts_batched";
+  if (n_sys < 1 || sys == nullptr) return fail(SR_ERR_INVALID, "%s: need n_sys >= 1 systems", name);
+  std::vector<std::vector<int>> orders(n_sys);
+  int64_t max_np = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    int rc = check_shift_system(name, &sys[i].O, sys[i].g, k, sys[i].eps, sys[i].X, orders[i]);
+    if (rc) return rc;
+    if (sys[i].O.dtype != sys[0].O.dtype) return fail(SR_ERR_INVALID, "%s: every system needs the same dtype", name);
+    max_np = std::max<int64_t>(max_np, sys[i].O.n_p);
+  }
+  sr_cg_opts o;
+  int rc = check_shift_opts(name, opt, o);
+  if (rc) return rc;
+  int dev;
+  DeviceInfo di;
+  rc = device_check(&dev, &di);
+  if (rc) return rc;
+  const int dt = sys[0].O.dtype;
+  // plans: one tile configuration for all (the kernel is instantiated per configuration),
+  // each system its own geometry
+  std::vector<Plan> pls(n_sys);
+  size_t prod_bytes = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    rc = make_plan(dt, di.grid, sys[i].O.n_s, sys[i].O.n_p, 1, &pls[i]);
+    if (rc) return rc;
+    if (pls[i].ke != pls[0].ke) return fail(SR_ERR_HIP, "%s: inconsistent tile choice", name);
+    prod_bytes = std::max(prod_bytes, prod_ws_bytes(pls[i], (int64_t)pls[i].pg.RG * sys[i].O.n_p));
+  }
+  const Plan &p0 = pls[0];
+  const void *fn = shift_kernel(dt, p0.ke->nv, p0.ke->r, p0.ke->look, p0.ke->poll, p0.ke->nt, true);
+  if (fn == nullptr) return fail(SR_ERR_INVALID, "%s: no multi-shift kernel for this configuration", name);
+  // own buffers: means of the systems without them, infos, the argument table
+  int64_t mean_total = 0;
+  for (int i = 0; i < n_sys; ++i)
+    if (!sys[i].O.col_mean) mean_total += round_up(sys[i].O.n_p, 32);
+  const size_t own = (size_t)mean_total * 8 + (size_t)n_sys * kShiftInfoWords * 8 +
+                     (size_t)n_sys * (sizeof(ShiftArgs) + 256) + 4096;
+  void *obase = nullptr;
+  rc = get_workspace(dev, stream, own, &obase, g_shift_ws);
+  if (rc) return rc;
+  Carve oc(obase);
+  double *means = oc.take<double>(std::max<int64_t>(mean_total, 1));
+  double *sinfo = oc.take<double>((int64_t)n_sys * kShiftInfoWords);
+  ShiftArgs *table = oc.take<ShiftArgs>(n_sys);
+  std::vector<sr_matrix> Oms(n_sys);
+  int64_t moff = 0;
+  for (int i = 0; i < n_sys; ++i) {
+    Oms[i] = sys[i].O;
+    if (!sys[i].O.col_mean) {
+      rc = run_grad(&sys[i].O, nullptr, nullptr, nullptr, means + moff, nullptr, dev, di, stream);
+      if (rc) return rc;
+      Oms[i].col_mean = means + moff;
+      moff += round_up(sys[i].O.n_p, 32);
+    }
+  }
+  // product buffers shared by the systems (one after another): the zeroed region (flags,
+  // abort, exchange ring), reductions and sink sit at the same place for every geometry;
+  // the vectors r, p, q and the shifts' directions are each system's own (chunked per
+  // system, so a shared vector would be written by different XCDs with plain stores)
+  int64_t vec_total = 0;
+  for (int i = 0; i < n_sys; ++i) vec_total += (int64_t)(3 + k) * round_up(sys[i].O.n_p, 32) + 64;
+  void *base = nullptr;
+  rc = get_workspace(dev, stream, round_up((int64_t)prod_bytes, 256) + (size_t)vec_total * 8 + 4096, &base);
+  if (rc) return rc;
+  std::vector<ShiftArgs> hsa(n_sys);
+  ProdWs w0;
+  Carve vc((char *)base + round_up((int64_t)prod_bytes, 256));
+  for (int i = 0; i < n_sys; ++i) {
+    Carve cv(base);
+    ProdWs w;
+    carve_prod(cv, pls[i], (int64_t)pls[i].pg.RG * sys[i].O.n_p, &w);
+    if (i == 0) w0 = w;
+    if (w.sb.flags != w0.sb.flags || w.pb.xchg != w0.pb.xchg || w.sb.red != w0.sb.red)
+      return fail(SR_ERR_HIP, "%s: inconsistent buffer layout", name);
+    const int64_t ld = round_up(sys[i].O.n_p, 32);
+    double *r = vc.take<double>(ld), *p = vc.take<double>(ld), *q = vc.take<double>(ld);
+    double *ps = vc.take<double>((int64_t)k * ld);
+    int64_t max_iter = o.max_iter > 0 ? o.max_iter : sys[i].O.n_p + 100;
+    if (max_iter > (1 << 30)) max_iter = 1 << 30;
+    shift_args(hsa[i], pls[i], w, Oms[i], sys[i].g, k, sys[i].eps, sys[i].X, orders[i], r, p, q, ps,
+               sinfo + (int64_t)i * kShiftInfoWords, o, max_iter);
+  }
+  rc = zero_sync(w0, stream);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(table, hsa.data(), (size_t)n_sys * sizeof(ShiftArgs), hipMemcpyHostToDevice, stream));
+  {
+    const ShiftArgs *tp = table;
+    int32_t n = n_sys;
+    void *args[] = {(void *)&tp, (void *)&n};
+    if (p0.ke->ring_bytes > 0)
+      HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, p0.ke->ring_bytes));
+    TimedLaunch tl(stream);
+    HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(p0.pg.G), dim3(p0.ke->nt), args, (unsigned)p0.ke->ring_bytes, stream));
+    tl.stop();
+    tl.record(kTimeSolveLaunch);
+  }
+  std::vector<double> hs((size_t)n_sys * kShiftInfoWords);
+  uint32_t habort = 0;
+  HIP_TRY(hipMemcpyAsync(hs.data(), sinfo, hs.size() * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&habort, w0.sb.abort, sizeof(habort), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (habort != 0u) return fail(SR_ERR_TIMEOUT, "%s: a cross-workgroup wait timed out", name);
+  int status = SR_OK;
+  for (int i = 0; i < n_sys; ++i) {
+    const int st = finish_shifts(name, &Oms[i], sys[i].g, k, sys[i].eps, sys[i].X, orders[i],
+                                 hs.data() + (size_t)i * kShiftInfoWords, o, info ? info + (int64_t)i * k : nullptr,
+                                 stream);
+    if (st < 0) return fail(st, "%s: system %d: %s", name, i, sr_status_string(st));
+    if (status == SR_OK && st != SR_OK) status = st;
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
   return status;
 }
 

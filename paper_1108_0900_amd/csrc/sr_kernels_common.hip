@@ -208,12 +208,12 @@ const KernelEntry *kernel_table_f16(int *count);
 const BatchEntry *batched_entry_f64();
 const BatchEntry *batched_entry_f32();
 
-const void *shift_kernel_f64(int nv, int r, int look, int poll, int nt);
-const void *shift_kernel_f32(int nv, int r, int look, int poll, int nt);
-const void *shift_kernel(int dt, int nv, int r, int look, int poll, int nt) {
+const void *shift_kernel_f64(int nv, int r, int look, int poll, int nt, bool batched);
+const void *shift_kernel_f32(int nv, int r, int look, int poll, int nt, bool batched);
+const void *shift_kernel(int dt, int nv, int r, int look, int poll, int nt, bool batched) {
   switch (dt) {
-    case DT_F64: return shift_kernel_f64(nv, r, look, poll, nt);
-    case DT_F32: return shift_kernel_f32(nv, r, look, poll, nt);
+    case DT_F64: return shift_kernel_f64(nv, r, look, poll, nt, batched);
+    case DT_F32: return shift_kernel_f32(nv, r, look, poll, nt, batched);
     default: return nullptr;
   }
 }

@@ -24,11 +24,13 @@ static const BatchEntry g_batch_f64 = {(const void *)&k_cg_batched<DT_F64, kBatc
 const BatchEntry *batched_entry_f64() { return &g_batch_f64; }
 
 // Multi-shift CG, one kernel per SR tile configuration.
-#define SR_REG_SHIFT(NV, R, L, P, NT) {NV, R, L, P, NT, (const void *)&k_cg_shifts<DT_F64, NV, R, L, P, NT>},
+#define SR_REG_SHIFT(NV, R, L, P, NT)                                                                \
+  {NV, R, L, P, NT, (const void *)&k_cg_shifts<DT_F64, NV, R, L, P, NT>,                              \
+   (const void *)&k_cg_shifts_batched<DT_F64, NV, R, L, P, NT>},
 static const ShiftEntry g_shift_f64[] = {SR_SR_CONFIGS_F64(SR_REG_SHIFT)};
-const void *shift_kernel_f64(int nv, int r, int look, int poll, int nt) {
+const void *shift_kernel_f64(int nv, int r, int look, int poll, int nt, bool batched) {
   for (const ShiftEntry &e : g_shift_f64)
-    if (e.nv == nv && e.r == r && e.look == look && e.poll == poll && e.nt == nt) return e.fn;
+    if (e.nv == nv && e.r == r && e.look == look && e.poll == poll && e.nt == nt) return batched ? e.batched : e.fn;
   return nullptr;
 }
 

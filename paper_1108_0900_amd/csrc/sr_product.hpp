@@ -646,9 +646,12 @@ struct Product {
     else
       ok = stream_rows<kPlain>(pg, pb, ctx, ops, n_my, rounds, E, v0, s_part, s_tot);
     // the next product starts on a fresh block of kRing steps, so no word this product
-    // left in the ring carries one of its tags (products may differ in words per slot)
-    const uint32_t used = ctx.xstep + (uint32_t)n_my;
-    ctx.xstep = (used + kRing - 1) / kRing * kRing;
+    // left in the ring carries one of its tags (products may differ in words per slot);
+    // every workgroup advances by the same amount (the most tiles of any row group), so
+    // the step count is the same in all of them, also when the next product has another
+    // geometry (several systems in one launch regroup the workgroups)
+    const uint32_t most = (uint32_t)((n_tiles + pg.RG - 1) / pg.RG);
+    ctx.xstep += (most + kRing - 1) / kRing * kRing;
     if (threadIdx.x == 0) s_ok = ok ? 1 : 0;
     __syncthreads();
     return s_ok != 0;

@@ -73,6 +73,10 @@ class SrBatchSystem(ctypes.Structure):
     _fields_ = [("O", SrMatrix), ("g", _c_p), ("x", _c_p), ("eps", _c_d * BATCH_MAX_RHS)]
 
 
+class SrShiftSystem(ctypes.Structure):
+    _fields_ = [("O", SrMatrix), ("g", _c_p), ("X", _c_p), ("eps", _c_d * BATCH_MAX_RHS)]
+
+
 PROTOTYPES = {
     "sr_grad": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_p, _c_p, _c_p, _c_p]),
     "sr_sv_product": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_p, _c_d, _c_p]),
@@ -83,6 +87,8 @@ PROTOTYPES = {
     "sr_cg_solve_shifts": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, _c_i32, _c_p, _c_p,
                                           ctypes.POINTER(SrCgOpts), _c_p, _c_p]),
     "sr_set_batch_config": (ctypes.c_int, [_c_i32, _c_i32]),
+    "sr_cg_solve_shifts_batched": (ctypes.c_int, [_c_i32, ctypes.POINTER(SrShiftSystem), _c_i32,
+                                                  ctypes.POINTER(SrCgOpts), ctypes.POINTER(SrCgInfo), _c_p]),
     "lm_davidson": (ctypes.c_int, [ctypes.POINTER(SrMatrix), _c_p, ctypes.POINTER(SrMatrix),
                                    ctypes.POINTER(LmDavidsonOpts), _c_p, ctypes.POINTER(LmDavidsonInfo), _c_p]),
     "sr_quantize": (ctypes.c_int, [_c_i64, _c_i64, _c_p, _c_i64, _c_i32, _c_p, _c_p, _c_i64, _c_i32, _c_p, _c_p]),
@@ -690,6 +696,44 @@ def sr_cg_solve_shifts(M: Matrix, g: torch.Tensor, eps, rtol: float = 1e-10, max
     out = [{"status": c.status, "iters": c.iters, "refreshes": c.refreshes, "products": c.products,
             "rel_res_recur": c.rel_res_recur, "rel_res_true": c.rel_res_true} for c in infos[:k]]
     return X, out, st
+
+
+def sr_cg_solve_shifts_batched(systems, rtol: float = 1e-10, max_iter: int = 0, refresh_every: int = 0,
+                               raise_on=(SR_ERR_INVALID, SR_ERR_NOMEM, SR_ERR_HIP, SR_ERR_NODEVICE, SR_ERR_TIMEOUT),
+                               stream=None):
+    """Multi-shift CG of many systems in one launch (sr_cg_solve_shifts_batched).
+    `systems` is a list of (Matrix, g, eps) with g a float64 (n_p,) right-hand side and eps a
+    list of k shifts (the same k for all).  Returns (list of X tensors (k, n_p), list of
+    per-system lists of per-shift info dicts, status)."""
+    k = None
+    descs = (SrShiftSystem * len(systems))()
+    keep, xs = [], []
+    for i, (M, g, eps) in enumerate(systems):
+        g = _vec(g, M.n_p, "g")
+        if k is None:
+            k = len(eps)
+        elif len(eps) != k:
+            raise ValueError("every system needs the same number of shifts")
+        X = torch.empty(k, M.n_p, dtype=torch.float64, device=g.device)
+        descs[i].O = M.c()
+        descs[i].g = g.data_ptr()
+        descs[i].X = X.data_ptr()
+        for j in range(BATCH_MAX_RHS):
+            descs[i].eps[j] = float(eps[j]) if j < k else 0.0
+        keep.append(g)
+        xs.append(X)
+    opts = SrCgOpts()
+    opts.rtol = float(rtol)
+    opts.max_iter = int(max_iter)
+    opts.refresh_every = int(refresh_every)
+    infos = (SrCgInfo * (len(systems) * k))()
+    st = lib().sr_cg_solve_shifts_batched(len(systems), descs, k, ctypes.byref(opts), infos, _stream(stream))
+    if st in raise_on:
+        raise SrError(st, "sr_cg_solve_shifts_batched")
+    out = [[{"status": infos[i * k + j].status, "iters": infos[i * k + j].iters,
+             "products": infos[i * k + j].products, "rel_res_recur": infos[i * k + j].rel_res_recur,
+             "rel_res_true": infos[i * k + j].rel_res_true} for j in range(k)] for i in range(len(systems))]
+    return xs, out, st
 
 
 def lm_davidson(M: Matrix, E: torch.Tensor, Dm: Matrix, tol: float = 1e-8, max_iter: int = 1000, max_sub: int = 40,

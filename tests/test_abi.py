@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
 
 _STRUCTS = {"sr_matrix": "SrMatrix", "sr_cg_opts": "SrCgOpts", "sr_cg_info": "SrCgInfo",
             "lm_davidson_opts": "LmDavidsonOpts", "lm_davidson_info": "LmDavidsonInfo",
-            "sr_batch_system": "SrBatchSystem", "sr_cps_matrix": "SrCpsMatrix", "sr_stream_acc": "SrStreamAcc"}
+            "sr_batch_system": "SrBatchSystem", "sr_cps_matrix": "SrCpsMatrix", "sr_stream_acc": "SrStreamAcc",
+            "sr_shift_system": "SrShiftSystem"}
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -373,3 +374,22 @@ def test_stream_invalid_batches_rejected():
     assert L.sr_stream_finish(ctypes.byref(a), z, -1.0, y, None, None, None, None) == sr.SR_ERR_INVALID
     assert L.sr_stream_finish(ctypes.byref(_acc(se=None)), z, 0.1, y, y, None, None, None) == sr.SR_ERR_INVALID
     assert L.sr_stream_finish(ctypes.byref(a), z, 0.1, z, None, None, None, None) == sr.SR_ERR_INVALID   # Y overlaps Z
+
+
+def test_shifts_batched_rejects_bad_arguments():
+    L = sr.lib()
+    d = (sr.SrShiftSystem * 2)()
+    for i in range(2):
+        d[i].O = _mat()
+        d[i].g, d[i].X = 1 << 20, 1 << 22
+        d[i].eps[0] = 0.1
+    assert L.sr_cg_solve_shifts_batched(0, d, 1, None, None, None) == sr.SR_ERR_INVALID
+    assert L.sr_cg_solve_shifts_batched(2, d, 9, None, None, None) == sr.SR_ERR_INVALID
+    d[1].O = _mat(dtype=sr.SR_F32, ld=4)
+    assert L.sr_cg_solve_shifts_batched(2, d, 1, None, None, None) == sr.SR_ERR_INVALID      # mixed dtypes
+    d[1].O = _mat()
+    d[1].eps[0] = -1.0
+    assert L.sr_cg_solve_shifts_batched(2, d, 1, None, None, None) == sr.SR_ERR_INVALID
+    d[1].eps[0] = 0.1
+    d[1].X = 1 << 20                                                                      # X overlaps g
+    assert L.sr_cg_solve_shifts_batched(2, d, 1, None, None, None) == sr.SR_ERR_INVALID

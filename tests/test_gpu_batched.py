@@ -216,3 +216,96 @@ def test_batched_full_size_workload():
         for i in (0, 7):
             r = orc.sv_product_swapped(Ocpu, to_np(X[s][i]), eps[i]) - g
             assert np.linalg.norm(r) <= 2 * cfg.rtol * np.linalg.norm(g), (s, i)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_shifts_batched_match_dense_solves(dtype):
+    """Multi-shift CG of several systems of different shapes in one launch (shifts given in
+    scrambled order) against the oracle's dense solve of each stored system and shift."""
+    shapes = [(300, 130), (1200, 4099), (77, 513), (2500, 2000)]
+    rel = list(10.0 ** np.linspace(-4, -1, 6))
+    systems, refs = [], []
+    for s, (n_s, n_p) in enumerate(shapes):
+        O, E = rand_dense(n_s, n_p, seed=90 + s)
+        Os = stored_dense(O, dtype)
+        M = device_matrix(O, dtype)
+        st = sr.sr_grad(M, to_dev(E))
+        if s % 2 == 0:
+            M.mean = st["mean"]                 # the others have their means computed by the call
+        dS = float(st["diag"].mean())
+        eps = [dS * rel[i] for i in (2, 0, 5, 1, 4, 3)]
+        systems.append((M, st["g"], eps))
+        g_ref = orc.energy_gradient(Os, E)
+        dS_ref = orc.diag_overlap(Os).mean()
+        refs.append([orc.solve_dense(Os, g_ref, e / dS * dS_ref) for e in eps])
+    X, info, status = sr.sr_cg_solve_shifts_batched(systems, rtol=1e-11)
+    assert status == 0, info
+    for s in range(len(shapes)):
+        for i in range(6):
+            assert info[s][i]["status"] == 0 and info[s][i]["rel_res_true"] <= 1e-11, (s, i, info[s][i])
+            err = rel_err(to_np(X[s][i]), refs[s][i])
+            assert err <= 1e-8, (s, i, err)
+
+
+def test_shifts_batched_equal_one_system_calls():
+    """The same systems one call each (sr_cg_solve_shifts) and all in one launch: the same
+    arithmetic in the same order, so the same solutions."""
+    systems = []
+    for s, (n_s, n_p) in enumerate([(500, 700), (900, 300)]):
+        O, E = rand_dense(n_s, n_p, seed=120 + s)
+        M = device_matrix(O, torch.float32)
+        st = sr.sr_grad(M, to_dev(E))
+        M.mean = st["mean"]
+        dS = float(st["diag"].mean())
+        systems.append((M, st["g"], [dS * 1e-3, dS * 1e-2, dS * 1e-1]))
+    Xb, _, sb = sr.sr_cg_solve_shifts_batched(systems, rtol=1e-10)
+    assert sb == 0
+    for s, (M, g, eps) in enumerate(systems):
+        X1, _, s1 = sr.sr_cg_solve_shifts(M, g, eps, rtol=1e-10)
+        assert s1 == 0
+        assert rel_err(to_np(Xb[s]), to_np(X1)) <= 1e-14
+
+
+def test_shifts_batched_full_size_workload():
+    """The 64-system workload (N_p in [1000, 60000], N_s in [4096, 32768], float32 O, 8
+    shifts 1e-4..1e-1 of mean(diag S), g the SR gradient) by multi-shift CG in one launch:
+    every shift converged, its residual re-checked with the one-column product, the two
+    smallest systems with the CPU oracle."""
+    cfg = synth.CONFIGS["batched_64sys"]
+    shapes = synth.batched_shapes(seed=cfg.seed)
+    shifts = synth.relative_shifts(8)
+    systems = []
+    for s, (n_s, n_p) in enumerate(shapes):
+        d = synth.dense_inputs(n_s, n_p, cfg.seed * 1000 + s, device=DEV, dtype=torch.float32)
+        M = sr.as_matrix(d["O"])
+        st = sr.sr_grad(M, d["E"])
+        M.mean = st["mean"]
+        dS = float(st["diag"].mean())
+        systems.append((M, st["g"], [dS * r for r in shifts]))
+    sr.timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    X, info, status = sr.sr_cg_solve_shifts_batched(systems, rtol=cfg.rtol, refresh_every=20)
+    e1.record()
+    e1.synchronize()
+    ms, launches = sr.timing_read("solve_launch")
+    sr.timing(False)
+    # a shift that missed rtol in the launch continued with its own solve: more products
+    cont = sum(1 for s in info for c in s if c["products"] > min(x["products"] for x in s))
+    print(f"[shifts-batched-full] {e0.elapsed_time(e1):.1f} ms, launch {ms:.1f} ms, launches {launches}, "
+          f"continued shifts {cont}", flush=True)
+    assert status == sr.SR_OK
+    assert launches == 1
+    for s, (M, g, eps) in enumerate(systems):
+        for i in range(8):
+            assert info[s][i]["status"] == 0 and info[s][i]["rel_res_true"] <= cfg.rtol, (s, i, info[s][i])
+            r = sr.sr_sv_product(M, X[s][i], eps[i]) - g
+            assert float(r.norm() / g.norm()) <= 2 * cfg.rtol, (s, i)
+    order = sorted(range(len(shapes)), key=lambda s: shapes[s][0] * shapes[s][1])[:2]
+    for s in order:
+        M, g, eps = systems[s]
+        Ocpu = M.O.double().cpu().numpy()
+        gh = g.cpu().numpy()
+        for i in (0, 7):
+            r = orc.sv_product_swapped(Ocpu, to_np(X[s][i]), eps[i]) - gh
+            assert np.linalg.norm(r) <= 2 * cfg.rtol * np.linalg.norm(gh), (s, i)
