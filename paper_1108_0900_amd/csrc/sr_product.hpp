@@ -193,6 +193,8 @@ struct Product {
   u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
   bool need_mask;
+  int mcode;                        // straddling vectors, one byte each: index * 8 + valid elements
+                                    // (NV * 8: none); at most two (the ends of the two planes)
   // --- exchange state (wave 0) ---
   static constexpr int kCh = 2;     // column groups per lane read ahead (C <= 128 asynchronously)
   u64 pw[kNPoll][kCh][PW];          // words of column groups lane, lane + 64 for the pending polls
@@ -236,6 +238,7 @@ struct Product {
     n_q = compact ? (int)ops[0].n_q : 0x7fffffff;
     n_qe = compact ? (int)(ops[0].n_q + ops[0].n_lo) : 0x7fffffff;
     bool straddles = false;
+    mcode = NV * 8 * 0x101;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int64_t col = colv(i);
@@ -244,7 +247,11 @@ struct Product {
       if (in) {
         nvec = i + 1;
         nvalid = valid_of(col);
-        if (nvalid < VEC) straddles = true;
+        if (nvalid < VEC) {
+          // the first straddling vector goes to byte 0, a second one (past n_q) to byte 1
+          mcode = straddles ? (mcode & 0xFF) | ((i * 8 + nvalid) << 8) : (mcode & 0xFF00) | (i * 8 + nvalid);
+          straddles = true;
+        }
       }
       const bool lo = col >= n_q;     // a vector of the compact remainder plane
 #pragma unroll
@@ -305,15 +312,24 @@ struct Product {
   template <int B>
   __device__ __forceinline__ void dots(acc_t (&part)[NDOT][R]) {
     if (need_mask) {
-      // zero the bytes past n_p (row padding may hold anything) before any use; the mask
-      // of each vector is computed, not looked up, so the tile stays in registers
+      // zero the bytes past the end of a plane's columns (row padding may hold anything)
+      // before any use.  A thread has at most two straddling vectors, one at the end of
+      // each plane (vectors outside the slice read valid columns with zero coefficients);
+      // their masks are rebuilt per tile from one packed code, kept opaque so that the
+      // compiler does not hoist NV masks out of the streaming loop
+      int code = mcode;
+      asm volatile("" : "+v"(code));
+      const u32x4 ma = elem_mask(code & 7), mb = elem_mask((code >> 8) & 7);
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        const u32x4 m = elem_mask(valid_of(colv(i)));
+        const bool ha = ((code >> 3) & 31) == i, hb = ((code >> 11) & 31) == i;
+        u32x4 mi;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) mi[w] = ha ? ma[w] : (hb ? mb[w] : 0xFFFFFFFFu);
 #pragma unroll
         for (int d = 0; d < NOPS; ++d)
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[B][d][r][i] &= m;
+          for (int r = 0; r < R; ++r) buf[B][d][r][i] &= mi;
       }
     }
 #pragma unroll
