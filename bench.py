@@ -59,7 +59,7 @@ def grad_bytes(n_s, n_p, dt, scaled):
 
 
 KERNEL_SOURCES = ("sr_device.hpp", "sr_product.hpp", "sr_kernels.hpp", "sr_launch.hpp", "sr_kernels_bf16.hip")
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_bf16_compact_cps500k_traffic.md")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_step_bf16_compact_cps500k_traffic.md")
 TRAFFIC_KERNEL = "void sr::k_cg_step<2, 2, 2, 1, 1, 512>(sr::CgArgs)"
 
 
@@ -717,8 +717,12 @@ def measure_single(args):
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
+        # the products' own load type: non-temporal 16-byte streaming reads of every byte
+        for _ in range(3):
+            sr.stream_read(src, 1, 4)
         torch.cuda.synchronize()
-        log(f"[bench] copy calibration: 3 copies of {nbytes} bytes (read {nbytes}, write {nbytes} each)")
+        log(f"[bench] counter calibration: 3 copies of {nbytes} bytes (read {nbytes}, write {nbytes} each), "
+            f"3 streaming reads of the same {nbytes} bytes")
         del src, dst
     if args.quick:
         sv = None
