@@ -14,7 +14,8 @@ from dataclasses import dataclass
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsr.so")
+# SR_LIBRARY names another build of the same library (the host-sanitizer build, say)
+LIB_PATH = os.environ.get("SR_LIBRARY") or os.path.join(_HERE, "libsr.so")
 
 # enum sr_status
 SR_OK, SR_NOT_CONVERGED, SR_BREAKDOWN = 0, 1, 2
