@@ -547,6 +547,58 @@ def measure_cps(cfg, x64, rtol, refresh, dev):
     return out
 
 
+def measure_stream(cfg, dev, n_batches=8):
+    """Products during sampling over the index-coded CPS workload: its N_s samples arrive as
+    n_batches batches of rows (the seeded per-batch generator stands in for a sampler), each
+    added to uncentred accumulators for m vectors, centred once at the end (sr_stream_*).
+    Time of one sample set, and GB/s against what the method must move: one read of every
+    batch (state bytes, pairing block, energies) plus the accumulators' read and write and
+    the m vectors per batch."""
+    import torch
+    import synth
+    from paper_1108_0900_amd import sr
+    rows = cfg.n_s // n_batches
+    layout = synth.cps_stream_layout(cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.seed, device=dev)
+    n_p = cfg.n_corr * cfg.n_states + cfg.n_dense
+    out = {"workload": "CPS %d correlators x %d states + %d pairing columns, %d samples fed as %d batches of "
+                       "%d rows (one state byte per correlator, pairing block dense), centred once at the end"
+                       % (cfg.n_corr, cfg.n_states, cfg.n_dense, cfg.n_s, n_batches, rows), "forms": {}}
+    for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16)):
+        batches = []
+        for b in range(n_batches):
+            bt = synth.cps_stream_batch(layout, b, rows, device=dev, dense_dtype=torch.float64)
+            if dt == torch.bfloat16:
+                q, s = sr.sr_quantize(bt["dense"], out_dtype=torch.bfloat16)
+                Md = sr.as_matrix(q, scale=s)
+            else:
+                Md = sr.as_matrix(bt["dense"].to(dt))
+            batches.append((sr.cps_matrix(bt["idx"], layout["val"], cfg.n_states, Md), bt["E"]))
+            del bt
+        sample_bytes = cfg.n_s * (cfg.n_corr + cfg.n_dense * elem_bytes(dt) + 8)
+        out["forms"][name] = {}
+        for m in (1, 8):
+            Z = torch.randn(m, n_p, dtype=torch.float64, device=dev)
+
+            def run():
+                acc = sr.sr_stream_begin(n_p, m, device=dev)
+                for M, E in batches:
+                    sr.sr_stream_accumulate(acc, M, E, Z)
+                return sr.sr_stream_finish(acc, Z, 0.0)
+            run()
+            ts = sorted(timed_events(run)[1] for _ in range(5))
+            ms = ts[len(ts) // 2]
+            # per batch: the accumulators A (m x n_p), s1, se read and written, Z read
+            acc_bytes = n_batches * n_p * 8 * (2 * m + 4 + m)
+            alg = sample_bytes + acc_bytes
+            out["forms"][name]["m%d" % m] = {"ms": round(ms, 3), "us_per_sample": round(1e3 * ms / cfg.n_s, 4),
+                                             "sample_bytes": int(sample_bytes), "accumulator_bytes": int(acc_bytes),
+                                             "GBps": round(alg / ms / 1e6, 1),
+                                             "frac": round(alg / ms / 1e6 / HBM_PEAK_GBPS, 4)}
+        log(f"[bench] products during sampling, {name} pairing block: {out['forms'][name]}")
+        del batches
+    return out
+
+
 def measure_single(args):
     import torch
     from paper_1108_0900_amd import sr
@@ -756,6 +808,7 @@ def measure_single(args):
     cps = None
     if scaled and not args.quick and not args.no_cps:
         cps = measure_cps(cfg, x64, rtol, refresh, dev)
+        cps["during_sampling"] = measure_stream(cfg, dev)
 
     # HBM traffic of the CG launch from the committed counter record (same kernel build and
     # same algorithmic bytes per launch), else null
