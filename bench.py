@@ -714,6 +714,10 @@ def measure_single(args):
     launch_cls = "search_step" if (form in ("compact", "one_plane", "plain") and not args.search_f64) \
         else "solve_launch"
     t_ms, t_n = sr.timing_read(launch_cls)
+    if launch_cls == "search_step" and t_n == 0 and sr.timing_read("solve_launch")[1] > 0:
+        # small float64 / float32 products run the one-launch solve
+        launch_cls = "solve_launch"
+        t_ms, t_n = sr.timing_read(launch_cls)
     sr.timing(False)
     ms_per_step = wall_ms / args.steps
     products = sum(i["products"] for i in infos) / len(infos)

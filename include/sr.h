@@ -157,7 +157,9 @@ int sr_sv_product_noalloc(const sr_matrix *O, const double *v, double *y, double
 
 /* ------------------------------------------------------------------------------------
  * sr_cg_solve: conjugate gradient on (S + eps I) x = g with S applied only through the
- * product above (Sec. II.A), all iterations in one persistent launch.
+ * product above (Sec. II.A).  One stored plane without a preconditioner (bf16/f16
+ * storage, or float64/float32 products of at least 2^31 bytes) runs split: one launch per
+ * search iteration plus residual-phase launches; every other solve is one persistent launch.
  * g: [n_p] float64 right-hand side.  x: [n_p] float64 solution (starting guess on
  * entry if opt->use_x0).  opt: host, may be NULL (rtol 1e-10, defaults otherwise).
  * info: host, may be NULL.  eps >= 0; with eps = 0 and a singular S the result is the
@@ -517,7 +519,8 @@ int64_t sr_workspace_held(hipStream_t stream);
  * stops it.  sr_timing_read gives the total milliseconds and the number of launches of a
  * class: 0 the search steps of a split solve (one stored plane, no preconditioner, the
  * storage type's own accumulation) that ran a product, 1 its residual phases that ran one,
- * 2 single-launch solves (two planes, Jacobi, float64 search products).  Split solves time their launches only where they check the state after every
+ * 2 single-launch solves (two planes, Jacobi, float64 search products, float64/float32
+ * products below 2^31 bytes).  Split solves time their launches only where they check the state after every
  * launch (products of at least 2^30 streamed bytes).  Timing adds a synchronization per
  * timed launch. */
 int sr_timing(int32_t enable);

@@ -673,6 +673,11 @@ int lm_lincomb(const double *X, const double *ca, int mx, const double *Z, const
 // Products of at least this many streamed bytes run their split solve with a state check
 // after every launch.
 constexpr int64_t kStepSyncBytes = (int64_t)1 << 30;
+// Float64 / float32 storage: products below this many bytes run the persistent solve (one
+// launch; per-launch costs outweigh the split form's register savings there: 136 against
+// 160 us per product at 8192 x 4000 float64, 269 against 285 at 16384 x 16384 float32,
+// equal from about 6 GB on).
+constexpr int64_t kSplitMinBytes = (int64_t)2 << 30;
 
 // Kernel timing (sr_timing): HIP events around the launches of the CG solves, on their
 // stream; accumulated per class while enabled.
@@ -2185,15 +2190,17 @@ int sr_cg_solve(const sr_matrix *O, const double *g, double eps, double *x, cons
   const bool exact_search = o.search_f64 != 0 && scaled(O->dtype) && !two_planes(O);
   // one stored plane without a preconditioner: one kernel per search iteration (only the
   // product is live during its streaming loop, which keeps the registers free of spills)
-  // and a resumable residual phase (for scaled storage the float64 residual products)
-  const bool split = !two_planes(O) && !exact_search && !o.precond;
+  // and a resumable residual phase (for scaled storage the float64 residual products);
+  // small float64 / float32 products keep the one-launch solve
+  const int64_t product_bytes = O->n_s * streamed_cols(O) * elem_bytes(O->dtype);
+  const bool split = !two_planes(O) && !exact_search && !o.precond &&
+                     (scaled(O->dtype) || product_bytes >= kSplitMinBytes);
   double hinfo[kInfoWords] = {};
   uint32_t habort = 0;
   if (split) {
     if (pl.ke->cgs == nullptr || pl.ke->cgr == nullptr || pl.ke->cgi == nullptr)
       return fail(SR_ERR_INVALID, "sr_cg_solve: no split CG kernels for this configuration");
     const SplitKernels k{pl.ke->cgi, pl.ke->cgs, pl.ke->cgr, pl.pg.G, pl.ke->nt, pl.ke->ring_bytes};
-    const int64_t product_bytes = O->n_s * streamed_cols(O) * elem_bytes(O->dtype);
     rc = run_split_cg(k, a, w.sb.abort, product_bytes, o.refresh_every, max_iter, stream, hinfo, &habort);
     if (rc) return rc;
   } else {
