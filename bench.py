@@ -60,7 +60,10 @@ def grad_bytes(n_s, n_p, dt, scaled):
 
 KERNEL_SOURCES = ("sr_device.hpp", "sr_product.hpp", "sr_kernels.hpp", "sr_launch.hpp", "sr_kernels_bf16.hip")
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_cg_step_bf16_compact_cps500k_traffic.md")
-TRAFFIC_KERNEL = "void sr::k_cg_step<2, 2, 2, 1, 1, 512>(sr::CgArgs)"
+def step_kernel_name(tile):
+    """Name of the bf16 split-CG search kernel of tile (nv, rows, lookahead, poll, threads)."""
+    nv, r, look, pd, nt = tile
+    return f"void sr::k_cg_step<2, {nv}, {r}, {look}, {pd}, {nt}>(sr::CgArgs)"
 
 
 def kernel_source_hash():
@@ -817,7 +820,8 @@ def measure_single(args):
     # HBM traffic of the CG launch from the committed counter record (same kernel build and
     # same algorithmic bytes per launch), else null
     traffic = None
-    rec_t = traffic_record(TRAFFIC_KERNEL) if (scaled and form == "compact") else None
+    used_tile = tuple(tiles[dtype_name]["best"]) if dtype_name in tiles else tuple(sr.tile_configs(dt_t, 0)[0])
+    rec_t = traffic_record(step_kernel_name(used_tile)) if (scaled and form == "compact") else None
     if rec_t is not None and abs(rec_t["algorithmic_bytes"] - alg_pb) <= 1e-6 * alg_pb:
         traffic = round(rec_t["traffic_bytes"] / 1e9, 1)
 

@@ -121,7 +121,7 @@ struct QuantArgs {
 #define SR_SR_CONFIGS_F64(X) X(4, 1, 1, 1, 512) X(4, 1, 2, 1, 512) X(2, 1, 2, 1, 512) X(2, 2, 1, 1, 512) \
   X(4, 1, 1, 2, 512) X(4, 1, 3, 2, 512)
 #define SR_SR_CONFIGS_F32(X) X(4, 1, 1, 1, 512) X(2, 1, 2, 1, 512) X(2, 2, 1, 1, 512)
-#define SR_SR_CONFIGS_BF16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(2, 1, 3, 1, 512) X(4, 1, 1, 1, 512) \
+#define SR_SR_CONFIGS_BF16(X) X(2, 2, 1, 0, 512) X(2, 1, 2, 1, 512) X(2, 1, 3, 1, 512) X(4, 1, 1, 1, 512) \
   X(2, 2, 2, 1, 512) X(1, 4, 1, 1, 512)
 #define SR_SR_CONFIGS_F16(X) X(2, 2, 1, 1, 512) X(2, 1, 2, 1, 512) X(4, 1, 1, 1, 512)
 #define SR_LM_CONFIGS(X) X(2, 1, 2, 1, 512) X(4, 1, 2, 1, 256)

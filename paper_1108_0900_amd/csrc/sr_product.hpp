@@ -147,7 +147,7 @@ template <int DT> struct AccOf<DT, true> { typedef double type; };
 //   R     rows per tile
 //   LOOK  tiles whose loads are in flight ahead of the one being consumed
 //   PD    poll depth: the other column groups' partial dots of tile t are loaded at the
-//         start of step t + 2 and used at the end of step t + 2 + PD, so PD steps of
+//         start of step t + kAdv and used at the end of step t + kAdv + PD, so PD steps of
 //         streaming cover the latency of those coherent loads
 //   NT    threads per workgroup
 //   PLANES 2: the operand is s_j (q + lo) read from two code planes (NDOT = 1 only)
@@ -160,14 +160,16 @@ struct Product {
   static constexpr bool kCompact = PLANES == 1 && NDOT == 1 && Storage<DT>::BYTES == 2;
   static constexpr int NW = NT / 64;          // waves per workgroup
   static constexpr int kLook = LOOK;
-  static constexpr int kAdv = 2;              // the poll of tile t starts at step t + kAdv
+  // the poll of tile t starts at step t + kAdv (PD = 0: one step later, finished in the
+  // same step; the tile is accumulated at the same step either way)
+  static constexpr int kAdv = PD == 0 ? 3 : 2;
   static constexpr int kPD = PD;
   static constexpr int kNPoll = PD + 1;       // poll buffers in flight
   static constexpr int kLag = kAdv + PD + 1;  // tile t is accumulated at step t + kLag
   // register ring: a tile lives from step t-LOOK to t+kLag; its size is a multiple of the
   // number of poll buffers so that both rings are indexed at compile time
   static constexpr int kNBuf = ((LOOK + kLag + 1) + kNPoll - 1) / kNPoll * kNPoll;
-  static_assert(PD >= 1, "a poll is used at the earliest one step after it was issued");
+  static_assert(PD >= 0, "poll depth");
   // A workgroup at step t has seen every member of its row group publish step
   // t - 1 - kAdv - PD, so each member is at step >= t - kAdv - PD and may still be
   // (re)reading step t - 2 (kAdv + PD).  Those slots must stay distinct from the one
