@@ -345,7 +345,7 @@ int run_grad(const sr_matrix *m, const double *E, double *g, double *Emean, doub
   const int vec = vec_of(dt);
   Plan pl;
   pl.words = 0;
-  int rc = geometry(di.grid, m->n_s, m->n_p, grad_nv(dt) * vec * kNT, vec, grad_rows(dt), 0, &pl.pg);
+  int rc = geometry(di.grid, m->n_s, m->n_p, grad_nv(dt) * vec * grad_threads(dt), vec, grad_rows(dt), 0, &pl.pg);
   if (rc) return rc;
   const int64_t ypd = (int64_t)pl.pg.RG * 3 * m->n_p;
   // a compact remainder plane: the pass over the first plane gives every column, then the
@@ -378,7 +378,7 @@ int run_grad(const sr_matrix *m, const double *E, double *g, double *Emean, doub
   }
   rc = zero_sync(w, s);
   if (rc) return rc;
-  rc = launch_coop(grad_kernel(dt), pl.pg.G, &a, s);
+  rc = launch_coop(grad_kernel(dt), pl.pg.G, &a, s, grad_threads(dt));
   if (rc || !cmp) return rc;
   GradLoArgs b{};
   b.Q = (const unsigned char *)m->O;
@@ -802,7 +802,7 @@ int64_t sr_workspace_bytes(const sr_matrix *O, int32_t call) {
   // the prepare pass (also run by the products and the solve when col_mean is NULL)
   Plan gp;
   gp.words = 0;
-  rc = geometry(di.grid, O->n_s, O->n_p, grad_nv(dt) * vec * kNT, vec, grad_rows(dt), 0, &gp.pg);
+  rc = geometry(di.grid, O->n_s, O->n_p, grad_nv(dt) * vec * grad_threads(dt), vec, grad_rows(dt), 0, &gp.pg);
   if (rc) return rc;
   size_t grad = prod_ws_bytes(gp, (int64_t)gp.pg.RG * 3 * O->n_p);
   if (compact(O)) grad += (size_t)(4 * cdiv(O->n_s, kGradLoRows) * O->n_lo + 64) * 8 + 512;

@@ -54,8 +54,11 @@ __device__ __forceinline__ double load_decoded(const unsigned char *rowp, const 
 // Prepare / gradient pass (one read of O):  column means, diag S, g, E mean.
 // Shifted sums about K_j = O_0j avoid the cancellation of sum(O^2) - N mean^2.
 // ======================================================================================
-template <int DT, int NV, int RT>
-__global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
+// NT threads per workgroup: 2-byte storage runs 512 (8 waves per CU keep enough tiles in
+// flight for its short rows), 4- and 8-byte storage 256 (their accumulators need the
+// registers of one wave per SIMD).
+template <int DT, int NV, int RT, int NT>
+__global__ __launch_bounds__(NT) void k_grad(GradArgs a) {
   typedef Storage<DT> St;
   constexpr int VEC = St::VEC;
   WgCtx ctx;
@@ -70,12 +73,12 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
     const int64_t ch = (a.pg.n_s + G - 1) / G;
     const int64_t k0 = min(a.pg.n_s, (int64_t)blockIdx.x * ch), k1 = min(a.pg.n_s, k0 + ch);
     double s = 0.0;
-    for (int64_t k = k0 + tid; k < k1; k += kNT) s += a.E[k];
+    for (int64_t k = k0 + tid; k < k1; k += NT) s += a.E[k];
     double dummy;
     if (!grid_allreduce2(s, 0.0, a.sb.red, nred, ctx.gs, Emean, dummy)) return;
     Emean *= inv_n;
     double se = 0.0;
-    for (int64_t k = k0 + tid; k < k1; k += kNT) se += a.E[k] - Emean;
+    for (int64_t k = k0 + tid; k < k1; k += NT) se += a.E[k] - Emean;
     if (!grid_allreduce2(se, 0.0, a.sb.red, nred, ctx.gs, sum_e, dummy)) return;
   }
 
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
   const unsigned char *O = a.op.O;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    const int64_t col = ctx.c0 + ((int64_t)i * kNT + tid) * VEC;
+    const int64_t col = ctx.c0 + ((int64_t)i * NT + tid) * VEC;
     colv[i] = (col < ctx.c1) ? col : -1;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -104,35 +107,62 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
     }
   const int64_t n_tiles = (a.pg.n_s + RT - 1) / RT;
   const unsigned char *LO = a.op.lo;
-  for (int64_t t = ctx.rg; t < n_tiles; t += a.pg.RG) {
-    u32x4 buf[RT][NV], bufl[RT][NV];
+  // Two register buffers: the loads of the next tile are in flight while this one is
+  // summed.  Loads are unconditional (rows past n_s read the last row, vectors past the
+  // slice read column 0; neither is summed into a stored column), so the compiler's wait
+  // for one tile leaves the other in flight.
+  // the tile's energies come with it: lane l loads row l % RT with a vector load (kept in
+  // order with the tile loads), broadcast per row when summed
+  static_assert(RT <= 64, "one lane per tile row");
+  const int lane = tid & 63;
+  auto load_tile = [&](int64_t t, u32x4 (&b)[RT][NV], u32x4 (&bl)[RT][NV], double &ev) {
+    {
+      int64_t row = t * RT + lane % RT;
+      row = row < a.pg.n_s ? row : a.pg.n_s - 1;
+      ev = a.E != nullptr ? a.E[row] : 0.0;
+    }
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
-      const int64_t row = t * RT + r;
+      int64_t row = t * RT + r;
+      row = row < a.pg.n_s ? row : a.pg.n_s - 1;
 #pragma unroll
       for (int i = 0; i < NV; ++i) {
-        if (row < a.pg.n_s && colv[i] >= 0) buf[r][i] = load_stream(O + row * a.op.ldb + colv[i] * St::BYTES);
-        else buf[r][i] = u32x4{0u, 0u, 0u, 0u};
-        if (LO != nullptr && row < a.pg.n_s && colv[i] >= 0)
-          bufl[r][i] = load_stream(LO + row * a.op.ldb + colv[i] * St::BYTES);
-        else bufl[r][i] = u32x4{0u, 0u, 0u, 0u};
+        const int64_t c = colv[i] >= 0 ? colv[i] : 0;
+        b[r][i] = load_stream(O + row * a.op.ldb + c * St::BYTES);
+        bl[r][i] = LO != nullptr ? load_stream(LO + row * a.op.ldb + c * St::BYTES) : u32x4{0u, 0u, 0u, 0u};
       }
     }
+  };
+  auto sum_tile = [&](int64_t t, const u32x4 (&b)[RT][NV], const u32x4 (&bl)[RT][NV], double ev) {
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
       const int64_t row = t * RT + r;
       if (row >= a.pg.n_s) continue;
-      const double e_k = (a.E != nullptr) ? a.E[row] - Emean : 0.0;
+      const double e_k = (a.E != nullptr) ? __shfl(ev, r, 64) - Emean : 0.0;
 #pragma unroll
       for (int i = 0; i < NV; ++i)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
-          const double q = (double)St::get(buf[r][i], e) + (double)St::get(bufl[r][i], e);
+          const double q = (double)St::get(b[r][i], e) + (double)St::get(bl[r][i], e);
           const double x = q * sc[i][e] - K[i][e];
           sA[i][e] += x;
           sB[i][e] = fma(x, x, sB[i][e]);
           sC[i][e] = fma(e_k, x, sC[i][e]);
         }
+    }
+  };
+  {
+    u32x4 bA[RT][NV], lA[RT][NV], bB[RT][NV], lB[RT][NV];
+    double eA = 0.0, eB = 0.0;
+    const int64_t RG = a.pg.RG;
+    int64_t t = ctx.rg;
+    if (t < n_tiles) load_tile(t, bA, lA, eA);
+    for (; t < n_tiles; t += 2 * RG) {
+      load_tile(t + RG, bB, lB, eB);
+      sum_tile(t, bA, lA, eA);
+      if (t + RG >= n_tiles) break;
+      load_tile(t + 2 * RG, bA, lA, eA);
+      sum_tile(t + RG, bB, lB, eB);
     }
   }
   // partials: ypart holds [RG][3][n_p]
@@ -154,7 +184,7 @@ __global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
   // --- finish owned column chunk ---
   const int64_t ch = (a.pg.n_p + G - 1) / G;
   const int64_t j0 = min(a.pg.n_p, (int64_t)blockIdx.x * ch), j1 = min(a.pg.n_p, j0 + ch);
-  for (int64_t j = j0 + tid; j < j1; j += kNT) {
+  for (int64_t j = j0 + tid; j < j1; j += NT) {
     double A = 0.0, B = 0.0, Cg = 0.0;
     for (int rg = 0; rg < a.pg.RG; ++rg) {
       const double *base = a.pb.ypart + (int64_t)rg * 3 * a.pg.n_p;

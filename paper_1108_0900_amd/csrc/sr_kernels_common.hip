@@ -249,13 +249,14 @@ const KernelEntry *kernel_table(int dt, int *count) {
 
 const void *grad_kernel(int dt) {
   switch (dt) {
-    case DT_F64: return (const void *)&k_grad<DT_F64, 4, 4>;
-    case DT_F32: return (const void *)&k_grad<DT_F32, 2, 8>;
-    case DT_BF16: return (const void *)&k_grad<DT_BF16, 1, 8>;
-    default: return (const void *)&k_grad<DT_F16, 1, 8>;
+    case DT_F64: return (const void *)&k_grad<DT_F64, 4, 4, 256>;
+    case DT_F32: return (const void *)&k_grad<DT_F32, 2, 8, 256>;
+    case DT_BF16: return (const void *)&k_grad<DT_BF16, 1, 8, 512>;
+    default: return (const void *)&k_grad<DT_F16, 1, 8, 512>;
   }
 }
 int grad_nv(int dt) { return dt == DT_F64 ? 4 : dt == DT_F32 ? 2 : 1; }
+int grad_threads(int dt) { return dt == DT_F64 || dt == DT_F32 ? 256 : 512; }
 int grad_rows(int dt) { return dt == DT_F64 ? 4 : 8; }
 
 const void *absmax_kernel(int in_dt) {

@@ -258,6 +258,7 @@ struct StreamArgs {
 const void *stream_kernel(int which);   // 0 stats, 1 addy, 2 dots, 3 finish
 const void *grad_kernel(int dt);
 int grad_nv(int dt);
+int grad_threads(int dt);
 int grad_rows(int dt);
 const void *absmax_kernel(int in_dt);
 const void *quantize_kernel(int in_dt, int out_dt);
