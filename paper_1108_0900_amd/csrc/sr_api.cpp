@@ -631,9 +631,9 @@ struct LmBufs {
   double *part, *dots;             // [nb][kLmMaxSub], [kLmMaxSub]
   int nb;
 };
-// out_host[i] = X[i] . w for i < m (device reduction in fixed order, then a copy).
-int lm_mdot(const LmBufs &b, const double *X, int64_t ld, int m, const double *w, int64_t n, double *out_host,
-            hipStream_t s) {
+// out_dev[i] = X[i] . w for i < m in device memory (fixed-order reduction), queued only.
+int lm_mdot_dev(const LmBufs &b, const double *X, int64_t ld, int m, const double *w, int64_t n, double *out_dev,
+                hipStream_t s) {
   MdotArgs a{};
   a.X = X;
   a.ld = ld;
@@ -642,12 +642,38 @@ int lm_mdot(const LmBufs &b, const double *X, int64_t ld, int m, const double *w
   a.nb = b.nb;
   a.w = w;
   a.part = b.part;
-  a.out = b.dots;
+  a.out = out_dev;
   void *args[] = {&a};
   HIP_TRY(hipLaunchKernel(mdot_part_kernel(), dim3(b.nb, m), dim3(lm_threads()), args, 0, s));
   HIP_TRY(hipLaunchKernel(mdot_final_kernel(), dim3(1), dim3(64), args, 0, s));
+  return SR_OK;
+}
+// out_host[i] = X[i] . w for i < m (device reduction in fixed order, then a copy).
+int lm_mdot(const LmBufs &b, const double *X, int64_t ld, int m, const double *w, int64_t n, double *out_host,
+            hipStream_t s) {
+  int rc = lm_mdot_dev(b, X, ld, m, w, n, b.dots, s);
+  if (rc) return rc;
   HIP_TRY(hipMemcpyAsync(out_host, b.dots, (size_t)m * 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return SR_OK;
+}
+// out = beta out + sign * sum_i cdev[i] X[i] with cdev in device memory, or (X = nullptr,
+// bdev given) out = out / sqrt(*bdev).
+int lm_lincomb_dev(const double *X, const double *cdev, double sign, int mx, const double *bdev, int64_t ld,
+                   double beta, double *out, int64_t n, hipStream_t s) {
+  LincombArgs a{};
+  a.X = X;
+  a.mx = mx;
+  a.ld = ld;
+  a.n = n;
+  a.beta = beta;
+  a.out = out;
+  a.cdev = cdev;
+  a.cdev_sign = sign;
+  a.bdev = bdev;
+  void *args[] = {&a};
+  const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, cdiv(n, lm_threads())));
+  HIP_TRY(hipLaunchKernel(lincomb_kernel(), dim3(blocks), dim3(lm_threads()), args, 0, s));
   return SR_OK;
 }
 // out = beta out + sum_i ca[i] X[i] + sum_i cz[i] Z[i].
@@ -1365,7 +1391,7 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   const int nb = std::min(di.grid, (int)std::max<int64_t>(1, cdiv(n, 4096)));
   // V, HV, SV [ms][ld]; r, c-temporaries [3][ld]; column means [ld]; reduction buffers
   const int sp_h = (int)std::min<int64_t>(64, std::max<int64_t>(1, cdiv(O->n_s, 128)));   // diag H splits
-  const size_t bytes = ((size_t)3 * ms + 6) * ld * 8 + ((size_t)nb + 1) * kLmMaxSub * 8 +
+  const size_t bytes = ((size_t)3 * ms + 6) * ld * 8 + ((size_t)nb + 4) * kLmMaxSub * 8 +
                        (o.precond == 2 ? (size_t)sp_h * n_p * 8 : 0) + 4096;
   void *base = nullptr;
   rc = get_workspace(dev, stream, bytes, &base, g_lm_ws);
@@ -1376,7 +1402,11 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
   double *R = cv.take<double>(ld), *T1 = cv.take<double>(ld), *T2 = cv.take<double>(ld);
   double *mean = cv.take<double>(ld), *dvec = cv.take<double>(ld), *dhvec = cv.take<double>(ld);
   double *hpart = o.precond == 2 ? cv.take<double>((int64_t)sp_h * n_p) : nullptr;
-  LmBufs lb{cv.take<double>((int64_t)nb * kLmMaxSub), cv.take<double>(kLmMaxSub), nb};
+  LmBufs lb{cv.take<double>((int64_t)nb * kLmMaxSub), cv.take<double>(4 * kLmMaxSub), nb};
+  // device results read back together once per new direction: its column and row of the
+  // projected matrix and its S-norm before scaling (the Gram-Schmidt coefficients use
+  // lb.dots[0, kLmMaxSub) and never leave the device)
+  double *d_col = lb.dots + kLmMaxSub, *d_row = lb.dots + 2 * kLmMaxSub, *d_nrm = lb.dots + 3 * kLmMaxSub;
   // the column means once, so that the products do not recompute them; for the diagonal
   // correction dvec = (1, diag S) and, for the exact one, dhvec = (<E>, diag H)
   sr_matrix Om = *O, Dm = *D;
@@ -1427,7 +1457,7 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
     HIP_TRY(hipMemcpyAsync(st, t, 8, hipMemcpyDeviceToDevice, stream));
     return sr_sv_product(&Om, t + 1, st + 1, 0.0, stream);
   };
-  std::vector<double> A((size_t)ms * ms, 0.0), h(ms), y, tmp(ms);
+  std::vector<double> A((size_t)ms * ms, 0.0), y, tmp(ms);
   int m = 0, iters = 0, restarts = 0, status = SR_NOT_CONVERGED;
   double theta = 0.0, rnorm = INFINITY, ref_norm = 1.0;
   // start vector: Psi, c = e_0 (S-norm 1)
@@ -1446,37 +1476,40 @@ int lm_davidson(const sr_matrix *O, const double *E, const sr_matrix *D, const l
       if (rc) return rc;
       iters++;
       // S-orthogonalize against the basis (classical Gram-Schmidt, twice); S t follows
-      // by linearity
+      // by linearity.  The coefficients and the norm stay on the device: the host waits
+      // once per direction, for the new row and column of the projected matrix.
       for (int pass = 0; pass < 2 && m > 0; ++pass) {
-        rc = lm_mdot(lb, SV, ld, m, t, n, h.data(), stream);
+        rc = lm_mdot_dev(lb, SV, ld, m, t, n, lb.dots, stream);
         if (rc) return rc;
-        for (int i = 0; i < m; ++i) tmp[i] = -h[i];
-        rc = lm_lincomb(V, tmp.data(), m, nullptr, nullptr, 0, ld, 1.0, t, n, stream);
+        rc = lm_lincomb_dev(V, lb.dots, -1.0, m, nullptr, ld, 1.0, t, n, stream);
         if (rc) return rc;
-        rc = lm_lincomb(SV, tmp.data(), m, nullptr, nullptr, 0, ld, 1.0, st, n, stream);
+        rc = lm_lincomb_dev(SV, lb.dots, -1.0, m, nullptr, ld, 1.0, st, n, stream);
         if (rc) return rc;
       }
-      double nrm2 = 0.0;
-      rc = lm_mdot(lb, t, ld, 1, st, n, &nrm2, stream);
+      rc = lm_mdot_dev(lb, t, ld, 1, st, n, d_nrm, stream);
       if (rc) return rc;
-      if (m == 0) ref_norm = nrm2;
-      if (!(nrm2 > 1e-28 * ref_norm)) break;  // no new direction (converged or S singular there)
-      const double inv = 1.0 / std::sqrt(nrm2);
-      rc = lm_lincomb(nullptr, nullptr, 0, nullptr, nullptr, 0, ld, inv, t, n, stream);
+      rc = lm_lincomb_dev(nullptr, nullptr, 0.0, 0, d_nrm, ld, 0.0, t, n, stream);
       if (rc) return rc;
-      rc = lm_lincomb(nullptr, nullptr, 0, nullptr, nullptr, 0, ld, inv, st, n, stream);
+      rc = lm_lincomb_dev(nullptr, nullptr, 0.0, 0, d_nrm, ld, 0.0, st, n, stream);
       if (rc) return rc;
       rc = lm_hv_product(&Om, E, &Dm, t, ht, stream);
       if (rc) return rc;
       // the new row and column of the projected matrix A = V^T H V
-      std::vector<double> col(m + 1), rw(m + 1);
-      rc = lm_mdot(lb, V, ld, m + 1, ht, n, col.data(), stream);
+      rc = lm_mdot_dev(lb, V, ld, m + 1, ht, n, d_col, stream);
       if (rc) return rc;
-      rc = lm_mdot(lb, HV, ld, m + 1, t, n, rw.data(), stream);
+      rc = lm_mdot_dev(lb, HV, ld, m + 1, t, n, d_row, stream);
       if (rc) return rc;
+      std::vector<double> back((size_t)3 * kLmMaxSub);
+      HIP_TRY(hipMemcpyAsync(back.data(), d_col, back.size() * 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      const double nrm2 = back[2 * kLmMaxSub];
+      if (m == 0) ref_norm = nrm2;
+      // no new direction (converged or S singular there): its scaled copy and products are
+      // dropped with it
+      if (!(nrm2 > 1e-28 * ref_norm)) break;
       for (int i = 0; i <= m; ++i) {
-        A[(size_t)i * ms + m] = col[i];
-        A[(size_t)m * ms + i] = rw[i];
+        A[(size_t)i * ms + m] = back[i];
+        A[(size_t)m * ms + i] = back[kLmMaxSub + i];
       }
       m++;
     }

@@ -38,11 +38,14 @@ __global__ __launch_bounds__(64) void k_mdot_final(MdotArgs a) {
 }
 
 // out[j] = beta out[j] + sum_i ca[i] X[i][j] + sum_i cz[i] Z[i][j]  (out may be a row of X
-// or Z only when that row's coefficient is zero).
+// or Z only when that row's coefficient is zero).  X's coefficients and beta may instead
+// come from device memory (cdev, bdev), so that no host round trip sits between the dot
+// products that produce them and this combination.
 __global__ __launch_bounds__(kLmNT) void k_lincomb(LincombArgs a) {
+  const double beta = a.bdev != nullptr ? 1.0 / sqrt(*a.bdev) : a.beta;
   for (int64_t j = (int64_t)blockIdx.x * kLmNT + threadIdx.x; j < a.n; j += (int64_t)gridDim.x * kLmNT) {
-    double t = a.beta == 0.0 ? 0.0 : a.beta * a.out[j];
-    for (int i = 0; i < a.mx; ++i) t += a.ca[i] * a.X[i * a.ld + j];
+    double t = beta == 0.0 ? 0.0 : beta * a.out[j];
+    for (int i = 0; i < a.mx; ++i) t += (a.cdev != nullptr ? a.cdev_sign * a.cdev[i] : a.ca[i]) * a.X[i * a.ld + j];
     for (int i = 0; i < a.mz; ++i) t += a.cz[i] * a.Z[i * a.ld + j];
     a.out[j] = t;
   }

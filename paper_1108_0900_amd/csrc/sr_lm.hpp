@@ -21,6 +21,9 @@ struct LincombArgs {
   double beta;
   double *out;                       // [n]
   double ca[kLmMaxSub], cz[kLmMaxSub];
+  const double *cdev;                // or nullptr: X's coefficients are cdev_sign * cdev[i]
+  double cdev_sign;                  // (device memory, written by an earlier kernel)
+  const double *bdev;                // or nullptr: beta = 1 / sqrt(*bdev) (device memory)
 };
 struct DivArgs {
   const double *in;                  // [n]
