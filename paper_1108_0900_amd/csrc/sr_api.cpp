@@ -216,17 +216,29 @@ struct TileForce {
 };
 TileForce g_force[4][2] = {};
 
-// Column groups and slices over the n_v streamed columns (n_v < 0: n_v = n_p).
+// Column groups and slices over the n_v streamed columns (n_v < 0: n_v = n_p).  C is a
+// power of two (RG = G / C), or with any_c the least number of column groups that holds
+// the columns when that gives more row groups: each XCD holds (G/8)/C row groups and
+// leaves its other workgroups idle (a product's time goes with its rows per row group,
+// not with how full a workgroup's slice is).
 int geometry(int G, int64_t n_s, int64_t n_p, int cols_per_wg, int vec, int r, int force_c, ProdGeom *pg,
-             int64_t n_v = -1) {
+             int64_t n_v = -1, bool any_c = false) {
   if (n_v < 0) n_v = n_p;
-  int64_t C = pow2_ceil(cdiv(n_v, cols_per_wg));
-  if (force_c > 0 && force_c >= C) C = force_c;
+  const int64_t cmin = cdiv(n_v, cols_per_wg);
+  int64_t C = pow2_ceil(cmin);
+  int RG = C <= G ? G / (int)C : 0;
+  if (force_c > 0 && force_c >= C) {
+    C = force_c;
+    RG = G / (int)C;
+  } else if (any_c && G % 8 == 0 && cmin < C && cmin <= G / 8 && 8 * ((G / 8) / cmin) > RG) {
+    C = cmin;
+    RG = 8 * ((G / 8) / (int)cmin);
+  }
   if (C > G) return fail(SR_ERR_INVALID, "%lld columns exceed the column capacity of the built tiles (%lld)",
                          (long long)n_v, (long long)G * cols_per_wg);
   pg->G = G;
   pg->C = (int)C;
-  pg->RG = G / (int)C;
+  pg->RG = RG;
   pg->n_s = n_s;
   pg->n_p = n_p;
   pg->n_v = n_v;
@@ -256,7 +268,7 @@ int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan, int
   }
   plan->ke = pick;
   const int cols = pick->nv * vec * pick->nt;
-  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg, n_v);
+  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg, n_v, true);
   if (rc) return rc;
   plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
   return SR_OK;
@@ -276,7 +288,9 @@ void carve_prod(Carve &cv, const Plan &pl, int64_t ypart_doubles, ProdWs *w) {
   const size_t start = (size_t)round_up((int64_t)cv.off, 256);
   w->sb.flags = cv.take<uint32_t>(pg.G);
   w->sb.abort = cv.take<uint32_t>(64);
-  w->pb.xchg = cv.take<u64>((int64_t)pg.RG * kRing * pg.C * (pl.words > 0 ? pl.words : 1));
+  // the ring is sized for G workgroups (RG * C <= G), so that plans of one launch with
+  // different geometries keep one layout
+  w->pb.xchg = cv.take<u64>((int64_t)pg.G * kRing * (pl.words > 0 ? pl.words : 1));
   const size_t end = cv.off;
   w->zero_base = (uint32_t *)(cv.base + start);
   w->zero_words = (int64_t)((end - start + 3) / 4);
@@ -292,7 +306,7 @@ size_t prod_ws_bytes(const Plan &pl, int64_t ypart_doubles) {
   auto add = [&](size_t n) { b = (size_t)round_up((int64_t)b, 256) + n; };
   add(pg.G * 4);
   add(64 * 4);
-  add((size_t)pg.RG * kRing * pg.C * (pl.words > 0 ? pl.words : 1) * 8);
+  add((size_t)pg.G * kRing * (pl.words > 0 ? pl.words : 1) * 8);
   add((size_t)4 * 2 * pg.G * 8);
   add((size_t)pg.G * (pl.words > 0 ? pl.words : 1) * 8);
   add((size_t)ypart_doubles * 8);

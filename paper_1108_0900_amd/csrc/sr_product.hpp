@@ -37,7 +37,8 @@ constexpr int kNT = 256;            // workgroup size of the column-statistics k
 constexpr int kRing = 16;           // exchange slots per row group (> 2 * poll delay + 1)
 
 struct ProdGeom {
-  int G, C, RG;                     // grid size, column groups, row groups (G = C*RG)
+  int G, C, RG;                     // grid size, column groups, row groups (C*RG <= G: the
+                                    // workgroups past them, if any, are idle in products)
   int n_tiles;                      // ceil(n_s / R)
   int64_t n_s, n_p, wslice;         // wslice: columns per column group, multiple of VEC
   int64_t n_v;                      // streamed columns: n_p, or with a compact remainder
@@ -60,13 +61,21 @@ struct WgCtx {
 
 // Workgroup -> (row group, column group).  Workgroup b runs on XCD b % 8 (round-robin
 // dispatch); the column groups of one row group are placed on as few XCDs as possible so
-// their exchanges stay local when they can.  Requires G % 8 == 0 and C | G/8 or G/8 | C.
+// their exchanges stay local when they can.  Requires G % 8 == 0 and C <= G/8 (then each
+// XCD holds (G/8)/C row groups, RG = 8 (G/8)/C, and an XCD's workgroups past them get
+// rg = G: idle) or G/8 | C (RG = G/C).
 __device__ __forceinline__ void map_workgroup(int b, int G, int C, int &rg, int &cg) {
   const int L = G / 8;
   const int xcd = b % 8, local = b / 8;
   if (C <= L) {
-    rg = xcd * (L / C) + local / C;
-    cg = local % C;
+    const int per = L / C;
+    if (local < per * C) {
+      rg = xcd * per + local / C;
+      cg = local % C;
+    } else {
+      rg = G;
+      cg = 0;
+    }
   } else {
     const int xpg = C / L;
     rg = xcd / xpg;
@@ -359,7 +368,10 @@ struct Product {
   __device__ __forceinline__ u64 *slot_base(const ProdBufs &pb, const ProdGeom &pg, const WgCtx &ctx,
                                              uint32_t step) const {
     const int slot = (int)(step % kRing);
-    return pb.xchg + (((int64_t)ctx.rg * kRing + slot) * pg.C) * WORDS;
+    // an idle workgroup (rg >= RG) only issues the unconditional poll loads, whose words
+    // it never uses: it reads the last row group's slots
+    const int rg = ctx.rg < pg.RG ? ctx.rg : pg.RG - 1;
+    return pb.xchg + (((int64_t)rg * kRing + slot) * pg.C) * WORDS;
   }
 
   // Exchange wave: publish this column group's partial dots of exchange step `step`.
@@ -649,7 +661,9 @@ struct Product {
     __shared__ double s_tot[kNBuf][NDOT][R];
     __shared__ int s_ok;
     const int n_tiles = (int)((pg.n_s + R - 1) / R);
-    const int n_my = (ctx.rg < n_tiles) ? (n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
+    // an idle workgroup (rg >= RG) has no tiles: it runs the tail steps only (clamped rows,
+    // publishes to its sink) and every barrier
+    const int n_my = (ctx.rg < pg.RG && ctx.rg < n_tiles) ? (n_tiles - ctx.rg + pg.RG - 1) / pg.RG : 0;
     static_assert(kLook <= 4, "prologue issues at most 4 tiles");
     // whole rounds of kNBuf steps: no step is skipped, so the loop body has no branch
     // around loads (steps past n_my + kLag only stream clamped rows)
@@ -680,6 +694,7 @@ struct Product {
 
   // Store the row group's partial y (float64) and scalars, coherently.
   __device__ __forceinline__ void store_partials(const ProdGeom &pg, const ProdBufs &pb, const WgCtx &ctx) {
+    if (ctx.rg >= pg.RG) return;     // idle workgroup
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       if (i >= nvec) continue;

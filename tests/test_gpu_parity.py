@@ -119,6 +119,38 @@ def test_cg_matches_cholesky(shape, dtype):
     assert info["rel_res_true"] <= 1e-13
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16], ids=_dname)
+@pytest.mark.parametrize("n_p", [17001, 41001])
+def test_cg_wide_rows_uneven_column_groups(n_p, dtype):
+    """Wide rows whose column groups are not a power of two (float64 17001: 5 groups,
+    41001: 11 -> 16; float32 / bf16 17001: 3, 41001: 6), so some workgroups of each XCD
+    stay idle in every product; N_s << N_p, so the reference is the oracle's dual
+    (Woodbury) solve and the true residual is the oracle's matrix-free product."""
+    n_s = 200
+    print(f"[cg-wide] {n_s}x{n_p} {dtype}", flush=True)
+    O, E = rand_dense(n_s, n_p, seed=27 + n_p)
+    Os = stored_dense(O, dtype)
+    M = device_matrix(O, dtype)
+    st = sr.sr_grad(M, to_dev(E))
+    M.mean = st["mean"]
+    eps = 1e-3 * float(st["diag"].mean())
+    # kappa is about 1e5 here, so float64 attains about 1e-11: rtol 1e-10 (bf16 1e-6)
+    rtol = 1e-10 if dtype != torch.bfloat16 else 1e-6
+    x, info = sr.sr_cg_solve(M, st["g"], eps, rtol=rtol, refresh_every=20)
+    assert info["status"] == 0 and info["rel_res_true"] <= rtol, info
+    g_ref = orc.energy_gradient(Os, E)
+    eps_ref = 1e-3 * orc.diag_overlap(Os).mean()
+    xh = to_np(x)
+    r = orc.sv_product_swapped(Os, xh, eps_ref) - g_ref
+    assert np.linalg.norm(r) <= 4 * rtol * np.linalg.norm(g_ref), np.linalg.norm(r) / np.linalg.norm(g_ref)
+    x_ref = orc.solve_dual(Os, g_ref, eps_ref)
+    # the solution error is at most kappa times the residual (kappa of S + eps I on the
+    # range of Oc is about (max eigenvalue + eps) / eps here)
+    lam_max = np.linalg.eigvalsh(orc.centred(Os) @ orc.centred(Os).T / n_s)[-1]
+    kappa = (lam_max + eps_ref) / eps_ref
+    assert rel_err(xh, x_ref) <= 4 * kappa * rtol, (rel_err(xh, x_ref), kappa)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=_dname)
 @pytest.mark.parametrize("shape", [(50, 9), (1500, 1200), (3000, 5000), (6000, 2000)], ids=lambda s: f"{s[0]}x{s[1]}")
 def test_cg_jacobi_matches_cholesky(shape, dtype):
