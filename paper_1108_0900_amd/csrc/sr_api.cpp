@@ -2407,7 +2407,10 @@ static int cps_args(const sr_cps_matrix *M, const double *mean, double eps, bool
   c.val = M->val;
   c.n_corr = M->n_corr;
   c.n_states = M->n_states;
-  c.tiles = (int32_t)cdiv(M->n_s, kCpsTileRows);
+  int tr = kCpsTileRows;
+  while (tr > kCpsMinTileRows && cdiv(M->n_s, tr) < G) tr /= 2;
+  c.tile_rows = tr;
+  c.tiles = (int32_t)cdiv(M->n_s, tr);
   c.n_sp = n_sp;
   c.n_d = n_d;
   c.dO = (const unsigned char *)M->dense.O;

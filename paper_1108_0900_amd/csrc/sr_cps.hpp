@@ -13,7 +13,8 @@
 //   A. partial row sums over groups of correlators: a workgroup stages its group's table
 //      u_j = val_j v_j in LDS and gathers u[p, s_kp] for a range of rows; its share of
 //      c = obar_D . v_D over the dense columns is reduced at the barrier;
-//   1. row pass over row tiles of 128 rows: w_k = (sum of the groups' partials) +
+//   1. row pass over row tiles of 128 rows (fewer when there are few samples, so that
+//      every workgroup has one): w_k = (sum of the groups' partials) +
 //      D_k . (s v)_D - c (the dense rows read once into registers), then the dense
 //      partial sums P_d += D_kd w_k from the same registers;
 //   2. per correlator, the histogram T_{p,s} = sum_{k: s_kp = s} (w_k - wbar) in int64
@@ -173,7 +174,10 @@ struct CpsKernel {
           P[m][e] = (acc_t)0;
         }
       }
+      // the correlator part of the tile's row sums: tile_rows rows x (NT / tile_rows) slices
       __shared__ acc_t s_sp[kSlices][kCpsTileRows];
+      acc_t *s_spf = &s_sp[0][0];
+      const int tr = c.tile_rows, nsl = NT / tr;
       __shared__ double s_red[2][NWAVE][RB];
       double wsum = 0.0, wabs = 0.0;
       int par = 0;
@@ -215,7 +219,7 @@ struct CpsKernel {
           double wr = 0.0;
           if (k < n_s) {
             for (int wv = 0; wv < NWAVE; ++wv) wr += s_red[par][wv][r];
-            for (int pi = 0; pi < kSlices; ++pi) wr += (double)s_sp[pi][rb + r];
+            for (int pi = 0; pi < nsl; ++pi) wr += (double)s_spf[pi * tr + rb + r];
             wr -= cD;
           }
           if (tid == r && k < n_s) st_coh(&c.w[k], wr);
@@ -237,22 +241,22 @@ struct CpsKernel {
                     // this batch's reads from the writes two batches on
       };
       for (int t = b; t < c.tiles; t += G) {
-        const int64_t k0 = (int64_t)t * kCpsTileRows;
+        const int64_t k0 = (int64_t)t * tr;
         // 1a. correlator part of w for the tile's rows: the groups' partial sums, each of the
-        //     kSlices slices of threads summing a fixed subset of the groups
+        //     nsl slices of threads summing a fixed subset of the groups
         {
-          const int row = tid & (kCpsTileRows - 1), sl = tid / kCpsTileRows;
+          const int row = tid & (tr - 1), sl = tid / tr;
           const int64_t k = k0 + row;
           acc_t t = (acc_t)0;
           if (k < n_s) {
             const acc_t *part_sp = (const acc_t *)c.part_sp;
-            for (int g = sl; g < c.n_grp; g += kSlices) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
+            for (int g = sl; g < c.n_grp; g += nsl) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
           }
-          s_sp[sl][row] = t;
+          s_spf[sl * tr + row] = t;
         }
         __syncthreads();
         // 1b. dense part in batches of RB rows
-        for (int rb = 0; rb < kCpsTileRows; rb += RB) {
+        for (int rb = 0; rb < tr; rb += RB) {
           u32x4 D[RB][NVT];
           load_batch(D, k0 + rb);
           process(D, k0, rb);

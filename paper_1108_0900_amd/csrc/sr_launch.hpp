@@ -40,9 +40,11 @@ struct CpsOp {
   const double *val;          // [n_sp] value of each correlator column
   int64_t n_corr;
   int32_t n_states;           // columns per correlator (states >= n_states select no column)
-  int32_t tiles;              // row tiles of kCpsTileRows rows
+  int32_t tiles;              // row tiles of tile_rows rows
   int32_t raw;                // 1: uncentred product O^T (O v) / n_s (with zero dense means)
-  int32_t pad;
+  int32_t tile_rows;          // rows per tile of the row pass: kCpsTileRows, or a smaller
+                              // power of two (>= kCpsMinTileRows) so that every workgroup
+                              // has a tile when there are few samples
   int64_t n_sp, n_d;          // correlator columns (n_corr * n_states) and dense columns
   const unsigned char *dO;    // dense block [n_s][ld_d] (nullptr when n_d == 0)
   const float *dscale;        // [n_d] column scales (bf16 / f16 dense block) or nullptr
@@ -57,6 +59,7 @@ struct CpsOp {
   double *red;                // [4][2][G] grid reductions of the product
 };
 constexpr int kCpsTileRows = 128;   // rows per tile of the row pass (64 lanes x 2 rows)
+constexpr int kCpsMinTileRows = 16; // the smallest tile (its rows' sums come from NT / 16 slices)
 constexpr int kCpsTableBytes = 65536;   // LDS table of one correlator group (float64 entries: 8192)
 
 struct CgArgs {
