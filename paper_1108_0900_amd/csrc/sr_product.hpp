@@ -150,6 +150,17 @@ __device__ __forceinline__ int64_t lower_bound_wave(const int32_t *L, int64_t n,
 template <int DT, bool EXACT> struct AccOf { typedef typename Storage<DT>::acc_t type; };
 template <int DT> struct AccOf<DT, true> { typedef double type; };
 
+// bf16 bits of a float, rounded to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+// c + a.lo * b.lo + a.hi * b.hi for two packed bf16 pairs, float32 accumulation.
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
+__device__ __forceinline__ float dot2_bf16(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+
 // NDOT = 1: SR overlap product.  NDOT = 2: linear-method product (second operand D is
 // only dotted, never accumulated).
 //   NV    16-byte vectors per thread and row (slice width NV*VEC*NT columns)
@@ -200,6 +211,12 @@ struct Product {
   int n_q, n_qe;                    // streamed columns [n_q, n_qe) are the compact remainder
                                     // plane's (n_q = n_qe = 2^31 - 1 without one)
   acc_t vc[NDOT][NV][VEC];          // v_j * s_j per operand (0 outside the slice)
+  // bf16 codes, float32 accumulation: the row dots run as packed bf16 pair products
+  // (v_dot2 with float32 accumulation), v_j s_j split into a bf16 high part and a bf16
+  // remainder (words 0-3: the high parts of element pairs 2w, 2w+1; words 4-7: the
+  // remainders), which keeps about 16 significant bits of each coefficient
+  static constexpr bool kDot2 = DT == DT_BF16 && !EXACT && PLANES == 1;
+  uint32_t vp[NDOT][NV][VEC];
   acc_t yacc[NV][VEC];              // partial (O^T w)_j
   u32x4 buf[kNBuf][NOPS][R][NV];    // register ring of row tiles
   double s1, s2;                    // row-group scalars (SR: sum w; LM: sum z, sum(E t + u))
@@ -283,6 +300,22 @@ struct Product {
         }
         yacc[i][e] = (acc_t)0;
       }
+      if constexpr (kDot2) {
+#pragma unroll
+        for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+          for (int w = 0; w < VEC / 2; ++w) {
+            uint32_t hi[2], lo[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const float f = (float)vc[d][i][2 * w + h];
+              hi[h] = bf16_rne(f);
+              lo[h] = bf16_rne(f - __uint_as_float(hi[h] << 16));   // f - hi is exact
+            }
+            vp[d][i][w] = hi[0] | (hi[1] << 16);
+            vp[d][i][VEC / 2 + w] = lo[0] | (lo[1] << 16);
+          }
+      }
     }
     s1 = 0.0;
     s2 = 0.0;
@@ -342,6 +375,25 @@ struct Product {
 #pragma unroll
           for (int r = 0; r < R; ++r) buf[B][d][r][i] &= mi;
       }
+    }
+    if constexpr (kDot2) {
+#pragma unroll
+      for (int d = 0; d < NDOT; ++d)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float ah = 0.0f, al = 0.0f;
+#pragma unroll
+          for (int i = 0; i < NV; ++i) {
+            const u32x4 x = buf[B][d][r][i];
+#pragma unroll
+            for (int w = 0; w < VEC / 2; ++w) {
+              ah = dot2_bf16(x[w], vp[d][i][w], ah);
+              al = dot2_bf16(x[w], vp[d][i][VEC / 2 + w], al);
+            }
+          }
+          part[d][r] = (acc_t)(ah + al);
+        }
+      return;
     }
 #pragma unroll
     for (int d = 0; d < NDOT; ++d)
