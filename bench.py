@@ -821,7 +821,7 @@ def measure_single(args):
     # same algorithmic bytes per launch), else null
     traffic = None
     used_tile = tuple(tiles[dtype_name]["best"]) if dtype_name in tiles else tuple(sr.tile_configs(dt_t, 0)[0])
-    rec_t = traffic_record(step_kernel_name(used_tile)) if (scaled and form == "compact") else None
+    rec_t = traffic_record(step_kernel_name(used_tile[:5])) if (scaled and form == "compact") else None
     if rec_t is not None and abs(rec_t["algorithmic_bytes"] - alg_pb) <= 1e-6 * alg_pb:
         traffic = round(rec_t["traffic_bytes"] / 1e9, 1)
 

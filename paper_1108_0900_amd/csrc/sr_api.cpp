@@ -268,7 +268,11 @@ int make_plan(int dt, int G, int64_t n_s, int64_t n_p, int ndot, Plan *plan, int
   }
   plan->ke = pick;
   const int cols = pick->nv * vec * pick->nt;
-  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg, n_v, true);
+  // uneven column groups by default for 4- and 2-byte storage (measured faster there);
+  // float64 keeps powers of two (on CPS 65536 x 24512 six groups ran 5-14 % slower than
+  // eight); the tuning hook forces either
+  int rc = geometry(G, n_s, n_p, cols, vec, pick->r, f.nv > 0 && pick->nv == f.nv ? f.c : 0, &plan->pg, n_v,
+                    dt != DT_F64);
   if (rc) return rc;
   plan->words = ndot * pick->r * 2;   // float64 partials (two tagged words each)
   return SR_OK;

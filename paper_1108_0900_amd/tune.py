@@ -66,6 +66,24 @@ def _median_ms(fn, reps: int, warm: int = 1) -> float:
     return ts[len(ts) // 2]
 
 
+_VEC = {torch.float64: 2, torch.float32: 4, torch.bfloat16: 8, torch.float16: 8}
+
+
+def _col_group_choices(M: sr.Matrix, cfg) -> list:
+    """0 (automatic) and, when the automatic choice may be an uneven number of column
+    groups, the power of two that holds the streamed columns."""
+    if M.O.dtype == torch.float64:
+        return [0]
+    nv, _, _, _, nt = cfg
+    vec = _VEC[M.O.dtype]
+    n_v = M.n_p if M.lo_cols is None else -(-M.n_p // vec) * vec + M.lo_cols.numel()
+    cmin = -(-n_v // (nv * vec * nt))
+    p2 = 1
+    while p2 < cmin:
+        p2 *= 2
+    return [0, p2] if cmin < p2 <= 256 and cmin <= 32 else [0]
+
+
 def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None = None,
              E: torch.Tensor | None = None, D: sr.Matrix | None = None, apply: bool = True,
              cg_iters: int = 0) -> dict:
@@ -75,7 +93,7 @@ def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None 
     kind 0 with cg_iters > 0 times a CG solve of cg_iters iterations instead (M may carry a
     compact remainder plane then).
 
-    Returns {"best": (nv, rows, lookahead, poll_depth, threads), "ms": {config: ms},
+    Returns {"best": (nv, rows, lookahead, poll_depth, threads, col_groups), "ms": {config: ms},
     "cached": bool}.  A configuration whose call fails (for example, one that cannot hold
     n_p columns) is skipped.  M's column means are computed first if missing.
     """
@@ -138,11 +156,14 @@ def autotune(M: sr.Matrix, kind: int = 0, reps: int = 3, cache_path: str | None 
     times = {}
     try:
         for cfg in sr.tile_configs(M.O.dtype, kind):
-            sr.set_tile_config(M.O.dtype, kind, *cfg)
-            try:
-                times[cfg] = _median_ms(call, reps)
-            except sr.SrError:
-                continue
+            # the automatic column groups (uneven ones where they give more row groups, for
+            # 4- and 2-byte storage) and, where that differs, the power of two above them
+            for cg in _col_group_choices(M, cfg):
+                sr.set_tile_config(M.O.dtype, kind, *cfg, col_groups=cg)
+                try:
+                    times[cfg + (cg,)] = _median_ms(call, reps)
+                except sr.SrError:
+                    continue
     finally:
         sr.set_tile_config(M.O.dtype, kind)
     if not times:

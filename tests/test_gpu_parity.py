@@ -498,7 +498,9 @@ def test_autotuner_selects_a_built_config_and_caches(tmp_path):
         for dtype in (torch.float64, torch.bfloat16):
             M = device_matrix(O, dtype)
             res = tune.autotune(M, kind=0, reps=2, cache_path=cache)
-            assert res["best"] in sr.tile_configs(dtype, 0) and not res["cached"]
+            # (tile..., column groups): 0 automatic, else the power of two above them
+            assert res["best"][:5] in sr.tile_configs(dtype, 0) and not res["cached"]
+            assert res["best"][5] == 0 or res["best"][5] & (res["best"][5] - 1) == 0
             assert res["ms"][res["best"]] == min(res["ms"].values())
             again = tune.autotune(M, kind=0, cache_path=cache)
             assert again["cached"] and again["best"] == res["best"]
@@ -511,7 +513,7 @@ def test_autotuner_selects_a_built_config_and_caches(tmp_path):
         D = device_matrix(0.1 * np.random.default_rng(3).standard_normal((n_s, n_p)), torch.float64)
         M = device_matrix(O, torch.float64)
         res = tune.autotune(M, kind=1, reps=2, E=to_dev(E), D=D)
-        assert res["best"] in sr.tile_configs(torch.float64, 1)
+        assert res["best"][:5] in sr.tile_configs(torch.float64, 1)
     finally:
         sr.set_tile_config()
 

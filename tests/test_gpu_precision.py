@@ -260,7 +260,7 @@ def test_autotune_on_cg_with_compact_plane(tmp_path):
     cache = str(tmp_path / "tune.json")
     try:
         res = tune.autotune(M, kind=0, reps=2, cache_path=cache, cg_iters=3)
-        assert res["best"] in sr.tile_configs(torch.bfloat16, 0) and not res["cached"]
+        assert res["best"][:5] in sr.tile_configs(torch.bfloat16, 0) and not res["cached"]
         again = tune.autotune(M, kind=0, cache_path=cache, cg_iters=3)
         assert again["cached"] and again["best"] == res["best"]
         Os = orc.dequantize_cols(*orc.quantize_cols(O, "bf16"), "bf16")
