@@ -55,13 +55,17 @@ template <int DDT, int NVT, bool X, int NT = 512>
 struct CpsKernel {
   static_assert(NT == 512, "the row pass maps 64 lanes x 2 rows to a 128-row tile and 8 waves to correlator parts");
   static constexpr int VEC = Storage<DDT>::VEC;
-  // rows per batch (RB rows x NVT vectors in registers); a second buffer to load the next
-  // batch while this one is reduced measured no faster (the row pass is bound by the
-  // decode and FMA work of the dot and the update, about 4.3 TB/s here, not by latency)
+  // rows per batch (RB rows x NVT vectors in registers)
   static constexpr int RB = NVT >= 12 ? 1 : (NVT >= 8 ? 2 : (NVT >= 3 ? 4 : 8));
+  // a second batch buffer (the next batch's loads in flight while this batch is reduced)
+  // for the narrow tiles whose registers have room for it (float32-accumulated 2-byte
+  // storage up to 4 vectors, float32 storage up to 3)
+  static constexpr bool kTwoBuf = !X && ((DDT == DT_BF16 || DDT == DT_F16) ? NVT <= 4 : (DDT == DT_F32 && NVT <= 3));
   static constexpr int NWAVE = NT / 64;
   static constexpr int kSlices = NT / kCpsTileRows;   // thread slices summing the group partials
   static constexpr int kPass = 8;               // correlators per histogram pass
+  static constexpr int kRowsA = 256;            // rows of one wave's block in the correlator phase
+  static constexpr int kBatchA = 16;            // correlators whose state words load together there
   static constexpr bool kExactResidual = (DDT == DT_BF16 || DDT == DT_F16);
 
   // q was written by other workgroups in this launch
@@ -97,9 +101,10 @@ struct CpsKernel {
 
     // ---- A. correlator partial row sums ----
     // Work item (group g, row range rr): correlators [g cpg, (g+1) cpg) and rows
-    // [rr rpr, (rr+1) rpr).  The group's table u = val * v goes to LDS; lanes take pairs of
-    // rows (one 2-byte state load per correlator), waves share the group's correlators, and
-    // the waves' sums of each row are combined in a fixed order into part_sp[g][k].
+    // [rr rpr, (rr+1) rpr).  The group's table u = val * v goes to LDS; each wave takes
+    // whole blocks of 256 rows (four per lane, one 4-byte state load per correlator) through
+    // all the group's correlators, so no two waves share a row and no barrier is needed.
+    // A row's sum runs over the group's correlators in order into part_sp[g][k].
     {
       __shared__ acc_t s_u[kCpsTableBytes / sizeof(acc_t)];
       const int wave = tid >> 6, lane = tid & 63;
@@ -109,46 +114,78 @@ struct CpsKernel {
         const int64_t p0 = min(c.n_corr, (int64_t)g * c.cpg), p1 = min(c.n_corr, p0 + c.cpg);
         const int np_ = (int)(p1 - p0);
         __syncthreads();                 // s_u of the previous item is no longer read
-        for (int e = tid; e < np_ * ns; e += NT) {
-          const int64_t j = p0 * ns + e;
-          s_u[e] = (acc_t)(c.val[j] * ld_coh(&vin[j]));
+        // four entries per thread load together
+        const int ne = np_ * ns;
+        for (int e0 = tid; e0 < ne; e0 += 4 * NT) {
+          double tv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * NT;
+            tv[u] = e < ne ? c.val[p0 * ns + e] * ld_coh(&vin[p0 * ns + e]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (e0 + u * NT < ne) s_u[e0 + u * NT] = (acc_t)tv[u];
         }
         __syncthreads();
-        // each wave takes whole blocks of 128 rows (a pair per lane, one 2-byte state load per
-        // correlator) through all the group's correlators, so no two waves share a row and
-        // no barrier is needed (16 rows per lane with 16-byte loads measured slower)
+        // The (block, batch of kBatchA correlators) pairs of this wave form one stream; the
+        // state words of the next pair load while the current pair's table entries are
+        // summed (issued one batch after another, the loads' latency bound this phase).
+        // Rows k0 .. k0+3 of a lane lie below ld_idx (a multiple of 16, >= n_s) whenever
+        // k0 < n_s, so the 4-byte loads stay inside the row.
         const int64_t r0 = min(n_s, (int64_t)rr * c.rpr), r1 = min(n_s, r0 + c.rpr);
-        for (int64_t kb = r0 + (int64_t)wave * kCpsTileRows; kb < r1; kb += (int64_t)NWAVE * kCpsTileRows) {
-          const int64_t kp = kb + 2 * lane;
-          acc_t s0 = (acc_t)0, s1 = (acc_t)0;
-          if (kp < r1) {
-            const unsigned char *ip = c.idx + p0 * c.ld_idx + kp;
-            const int64_t sti = c.ld_idx;
-            int i = 0;
-            for (; i + 7 < np_; i += 8) {
-              uint32_t pr[8];
+        const int64_t sti = c.ld_idx;
+        const int64_t kfirst = r0 + (int64_t)wave * kRowsA, wstride = (int64_t)NWAVE * kRowsA;
+        // (at least one batch: a group without correlators still stores its rows' zero sums)
+        const int nbat = max(1, (np_ + kBatchA - 1) / kBatchA);
+        const int nblk = kfirst < r1 ? (int)((r1 - kfirst + wstride - 1) / wstride) : 0;
+        const int total = nblk * nbat;
+        const unsigned char *ib = c.idx + p0 * sti;
+        auto fetch = [&](uint32_t (&dst)[kBatchA], int blk, int bt) __attribute__((always_inline)) {
+          const int64_t kp = kfirst + (int64_t)blk * wstride + 4 * lane;
+          const int i0 = bt * kBatchA;
+          const unsigned char *ip = ib + (int64_t)i0 * sti + kp;
 #pragma unroll
-              for (int d = 0; d < 8; ++d) pr[d] = *(const uint16_t *)(ip + d * sti);
+          for (int d = 0; d < kBatchA; ++d)
+            dst[d] = (kp < r1 && i0 + d < np_) ? *(const uint32_t *)(ip + (int64_t)d * sti) : 0u;
+        };
+        uint32_t cur[kBatchA], nxt[kBatchA];
 #pragma unroll
-              for (int d = 0; d < 8; ++d) {
-                const unsigned sa = pr[d] & 0xFFu, sb = pr[d] >> 8;
-                const acc_t *ut = s_u + (i + d) * ns;
-                if (sa < (unsigned)ns) s0 += ut[sa];
-                if (sb < (unsigned)ns) s1 += ut[sb];
-              }
-              ip += 8 * sti;
-            }
-            for (; i < np_; ++i) {
-              const unsigned pr = *(const uint16_t *)ip;
-              const unsigned sa = pr & 0xFFu, sb = pr >> 8;
-              const acc_t *ut = s_u + i * ns;
-              if (sa < (unsigned)ns) s0 += ut[sa];
-              if (sb < (unsigned)ns) s1 += ut[sb];
-              ip += sti;
-            }
-            st_acc(&part_sp[(int64_t)g * n_s + kp], s0);
-            if (kp + 1 < r1) st_acc(&part_sp[(int64_t)g * n_s + kp + 1], s1);
+        for (int d = 0; d < kBatchA; ++d) cur[d] = nxt[d] = 0u;
+        if (total > 0) fetch(cur, 0, 0);
+        acc_t s4[4] = {(acc_t)0, (acc_t)0, (acc_t)0, (acc_t)0};
+        int blk = 0, bt = 0;
+        for (int t = 0; t < total; ++t) {
+          int nb = blk, nt = bt + 1;
+          if (nt == nbat) {
+            nt = 0;
+            ++nb;
           }
+          if (t + 1 < total) fetch(nxt, nb, nt);
+          const int i0 = bt * kBatchA;
+#pragma unroll
+          for (int d = 0; d < kBatchA; ++d) {
+            if (i0 + d < np_) {
+              const acc_t *ut = s_u + (i0 + d) * ns;
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const unsigned st = (cur[d] >> (8 * r)) & 0xFFu;
+                if (st < (unsigned)ns) s4[r] += ut[st];
+              }
+            }
+          }
+          if (nt == 0) {                 // the block's last batch: its rows' sums are complete
+            const int64_t kp = kfirst + (int64_t)blk * wstride + 4 * lane;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (kp + r < r1) st_acc(&part_sp[(int64_t)g * n_s + kp + r], s4[r]);
+              s4[r] = (acc_t)0;
+            }
+          }
+          blk = nb;
+          bt = nt;
+#pragma unroll
+          for (int d = 0; d < kBatchA; ++d) cur[d] = nxt[d];
         }
       }
       // the dense block's centring share c = obar_D . v_D, reduced at the barrier
@@ -255,11 +292,25 @@ struct CpsKernel {
           s_spf[sl * tr + row] = t;
         }
         __syncthreads();
-        // 1b. dense part in batches of RB rows
-        for (int rb = 0; rb < tr; rb += RB) {
-          u32x4 D[RB][NVT];
-          load_batch(D, k0 + rb);
-          process(D, k0, rb);
+        // 1b. dense part in batches of RB rows; where the registers allow, the next batch
+        //     loads while this one is reduced
+        if constexpr (kTwoBuf && !EXACT) {
+          u32x4 D0[RB][NVT], D1[RB][NVT];
+          load_batch(D0, k0);
+          for (int rb = 0; rb < tr; rb += 2 * RB) {
+            if (rb + RB < tr) load_batch(D1, k0 + rb + RB);
+            process(D0, k0, rb);
+            if (rb + RB < tr) {
+              if (rb + 2 * RB < tr) load_batch(D0, k0 + rb + 2 * RB);
+              process(D1, k0, rb + RB);
+            }
+          }
+        } else {
+          for (int rb = 0; rb < tr; rb += RB) {
+            u32x4 D[RB][NVT];
+            load_batch(D, k0 + rb);
+            process(D, k0, rb);
+          }
         }
         __syncthreads();   // s_sp is rewritten by the next tile
       }
@@ -289,26 +340,60 @@ struct CpsKernel {
           if (p0 + (int64_t)e * G < c.n_corr) np = e + 1;
         for (int i = tid; i < kPass * 256; i += NT) (&s_bin[0][0])[i] = 0;
         __syncthreads();
-        for (int64_t k4 = (int64_t)tid * 4; k4 < n_s; k4 += (int64_t)NT * 4) {
+        // rows k4 .. k4+3 of every pass correlator: w and the state words of the thread's next
+        // rows load while this step's bins are added (issued after each other's atomics, the
+        // loads' latency bound this phase)
+        const int64_t kstep = (int64_t)NT * 4;
+        double wv[4], wn[4];
+        uint32_t sw[kPass], sn[kPass];
+        auto fetch = [&](double (&wo)[4], uint32_t (&so)[kPass], int64_t k4) __attribute__((always_inline)) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) wo[e] = (k4 + e < n_s) ? ld_coh(&c.w[k4 + e]) : 0.0;
+#pragma unroll
+          for (int e = 0; e < kPass; ++e)
+            so[e] = e < np ? *(const uint32_t *)(c.idx + (p0 + (int64_t)e * G) * c.ld_idx + k4) : 0u;
+        };
+#pragma unroll
+        for (int e = 0; e < 4; ++e) wv[e] = wn[e] = 0.0;
+#pragma unroll
+        for (int e = 0; e < kPass; ++e) sw[e] = sn[e] = 0u;
+        if ((int64_t)tid * 4 < n_s) fetch(wv, sw, (int64_t)tid * 4);
+        for (int64_t k4 = (int64_t)tid * 4; k4 < n_s; k4 += kstep) {
+          if (k4 + kstep < n_s) fetch(wn, sn, k4 + kstep);
           long long qv[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) qv[e] = (k4 + e < n_s) ? __double2ll_rn((ld_coh(&c.w[k4 + e]) - wbar) * sigma) : 0ll;
-          for (int e = 0; e < np; ++e) {
-            const uint32_t word = *(const uint32_t *)(c.idx + (p0 + (int64_t)e * G) * c.ld_idx + k4);
+          for (int e = 0; e < 4; ++e) qv[e] = (k4 + e < n_s) ? __double2ll_rn((wv[e] - wbar) * sigma) : 0ll;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const unsigned s_ = (word >> (8 * r)) & 0xFFu;
-              if (k4 + r < n_s && s_ < (unsigned)ns) atomicAdd((unsigned long long *)&s_bin[e][s_], (unsigned long long)qv[r]);
+          for (int e = 0; e < kPass; ++e) {
+            if (e < np) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const unsigned s_ = (sw[e] >> (8 * r)) & 0xFFu;
+                if (k4 + r < n_s && s_ < (unsigned)ns) atomicAdd((unsigned long long *)&s_bin[e][s_], (unsigned long long)qv[r]);
+              }
             }
           }
+#pragma unroll
+          for (int e = 0; e < 4; ++e) wv[e] = wn[e];
+#pragma unroll
+          for (int e = 0; e < kPass; ++e) sw[e] = sn[e];
         }
         __syncthreads();
-        for (int e = 0; e < np; ++e) {
-          const int64_t p = p0 + (int64_t)e * G;
-          for (int s_ = tid; s_ < ns; s_ += NT) {
-            const int64_t j = p * ns + s_;
-            const double T = (double)s_bin[e][s_] * inv_sigma;
-            st_coh(&q[j], c.val[j] * T * inv_n + a.eps * ld_coh(&vin[j]));
+        // the pass correlators' values and v load together
+        for (int s_ = tid; s_ < ns; s_ += NT) {
+          double vv[kPass], vl[kPass];
+#pragma unroll
+          for (int e = 0; e < kPass; ++e) {
+            const int64_t j = (p0 + (int64_t)e * G) * ns + s_;
+            vv[e] = e < np ? c.val[j] : 0.0;
+            vl[e] = e < np ? ld_coh(&vin[j]) : 0.0;
+          }
+#pragma unroll
+          for (int e = 0; e < kPass; ++e) {
+            if (e < np) {
+              const double T = (double)s_bin[e][s_] * inv_sigma;
+              st_coh(&q[(p0 + (int64_t)e * G) * ns + s_], vv[e] * T * inv_n + a.eps * vl[e]);
+            }
           }
         }
         __syncthreads();
@@ -323,7 +408,16 @@ struct CpsKernel {
           double acc = 0.0;
           if (d < d1) {
             const int g0 = wave * gpw, g1 = min(G, g0 + gpw);
-            for (int g = g0; g < g1; ++g) acc += (double)ld_acc(&part[(int64_t)g * c.n_dp + d]);
+            // eight workgroups' partials load together, then add in workgroup order
+            int g = g0;
+            for (; g + 8 <= g1; g += 8) {
+              acc_t t8[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u) t8[u] = ld_acc(&part[(int64_t)(g + u) * c.n_dp + d]);
+#pragma unroll
+              for (int u = 0; u < 8; ++u) acc += (double)t8[u];
+            }
+            for (; g < g1; ++g) acc += (double)ld_acc(&part[(int64_t)g * c.n_dp + d]);
           }
           s_col[wave][lane] = acc;
           __syncthreads();
