@@ -58,9 +58,9 @@ struct CpsKernel {
   // rows per batch (RB rows x NVT vectors in registers)
   static constexpr int RB = NVT >= 12 ? 1 : (NVT >= 8 ? 2 : (NVT >= 3 ? 4 : 8));
   // a second batch buffer (the next batch's loads in flight while this batch is reduced)
-  // for the narrow tiles whose registers have room for it (float32-accumulated 2-byte
-  // storage up to 4 vectors, float32 storage up to 3)
-  static constexpr bool kTwoBuf = !X && ((DDT == DT_BF16 || DDT == DT_F16) ? NVT <= 4 : (DDT == DT_F32 && NVT <= 3));
+  // where the registers have room for it: float32-accumulated 2-byte storage with at most
+  // 12 vectors per batch (larger batches, or float64 accumulation, spill)
+  static constexpr bool kTwoBuf = !X && (DDT == DT_BF16 || DDT == DT_F16) && RB * NVT <= 12;
   static constexpr int NWAVE = NT / 64;
   static constexpr int kSlices = NT / kCpsTileRows;   // thread slices summing the group partials
   static constexpr int kPass = 8;               // correlators per histogram pass
@@ -211,6 +211,27 @@ struct CpsKernel {
           P[m][e] = (acc_t)0;
         }
       }
+      // bf16 block with float32 accumulation: the row dots take packed bf16 pair products,
+      // (s v) split into a bf16 high part and the bf16 rounding of its remainder (about 16
+      // significant bits), so the stored pairs need no decoding for the dot
+      constexpr bool kDot2 = DDT == DT_BF16 && !(EXACT || X);
+      uint32_t vp[kDot2 ? NVT : 1][VEC];
+      if constexpr (kDot2) {
+#pragma unroll
+        for (int m = 0; m < NVT; ++m)
+#pragma unroll
+          for (int w = 0; w < VEC / 2; ++w) {
+            uint32_t hi[2], lo[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const float f = (float)vs[m][2 * w + h];
+              hi[h] = bf16_rne(f);
+              lo[h] = bf16_rne(f - __uint_as_float(hi[h] << 16));   // f - hi is exact
+            }
+            vp[m][w] = hi[0] | (hi[1] << 16);
+            vp[m][VEC / 2 + w] = lo[0] | (lo[1] << 16);
+          }
+      }
       // the correlator part of the tile's row sums: tile_rows rows x (NT / tile_rows) slices
       __shared__ acc_t s_sp[kSlices][kCpsTileRows];
       acc_t *s_spf = &s_sp[0][0];
@@ -220,29 +241,52 @@ struct CpsKernel {
       int par = 0;
       // one batch of RB dense rows into registers (rows past n_s and vectors past the row
       // load nothing)
+      // Rows past n_s and vectors past the row load the last row's or vector's data
+      // instead (no branch around a load: the compiler's wait counting then keeps the other
+      // batch's loads in flight).  Such values only ever meet a zero weight (w_k = 0 for
+      // k >= n_s, v = 0 past the row) and are never stored.
       auto load_batch = [&](u32x4 (&D)[RB][NVT], int64_t k0b) __attribute__((always_inline)) {
+        if (nvec == 0) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int m = 0; m < NVT; ++m) D[r][m] = u32x4{0u, 0u, 0u, 0u};
+          return;
+        }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-          const int64_t k = k0b + r;
+          const int64_t k = min(k0b + r, n_s - 1);
           const unsigned char *rowp = c.dO + k * c.ldb_d;
 #pragma unroll
           for (int m = 0; m < NVT; ++m) {
-            const int64_t vi = tid + (int64_t)m * NT;
-            if (k < n_s && vi < nvec) D[r][m] = load_stream(rowp + vi * 16);
-            else D[r][m] = u32x4{0u, 0u, 0u, 0u};
+            const int64_t vi = min(tid + (int64_t)m * NT, nvec - 1);
+            D[r][m] = load_stream(rowp + vi * 16);
           }
         }
       };
+      double my_w = 0.0;                 // w of the tile's row k0 + tid (threads below tile_rows)
       // row dots of a batch, their workgroup sums, w_k, then P += D w from the same registers
       auto process = [&](u32x4 (&D)[RB][NVT], int64_t k0, int rb) __attribute__((always_inline)) {
         acc_t pd[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           acc_t acc = (acc_t)0;
+          if constexpr (kDot2) {
+            float ah = 0.0f, al = 0.0f;
 #pragma unroll
-          for (int m = 0; m < NVT; ++m)
+            for (int m = 0; m < NVT; ++m)
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) acc += (acc_t)Storage<DDT>::get(D[r][m], e) * vs[m][e];
+              for (int w = 0; w < VEC / 2; ++w) {
+                ah = dot2_bf16(D[r][m][w], vp[m][w], ah);
+                al = dot2_bf16(D[r][m][w], vp[m][VEC / 2 + w], al);
+              }
+            acc = (acc_t)(ah + al);
+          } else {
+#pragma unroll
+            for (int m = 0; m < NVT; ++m)
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) acc += (acc_t)Storage<DDT>::get(D[r][m], e) * vs[m][e];
+          }
           pd[r] = wave_sum(acc);
         }
         if (lane == 0) {
@@ -259,7 +303,7 @@ struct CpsKernel {
             for (int pi = 0; pi < nsl; ++pi) wr += (double)s_spf[pi * tr + rb + r];
             wr -= cD;
           }
-          if (tid == r && k < n_s) st_coh(&c.w[k], wr);
+          if (tid == rb + r) my_w = wr;   // stored after the tile (no store inside the batch loop)
           if (tid == 0) {
             wsum += wr;
             wabs += fabs(wr);
@@ -277,42 +321,58 @@ struct CpsKernel {
         par ^= 1;   // the next batch writes the other half of s_red; a barrier separates
                     // this batch's reads from the writes two batches on
       };
-      for (int t = b; t < c.tiles; t += G) {
-        const int64_t k0 = (int64_t)t * tr;
-        // 1a. correlator part of w for the tile's rows: the groups' partial sums, each of the
-        //     nsl slices of threads summing a fixed subset of the groups
-        {
-          const int row = tid & (tr - 1), sl = tid / tr;
-          const int64_t k = k0 + row;
-          acc_t t = (acc_t)0;
-          if (k < n_s) {
-            const acc_t *part_sp = (const acc_t *)c.part_sp;
-            for (int g = sl; g < c.n_grp; g += nsl) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
-          }
-          s_spf[sl * tr + row] = t;
+      // 1a. correlator part of w for the tile's rows: the groups' partial sums, each of the
+      //     nsl slices of threads summing a fixed subset of the groups
+      auto tile_head = [&](int64_t k0) __attribute__((always_inline)) {
+        const int row = tid & (tr - 1), sl = tid / tr;
+        const int64_t k = k0 + row;
+        acc_t t = (acc_t)0;
+        if (k < n_s) {
+          const acc_t *part_sp = (const acc_t *)c.part_sp;
+          for (int g = sl; g < c.n_grp; g += nsl) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
         }
+        s_spf[sl * tr + row] = t;
         __syncthreads();
-        // 1b. dense part in batches of RB rows; where the registers allow, the next batch
-        //     loads while this one is reduced
-        if constexpr (kTwoBuf && !EXACT) {
+      };
+      auto tile_tail = [&](int64_t k0) __attribute__((always_inline)) {
+        if (tid < tr && k0 + tid < n_s) st_coh(&c.w[k0 + tid], my_w);
+        __syncthreads();                 // s_sp is rewritten by the next tile
+      };
+      // 1b. dense part in batches of RB rows.  Where the registers allow, two buffers: the
+      //     next batch loads while this one is reduced, with no branch around any load (a
+      //     tile has an even number of batches; the last one of a tile loads the first batch
+      //     of the workgroup's next tile, past the end a clamped row that is never used).
+      bool piped = false;
+      if constexpr (kTwoBuf && !EXACT) {
+        static_assert(kCpsMinTileRows % (2 * RB) == 0, "an even number of batches per tile");
+        if (nvec > 0) {
+          piped = true;
           u32x4 D0[RB][NVT], D1[RB][NVT];
-          load_batch(D0, k0);
-          for (int rb = 0; rb < tr; rb += 2 * RB) {
-            if (rb + RB < tr) load_batch(D1, k0 + rb + RB);
-            process(D0, k0, rb);
-            if (rb + RB < tr) {
-              if (rb + 2 * RB < tr) load_batch(D0, k0 + rb + 2 * RB);
+          load_batch(D0, (int64_t)b * tr);
+          for (int t = b; t < c.tiles; t += G) {
+            const int64_t k0 = (int64_t)t * tr, k0n = (int64_t)(t + G) * tr;
+            tile_head(k0);
+            for (int rb = 0; rb < tr; rb += 2 * RB) {
+              load_batch(D1, k0 + rb + RB);
+              process(D0, k0, rb);
+              load_batch(D0, rb + 2 * RB < tr ? k0 + rb + 2 * RB : k0n);
               process(D1, k0, rb + RB);
             }
+            tile_tail(k0);
           }
-        } else {
+        }
+      }
+      if (!piped) {
+        for (int t = b; t < c.tiles; t += G) {
+          const int64_t k0 = (int64_t)t * tr;
+          tile_head(k0);
           for (int rb = 0; rb < tr; rb += RB) {
             u32x4 D[RB][NVT];
             load_batch(D, k0 + rb);
             process(D, k0, rb);
           }
+          tile_tail(k0);
         }
-        __syncthreads();   // s_sp is rewritten by the next tile
       }
       // dense partial sums of this workgroup (zeros when it had no tile)
 #pragma unroll
