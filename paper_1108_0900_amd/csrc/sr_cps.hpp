@@ -106,7 +106,10 @@ struct CpsKernel {
     // all the group's correlators, so no two waves share a row and no barrier is needed.
     // A row's sum runs over the group's correlators in order into part_sp[g][k].
     {
-      __shared__ acc_t s_u[kCpsTableBytes / sizeof(acc_t)];
+      // the group's table, then one zero entry (states outside a correlator read it)
+      constexpr int kZeroSlot = kCpsTableBytes / sizeof(acc_t);
+      __shared__ acc_t s_u[kZeroSlot + 1];
+      if (tid == 0) s_u[kZeroSlot] = (acc_t)0;   // the fill below never writes it
       const int wave = tid >> 6, lane = tid & 63;
       acc_t *part_sp = (acc_t *)c.part_sp;
       for (int it = b; it < c.n_items; it += G) {
@@ -141,18 +144,36 @@ struct CpsKernel {
         const int nblk = kfirst < r1 ? (int)((r1 - kfirst + wstride - 1) / wstride) : 0;
         const int total = nblk * nbat;
         const unsigned char *ib = c.idx + p0 * sti;
-        auto fetch = [&](uint32_t (&dst)[kBatchA], int blk, int bt) __attribute__((always_inline)) {
-          const int64_t kp = kfirst + (int64_t)blk * wstride + 4 * lane;
-          const int i0 = bt * kBatchA;
-          const unsigned char *ip = ib + (int64_t)i0 * sti + kp;
+        if (np_ == 0) {                  // no correlators in the group: zero row sums
+          for (int64_t kb = kfirst; kb < r1; kb += wstride) {
+            const int64_t kp = kb + 4 * lane;
 #pragma unroll
-          for (int d = 0; d < kBatchA; ++d)
-            dst[d] = (kp < r1 && i0 + d < np_) ? *(const uint32_t *)(ip + (int64_t)d * sti) : 0u;
+            for (int r = 0; r < 4; ++r)
+              if (kp + r < r1) st_acc(&part_sp[(int64_t)g * n_s + kp + r], (acc_t)0);
+          }
+          continue;
+        }
+        // No branch around a load or a table read (a branch makes the compiler wait for
+        // every outstanding access at the join): lanes past the range read its last four
+        // rows (kmax <= r1 - 1 < ld_idx - 3), batches past the group's correlators read its
+        // last one, and states outside the correlator (s >= n_states) read the table's
+        // zero entry (no select after the read, so the reads of a batch issue together).
+        const int64_t kmax = (r1 - 1) & ~(int64_t)3;
+        auto fetch = [&](uint32_t (&dst)[kBatchA], int blk, int bt) __attribute__((always_inline)) {
+          const int64_t kp = min(kfirst + (int64_t)blk * wstride + 4 * lane, kmax);
+          const int i0 = bt * kBatchA;
+#pragma unroll
+          for (int d = 0; d < kBatchA; ++d) dst[d] = *(const uint32_t *)(ib + (int64_t)min(i0 + d, np_ - 1) * sti + kp);
+        };
+        auto add_entry = [&](acc_t (&s4)[4], uint32_t word, int base) __attribute__((always_inline)) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const unsigned st = (word >> (8 * r)) & 0xFFu;
+            s4[r] += s_u[st < (unsigned)ns ? base + (int)st : kZeroSlot];
+          }
         };
         uint32_t cur[kBatchA], nxt[kBatchA];
-#pragma unroll
-        for (int d = 0; d < kBatchA; ++d) cur[d] = nxt[d] = 0u;
-        if (total > 0) fetch(cur, 0, 0);
+        fetch(cur, 0, 0);
         acc_t s4[4] = {(acc_t)0, (acc_t)0, (acc_t)0, (acc_t)0};
         int blk = 0, bt = 0;
         for (int t = 0; t < total; ++t) {
@@ -161,18 +182,15 @@ struct CpsKernel {
             nt = 0;
             ++nb;
           }
-          if (t + 1 < total) fetch(nxt, nb, nt);
+          fetch(nxt, nb, nt);            // past the wave's last block: clamped, unused
           const int i0 = bt * kBatchA;
+          if (i0 + kBatchA <= np_) {     // a full batch: straight-line table reads
 #pragma unroll
-          for (int d = 0; d < kBatchA; ++d) {
-            if (i0 + d < np_) {
-              const acc_t *ut = s_u + (i0 + d) * ns;
+            for (int d = 0; d < kBatchA; ++d) add_entry(s4, cur[d], (i0 + d) * ns);
+          } else {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const unsigned st = (cur[d] >> (8 * r)) & 0xFFu;
-                if (st < (unsigned)ns) s4[r] += ut[st];
-              }
-            }
+            for (int d = 0; d < kBatchA; ++d)
+              if (i0 + d < np_) add_entry(s4, cur[d], (i0 + d) * ns);
           }
           if (nt == 0) {                 // the block's last batch: its rows' sums are complete
             const int64_t kp = kfirst + (int64_t)blk * wstride + 4 * lane;
@@ -401,25 +419,25 @@ struct CpsKernel {
         for (int i = tid; i < kPass * 256; i += NT) (&s_bin[0][0])[i] = 0;
         __syncthreads();
         // rows k4 .. k4+3 of every pass correlator: w and the state words of the thread's next
-        // rows load while this step's bins are added (issued after each other's atomics, the
-        // loads' latency bound this phase)
-        const int64_t kstep = (int64_t)NT * 4;
+        // rows load while this step's bins are added.  No branch around a load or an atomic
+        // (a branch makes the compiler wait for every outstanding access at the join):
+        // loads past the rows or the pass's correlators read clamped addresses (the last
+        // rows, kmax4 + 3 < ld_idx; the pass's first correlator), and an entry outside the
+        // rows or the correlator's states adds zero to bin 0.
+        const int64_t kstep = (int64_t)NT * 4, kmax4 = (n_s - 1) & ~(int64_t)3;
         double wv[4], wn[4];
         uint32_t sw[kPass], sn[kPass];
         auto fetch = [&](double (&wo)[4], uint32_t (&so)[kPass], int64_t k4) __attribute__((always_inline)) {
+          const int64_t kc = min(k4, kmax4);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) wo[e] = (k4 + e < n_s) ? ld_coh(&c.w[k4 + e]) : 0.0;
+          for (int e = 0; e < 4; ++e) wo[e] = ld_coh(&c.w[min(kc + e, n_s - 1)]);
 #pragma unroll
           for (int e = 0; e < kPass; ++e)
-            so[e] = e < np ? *(const uint32_t *)(c.idx + (p0 + (int64_t)e * G) * c.ld_idx + k4) : 0u;
+            so[e] = *(const uint32_t *)(c.idx + (p0 + (int64_t)(e < np ? e : 0) * G) * c.ld_idx + kc);
         };
-#pragma unroll
-        for (int e = 0; e < 4; ++e) wv[e] = wn[e] = 0.0;
-#pragma unroll
-        for (int e = 0; e < kPass; ++e) sw[e] = sn[e] = 0u;
-        if ((int64_t)tid * 4 < n_s) fetch(wv, sw, (int64_t)tid * 4);
+        fetch(wv, sw, (int64_t)tid * 4);
         for (int64_t k4 = (int64_t)tid * 4; k4 < n_s; k4 += kstep) {
-          if (k4 + kstep < n_s) fetch(wn, sn, k4 + kstep);
+          fetch(wn, sn, k4 + kstep);     // past the rows: clamped, unused
           long long qv[4];
 #pragma unroll
           for (int e = 0; e < 4; ++e) qv[e] = (k4 + e < n_s) ? __double2ll_rn((wv[e] - wbar) * sigma) : 0ll;
@@ -429,7 +447,8 @@ struct CpsKernel {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const unsigned s_ = (sw[e] >> (8 * r)) & 0xFFu;
-                if (k4 + r < n_s && s_ < (unsigned)ns) atomicAdd((unsigned long long *)&s_bin[e][s_], (unsigned long long)qv[r]);
+                const bool in = k4 + r < n_s && s_ < (unsigned)ns;
+                atomicAdd((unsigned long long *)&s_bin[e][in ? s_ : 0u], (unsigned long long)(in ? qv[r] : 0ll));
               }
             }
           }
