@@ -252,6 +252,7 @@ struct CpsKernel {
       }
       // the correlator part of the tile's row sums: tile_rows rows x (NT / tile_rows) slices
       __shared__ acc_t s_sp[kSlices][kCpsTileRows];
+      __shared__ double s_spr[kCpsTileRows];      // the correlator part of each tile row's w
       acc_t *s_spf = &s_sp[0][0];
       const int tr = c.tile_rows, nsl = NT / tr;
       __shared__ double s_red[2][NWAVE][RB];
@@ -318,7 +319,7 @@ struct CpsKernel {
           double wr = 0.0;
           if (k < n_s) {
             for (int wv = 0; wv < NWAVE; ++wv) wr += s_red[par][wv][r];
-            for (int pi = 0; pi < nsl; ++pi) wr += (double)s_spf[pi * tr + rb + r];
+            wr += s_spr[rb + r];
             wr -= cD;
           }
           if (tid == rb + r) my_w = wr;   // stored after the tile (no store inside the batch loop)
@@ -350,6 +351,13 @@ struct CpsKernel {
           for (int g = sl; g < c.n_grp; g += nsl) t += ld_acc(&part_sp[(int64_t)g * n_s + k]);
         }
         s_spf[sl * tr + row] = t;
+        __syncthreads();
+        // each row's slices summed once for the tile (not once per row inside the batches)
+        if (tid < tr) {
+          double sp = 0.0;
+          for (int pi = 0; pi < nsl; ++pi) sp += (double)s_spf[pi * tr + tid];
+          s_spr[tid] = sp;
+        }
         __syncthreads();
       };
       auto tile_tail = [&](int64_t k0) __attribute__((always_inline)) {
