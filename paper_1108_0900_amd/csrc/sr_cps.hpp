@@ -217,16 +217,33 @@ struct CpsKernel {
       // ---- 1. row pass ----
       const int64_t nvec = (n_d + VEC - 1) / VEC;
       acc_t vs[NVT][VEC], P[NVT][VEC];
+      {
+        // (s v) of the thread's columns with no branch around a load (columns past the
+        // block read its last column and are zeroed), so the loads issue together
+        const int64_t dmax = n_d > 0 ? n_d - 1 : 0;
+        auto coef = [&](bool scaled) __attribute__((always_inline)) {
 #pragma unroll
-      for (int m = 0; m < NVT; ++m) {
-        const int64_t vi = tid + (int64_t)m * NT;
+          for (int m = 0; m < NVT; ++m) {
+            const int64_t vi = tid + (int64_t)m * NT;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const int64_t col = vi * VEC + e;
-          double sv = 0.0;
-          if (vi < nvec && col < n_d) sv = (c.dscale ? (double)c.dscale[col] : 1.0) * ld_coh(&vin[n_sp + col]);
-          vs[m][e] = (acc_t)sv;
-          P[m][e] = (acc_t)0;
+            for (int e = 0; e < VEC; ++e) {
+              const int64_t col = vi * VEC + e, cc = min(col, dmax);
+              double sv = ld_coh(&vin[n_sp + cc]);
+              if (scaled) sv *= (double)c.dscale[cc];
+              vs[m][e] = (vi < nvec && col < n_d) ? (acc_t)sv : (acc_t)0;
+              P[m][e] = (acc_t)0;
+            }
+          }
+        };
+        if (n_d == 0) {
+#pragma unroll
+          for (int m = 0; m < NVT; ++m)
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) vs[m][e] = P[m][e] = (acc_t)0;
+        } else if (c.dscale) {
+          coef(true);
+        } else {
+          coef(false);
         }
       }
       // bf16 block with float32 accumulation: the row dots take packed bf16 pair products,
@@ -405,8 +422,17 @@ struct CpsKernel {
       for (int m = 0; m < NVT; ++m) {
         const int64_t vi = tid + (int64_t)m * NT;
         if (vi < nvec) {
+          acc_t *dst = &part[(int64_t)b * c.n_dp + vi * VEC];
+          if constexpr (sizeof(acc_t) == 4) {
+            // float partials in pairs (8-byte aligned: n_dp and the vector start are
+            // multiples of VEC)
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) st_acc(&part[(int64_t)b * c.n_dp + vi * VEC + e], P[m][e]);
+            for (int e = 0; e < VEC; e += 2)
+              st_coh64((u64 *)(dst + e), (u64)__float_as_uint((float)P[m][e]) | ((u64)__float_as_uint((float)P[m][e + 1]) << 32));
+          } else {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) st_acc(&dst[e], P[m][e]);
+          }
         }
       }
       double Sw, Sa;
