@@ -235,11 +235,21 @@ struct CpsKernel {
             }
           }
         };
-        if (n_d == 0) {
+        if (EXACT || n_d == 0) {
+          // (the float64-accumulated product, run inside the CG's residual logic, loads them
+          // one after another: its registers are the scarcer)
 #pragma unroll
-          for (int m = 0; m < NVT; ++m)
+          for (int m = 0; m < NVT; ++m) {
+            const int64_t vi = tid + (int64_t)m * NT;
 #pragma unroll
-            for (int e = 0; e < VEC; ++e) vs[m][e] = P[m][e] = (acc_t)0;
+            for (int e = 0; e < VEC; ++e) {
+              const int64_t col = vi * VEC + e;
+              double sv = 0.0;
+              if (vi < nvec && col < n_d) sv = (c.dscale ? (double)c.dscale[col] : 1.0) * ld_coh(&vin[n_sp + col]);
+              vs[m][e] = (acc_t)sv;
+              P[m][e] = (acc_t)0;
+            }
+          }
         } else if (c.dscale) {
           coef(true);
         } else {
@@ -492,7 +502,18 @@ struct CpsKernel {
           for (int e = 0; e < kPass; ++e) sw[e] = sn[e];
         }
         __syncthreads();
-        // the pass correlators' values and v load together
+        // the pass correlators' values and v load together (one after another in the
+        // float64-accumulated product, whose registers are the scarcer)
+        if constexpr (EXACT) {
+          for (int e = 0; e < np; ++e) {
+            const int64_t p = p0 + (int64_t)e * G;
+            for (int s_ = tid; s_ < ns; s_ += NT) {
+              const int64_t j = p * ns + s_;
+              const double T = (double)s_bin[e][s_] * inv_sigma;
+              st_coh(&q[j], c.val[j] * T * inv_n + a.eps * ld_coh(&vin[j]));
+            }
+          }
+        } else
         for (int s_ = tid; s_ < ns; s_ += NT) {
           double vv[kPass], vl[kPass];
 #pragma unroll
