@@ -466,8 +466,8 @@ struct CpsKernel {
         // rows load while this step's bins are added.  No branch around a load or an atomic
         // (a branch makes the compiler wait for every outstanding access at the join):
         // loads past the rows or the pass's correlators read clamped addresses (the last
-        // rows, kmax4 + 3 < ld_idx; the pass's first correlator), and an entry outside the
-        // rows or the correlator's states adds zero to bin 0.
+        // rows, kmax4 + 3 < ld_idx; the pass's first correlator); rows past n_s add zero,
+        // and a state outside the correlator adds to its own bin, which is never read.
         const int64_t kstep = (int64_t)NT * 4, kmax4 = (n_s - 1) & ~(int64_t)3;
         double wv[4], wn[4];
         uint32_t sw[kPass], sn[kPass];
@@ -489,11 +489,8 @@ struct CpsKernel {
           for (int e = 0; e < kPass; ++e) {
             if (e < np) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const unsigned s_ = (sw[e] >> (8 * r)) & 0xFFu;
-                const bool in = k4 + r < n_s && s_ < (unsigned)ns;
-                atomicAdd((unsigned long long *)&s_bin[e][in ? s_ : 0u], (unsigned long long)(in ? qv[r] : 0ll));
-              }
+              for (int r = 0; r < 4; ++r)   // (a state s >= n_states adds to a bin never read)
+                atomicAdd((unsigned long long *)&s_bin[e][(sw[e] >> (8 * r)) & 0xFFu], (unsigned long long)qv[r]);
             }
           }
 #pragma unroll
