@@ -2525,6 +2525,19 @@ static int check_stream_acc(const sr_stream_acc *acc, const char *name) {
   return SR_OK;
 }
 
+extern "C++" {
+namespace sr {
+int stream_dot_blocks();   // workgroups per vector of the partial-dot kernel (sr_kernels_common.hip)
+}
+}
+
+// Stream scratch, one size for every call on an accumulator (so that the finish does not
+// grow the workspace): batch means, batch gradient, one raw product, zero means, <E>_b,
+// then the partial dots of the finish (m x stream_dot_blocks()).
+static size_t stream_ws_bytes(int64_t n_p, int m) {
+  return (size_t)(4 * round_up(n_p, 32) + 64 + (int64_t)m * sr::stream_dot_blocks()) * 8;
+}
+
 static int stream_launch(int which, const StreamArgs &a, int blocks, hipStream_t s) {
   StreamArgs b = a;
   void *args[] = {&b};
@@ -2573,7 +2586,7 @@ int sr_stream_accumulate(const sr_stream_acc *acc, const sr_matrix *O, const sr_
   if (rc) return rc;
   // scratch: batch means, batch gradient, one raw product, zero means, <E>_b
   double *scr = nullptr;
-  rc = get_workspace(dev, stream, (size_t)(4 * round_up(n_p, 32) + 64) * 8, (void **)&scr, g_stream_ws);
+  rc = get_workspace(dev, stream, stream_ws_bytes(n_p, acc->m), (void **)&scr, g_stream_ws);
   if (rc) return rc;
   const int64_t np32 = round_up(n_p, 32);
   double *mean_b = scr, *g_b = scr + np32, *y_b = scr + 2 * np32, *zeros = scr + 3 * np32, *Eb = scr + 4 * np32;
@@ -2629,8 +2642,10 @@ int sr_stream_finish(const sr_stream_acc *acc, const double *Z, double eps, doub
   DeviceInfo di;
   rc = device_check(&dev, &di);
   if (rc) return rc;
+  // partial dots of s1 . z_i: stream_dot_blocks() per vector (summed by the finish kernel)
+  const int dot_blocks = sr::stream_dot_blocks();
   double *scr = nullptr;
-  rc = get_workspace(dev, stream, (size_t)(4 * round_up(n_p, 32) + 64) * 8, (void **)&scr, g_stream_ws);
+  rc = get_workspace(dev, stream, stream_ws_bytes(n_p, acc->m), (void **)&scr, g_stream_ws);
   if (rc) return rc;
   StreamArgs a{};
   a.n_p = n_p;
@@ -2646,7 +2661,7 @@ int sr_stream_finish(const sr_stream_acc *acc, const double *Z, double eps, doub
   a.col_mean = col_mean;
   a.E_mean = E_mean;
   a.dots = scr + 4 * round_up(n_p, 32) + 16;
-  if ((rc = stream_launch(2, a, acc->m, stream))) return rc;
+  if ((rc = stream_launch(2, a, acc->m * dot_blocks, stream))) return rc;
   const int blocks = (int)std::min<int64_t>(4 * (int64_t)di.cus, std::max<int64_t>(1, cdiv(n_p, 256)));
   return stream_launch(3, a, blocks, stream);
 }

@@ -130,11 +130,19 @@ __global__ void k_stream_addy(StreamArgs a) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n_p; j += (int64_t)gridDim.x * blockDim.x)
     Ai[j] += a.B * a.y_b[j];
 }
-// dots[i] = s1 . z_i, one workgroup per vector (fixed order)
+// Partial dots of s1 . z_i: kStreamDotBlocks workgroups per vector, each over a fixed chunk
+// of the parameters, write dots[i * kStreamDotBlocks + b]; k_stream_finish sums them in
+// block order (a fixed order: the result is the same on every run).
+constexpr int kStreamDotBlocks = 64;
+constexpr int kStreamDotVectors = 8;     // at most this many vectors (the host checks m)
+int stream_dot_blocks() { return kStreamDotBlocks; }
 __global__ __launch_bounds__(512) void k_stream_dots(StreamArgs a) {
-  const double *z = a.Z + (int64_t)blockIdx.x * a.n_p;
+  const int i = (int)blockIdx.x / kStreamDotBlocks, b = (int)blockIdx.x % kStreamDotBlocks;
+  const int64_t ch = (a.n_p + kStreamDotBlocks - 1) / kStreamDotBlocks;
+  const int64_t j0 = min(a.n_p, (int64_t)b * ch), j1 = min(a.n_p, j0 + ch);
+  const double *z = a.Z + (int64_t)i * a.n_p;
   double acc = 0.0;
-  for (int64_t j = threadIdx.x; j < a.n_p; j += 512) acc += a.s1[j] * z[j];
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += 512) acc += a.s1[j] * z[j];
   acc = block_sum(acc);
   if (threadIdx.x == 0) a.dots[blockIdx.x] = acc;
 }
@@ -142,11 +150,18 @@ __global__ __launch_bounds__(512) void k_stream_dots(StreamArgs a) {
 // g = 2 (se / n - <E> obar), col_mean = obar, E_mean = <E>
 __global__ void k_stream_finish(StreamArgs a) {
   const double n = a.scal[0], inv_n = 1.0 / n, Ebar = a.scal[1] * inv_n;
+  __shared__ double s_dots[kStreamDotVectors];
+  if ((int)threadIdx.x < a.m && (int)threadIdx.x < kStreamDotVectors) {
+    double t = 0.0;
+    for (int b = 0; b < kStreamDotBlocks; ++b) t += a.dots[threadIdx.x * kStreamDotBlocks + b];
+    s_dots[threadIdx.x] = t;
+  }
+  __syncthreads();
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < a.n_p; j += (int64_t)gridDim.x * blockDim.x) {
     const double ob = a.s1[j] * inv_n;
     for (int i = 0; i < a.m; ++i) {
       const int64_t ij = (int64_t)i * a.n_p + j;
-      a.Y[ij] = a.A[ij] * inv_n - ob * (a.dots[i] * inv_n) + a.eps * a.Z[ij];
+      a.Y[ij] = a.A[ij] * inv_n - ob * (s_dots[i] * inv_n) + a.eps * a.Z[ij];
     }
     if (a.col_mean) a.col_mean[j] = ob;
     if (a.g && a.se) a.g[j] = 2.0 * (a.se[j] * inv_n - Ebar * ob);
