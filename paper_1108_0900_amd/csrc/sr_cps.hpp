@@ -133,14 +133,12 @@ struct CpsKernel {
         __syncthreads();
         // The (block, batch of kBatchA correlators) pairs of this wave form one stream; the
         // state words of the next pair load while the current pair's table entries are
-        // summed (issued one batch after another, the loads' latency bound this phase).
-        // Rows k0 .. k0+3 of a lane lie below ld_idx (a multiple of 16, >= n_s) whenever
-        // k0 < n_s, so the 4-byte loads stay inside the row.
+        // summed.  Rows k0 .. k0+3 of a lane lie below ld_idx (a multiple of 16, >= n_s)
+        // whenever k0 < n_s, so the 4-byte loads stay inside the row.
         const int64_t r0 = min(n_s, (int64_t)rr * c.rpr), r1 = min(n_s, r0 + c.rpr);
         const int64_t sti = c.ld_idx;
         const int64_t kfirst = r0 + (int64_t)wave * kRowsA, wstride = (int64_t)NWAVE * kRowsA;
-        // (at least one batch: a group without correlators still stores its rows' zero sums)
-        const int nbat = max(1, (np_ + kBatchA - 1) / kBatchA);
+        const int nbat = (np_ + kBatchA - 1) / kBatchA;
         const int nblk = kfirst < r1 ? (int)((r1 - kfirst + wstride - 1) / wstride) : 0;
         const int total = nblk * nbat;
         const unsigned char *ib = c.idx + p0 * sti;
