@@ -283,12 +283,11 @@ struct CpsKernel {
       __shared__ double s_red[2][NWAVE][RB];
       double wsum = 0.0, wabs = 0.0;
       int par = 0;
-      // one batch of RB dense rows into registers (rows past n_s and vectors past the row
-      // load nothing)
-      // Rows past n_s and vectors past the row load the last row's or vector's data
-      // instead (no branch around a load: the compiler's wait counting then keeps the other
-      // batch's loads in flight).  Such values only ever meet a zero weight (w_k = 0 for
-      // k >= n_s, v = 0 past the row) and are never stored.
+      // One batch of RB dense rows into registers.  Rows past n_s and vectors past the row
+      // load the last row's or vector's data instead (no branch around a load: the
+      // compiler's wait counting then keeps the other batch's loads in flight).  Such
+      // values only ever meet a zero weight (w_k = 0 for k >= n_s, v = 0 past the row) and
+      // are never stored.
       auto load_batch = [&](u32x4 (&D)[RB][NVT], int64_t k0b) __attribute__((always_inline)) {
         if (nvec == 0) {
 #pragma unroll
